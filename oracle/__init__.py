@@ -1,0 +1,112 @@
+"""CPU oracle for the exact directed motif census -- test infrastructure only.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It computes the census from its plain
+definition (paper, Section "Problem statement": count the weakly connected
+induced k-subgraphs, k = 3, 4, 5, grouped by isomorphism class) by ESU
+enumeration plus canonical labelling over all k! vertex permutations, and it
+shares no code with the GPU library.
+
+Class ids: rank of the canonical code (minimum over all k! relabellings of the
+k(k-1)-bit adjacency code, arc i->j at bit i*(k-1) + (j<i ? j : j-1)) among the
+weakly connected classes, ascending.  The paper leaves the numbering free
+("arbitrarily associated", "hard coded").
+
+Parity: every function here is pinned in ``tests/test_oracle.py`` against the
+paper's class counts, its star worked example, its multiplicities and closed
+forms, and against the independent pure-Python all-subsets checker in
+``oracle/brute.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import functools
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+N_CLASSES = {3: 13, 4: 199, 5: 9364}
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+@functools.lru_cache(maxsize=1)
+def _lib():
+    lib = ctypes.CDLL(build())
+    P = ctypes.c_void_p
+    lib.oracle_class_table.argtypes = [ctypes.c_int, P, P, P, P, P]
+    lib.oracle_class_table.restype = ctypes.c_int
+    lib.oracle_multiplicity.argtypes = [ctypes.c_int, ctypes.c_uint32]
+    lib.oracle_multiplicity.restype = ctypes.c_int
+    lib.oracle_census.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, P, ctypes.c_int32, P, ctypes.c_int32]
+    lib.oracle_census.restype = ctypes.c_int
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+@functools.lru_cache(maxsize=4)
+def class_table(k: int):
+    """(cls_of_code uint16[2^(k(k-1))], canon_of_class uint32[C], n_all_classes,
+    n_connected_codes) computed by brute force over all codes and permutations."""
+    lib = _lib()
+    nb = k * (k - 1)
+    cls = np.empty(1 << nb, dtype=np.uint16)
+    canon = np.zeros(16384, dtype=np.uint32)
+    nc = np.zeros(1, np.int32)
+    na = np.zeros(1, np.int32)
+    ncodes = np.zeros(1, np.int64)
+    rc = lib.oracle_class_table(k, _ptr(cls), _ptr(canon), _ptr(nc), _ptr(na), _ptr(ncodes))
+    if rc != 0:
+        raise RuntimeError(f"oracle_class_table failed: {rc}")
+    cls.setflags(write=False)
+    c = canon[: int(nc[0])].copy()
+    c.setflags(write=False)
+    return cls, c, int(na[0]), int(ncodes[0])
+
+
+def multiplicity(k: int, code: int) -> int:
+    """Number of connected (k-2)-subsets dominating the other two vertices."""
+    return int(_lib().oracle_multiplicity(k, code))
+
+
+def census(g, k: int, threads: int = 0) -> np.ndarray:
+    """uint64 histogram over the classes for graph ``g`` (graphgen.Digraph or
+    anything with n, out_off, out_idx)."""
+    cls, canon, _, _ = class_table(k)
+    hist = np.zeros(len(canon), dtype=np.uint64)
+    off = np.ascontiguousarray(g.out_off, dtype=np.int32)
+    idx = np.ascontiguousarray(g.out_idx, dtype=np.int32)
+    if idx.size == 0:
+        idx = np.zeros(1, np.int32)
+    rc = _lib().oracle_census(int(g.n), _ptr(off), _ptr(idx), k, _ptr(cls), len(canon), _ptr(hist), threads)
+    if rc != 0:
+        raise RuntimeError(f"oracle_census failed: {rc}")
+    return hist
+
+
+def code_of(k: int, arcs) -> int:
+    """Adjacency code of a k-vertex pattern given as (i, j) arcs."""
+    code = 0
+    for i, j in arcs:
+        code |= 1 << (i * (k - 1) + (j if j < i else j - 1))
+    return code
+
+
+def class_of(k: int, arcs) -> int:
+    """Class id of the k-vertex pattern with these arcs (0xFFFF if disconnected)."""
+    return int(class_table(k)[0][code_of(k, arcs)])

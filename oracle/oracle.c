@@ -1,0 +1,316 @@
+/*
+ * CPU oracle for the exact directed motif census -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg use
+ * this file.  It shares no code, header, table or constant with the GPU
+ * library: it computes the census from its plain definition.
+ *
+ * Definition (paper, Section "Problem statement", Problems Motifs-3/4/5, with
+ * the undirected version G* of Section "Notation and definitions"):
+ *   hist[c] = #{ S subset V : |S| = k, G*[S] connected, class(G[S]) = c }
+ * where "connected" is weak connectivity (connectivity of G*) and class(H) is
+ * the isomorphism class of the induced digraph H.
+ *
+ * Class numbering (the paper fixes none; it says positions are arbitrary and
+ * hard coded, Algorithms "Count 3/4/5 Sized Patterns"): for k vertices, the
+ * arc i->j (i != j) is bit  i*(k-1) + (j < i ? j : j-1)  of a k(k-1)-bit code.
+ * canon(x) = min over all k! vertex permutations of the permuted code.  Class
+ * id = rank of canon(x) among the distinct canonical codes of weakly connected
+ * codes, ascending.
+ *
+ * Enumeration: ESU (Wernicke's exact subgraph enumeration, the algorithm of
+ * the FANMOD tool the paper compares against): every connected k-subset is
+ * emitted exactly once; its code is built over its vertices sorted by id and
+ * mapped through the class table.
+ *
+ * Multiplicity (used only to test the GPU's final division): for a k-vertex
+ * pattern, the number of (k-2)-subsets T whose G*[T] is connected and which
+ * dominate the rest (every vertex outside T is adjacent to a vertex of T).
+ * This is the number of anchors -- a vertex for k=3 (v-Patterns), an edge for
+ * k=4 (e-Patterns, Fact "correction"), a connected triple for k=5
+ * (Delta-Patterns) -- whose pattern set contains the k-set.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_EINVAL (-1)
+#define OR_ENOMEM (-2)
+
+static int bitpos(int k, int i, int j) { return i * (k - 1) + (j < i ? j : j - 1); }
+
+/* All k! permutations of 0..k-1 in lexicographic order. */
+static int all_perms(int k, int* out /* [k! * k] */) {
+    int p[8], cnt = 0;
+    for (int i = 0; i < k; ++i) p[i] = i;
+    for (;;) {
+        memcpy(out + cnt * k, p, sizeof(int) * k);
+        ++cnt;
+        int i = k - 2;
+        while (i >= 0 && p[i] > p[i + 1]) --i;
+        if (i < 0) break;
+        int j = k - 1;
+        while (p[j] < p[i]) --j;
+        int t = p[i]; p[i] = p[j]; p[j] = t;
+        for (int a = i + 1, b = k - 1; a < b; ++a, --b) { t = p[a]; p[a] = p[b]; p[b] = t; }
+    }
+    return cnt;
+}
+
+/* Code of the relabelled digraph: arc i->j becomes arc perm[i]->perm[j]. */
+static uint32_t permute_code(int k, uint32_t code, const int* perm) {
+    uint32_t out = 0;
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j)
+            if (i != j && ((code >> bitpos(k, i, j)) & 1u))
+                out |= 1u << bitpos(k, perm[i], perm[j]);
+    return out;
+}
+
+/* Weak connectivity of the k-vertex digraph with this code (DFS on G*). */
+static int code_connected(int k, uint32_t code) {
+    int adj[8][8] = {{0}};
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j)
+            if (i != j && ((code >> bitpos(k, i, j)) & 1u)) adj[i][j] = adj[j][i] = 1;
+    int seen[8] = {0}, stack[8], sp = 0, nseen = 1;
+    seen[0] = 1; stack[sp++] = 0;
+    while (sp) {
+        int a = stack[--sp];
+        for (int b = 0; b < k; ++b)
+            if (adj[a][b] && !seen[b]) { seen[b] = 1; ++nseen; stack[sp++] = b; }
+    }
+    return nseen == k;
+}
+
+static int cmp_u32(const void* a, const void* b) {
+    uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+    return x < y ? -1 : x > y;
+}
+
+/*
+ * Brute-force class table: cls_of_code[x] for every x in [0, 2^(k(k-1))),
+ * 0xFFFF for codes whose G* is disconnected.  canon_of_class[c] receives the
+ * canonical code of class c (room for 16384 entries).  Also reports the number
+ * of isomorphism classes of all digraphs and the number of connected codes.
+ */
+int oracle_class_table(int k, uint16_t* cls_of_code, uint32_t* canon_of_class,
+                       int32_t* n_classes, int32_t* n_all_classes, int64_t* n_connected_codes) {
+    if (k < 2 || k > 5) return OR_EINVAL;
+    const int nb = k * (k - 1);
+    const uint32_t N = 1u << nb;
+    int perms[120 * 5];
+    const int np = all_perms(k, perms);
+    uint32_t* canon = (uint32_t*)malloc(sizeof(uint32_t) * N);
+    uint8_t* conn = (uint8_t*)malloc(N);
+    if (!canon || !conn) { free(canon); free(conn); return OR_ENOMEM; }
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t x = 0; x < (int64_t)N; ++x) {
+        uint32_t best = (uint32_t)x;
+        for (int p = 0; p < np; ++p) {
+            uint32_t y = permute_code(k, (uint32_t)x, perms + p * k);
+            if (y < best) best = y;
+        }
+        canon[x] = best;
+        conn[x] = (uint8_t)code_connected(k, (uint32_t)x);
+    }
+    /* distinct canonical codes: those x with canon[x] == x */
+    int32_t all = 0, nc = 0;
+    int64_t ncodes = 0;
+    uint32_t* reps = (uint32_t*)malloc(sizeof(uint32_t) * 16384);
+    if (!reps) { free(canon); free(conn); return OR_ENOMEM; }
+    for (uint32_t x = 0; x < N; ++x) {
+        if (conn[x]) ++ncodes;
+        if (canon[x] == x) {
+            ++all;
+            if (conn[x]) { if (nc < 16384) reps[nc] = x; ++nc; }
+        }
+    }
+    qsort(reps, (size_t)nc, sizeof(uint32_t), cmp_u32);
+    for (uint32_t x = 0; x < N; ++x) {
+        if (!conn[x]) { cls_of_code[x] = 0xFFFF; continue; }
+        uint32_t c = canon[x];
+        int lo = 0, hi = nc - 1;
+        while (lo < hi) { int mid = (lo + hi) / 2; if (reps[mid] < c) lo = mid + 1; else hi = mid; }
+        cls_of_code[x] = (uint16_t)lo;
+    }
+    if (canon_of_class) memcpy(canon_of_class, reps, sizeof(uint32_t) * (size_t)nc);
+    *n_classes = nc;
+    *n_all_classes = all;
+    *n_connected_codes = ncodes;
+    free(reps); free(canon); free(conn);
+    return 0;
+}
+
+/* Number of (k-2)-subsets of the code's vertices that induce a connected G*
+ * and dominate the remaining two vertices. */
+int oracle_multiplicity(int k, uint32_t code) {
+    if (k < 3 || k > 5) return OR_EINVAL;
+    int adj[8][8] = {{0}};
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j)
+            if (i != j && ((code >> bitpos(k, i, j)) & 1u)) adj[i][j] = adj[j][i] = 1;
+    int count = 0;
+    for (int mask = 0; mask < (1 << k); ++mask) {
+        if (__builtin_popcount((unsigned)mask) != k - 2) continue;
+        /* connectivity of the subset */
+        int first = __builtin_ctz((unsigned)mask), seen = 1 << first, grow = 1;
+        while (grow) {
+            grow = 0;
+            for (int a = 0; a < k; ++a) if (seen >> a & 1)
+                for (int b = 0; b < k; ++b)
+                    if ((mask >> b & 1) && !(seen >> b & 1) && adj[a][b]) { seen |= 1 << b; grow = 1; }
+        }
+        if (seen != mask) continue;
+        int dom = 1;
+        for (int w = 0; w < k; ++w) {
+            if (mask >> w & 1) continue;
+            int hit = 0;
+            for (int a = 0; a < k; ++a) if ((mask >> a & 1) && adj[a][w]) hit = 1;
+            if (!hit) dom = 0;
+        }
+        count += dom;
+    }
+    return count;
+}
+
+/* ---------------------------------------------------------------- ESU ---- */
+
+typedef struct {
+    int n;
+    const int64_t* uoff;   /* undirected (G*) adjacency, sorted, unique */
+    const int32_t* uidx;
+    const int64_t* aoff;   /* out-arcs, sorted */
+    const int32_t* aidx;
+    int k;
+    const uint16_t* cls;
+    uint64_t* hist;        /* this thread's histogram */
+} esu_ctx;
+
+static int has_edge_u(const esu_ctx* c, int a, int b) {
+    int64_t lo = c->uoff[a], hi = c->uoff[a + 1];
+    while (lo < hi) { int64_t mid = lo + (hi - lo) / 2; if (c->uidx[mid] < b) lo = mid + 1; else hi = mid; }
+    return lo < c->uoff[a + 1] && c->uidx[lo] == b;
+}
+
+static int has_arc(const esu_ctx* c, int a, int b) {
+    int64_t lo = c->aoff[a], hi = c->aoff[a + 1];
+    while (lo < hi) { int64_t mid = lo + (hi - lo) / 2; if (c->aidx[mid] < b) lo = mid + 1; else hi = mid; }
+    return lo < c->aoff[a + 1] && c->aidx[lo] == b;
+}
+
+static void emit(esu_ctx* c, const int* sub) {
+    int k = c->k, v[5];
+    memcpy(v, sub, sizeof(int) * k);
+    for (int i = 1; i < k; ++i) { int t = v[i], j = i - 1; while (j >= 0 && v[j] > t) { v[j + 1] = v[j]; --j; } v[j + 1] = t; }
+    uint32_t code = 0;
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j)
+            if (i != j && has_arc(c, v[i], v[j])) code |= 1u << bitpos(k, i, j);
+    uint16_t cl = c->cls[code];
+    if (cl != 0xFFFF) c->hist[cl] += 1;   /* ESU only emits connected sets */
+}
+
+/* sub[0..depth) is the current subgraph, ext the extension set. */
+static void extend(esu_ctx* c, int* sub, int depth, const int* ext, int next, int root) {
+    if (depth == c->k) { emit(c, sub); return; }
+    int* work = (int*)malloc(sizeof(int) * (size_t)next);
+    memcpy(work, ext, sizeof(int) * (size_t)next);
+    int nwork = next;
+    while (nwork > 0) {
+        int w = work[--nwork];
+        /* ext' = remaining ext  U  { u in N(w) : u > root, u not in sub,
+         *                             u not adjacent to any vertex of sub } */
+        int64_t dw = c->uoff[w + 1] - c->uoff[w];
+        int* ext2 = (int*)malloc(sizeof(int) * (size_t)(nwork + dw + 1));
+        memcpy(ext2, work, sizeof(int) * (size_t)nwork);
+        int n2 = nwork;
+        for (int64_t p = c->uoff[w]; p < c->uoff[w + 1]; ++p) {
+            int u = c->uidx[p];
+            if (u <= root) continue;
+            int bad = 0;
+            for (int s = 0; s < depth && !bad; ++s)
+                if (sub[s] == u || has_edge_u(c, sub[s], u)) bad = 1;
+            if (!bad) ext2[n2++] = u;
+        }
+        sub[depth] = w;
+        extend(c, sub, depth + 1, ext2, n2, root);
+        free(ext2);
+    }
+    free(work);
+}
+
+static int cmp_i32(const void* a, const void* b) {
+    int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    return x < y ? -1 : x > y;
+}
+
+/*
+ * Census of the simple digraph given as out-CSR (rows may be unsorted).
+ * hist[n_classes] is overwritten.  threads <= 0 means the OpenMP default.
+ */
+int oracle_census(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32_t k,
+                  const uint16_t* cls_of_code, int32_t n_classes, uint64_t* hist, int32_t threads) {
+    if (k < 3 || k > 5 || n < 0) return OR_EINVAL;
+    memset(hist, 0, sizeof(uint64_t) * (size_t)n_classes);
+    if (n == 0) return 0;
+    int64_t m = out_off[n];
+    int64_t* aoff = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int32_t* aidx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m + 1));
+    int64_t* deg = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t* uoff = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int32_t* uidx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
+    if (!aoff || !aidx || !deg || !uoff || !uidx) return OR_ENOMEM;
+    for (int v = 0; v <= n; ++v) aoff[v] = out_off[v];
+    memcpy(aidx, out_idx, sizeof(int32_t) * (size_t)m);
+    for (int v = 0; v < n; ++v) qsort(aidx + aoff[v], (size_t)(aoff[v + 1] - aoff[v]), sizeof(int32_t), cmp_i32);
+    /* G*: both directions, then sort + unique per row */
+    for (int v = 0; v < n; ++v)
+        for (int64_t p = aoff[v]; p < aoff[v + 1]; ++p) { deg[v]++; deg[aidx[p]]++; }
+    uoff[0] = 0;
+    for (int v = 0; v < n; ++v) uoff[v + 1] = uoff[v] + deg[v];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    for (int v = 0; v < n; ++v) fill[v] = uoff[v];
+    for (int v = 0; v < n; ++v)
+        for (int64_t p = aoff[v]; p < aoff[v + 1]; ++p) { uidx[fill[v]++] = aidx[p]; uidx[fill[aidx[p]]++] = v; }
+    int64_t w = 0;
+    int64_t* uoff2 = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    uoff2[0] = 0;
+    for (int v = 0; v < n; ++v) {
+        qsort(uidx + uoff[v], (size_t)(uoff[v + 1] - uoff[v]), sizeof(int32_t), cmp_i32);
+        int64_t start = w;
+        for (int64_t p = uoff[v]; p < uoff[v + 1]; ++p)
+            if (w == start || uidx[w - 1] != uidx[p]) uidx[w++] = uidx[p];
+        uoff2[v + 1] = w;
+    }
+    free(fill);
+    int nthreads = 1;
+#ifdef _OPENMP
+    nthreads = threads > 0 ? threads : omp_get_max_threads();
+#endif
+    uint64_t* th = (uint64_t*)calloc((size_t)nthreads * (size_t)n_classes, sizeof(uint64_t));
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+    for (int root = 0; root < n; ++root) {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        esu_ctx c = { n, uoff2, uidx, aoff, aidx, k, cls_of_code, th + (size_t)tid * n_classes };
+        int sub[5];
+        sub[0] = root;
+        int64_t d = uoff2[root + 1] - uoff2[root];
+        int* ext = (int*)malloc(sizeof(int) * (size_t)(d + 1));
+        int ne = 0;
+        for (int64_t p = uoff2[root]; p < uoff2[root + 1]; ++p)
+            if (uidx[p] > root) ext[ne++] = uidx[p];
+        extend(&c, sub, 1, ext, ne, root);
+        free(ext);
+    }
+    for (int t = 0; t < nthreads; ++t)
+        for (int cl = 0; cl < n_classes; ++cl) hist[cl] += th[(size_t)t * n_classes + cl];
+    free(th); free(aoff); free(aidx); free(deg); free(uoff); free(uoff2); free(uidx);
+    return 0;
+}
