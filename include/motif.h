@@ -1,0 +1,230 @@
+/*
+ * motif.h -- C ABI of the MI355X (gfx950) exact directed motif census.
+ *
+ * What is computed (paper, Section "Problem statement", Problems Motifs-3,
+ * Motifs-4 and Motifs-5): for a simple directed graph G and k in {3,4,5}, the
+ * number of k-vertex subsets S whose induced subgraph is weakly connected
+ * (connected in the undirected version G*, Section "Notation and
+ * definitions"), grouped by the isomorphism class of the induced digraph G[S]
+ * into 13, 199 or 9364 classes.  Counts are exact unsigned 64-bit integers.
+ *
+ * How (paper, "combinatorial acceleration"): every k-set is charged to the
+ * anchors that see it -- a vertex (v-Patterns, Theorem "teo3"), an undirected
+ * edge (e-Patterns, Theorem "lema4d" and its corollary) or a connected triple
+ * (Delta-Patterns, Lemma "lema5d") -- using closed forms for neighbour pairs
+ * with no edge between them (Facts "base"/"basefive") and edge counts between
+ * the neighbour sets for the rest; each class total is finally divided by the
+ * number of anchors that see one occurrence (Fact "correction").
+ *
+ * Class numbering.  The paper leaves positions arbitrary.  Here: for k
+ * vertices the arc i->j (i != j) is bit  i*(k-1) + (j < i ? j : j-1)  of a
+ * k(k-1)-bit code; the canonical code of a digraph is the minimum code over
+ * all k! relabellings; class ids are the ranks of the canonical codes of the
+ * weakly connected classes in ascending order.  motif_class_code() returns the
+ * canonical code of a class so callers can map ids to other tools' numbering.
+ *
+ * Conventions for every entry point:
+ *  - Return 0 on success, a negative MOTIF_E* code on error.  On error no
+ *    output buffer is written.
+ *  - Graphs are int32 out-CSR: the arcs of vertex u are u -> out_idx[j] for
+ *    out_off[u] <= j < out_off[u+1].  n < 2^30, m < 2^30.
+ *  - Device pointers are hipMalloc'ed (or torch CUDA) memory owned by the
+ *    caller; the library never frees them.  The library owns its internal
+ *    workspaces and class tables (device memory), released by
+ *    motif_shutdown().
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    on it; input validation ends with one host wait on that stream so that
+ *    an invalid graph is reported by the return code.  The histogram is
+ *    complete when the stream is synchronised.
+ *  - Thread safety: calls on different streams may run concurrently (each
+ *    stream gets its own workspace); calls on the same stream are ordered.
+ */
+#ifndef MOTIF_H_
+#define MOTIF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------- */
+#define MOTIF_OK 0
+#define MOTIF_EINVAL_K (-1)      /* k not in {3,4,5}                                  */
+#define MOTIF_EINVAL_SHAPE (-2)  /* n/m out of range, offsets not monotone,
+                                    out_off[0] != 0 or out_off[n] != m                */
+#define MOTIF_EINDEX (-3)        /* a neighbour index outside [0, n)                   */
+#define MOTIF_ESELFLOOP (-4)     /* an arc u -> u                                     */
+#define MOTIF_EDUP (-5)          /* the same arc listed twice                          */
+#define MOTIF_ETRANSPOSE (-6)    /* the in-CSR given is not the transpose of out-CSR  */
+#define MOTIF_ENOMEM (-7)        /* device or host allocation failed                  */
+#define MOTIF_EDEVICE (-8)       /* a HIP runtime call failed / no gfx950 device      */
+#define MOTIF_EAGAIN (-9)        /* server: not admitted now (memory or slots busy)   */
+#define MOTIF_ETOOBIG (-10)      /* server: request can never fit the HBM budget      */
+#define MOTIF_ETIMEOUT (-11)     /* server: wait timed out                             */
+#define MOTIF_ECANCELED (-12)    /* server: request was cancelled                      */
+#define MOTIF_EINVAL_ARG (-13)   /* other bad argument (NULL pointer, bad count...)   */
+#define MOTIF_EINTERNAL (-14)    /* self-check failed: a class total was not an exact
+                                    multiple of its anchor multiplicity               */
+
+/* One graph in int32 CSR.  in_off/in_idx may be NULL (the transpose is built
+ * internally); when given they must describe exactly the transpose of the
+ * out-CSR (rows in any order).  For motif_census_batch() all pointers are
+ * device pointers; for motif_server_submit() they are host pointers. */
+typedef struct motif_graph {
+  const int32_t* out_off; /* [n+1] */
+  const int32_t* out_idx; /* [m]   */
+  const int32_t* in_off;  /* [n+1] or NULL */
+  const int32_t* in_idx;  /* [m]   or NULL */
+  int32_t n;
+  int64_t m;
+} motif_graph_t;
+
+/* ---- library state and class tables (host) ------------------------------- */
+
+/* Builds the class tables for k = 3, 4, 5 on the host (code -> class, class
+ * multiplicities) and uploads them to the current device.  Idempotent; called
+ * implicitly by the census entry points.  Returns MOTIF_EDEVICE when no gfx950
+ * device is present; the host-only helpers below still work then. */
+int32_t motif_init(void);
+
+/* Frees every device buffer the library owns (tables, workspaces). */
+int32_t motif_shutdown(void);
+
+/* 13, 199 or 9364 (paper, Problems Motifs-3/4/5); MOTIF_EINVAL_K otherwise. */
+int32_t motif_num_classes(int32_t k);
+
+/* Canonical k(k-1)-bit code of class `cls` (see "Class numbering" above).
+ * Host-only; needs no device. */
+int32_t motif_class_code(int32_t k, int32_t cls, uint32_t* canon_code);
+
+/* Number of anchors that see one occurrence of class `cls`: vertices for k=3
+ * (1 for an open wedge, 3 for a triangle: Algorithm "Count 3 Sized Patterns"),
+ * undirected edges for k=4 (1/3/3/4/5/6 for P4/claw/tailed triangle/C4/
+ * K4-minus-edge/K4, Fact "correction"), connected triples for k=5 (5 for the
+ * 5-cycle, Figure "correction:five").  It is the number of connected
+ * (k-2)-subsets that dominate the other two vertices.  Host-only.  Returns the
+ * multiplicity (>= 1) or a negative error code. */
+int32_t motif_class_multiplicity(int32_t k, int32_t cls);
+
+/* Class id of an arbitrary k(k-1)-bit code, or -1 when the code's undirected
+ * version is disconnected.  Host-only. */
+int32_t motif_class_of_code(int32_t k, uint32_t code);
+
+/* Static description of an error code. */
+const char* motif_strerror(int32_t code);
+
+/* ---- census --------------------------------------------------------------- */
+
+/* Exact census of one graph (paper, Algorithms "Count 3/4/5 Sized Patterns").
+ *  out_off, out_idx : device, the graph (rows need not be sorted).
+ *  in_off, in_idx   : device or both NULL; validated against the out-CSR.
+ *  n, m             : vertex and arc counts.
+ *  k                : 3, 4 or 5.
+ *  hist             : device, motif_num_classes(k) uint64, overwritten.
+ * Validation errors: MOTIF_EINVAL_SHAPE, MOTIF_EINDEX, MOTIF_ESELFLOOP,
+ * MOTIF_EDUP, MOTIF_ETRANSPOSE.  n < k or m = 0 gives an all-zero histogram. */
+int32_t motif_census(const int32_t* out_off, const int32_t* out_idx, const int32_t* in_off,
+                     const int32_t* in_idx, int32_t n, int64_t m, int32_t k, uint64_t* hist,
+                     void* stream);
+
+/* Census of `count` graphs in one fused pass: the graphs are packed into one
+ * disjoint union on the device, built once, and censused by one persistent
+ * kernel that pulls anchor tiles from a device work queue; each tile's counts
+ * are routed to its own graph's histogram.  hists: device, count *
+ * motif_num_classes(k) uint64 (graph g at offset g*C).  hists[g] equals
+ * motif_census() on graph g alone, bit for bit.  `graphs` is a host array of
+ * descriptors holding device pointers.  Used for null-model ensembles of
+ * degree-preserving randomisations (paper, Section "Implementation", step
+ * (iii); Section "Results and Discussion", random-graph ensembles). */
+int32_t motif_census_batch(const motif_graph_t* graphs, int32_t count, int32_t k, uint64_t* hists,
+                           void* stream);
+
+/* Same result as motif_census_batch() by the plain route: one motif_census()
+ * pipeline per graph, enqueued back to back on `stream`.  Kept as the
+ * baseline the fused launch is measured against. */
+int32_t motif_census_batch_loop(const motif_graph_t* graphs, int32_t count, int32_t k,
+                                uint64_t* hists, void* stream);
+
+/* ---- tuning ---------------------------------------------------------------- */
+
+/* Tunable launch parameters of the census kernels. */
+typedef struct motif_tuning {
+  int32_t block;        /* threads per workgroup for the anchor kernels (64..1024)  */
+  int32_t grid_per_cu;  /* persistent workgroups per compute unit (1..16)           */
+  int32_t tile;         /* anchors per work-queue tile for light anchors (1..4096)  */
+  int32_t heavy;        /* adjacency size above which an anchor is "heavy" and is
+                           processed by a whole workgroup (0 = every anchor)        */
+} motif_tuning_t;
+
+/* Read / override the parameters used for k (0 in a field = keep default). */
+int32_t motif_get_tuning(int32_t k, motif_tuning_t* out);
+int32_t motif_set_tuning(int32_t k, const motif_tuning_t* in);
+
+/* Autotuner: times the fused batch census of `graphs` (device pointers, as for
+ * motif_census_batch) under a small grid of candidate tunings, keeps the
+ * fastest for k (it is then used by every later call) and writes it to *best.
+ * `hists` is scratch output (count * C uint64, device).  Every candidate's
+ * histograms are checked equal to the first candidate's; a mismatch returns
+ * MOTIF_EINTERNAL. */
+int32_t motif_autotune(const motif_graph_t* graphs, int32_t count, int32_t k, uint64_t* hists,
+                       void* stream, motif_tuning_t* best);
+
+/* ---- measurement ------------------------------------------------------------ */
+
+/* When enabled, every census call records HIP events on its stream around the
+ * G* build and around the main census kernel of k.  Off by default. */
+int32_t motif_profile_enable(int32_t on);
+
+/* Durations in ms of the census kernel and of the build in the most recent
+ * profiled call for k (waits for those events).  MOTIF_EINVAL_ARG if none. */
+int32_t motif_profile_read(int32_t k, float* kernel_ms, float* build_ms);
+
+/* ---- serving ---------------------------------------------------------------- */
+
+/* Continuous-batching census server on the current device.  Requests arrive
+ * with host CSR buffers; the server copies each graph into device memory it
+ * owns, admits a request only while the summed device footprint of admitted
+ * requests stays within hbm_budget_bytes and fewer than max_inflight requests
+ * are on the device, runs admitted requests concurrently on separate HIP
+ * streams (new requests start while others are still running) and copies each
+ * histogram back to the caller's host buffer. */
+typedef struct motif_server motif_server_t;
+
+/* Returns NULL on failure (no device, bad arguments). */
+motif_server_t* motif_server_create(size_t hbm_budget_bytes, int32_t max_inflight);
+
+/* Device bytes a request for this graph and k would hold while admitted. */
+int64_t motif_request_footprint(int32_t n, int64_t m, int32_t k);
+
+/* Queue one request.  `g` holds HOST pointers; they are copied before this
+ * call returns, so the caller may reuse them.  hist_out_host must stay valid
+ * until the request completes (motif_server_wait returns) or is cancelled.
+ * Returns MOTIF_ETOOBIG if the footprint exceeds the budget, MOTIF_EAGAIN if
+ * the pending queue is full.  *ticket identifies the request. */
+int32_t motif_server_submit(motif_server_t* s, const motif_graph_t* g, int32_t k,
+                            uint64_t* hist_out_host, uint64_t* ticket);
+
+/* Wait for a request.  timeout_us < 0 waits forever.  Returns the request's
+ * own status (0 or a census error code), MOTIF_ETIMEOUT, or MOTIF_ECANCELED.
+ * After a non-timeout return the ticket is released. */
+int32_t motif_server_wait(motif_server_t* s, uint64_t ticket, int64_t timeout_us);
+
+/* Cancel a request that has not started on the device yet (returns 0), or
+ * MOTIF_EAGAIN if it is already running (it will complete normally). */
+int32_t motif_server_cancel(motif_server_t* s, uint64_t ticket);
+
+/* Server counters: completed requests, currently admitted requests, bytes
+ * admitted, peak bytes admitted. */
+int32_t motif_server_stats(motif_server_t* s, int64_t* completed, int64_t* inflight,
+                           int64_t* bytes_inflight, int64_t* peak_bytes);
+
+/* Drains outstanding work and frees everything the server owns. */
+int32_t motif_server_destroy(motif_server_t* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOTIF_H_ */

@@ -1,0 +1,28 @@
+"""MI355X (gfx950) exact directed motif census for k = 3, 4, 5.
+
+Thin Python binding over the C ABI of ``libmotif.so`` (declared in
+``include/motif.h``).  Every step of the census runs in the library's HIP
+kernels; this package only marshals arguments.  Importing it does not load
+the library; the first call does, and raises if the library was not built.
+"""
+from .binding import (  # noqa: F401
+    MotifError,
+    NUM_CLASSES,
+    lib,
+    lib_path,
+    census,
+    census_batch,
+    census_batch_loop,
+    num_classes,
+    class_code,
+    class_multiplicity,
+    class_of_code,
+    get_tuning,
+    set_tuning,
+    autotune,
+    profile_enable,
+    profile_read,
+    to_device,
+    Server,
+    request_footprint,
+)

@@ -1,0 +1,304 @@
+"""ctypes binding of libmotif.so (argument marshalling only).
+
+Device buffers are torch CUDA tensors (torch provides memory and streams).
+Histograms come back as numpy uint64 arrays copied from the device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmotif.so")
+NUM_CLASSES = {3: 13, 4: 199, 5: 9364}
+
+_ERRORS = {
+    -1: "EINVAL_K", -2: "EINVAL_SHAPE", -3: "EINDEX", -4: "ESELFLOOP", -5: "EDUP", -6: "ETRANSPOSE",
+    -7: "ENOMEM", -8: "EDEVICE", -9: "EAGAIN", -10: "ETOOBIG", -11: "ETIMEOUT", -12: "ECANCELED",
+    -13: "EINVAL_ARG", -14: "EINTERNAL",
+}
+
+
+class MotifError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        self.code = int(code)
+        self.name = _ERRORS.get(self.code, "UNKNOWN")
+        msg = lib().motif_strerror(self.code).decode() if _lib_loaded() else self.name
+        super().__init__(f"{where}: MOTIF_{self.name} ({self.code}): {msg}")
+
+
+class _Graph(ctypes.Structure):
+    _fields_ = [
+        ("out_off", ctypes.c_void_p), ("out_idx", ctypes.c_void_p),
+        ("in_off", ctypes.c_void_p), ("in_idx", ctypes.c_void_p),
+        ("n", ctypes.c_int32), ("m", ctypes.c_int64),
+    ]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("heavy", ctypes.c_int32)]
+
+
+_LOCK = threading.Lock()
+_LIB = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def _lib_loaded() -> bool:
+    return _LIB is not None
+
+
+def lib():
+    """Load libmotif.so (once).  Raises if it has not been built: there is no
+    fallback implementation."""
+    global _LIB
+    with _LOCK:
+        if _LIB is not None:
+            return _LIB
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(_LIB_PATH)
+        I32, I64, P, U32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_uint32
+        sig = {
+            "motif_init": ([], I32),
+            "motif_shutdown": ([], I32),
+            "motif_num_classes": ([I32], I32),
+            "motif_class_code": ([I32, I32, ctypes.POINTER(U32)], I32),
+            "motif_class_multiplicity": ([I32, I32], I32),
+            "motif_class_of_code": ([I32, U32], I32),
+            "motif_strerror": ([I32], ctypes.c_char_p),
+            "motif_census": ([P, P, P, P, I32, I64, I32, P, P], I32),
+            "motif_census_batch": ([P, I32, I32, P, P], I32),
+            "motif_census_batch_loop": ([P, I32, I32, P, P], I32),
+            "motif_get_tuning": ([I32, ctypes.POINTER(_Tuning)], I32),
+            "motif_set_tuning": ([I32, ctypes.POINTER(_Tuning)], I32),
+            "motif_autotune": ([P, I32, I32, P, P, ctypes.POINTER(_Tuning)], I32),
+            "motif_profile_enable": ([I32], I32),
+            "motif_profile_read": ([I32, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)], I32),
+            "motif_server_create": ([ctypes.c_size_t, I32], P),
+            "motif_request_footprint": ([I32, I64, I32], I64),
+            "motif_server_submit": ([P, ctypes.POINTER(_Graph), I32, P, ctypes.POINTER(ctypes.c_uint64)], I32),
+            "motif_server_wait": ([P, ctypes.c_uint64, I64], I32),
+            "motif_server_cancel": ([P, ctypes.c_uint64], I32),
+            "motif_server_stats": ([P] + [ctypes.POINTER(I64)] * 4, I32),
+            "motif_server_destroy": ([P], I32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _LIB = L
+        return L
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise MotifError(rc, where)
+
+
+def num_classes(k: int) -> int:
+    return int(lib().motif_num_classes(k))
+
+
+def class_code(k: int, cls: int) -> int:
+    out = ctypes.c_uint32()
+    _check(lib().motif_class_code(k, cls, ctypes.byref(out)), "motif_class_code")
+    return int(out.value)
+
+
+def class_multiplicity(k: int, cls: int) -> int:
+    r = lib().motif_class_multiplicity(k, cls)
+    if r < 0:
+        raise MotifError(r, "motif_class_multiplicity")
+    return int(r)
+
+
+def class_of_code(k: int, code: int) -> int:
+    return int(lib().motif_class_of_code(k, code))
+
+
+# ---------------------------------------------------------------- device --
+
+def _torch():
+    import torch
+    return torch
+
+
+def to_device(off, idx, device="cuda"):
+    """Copy a CSR (numpy or torch) to int32 device tensors."""
+    torch = _torch()
+    off_t = torch.as_tensor(np.ascontiguousarray(off, dtype=np.int32) if not torch.is_tensor(off) else off)
+    idx_t = torch.as_tensor(np.ascontiguousarray(idx, dtype=np.int32) if not torch.is_tensor(idx) else idx)
+    return off_t.to(device=device, dtype=torch.int32).contiguous(), idx_t.to(device=device, dtype=torch.int32).contiguous()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() else ctypes.c_void_p(0)
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_dev(t, name):
+    torch = _torch()
+    if t is None:
+        return
+    if not (torch.is_tensor(t) and t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous int32 CUDA tensor")
+
+
+def census(out_off, out_idx, n: int, k: int, in_off=None, in_idx=None, stream=None, out=None):
+    """Census of one graph given as int32 CUDA tensors.  Returns numpy uint64
+    [C] (or fills `out`, an int64 CUDA tensor of C entries, and returns it)."""
+    torch = _torch()
+    for t, nm in ((out_off, "out_off"), (out_idx, "out_idx"), (in_off, "in_off"), (in_idx, "in_idx")):
+        _check_dev(t, nm)
+    C = NUM_CLASSES.get(k)
+    if C is None:
+        raise MotifError(-1, "census")
+    hist = out if out is not None else torch.empty(C, dtype=torch.int64, device=out_off.device)
+    m = int(out_idx.numel())
+    rc = lib().motif_census(_ptr(out_off), _ptr(out_idx), _ptr(in_off), _ptr(in_idx), int(n), m, int(k),
+                            _ptr(hist), _stream_handle(stream))
+    _check(rc, "motif_census")
+    if out is not None:
+        return out
+    return hist.cpu().numpy().view(np.uint64)
+
+
+def _graph_array(graphs):
+    arr = (_Graph * len(graphs))()
+    for i, g in enumerate(graphs):
+        out_off, out_idx, n = g[0], g[1], g[2]
+        in_off = g[3] if len(g) > 3 else None
+        in_idx = g[4] if len(g) > 4 else None
+        for t, nm in ((out_off, "out_off"), (out_idx, "out_idx"), (in_off, "in_off"), (in_idx, "in_idx")):
+            _check_dev(t, nm)
+        arr[i] = _Graph(out_off.data_ptr() if out_off.numel() else 0,
+                        out_idx.data_ptr() if out_idx.numel() else 0,
+                        in_off.data_ptr() if in_off is not None else None,
+                        in_idx.data_ptr() if in_idx is not None and in_idx.numel() else None,
+                        int(n), int(out_idx.numel()))
+    return arr
+
+
+def census_batch(graphs, k: int, stream=None, out=None, loop: bool = False):
+    """Census of many graphs [(out_off, out_idx, n[, in_off, in_idx]), ...]
+    in one fused launch (loop=False) or by the per-graph launch loop.
+    Returns numpy uint64 [len(graphs), C] (or fills `out`)."""
+    torch = _torch()
+    C = NUM_CLASSES.get(k)
+    if C is None:
+        raise MotifError(-1, "census_batch")
+    arr = _graph_array(graphs)
+    dev = graphs[0][0].device if graphs else torch.device("cuda")
+    hist = out if out is not None else torch.empty((len(graphs), C), dtype=torch.int64, device=dev)
+    fn = lib().motif_census_batch_loop if loop else lib().motif_census_batch
+    _check(fn(ctypes.cast(arr, ctypes.c_void_p), len(graphs), int(k), _ptr(hist), _stream_handle(stream)),
+           "motif_census_batch")
+    if out is not None:
+        return out
+    return hist.cpu().numpy().view(np.uint64)
+
+
+def census_batch_loop(graphs, k: int, stream=None, out=None):
+    return census_batch(graphs, k, stream=stream, out=out, loop=True)
+
+
+def get_tuning(k: int) -> dict:
+    t = _Tuning()
+    _check(lib().motif_get_tuning(k, ctypes.byref(t)), "motif_get_tuning")
+    return {"block": t.block, "grid_per_cu": t.grid_per_cu, "tile": t.tile, "heavy": t.heavy}
+
+
+def set_tuning(k: int, block=0, grid_per_cu=0, tile=0, heavy=0):
+    t = _Tuning(block, grid_per_cu, tile, heavy)
+    _check(lib().motif_set_tuning(k, ctypes.byref(t)), "motif_set_tuning")
+
+
+def autotune(graphs, k: int, stream=None) -> dict:
+    torch = _torch()
+    C = NUM_CLASSES[k]
+    arr = _graph_array(graphs)
+    hist = torch.empty((len(graphs), C), dtype=torch.int64, device=graphs[0][0].device)
+    t = _Tuning()
+    _check(lib().motif_autotune(ctypes.cast(arr, ctypes.c_void_p), len(graphs), int(k), _ptr(hist),
+                                _stream_handle(stream), ctypes.byref(t)), "motif_autotune")
+    return {"block": t.block, "grid_per_cu": t.grid_per_cu, "tile": t.tile, "heavy": t.heavy}
+
+
+def profile_enable(on: bool = True):
+    lib().motif_profile_enable(1 if on else 0)
+
+
+def profile_read(k: int):
+    """(census kernel ms, build ms) of the last profiled call for k."""
+    a, b = ctypes.c_float(), ctypes.c_float()
+    _check(lib().motif_profile_read(k, ctypes.byref(a), ctypes.byref(b)), "motif_profile_read")
+    return float(a.value), float(b.value)
+
+
+# --------------------------------------------------------------- serving --
+
+def request_footprint(n: int, m: int, k: int) -> int:
+    return int(lib().motif_request_footprint(int(n), int(m), int(k)))
+
+
+class Server:
+    """Continuous-batching census server (host CSR in, host histogram out)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 8):
+        self._h = lib().motif_server_create(int(hbm_budget_bytes), int(max_inflight))
+        if not self._h:
+            raise MotifError(-8, "motif_server_create")
+        self._keep = {}
+
+    def submit(self, out_off: np.ndarray, out_idx: np.ndarray, n: int, k: int) -> int:
+        off = np.ascontiguousarray(out_off, dtype=np.int32)
+        idx = np.ascontiguousarray(out_idx, dtype=np.int32)
+        hist = np.zeros(NUM_CLASSES[k], dtype=np.uint64)
+        g = _Graph(off.ctypes.data, idx.ctypes.data if idx.size else 0, None, None, int(n), int(idx.size))
+        ticket = ctypes.c_uint64()
+        rc = lib().motif_server_submit(self._h, ctypes.byref(g), int(k), hist.ctypes.data, ctypes.byref(ticket))
+        _check(rc, "motif_server_submit")
+        self._keep[ticket.value] = hist
+        return int(ticket.value)
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> np.ndarray:
+        rc = lib().motif_server_wait(self._h, ctypes.c_uint64(ticket), int(timeout_us))
+        if rc == -11:
+            raise TimeoutError(f"ticket {ticket}")
+        hist = self._keep.pop(ticket)
+        _check(rc, "motif_server_wait")
+        return hist
+
+    def cancel(self, ticket: int) -> int:
+        return int(lib().motif_server_cancel(self._h, ctypes.c_uint64(ticket)))
+
+    def stats(self) -> dict:
+        v = [ctypes.c_int64() for _ in range(4)]
+        _check(lib().motif_server_stats(self._h, *[ctypes.byref(x) for x in v]), "motif_server_stats")
+        return dict(zip(["completed", "inflight", "bytes_inflight", "peak_bytes"], [x.value for x in v]))
+
+    def close(self):
+        if self._h:
+            lib().motif_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

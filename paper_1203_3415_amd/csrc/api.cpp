@@ -1,0 +1,451 @@
+// C ABI entry points: argument checks, device class tables, per-stream
+// workspaces, the single-graph and batched census pipelines, tuning and the
+// autotuner.  All arithmetic of the census runs in the kernels of graph.hip
+// and census.hip; this file only orchestrates.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "classes.h"
+#include "internal.h"
+
+namespace motif {
+
+namespace {
+
+std::mutex g_mu;
+
+struct DeviceState {
+  bool ready = false;
+  int num_cus = 0;
+  DevTables tables;
+  std::vector<void*> owned;  // table buffers
+  std::map<hipStream_t, Pipeline*> pipes;
+};
+
+std::map<int, DeviceState> g_dev;
+int32_t g_init_err = 0;
+
+Tuning g_tuning[6] = {
+    {256, 4, 16, 0}, {256, 4, 16, 0}, {256, 4, 16, 0},
+    {256, 4, 16, 0},   // k = 3: tile*16 vertices per tile
+    {256, 2, 8, 0},    // k = 4
+    {1024, 1, 2, 0},   // k = 5
+};
+
+int32_t current_device(int* dev) {
+  if (hipGetDevice(dev) != hipSuccess) return MOTIF_EDEVICE;
+  return 0;
+}
+
+// Upload class tables to the current device (caller holds g_mu).
+int32_t init_device_locked(int dev) {
+  DeviceState& d = g_dev[dev];
+  if (d.ready) return 0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MOTIF_EDEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MOTIF_EDEVICE;
+  d.num_cus = prop.multiProcessorCount;
+  for (int k = 3; k <= 5; ++k) {
+    const ClassTable* t = class_table(k);
+    void *lut = nullptr, *mult = nullptr;
+    if (hipMalloc(&lut, t->lut.size() * sizeof(uint16_t)) != hipSuccess) return MOTIF_ENOMEM;
+    if (hipMalloc(&mult, t->mult.size()) != hipSuccess) return MOTIF_ENOMEM;
+    d.owned.push_back(lut);
+    d.owned.push_back(mult);
+    if (hipMemcpy(lut, t->lut.data(), t->lut.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(mult, t->mult.data(), t->mult.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return MOTIF_EDEVICE;
+    d.tables.lut[k] = (const uint16_t*)lut;
+    d.tables.mult[k] = (const uint8_t*)mult;
+  }
+  d.ready = true;
+  return 0;
+}
+
+}  // namespace
+
+int32_t ensure_init(int* dev_out) {
+  int dev;
+  if (current_device(&dev)) return MOTIF_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  int32_t rc = init_device_locked(dev);
+  if (dev_out) *dev_out = dev;
+  return rc;
+}
+
+int device_cus(int dev) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_dev[dev].num_cus;
+}
+
+namespace {
+
+// Pipeline (workspace) of a stream on a device, with at least `bytes` of arena.
+int32_t get_pipeline(int dev, hipStream_t s, size_t bytes, Pipeline** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceState& d = g_dev[dev];
+  Pipeline*& p = d.pipes[s];
+  if (!p) {
+    p = new Pipeline();
+    p->num_cus = d.num_cus;
+    if (hipMalloc(&p->status, kStatusWords * sizeof(int32_t)) != hipSuccess) return MOTIF_ENOMEM;
+    if (hipHostMalloc(&p->host_status, kStatusWords * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+      return MOTIF_ENOMEM;
+  }
+  if (p->arena.cap < bytes) {
+    if (p->arena.base) {
+      hipStreamSynchronize(s);
+      hipFree(p->arena.base);
+      p->arena.base = nullptr;
+      p->arena.cap = 0;
+    }
+    size_t want = std::max(bytes, p->arena.cap + p->arena.cap / 2);
+    if (hipMalloc(&p->arena.base, want) != hipSuccess) {
+      p->arena.base = nullptr;
+      if (hipMalloc(&p->arena.base, bytes) != hipSuccess) {
+        p->arena.base = nullptr;
+        return MOTIF_ENOMEM;
+      }
+      want = bytes;
+    }
+    p->arena.cap = want;
+  }
+  p->arena.reset();
+  *out = p;
+  return 0;
+}
+
+}  // namespace
+
+// Copy the device status word to the host and wait for the stream.
+int32_t read_status(Pipeline& p, hipStream_t s) {
+  if (hipMemcpyAsync(p.host_status, p.status, sizeof(int32_t) * kStatusWords, hipMemcpyDeviceToHost, s) !=
+      hipSuccess)
+    return MOTIF_EDEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return MOTIF_EDEVICE;
+  return p.host_status[kStatus];
+}
+
+namespace {
+
+bool check_shape(int32_t n, int64_t m) { return n >= 0 && m >= 0 && n < kMaxN && m < kMaxN; }
+
+// ---- profiling ----
+struct ProfState {
+  bool on = false;
+  hipEvent_t ev[6][4] = {};
+  bool have[6] = {};
+};
+ProfState g_prof;
+
+}  // namespace
+
+const DevTables& dev_tables() {
+  int dev = 0;
+  hipGetDevice(&dev);
+  return g_dev[dev].tables;
+}
+
+Tuning& tuning_for(int k) { return g_tuning[k]; }
+
+void profile_mark(int k, int what, bool begin, hipStream_t s) {
+  if (!g_prof.on || k < 3 || k > 5) return;
+  hipEvent_t& e = g_prof.ev[k][what * 2 + (begin ? 0 : 1)];
+  if (!e) hipEventCreate(&e);
+  hipEventRecord(e, s);
+  if (what == 1 && !begin) g_prof.have[k] = true;
+}
+
+// One census on a sized pipeline: build + status wait + census + status wait.
+int32_t run_census_on(Pipeline& p, const BuildInput& in, int32_t k, uint64_t* hist, hipStream_t s) {
+  const int C = motif_num_classes(k);
+  p.arena.reset();
+  enqueue_zero(p.status, sizeof(int32_t) * kStatusWords, s);
+  profile_mark(k, 0, true, s);
+  DevGraph g = enqueue_build(p, in, s);
+  profile_mark(k, 0, false, s);
+  int32_t rc = read_status(p, s);
+  if (rc) return rc;
+  uint64_t* acc = p.arena.take<uint64_t>((size_t)in.ngraphs * C);
+  enqueue_census(p, g, k, acc, hist, s);
+  return read_status(p, s);
+}
+
+int32_t run_census(const BuildInput& in, int32_t k, uint64_t* hist, hipStream_t s) {
+  int dev;
+  int32_t rc = ensure_init(&dev);
+  if (rc) return rc;
+  Pipeline* p = nullptr;
+  rc = get_pipeline(dev, s, pipeline_bytes(in.n, in.m, in.ngraphs, false, k, device_cus(dev)), &p);
+  if (rc) return rc;
+  return run_census_on(*p, in, k, hist, s);
+}
+
+}  // namespace motif
+
+using namespace motif;
+
+extern "C" {
+
+int32_t motif_init(void) {
+  int dev;
+  return ensure_init(&dev);
+}
+
+int32_t motif_shutdown(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_dev) {
+    hipSetDevice(kv.first);
+    hipDeviceSynchronize();
+    for (void* ptr : kv.second.owned) hipFree(ptr);
+    for (auto& pp : kv.second.pipes) {
+      if (pp.second->arena.base) hipFree(pp.second->arena.base);
+      if (pp.second->status) hipFree(pp.second->status);
+      if (pp.second->host_status) hipHostFree(pp.second->host_status);
+      delete pp.second;
+    }
+  }
+  g_dev.clear();
+  return 0;
+}
+
+int32_t motif_num_classes(int32_t k) {
+  switch (k) {
+    case 3: return 13;
+    case 4: return 199;
+    case 5: return 9364;
+    default: return MOTIF_EINVAL_K;
+  }
+}
+
+int32_t motif_class_code(int32_t k, int32_t cls, uint32_t* canon_code) {
+  const ClassTable* t = class_table(k);
+  if (!t) return MOTIF_EINVAL_K;
+  if (cls < 0 || cls >= (int32_t)t->canon.size() || !canon_code) return MOTIF_EINVAL_ARG;
+  *canon_code = t->canon[cls];
+  return 0;
+}
+
+int32_t motif_class_multiplicity(int32_t k, int32_t cls) {
+  const ClassTable* t = class_table(k);
+  if (!t) return MOTIF_EINVAL_K;
+  if (cls < 0 || cls >= (int32_t)t->mult.size()) return MOTIF_EINVAL_ARG;
+  return t->mult[cls];
+}
+
+int32_t motif_class_of_code(int32_t k, uint32_t code) {
+  const ClassTable* t = class_table(k);
+  if (!t) return MOTIF_EINVAL_K;
+  if (code >= t->lut.size()) return MOTIF_EINVAL_ARG;
+  return t->lut[code] == 0xFFFF ? -1 : (int32_t)t->lut[code];
+}
+
+const char* motif_strerror(int32_t code) {
+  switch (code) {
+    case MOTIF_OK: return "ok";
+    case MOTIF_EINVAL_K: return "k must be 3, 4 or 5";
+    case MOTIF_EINVAL_SHAPE: return "invalid CSR shape (n, m or offsets)";
+    case MOTIF_EINDEX: return "neighbour index out of range";
+    case MOTIF_ESELFLOOP: return "self-loop";
+    case MOTIF_EDUP: return "repeated arc";
+    case MOTIF_ETRANSPOSE: return "in-CSR is not the transpose of the out-CSR";
+    case MOTIF_ENOMEM: return "out of memory";
+    case MOTIF_EDEVICE: return "HIP device error or no gfx950 device";
+    case MOTIF_EAGAIN: return "not admitted now; retry";
+    case MOTIF_ETOOBIG: return "request exceeds the server's memory budget";
+    case MOTIF_ETIMEOUT: return "timed out";
+    case MOTIF_ECANCELED: return "cancelled";
+    case MOTIF_EINVAL_ARG: return "invalid argument";
+    case MOTIF_EINTERNAL: return "internal self-check failed";
+    default: return "unknown error";
+  }
+}
+
+int32_t motif_census(const int32_t* out_off, const int32_t* out_idx, const int32_t* in_off, const int32_t* in_idx,
+                     int32_t n, int64_t m, int32_t k, uint64_t* hist, void* stream) {
+  if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
+  if (!check_shape(n, m)) return MOTIF_EINVAL_SHAPE;
+  if (!hist || !out_off || (m > 0 && !out_idx)) return MOTIF_EINVAL_ARG;
+  if (in_off && m > 0 && !in_idx) return MOTIF_EINVAL_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (n == 0) {
+    if (m != 0) return MOTIF_EINVAL_SHAPE;
+    int dev;
+    int32_t rc = ensure_init(&dev);
+    if (rc) return rc;
+    enqueue_zero(hist, sizeof(uint64_t) * motif_num_classes(k), s);
+    return hipStreamSynchronize(s) == hipSuccess ? 0 : MOTIF_EDEVICE;
+  }
+  BuildInput in{};
+  in.out_off = out_off;
+  in.out_idx = out_idx;
+  in.in_off = in_off;
+  in.in_idx = in_off ? in_idx : nullptr;
+  in.n = n;
+  in.m = m;
+  return run_census(in, k, hist, s);
+}
+
+int32_t motif_census_batch(const motif_graph_t* graphs, int32_t count, int32_t k, uint64_t* hists, void* stream) {
+  if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
+  if (count < 0 || (count > 0 && (!graphs || !hists))) return MOTIF_EINVAL_ARG;
+  if (count == 0) return 0;
+  std::vector<int64_t> voff(count + 1, 0), aoff(count + 1, 0);
+  for (int32_t g = 0; g < count; ++g) {
+    const motif_graph_t& G = graphs[g];
+    if (!check_shape(G.n, G.m)) return MOTIF_EINVAL_SHAPE;
+    if (G.n == 0 && G.m != 0) return MOTIF_EINVAL_SHAPE;
+    if ((G.n > 0 && !G.out_off) || (G.m > 0 && !G.out_idx)) return MOTIF_EINVAL_ARG;
+    if (G.in_off && G.m > 0 && !G.in_idx) return MOTIF_EINVAL_ARG;
+    voff[g + 1] = voff[g] + G.n;
+    aoff[g + 1] = aoff[g] + G.m;
+  }
+  if (voff[count] >= kMaxN || aoff[count] >= kMaxN) return MOTIF_EINVAL_SHAPE;
+  int dev;
+  int32_t rc = ensure_init(&dev);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int C = motif_num_classes(k);
+  if (voff[count] == 0) {
+    enqueue_zero(hists, sizeof(uint64_t) * C * (size_t)count, s);
+    return hipStreamSynchronize(s) == hipSuccess ? 0 : MOTIF_EDEVICE;
+  }
+  // Graphs with n = 0 contribute no vertices; the pack kernel never sees them.
+  Pipeline* p = nullptr;
+  rc = get_pipeline(dev, s, pipeline_bytes(voff[count], aoff[count], count, true, k, device_cus(dev)), &p);
+  if (rc) return rc;
+  p->arena.reset();
+  enqueue_zero(p->status, sizeof(int32_t) * kStatusWords, s);
+  profile_mark(k, 0, true, s);
+  BuildInput in = enqueue_pack(*p, graphs, count, voff.data(), aoff.data(), s);
+  DevGraph g = enqueue_build(*p, in, s);
+  profile_mark(k, 0, false, s);
+  rc = read_status(*p, s);
+  if (rc) return rc;
+  uint64_t* acc = p->arena.take<uint64_t>((size_t)count * C);
+  enqueue_census(*p, g, k, acc, hists, s);
+  return read_status(*p, s);
+}
+
+int32_t motif_census_batch_loop(const motif_graph_t* graphs, int32_t count, int32_t k, uint64_t* hists,
+                                void* stream) {
+  if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
+  if (count < 0 || (count > 0 && (!graphs || !hists))) return MOTIF_EINVAL_ARG;
+  const int C = motif_num_classes(k);
+  for (int32_t g = 0; g < count; ++g) {
+    const motif_graph_t& G = graphs[g];
+    int32_t rc = motif_census(G.out_off, G.out_idx, G.in_off, G.in_idx, G.n, G.m, k, hists + (size_t)g * C, stream);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+int32_t motif_get_tuning(int32_t k, motif_tuning_t* out) {
+  if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
+  if (!out) return MOTIF_EINVAL_ARG;
+  const Tuning& t = tuning_for(k);
+  out->block = t.block;
+  out->grid_per_cu = t.grid_per_cu;
+  out->tile = t.tile;
+  out->heavy = t.heavy;
+  return 0;
+}
+
+int32_t motif_set_tuning(int32_t k, const motif_tuning_t* in) {
+  if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
+  if (!in) return MOTIF_EINVAL_ARG;
+  Tuning& t = tuning_for(k);
+  if (in->block) {
+    const bool ok = k == 3 ? in->block == 256 : k == 4 ? (in->block == 256 || in->block == 512 || in->block == 1024)
+                                                      : (in->block == 512 || in->block == 1024);
+    if (!ok) return MOTIF_EINVAL_ARG;
+    t.block = in->block;
+  }
+  if (in->grid_per_cu) {
+    if (in->grid_per_cu < 1 || in->grid_per_cu > 16) return MOTIF_EINVAL_ARG;
+    t.grid_per_cu = in->grid_per_cu;
+  }
+  if (in->tile) {
+    if (in->tile < 1 || in->tile > 4096) return MOTIF_EINVAL_ARG;
+    t.tile = in->tile;
+  }
+  if (in->heavy) {
+    if (in->heavy < 0) return MOTIF_EINVAL_ARG;
+    t.heavy = in->heavy;
+  }
+  return 0;
+}
+
+int32_t motif_autotune(const motif_graph_t* graphs, int32_t count, int32_t k, uint64_t* hists, void* stream,
+                       motif_tuning_t* best) {
+  if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
+  if (count <= 0 || !graphs || !hists) return MOTIF_EINVAL_ARG;
+  const int C = motif_num_classes(k);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<motif_tuning_t> cands;
+  if (k == 3) {
+    for (int tile : {4, 16, 64})
+      for (int gpc : {2, 4, 8}) cands.push_back({256, gpc, tile, 0});
+  } else if (k == 4) {
+    for (int block : {256, 512})
+      for (int gpc : {1, 2, 4})
+        for (int tile : {1, 8, 32}) cands.push_back({block, gpc, tile, 0});
+  } else {
+    for (int block : {512, 1024})
+      for (int tile : {1, 2, 8}) cands.push_back({block, 1, tile, 0});
+  }
+  const Tuning saved = tuning_for(k);
+  std::vector<uint64_t> ref((size_t)count * C), cur((size_t)count * C);
+  double best_ms = 1e300;
+  motif_tuning_t best_t{saved.block, saved.grid_per_cu, saved.tile, saved.heavy};
+  for (size_t i = 0; i < cands.size(); ++i) {
+    Tuning& t = tuning_for(k);
+    t.block = cands[i].block;
+    t.grid_per_cu = cands[i].grid_per_cu;
+    t.tile = cands[i].tile;
+    int32_t rc = motif_census_batch(graphs, count, k, hists, stream);  // warm-up
+    if (rc) { tuning_for(k) = saved; return rc; }
+    auto t0 = std::chrono::steady_clock::now();
+    rc = motif_census_batch(graphs, count, k, hists, stream);
+    auto t1 = std::chrono::steady_clock::now();
+    if (rc) { tuning_for(k) = saved; return rc; }
+    hipMemcpyAsync(i == 0 ? ref.data() : cur.data(), hists, sizeof(uint64_t) * ref.size(), hipMemcpyDeviceToHost, s);
+    hipStreamSynchronize(s);
+    if (i > 0 && cur != ref) { tuning_for(k) = saved; return MOTIF_EINTERNAL; }
+    const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_t = cands[i];
+    }
+  }
+  Tuning& t = tuning_for(k);
+  t.block = best_t.block;
+  t.grid_per_cu = best_t.grid_per_cu;
+  t.tile = best_t.tile;
+  if (best) *best = best_t;
+  return 0;
+}
+
+int32_t motif_profile_enable(int32_t on) {
+  g_prof.on = on != 0;
+  for (bool& h : g_prof.have) h = false;
+  return 0;
+}
+
+int32_t motif_profile_read(int32_t k, float* kernel_ms, float* build_ms) {
+  if (k < 3 || k > 5) return MOTIF_EINVAL_K;
+  if (!g_prof.have[k]) return MOTIF_EINVAL_ARG;
+  hipEvent_t* e = g_prof.ev[k];
+  if (hipEventSynchronize(e[3]) != hipSuccess) return MOTIF_EDEVICE;
+  if (kernel_ms && hipEventElapsedTime(kernel_ms, e[2], e[3]) != hipSuccess) return MOTIF_EDEVICE;
+  if (build_ms && hipEventElapsedTime(build_ms, e[0], e[1]) != hipSuccess) return MOTIF_EDEVICE;
+  return 0;
+}
+
+}  // extern "C"

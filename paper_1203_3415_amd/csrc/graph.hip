@@ -1,0 +1,565 @@
+// Ingest, validation and typed-G* build on the device.
+//
+// Paper, Section "Notation and definitions" and Algorithm "Create A,B,C sets"
+// (the O(m) partition of each vertex's neighbours into A^v bidirected, B^v
+// outgoing-only and C^v incoming-only), realised as one typed, id-sorted
+// neighbour list per vertex of the undirected version G*, plus the oriented
+// lists N+(v) = { w in N(v) : (d*(v), v) < (d*(w), w) } that make every edge of
+// G* appear in exactly one list (the degree ordering behind the triangle
+// listing the paper cites for Algorithm "alternative").
+//
+// Pipeline (all kernels; one host wait at the end of validation, done by the
+// caller):
+//   offsets check -> arc check + in-degree count -> half-edge offsets (scan)
+//   -> half-edge scatter (key = id<<1 | dir) -> per-row sort (small rows in
+//   registers, mid rows by LDS bitonic sort, big rows by a bitmap over the key
+//   space) -> merge of equal ids into typed entries -> G* offsets (scan) ->
+//   G* write -> N+ count, scan, write -> optional in-CSR transpose check.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace motif {
+
+namespace {
+
+constexpr int kB = 256;           // threads per block for streaming kernels
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kB * kScanItems;
+constexpr int kSmallRow = 32;     // rows up to this length: sorted by one thread
+constexpr int kMidRow = 4096;     // rows up to this length: LDS bitonic sort
+constexpr int kBigSlots = 32;     // concurrent bitmap sorts
+
+__device__ __forceinline__ void set_status(int32_t* st, int32_t code) { atomicMin(&st[kStatus], code); }
+
+__device__ __forceinline__ int32_t row_of(const int32_t* off, int32_t n, int64_t i) {
+  // last v in [0, n) with off[v] <= i (off valid, off[n] > i)
+  int32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool rank_less(int32_t dv, int32_t v, int32_t dw, int32_t w) {
+  return dv < dw || (dv == dw && v < w);
+}
+
+// ---------------------------------------------------------------- helpers --
+
+__global__ void k_zero(uint32_t* p, size_t words) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// Exclusive block scan of one value per thread (wave64 shuffles + LDS).
+__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* sh, int32_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    int32_t s = lane < nw ? sh[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int32_t y = __shfl_up(s, o, 64);
+      if (lane >= o) s += y;
+    }
+    if (lane < nw) sh[lane] = s;
+  }
+  __syncthreads();
+  int32_t r = x - v + (w ? sh[w - 1] : 0);
+  *total = sh[nw - 1];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kB) void k_scan_local(int32_t* data, int64_t len, int32_t* bsum) {
+  __shared__ int32_t sh[kB / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int32_t vals[kScanItems];
+  int32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    vals[i] = base + i < len ? data[base + i] : 0;
+    sum += vals[i];
+  }
+  int32_t total;
+  int32_t run = block_excl_scan(sum, sh, &total);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < len) data[base + i] = run;
+    run += vals[i];
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kB) void k_scan_add(int32_t* data, int64_t len, const int32_t* bsum) {
+  const int32_t add = bsum[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  for (int i = threadIdx.x; i < kScanTile; i += kB)
+    if (base + i < len) data[base + i] += add;
+}
+
+// In-place exclusive scan of data[0..len); scratch needs scan_scratch(len) ints.
+void scan_excl(int32_t* data, int64_t len, int32_t* scratch, hipStream_t s) {
+  if (len <= 0) return;
+  const int64_t nb = (len + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kB), 0, s, data, len, scratch);
+  if (nb > 1) {
+    scan_excl(scratch, nb, scratch + ((nb + 63) & ~int64_t(63)), s);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kB), 0, s, data, len, scratch);
+  }
+}
+
+int64_t scan_scratch(int64_t len) {
+  int64_t total = 64;
+  while (len > 1) {
+    int64_t nb = (len + kScanTile - 1) / kScanTile;
+    total += (nb + 63) & ~int64_t(63);
+    len = nb;
+  }
+  return total;
+}
+
+unsigned grid_for(int64_t items, int block = kB) {
+  int64_t g = (items + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (unsigned)g;
+}
+
+// ------------------------------------------------------------- validation --
+
+__global__ void k_check_offsets(const int32_t* off, int32_t n, int64_t m, int32_t* st) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += (int64_t)gridDim.x * blockDim.x) {
+    int32_t a = off[v];
+    if (v == 0 && a != 0) set_status(st, MOTIF_EINVAL_SHAPE);
+    if (v == n && (int64_t)a != m) set_status(st, MOTIF_EINVAL_SHAPE);
+    if (v < n && off[v + 1] < a) set_status(st, MOTIF_EINVAL_SHAPE);
+  }
+}
+
+// Every arc: index range, self-loop, in-degree count.
+__global__ void k_count_in(const int32_t* off, const int32_t* idx, int32_t n, int64_t m, int32_t* in_cnt,
+                           int32_t* st) {
+  if (st[kStatus] != 0) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t d = idx[i];
+    if (d < 0 || d >= n) { set_status(st, MOTIF_EINDEX); continue; }
+    int32_t u = row_of(off, n, i);
+    if (d == u) { set_status(st, MOTIF_ESELFLOOP); continue; }
+    atomicAdd(&in_cnt[d], 1);
+  }
+}
+
+// hcnt[v] = out-degree + in-degree (half-edges of row v); hcnt[n] = 0.
+__global__ void k_half_counts(const int32_t* off, const int32_t* in_cnt, int32_t n, int32_t* hcnt,
+                              int32_t* fill, const int32_t* st) {
+  if (st[kStatus] != 0) return;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += (int64_t)gridDim.x * blockDim.x) {
+    hcnt[v] = v < n ? (off[v + 1] - off[v]) + in_cnt[v] : 0;
+    if (v < n) fill[v] = 0;
+  }
+}
+
+// Half-edge keys: row u gets (d<<1|0) for arc u->d, row d gets (u<<1|1).
+__global__ void k_scatter(const int32_t* off, const int32_t* idx, int32_t n, int64_t m, const int32_t* hoff,
+                          int32_t* fill, uint32_t* keys, const int32_t* st) {
+  if (st[kStatus] != 0) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t u = row_of(off, n, i);
+    int32_t d = idx[i];
+    keys[hoff[u] + (i - off[u])] = ((uint32_t)d << 1);
+    int32_t p = atomicAdd(&fill[d], 1);
+    keys[hoff[d] + (off[d + 1] - off[d]) + p] = ((uint32_t)u << 1) | 1u;
+  }
+}
+
+// Small rows sorted by their own thread; longer rows queued.
+__global__ void k_sort_small(const int32_t* hoff, int32_t n, uint32_t* keys, int32_t* midq, int32_t* bigq,
+                             int32_t* st) {
+  if (st[kStatus] != 0) return;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = hoff[v], len = hoff[v + 1] - a;
+    if (len <= 1) continue;
+    if (len <= kSmallRow) {
+      uint32_t* r = keys + a;
+      for (int i = 1; i < len; ++i) {
+        uint32_t t = r[i];
+        int j = i - 1;
+        while (j >= 0 && r[j] > t) { r[j + 1] = r[j]; --j; }
+        r[j + 1] = t;
+      }
+    } else if (len <= kMidRow) {
+      midq[atomicAdd(&st[kMidCount], 1)] = (int32_t)v;
+    } else {
+      bigq[atomicAdd(&st[kBigCount], 1)] = (int32_t)v;
+    }
+  }
+}
+
+// Mid rows: bitonic sort in LDS, one workgroup per row (persistent grid).
+__global__ __launch_bounds__(kB) void k_sort_mid(const int32_t* hoff, uint32_t* keys, const int32_t* midq,
+                                                 const int32_t* st) {
+  __shared__ uint32_t s[kMidRow];
+  if (st[kStatus] != 0) return;
+  const int32_t count = st[kMidCount];
+  for (int32_t q = blockIdx.x; q < count; q += gridDim.x) {
+    const int32_t v = midq[q];
+    const int32_t a = hoff[v], len = hoff[v + 1] - a;
+    int P = 1;
+    while (P < len) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += kB) s[i] = i < len ? keys[a + i] : 0xFFFFFFFFu;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = threadIdx.x; i < P; i += kB) {
+          int ij = i ^ j;
+          if (ij > i) {
+            uint32_t x = s[i], y = s[ij];
+            bool up = (i & k) == 0;
+            if ((x > y) == up) { s[i] = y; s[ij] = x; }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = threadIdx.x; i < len; i += kB) keys[a + i] = s[i];
+    __syncthreads();
+  }
+}
+
+// Big rows: set one bit per key in a bitmap over [0, 2n), then compact in
+// order.  A key seen twice is a repeated arc.
+__global__ __launch_bounds__(kB) void k_sort_big(const int32_t* hoff, int32_t n, uint32_t* keys,
+                                                 const int32_t* bigq, uint32_t* bitmaps, int32_t* st) {
+  __shared__ int32_t sh[kB / 64];
+  if (st[kStatus] != 0) return;
+  const int32_t count = st[kBigCount];
+  const int64_t words = ((int64_t)2 * n + 31) / 32;
+  uint32_t* bm = bitmaps + (int64_t)blockIdx.x * words;
+  const int64_t per = (words + kB - 1) / kB;
+  for (int32_t q = blockIdx.x; q < count; q += gridDim.x) {
+    const int32_t v = bigq[q];
+    const int32_t a = hoff[v], len = hoff[v + 1] - a;
+    for (int64_t w = threadIdx.x; w < words; w += kB) bm[w] = 0u;
+    __syncthreads();
+    for (int i = threadIdx.x; i < len; i += kB) {
+      uint32_t key = keys[a + i];
+      uint32_t bit = 1u << (key & 31u);
+      uint32_t old = atomicOr(&bm[key >> 5], bit);
+      if (old & bit) set_status(st, MOTIF_EDUP);
+    }
+    __syncthreads();
+    const int64_t w0 = threadIdx.x * per, w1 = w0 + per < words ? w0 + per : words;
+    int32_t cnt = 0;
+    for (int64_t w = w0; w < w1; ++w) cnt += __popc(bm[w]);
+    int32_t total;
+    int32_t pos = block_excl_scan(cnt, sh, &total);
+    for (int64_t w = w0; w < w1; ++w) {
+      uint32_t b = bm[w];
+      while (b) {
+        int t = __ffs(b) - 1;
+        b &= b - 1;
+        if (pos < len) keys[a + pos] = (uint32_t)(w * 32 + t);
+        ++pos;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Distinct neighbours per row (a pair id<<1, id<<1|1 is one bidirected
+// neighbour); equal keys mean a repeated arc.
+__global__ void k_row_degree(const int32_t* hoff, int32_t n, const uint32_t* keys, int32_t* deg, int32_t* st) {
+  if (st[kStatus] != 0) return;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = hoff[v], b = hoff[v + 1];
+    int32_t cnt = 0;
+    for (int32_t i = a; i < b;) {
+      uint32_t k = keys[i];
+      if (i + 1 < b && keys[i + 1] == k) { set_status(st, MOTIF_EDUP); break; }
+      i += (i + 1 < b && (keys[i + 1] >> 1) == (k >> 1)) ? 2 : 1;
+      ++cnt;
+    }
+    deg[v] = cnt;
+  }
+}
+
+__global__ void k_copy_pad(const int32_t* src, int32_t n, int32_t* dst, const int32_t* st) {
+  if (st[kStatus] != 0) return;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += (int64_t)gridDim.x * blockDim.x)
+    dst[v] = v < n ? src[v] : 0;
+}
+
+__global__ void k_write_gstar(const int32_t* hoff, int32_t n, const uint32_t* keys, const int32_t* gs_off,
+                              uint32_t* gs_idx, const int32_t* st) {
+  if (st[kStatus] != 0) return;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = hoff[v], b = hoff[v + 1];
+    int32_t o = gs_off[v];
+    for (int32_t i = a; i < b;) {
+      uint32_t k = keys[i];
+      uint32_t t;
+      if (i + 1 < b && (keys[i + 1] >> 1) == (k >> 1)) { t = 3u; i += 2; }
+      else { t = (k & 1u) ? 2u : 1u; i += 1; }
+      gs_idx[o++] = (k >> 1) | (t << kTypeShift);
+    }
+  }
+}
+
+__global__ void k_count_plus(const int32_t* gs_off, const uint32_t* gs_idx, const int32_t* deg, int32_t n,
+                             int32_t* dplus, const int32_t* st) {
+  if (st[kStatus] != 0) return;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += (int64_t)gridDim.x * blockDim.x) {
+    if (v == n) { dplus[v] = 0; continue; }
+    const int32_t dv = deg[v];
+    int32_t c = 0;
+    for (int32_t j = gs_off[v]; j < gs_off[v + 1]; ++j) {
+      int32_t w = (int32_t)(gs_idx[j] & kIdMask);
+      c += rank_less(dv, (int32_t)v, deg[w], w);
+    }
+    dplus[v] = c;
+  }
+}
+
+__global__ void k_write_plus(const int32_t* gs_off, const uint32_t* gs_idx, const int32_t* deg, int32_t n,
+                             const int32_t* np_off, uint32_t* np_idx, const int32_t* st) {
+  if (st[kStatus] != 0) return;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t dv = deg[v];
+    int32_t o = np_off[v];
+    for (int32_t j = gs_off[v]; j < gs_off[v + 1]; ++j) {
+      uint32_t e = gs_idx[j];
+      int32_t w = (int32_t)(e & kIdMask);
+      if (rank_less(dv, (int32_t)v, deg[w], w)) np_idx[o++] = e;
+    }
+  }
+}
+
+// In-CSR given by the caller: every listed in-arc s -> v must be an arc of
+// the out-CSR, listed once, and each row must have the in-degree counted from
+// the out-CSR.  `has_in` (batch) marks the graphs that supplied an in-CSR.
+__global__ void k_check_in_rows(const int32_t* in_off, const int32_t* in_cnt, int32_t n, const int32_t* gid,
+                                const int32_t* has_in, int32_t* st) {
+  if (st[kStatus] != 0) return;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    if (gid && !has_in[gid[v]]) continue;
+    if (in_off[v + 1] - in_off[v] != in_cnt[v]) set_status(st, MOTIF_ETRANSPOSE);
+  }
+}
+
+__global__ void k_check_in_arcs(const int32_t* in_off, const int32_t* in_idx, int32_t n, int64_t m,
+                                const int32_t* gs_off, const uint32_t* gs_idx, const int32_t* gid,
+                                const int32_t* has_in, uint32_t* marks, int32_t* st) {
+  if (st[kStatus] != 0) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t v = row_of(in_off, n, i);
+    if (gid && !has_in[gid[v]]) continue;
+    int32_t s = in_idx[i];
+    if (s < 0 || s >= n) { set_status(st, MOTIF_EINDEX); continue; }
+    int32_t lo = gs_off[v], hi = gs_off[v + 1];
+    while (lo < hi) {
+      int32_t mid = (lo + hi) >> 1;
+      if ((int32_t)(gs_idx[mid] & kIdMask) < s) lo = mid + 1; else hi = mid;
+    }
+    if (lo >= gs_off[v + 1] || (int32_t)(gs_idx[lo] & kIdMask) != s || !((gs_idx[lo] >> kTypeShift) & 2u)) {
+      set_status(st, MOTIF_ETRANSPOSE);
+      continue;
+    }
+    uint32_t bit = 1u << (lo & 31);
+    if (atomicOr(&marks[lo >> 5], bit) & bit) set_status(st, MOTIF_ETRANSPOSE);
+  }
+}
+
+// ------------------------------------------------------------------- pack --
+
+__device__ __forceinline__ int32_t graph_of(const int64_t* pre, int32_t count, int64_t x) {
+  int32_t lo = 0, hi = count - 1;  // last g with pre[g] <= x
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_pack_rows(const motif_graph_t* gs, int32_t count, const int64_t* voff, const int64_t* aoff,
+                            int64_t N, int64_t M, int32_t* uoff, int32_t* uin_off, int32_t* gid, int32_t* has_in,
+                            int32_t* st) {
+  for (int64_t V = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; V <= N; V += (int64_t)gridDim.x * blockDim.x) {
+    if (V == N) {
+      uoff[N] = (int32_t)M;
+      uin_off[N] = (int32_t)M;
+      continue;
+    }
+    const int32_t g = graph_of(voff, count, V);
+    const motif_graph_t G = gs[g];
+    const int64_t v = V - voff[g];
+    const int32_t a = G.out_off[v], b = G.out_off[v + 1];
+    if (v == 0) has_in[g] = G.in_off != nullptr;
+    if ((v == 0 && a != 0) || b < a || (v == G.n - 1 && (int64_t)b != G.m)) set_status(st, MOTIF_EINVAL_SHAPE);
+    uoff[V] = (int32_t)(aoff[g] + a);
+    gid[V] = g;
+    if (G.in_off) {
+      const int32_t ia = G.in_off[v], ib = G.in_off[v + 1];
+      if ((v == 0 && ia != 0) || ib < ia || (v == G.n - 1 && (int64_t)ib != G.m)) set_status(st, MOTIF_EINVAL_SHAPE);
+      uin_off[V] = (int32_t)(aoff[g] + ia);
+    } else {
+      uin_off[V] = (int32_t)aoff[g];  // empty in-rows; not checked
+    }
+  }
+}
+
+__global__ void k_pack_arcs(const motif_graph_t* gs, int32_t count, const int64_t* voff, const int64_t* aoff,
+                            int64_t M, int32_t* uidx, int32_t* uin_idx, int32_t* st) {
+  for (int64_t A = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; A < M; A += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = graph_of(aoff, count, A);
+    const motif_graph_t G = gs[g];
+    const int64_t a = A - aoff[g];
+    int32_t d = G.out_idx[a];
+    if (d < 0 || d >= G.n) { set_status(st, MOTIF_EINDEX); d = 0; }
+    uidx[A] = (int32_t)(voff[g] + d);
+    if (G.in_idx) {
+      int32_t s = G.in_idx[a];
+      if (s < 0 || s >= G.n) { set_status(st, MOTIF_EINDEX); s = 0; }
+      uin_idx[A] = (int32_t)(voff[g] + s);
+    }
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host ---
+
+void enqueue_zero(void* ptr, size_t bytes, hipStream_t s) {
+  size_t words = (bytes + 3) / 4;
+  if (!words) return;
+  hipLaunchKernelGGL(k_zero, dim3(grid_for((int64_t)words)), dim3(kB), 0, s, (uint32_t*)ptr, words);
+}
+
+size_t build_bytes(int64_t N, int64_t M, int32_t G, bool batch) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  size_t b = 0;
+  b += 5 * al(sizeof(int32_t) * (N + 1));          // in_cnt, hoff, fill, deg, dplus/np_off
+  b += al(sizeof(int32_t) * (N + 1));              // gs_off
+  b += al(sizeof(int32_t) * (N + 1));              // np_off
+  b += al(sizeof(uint32_t) * 2 * (M + 1));         // keys
+  b += al(sizeof(uint32_t) * 2 * (M + 1));         // gs_idx
+  b += al(sizeof(uint32_t) * (M + 1));             // np_idx
+  b += 2 * al(sizeof(int32_t) * (N + 1));          // sort queues
+  b += al(sizeof(uint32_t) * kBigSlots * ((2 * N + 31) / 32 + 1));
+  b += al(sizeof(uint32_t) * ((2 * M + 31) / 32 + 1));  // transpose marks
+  b += al(sizeof(int32_t) * scan_scratch(N + 1));
+  if (batch) {
+    b += 2 * al(sizeof(int32_t) * (N + 1)) + 2 * al(sizeof(int32_t) * (M + 1)) + al(sizeof(int32_t) * (N + 1));
+    b += 2 * al(sizeof(int64_t) * (G + 1)) + al(sizeof(motif_graph_t) * G) + al(sizeof(int32_t) * G);
+  }
+  return b;
+}
+
+BuildInput enqueue_pack(Pipeline& p, const motif_graph_t* graphs, int32_t count, const int64_t* voff,
+                        const int64_t* aoff, hipStream_t s) {
+  const int64_t N = voff[count], M = aoff[count];
+  Arena& A = p.arena;
+  int32_t* uoff = A.take<int32_t>(N + 1);
+  int32_t* uidx = A.take<int32_t>(M + 1);
+  int32_t* uin_off = A.take<int32_t>(N + 1);
+  int32_t* uin_idx = A.take<int32_t>(M + 1);
+  int32_t* gid = A.take<int32_t>(N + 1);
+  int64_t* dvoff = A.take<int64_t>(count + 1);
+  int64_t* daoff = A.take<int64_t>(count + 1);
+  motif_graph_t* dg = A.take<motif_graph_t>(count);
+  int32_t* has_in = A.take<int32_t>(count);
+  hipMemcpyAsync(dvoff, voff, sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(daoff, aoff, sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(dg, graphs, sizeof(motif_graph_t) * count, hipMemcpyHostToDevice, s);
+  hipLaunchKernelGGL(k_pack_rows, dim3(grid_for(N + 1)), dim3(kB), 0, s, dg, count, dvoff, daoff, N, M, uoff,
+                     uin_off, gid, has_in, p.status);
+  bool any_in = false;
+  for (int32_t g = 0; g < count; ++g) any_in |= graphs[g].in_off != nullptr;
+  if (M > 0)
+    hipLaunchKernelGGL(k_pack_arcs, dim3(grid_for(M)), dim3(kB), 0, s, dg, count, dvoff, daoff, M, uidx,
+                       any_in ? uin_idx : nullptr, p.status);
+  BuildInput in{};
+  in.out_off = uoff;
+  in.out_idx = uidx;
+  in.in_off = any_in ? uin_off : nullptr;
+  in.in_idx = any_in ? uin_idx : nullptr;
+  in.n = (int32_t)N;
+  in.m = M;
+  in.gid = gid;
+  in.ngraphs = count;
+  in.has_in = has_in;
+  return in;
+}
+
+DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s) {
+  Arena& A = p.arena;
+  const int32_t n = in.n;
+  const int64_t m = in.m;
+  int32_t* st = p.status;
+  int32_t* in_cnt = A.take<int32_t>(n + 1);
+  int32_t* hoff = A.take<int32_t>(n + 1);
+  int32_t* fill = A.take<int32_t>(n + 1);
+  int32_t* deg = A.take<int32_t>(n + 1);
+  int32_t* gs_off = A.take<int32_t>(n + 1);
+  int32_t* np_off = A.take<int32_t>(n + 1);
+  uint32_t* keys = A.take<uint32_t>(2 * m + 1);
+  uint32_t* gs_idx = A.take<uint32_t>(2 * m + 1);
+  uint32_t* np_idx = A.take<uint32_t>(m + 1);
+  int32_t* midq = A.take<int32_t>(n + 1);
+  int32_t* bigq = A.take<int32_t>(n + 1);
+  const int64_t bm_words = (2 * (int64_t)n + 31) / 32 + 1;
+  uint32_t* bitmaps = A.take<uint32_t>(kBigSlots * bm_words);
+  uint32_t* marks = A.take<uint32_t>((2 * m + 31) / 32 + 1);
+  int32_t* scratch = A.take<int32_t>(scan_scratch(n + 1));
+
+  DevGraph g;
+  g.n = n;
+  g.gs_off = gs_off;
+  g.gs_idx = gs_idx;
+  g.np_off = np_off;
+  g.np_idx = np_idx;
+  g.gid = in.gid;
+  g.ngraphs = in.ngraphs;
+  if (n == 0) return g;
+
+  enqueue_zero(in_cnt, sizeof(int32_t) * (n + 1), s);
+  if (!in.gid) hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.out_off, n, m, st);
+  if (m > 0)
+    hipLaunchKernelGGL(k_count_in, dim3(grid_for(m)), dim3(kB), 0, s, in.out_off, in.out_idx, n, m, in_cnt, st);
+  hipLaunchKernelGGL(k_half_counts, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.out_off, in_cnt, n, hoff, fill, st);
+  scan_excl(hoff, n + 1, scratch, s);
+  if (m > 0)
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(m)), dim3(kB), 0, s, in.out_off, in.out_idx, n, m, hoff, fill, keys,
+                       st);
+  hipLaunchKernelGGL(k_sort_small, dim3(grid_for(n)), dim3(kB), 0, s, hoff, n, keys, midq, bigq, st);
+  hipLaunchKernelGGL(k_sort_mid, dim3(512), dim3(kB), 0, s, hoff, keys, midq, st);
+  hipLaunchKernelGGL(k_sort_big, dim3(kBigSlots), dim3(kB), 0, s, hoff, n, keys, bigq, bitmaps, st);
+  hipLaunchKernelGGL(k_row_degree, dim3(grid_for(n)), dim3(kB), 0, s, hoff, n, keys, deg, st);
+  hipLaunchKernelGGL(k_copy_pad, dim3(grid_for(n + 1)), dim3(kB), 0, s, deg, n, gs_off, st);
+  scan_excl(gs_off, n + 1, scratch, s);
+  hipLaunchKernelGGL(k_write_gstar, dim3(grid_for(n)), dim3(kB), 0, s, hoff, n, keys, gs_off, gs_idx, st);
+  hipLaunchKernelGGL(k_count_plus, dim3(grid_for(n + 1)), dim3(kB), 0, s, gs_off, gs_idx, deg, n, np_off, st);
+  scan_excl(np_off, n + 1, scratch, s);
+  hipLaunchKernelGGL(k_write_plus, dim3(grid_for(n)), dim3(kB), 0, s, gs_off, gs_idx, deg, n, np_off, np_idx, st);
+  if (in.in_off) {
+    if (!in.gid) hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.in_off, n, m, st);
+    hipLaunchKernelGGL(k_check_in_rows, dim3(grid_for(n)), dim3(kB), 0, s, in.in_off, in_cnt, n, in.gid, in.has_in,
+                       st);
+    enqueue_zero(marks, sizeof(uint32_t) * ((2 * m + 31) / 32 + 1), s);
+    if (m > 0)
+      hipLaunchKernelGGL(k_check_in_arcs, dim3(grid_for(m)), dim3(kB), 0, s, in.in_off, in.in_idx, n, m, gs_off,
+                         gs_idx, in.gid, in.has_in, marks, st);
+  }
+  return g;
+}
+
+}  // namespace motif

@@ -1,0 +1,137 @@
+// Internal declarations shared by the host orchestration (api.cpp, server.cpp)
+// and the device code (graph.hip, census.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+
+#include "../../include/motif.h"
+
+namespace motif {
+
+// G* entry: neighbour id in bits 0..29, type in bits 30..31 relative to the
+// row vertex r: 1 = B (arc r->x only), 2 = C (arc x->r only), 3 = A (both),
+// the partition A^v / B^v / C^v of Section "Notation and definitions".
+constexpr uint32_t kIdMask = 0x3FFFFFFFu;
+constexpr int kTypeShift = 30;
+constexpr int32_t kMaxN = 1 << 30;
+
+// Device status word slots.
+enum StatusSlot : int {
+  kStatus = 0,       // 0 or a MOTIF_E* code (the most negative one wins)
+  kMidCount = 1,     // number of mid-size segments queued for sorting
+  kBigCount = 2,     // number of big segments queued for sorting
+  kQueue = 3,        // anchor work-queue cursor
+  kQueue2 = 4,       // second work-queue cursor
+  kStatusWords = 16,
+};
+
+// Built undirected typed graph (possibly the disjoint union of a batch).
+struct DevGraph {
+  int32_t n = 0;
+  const int32_t* gs_off = nullptr;  // [n+1]
+  const uint32_t* gs_idx = nullptr; // [2m*] sorted by id per row, typed
+  const int32_t* np_off = nullptr;  // [n+1]
+  const uint32_t* np_idx = nullptr; // [m*]  N+(v): neighbours of higher rank
+  const int32_t* gid = nullptr;     // [n] graph of each vertex (batch) or null
+  int32_t ngraphs = 1;
+};
+
+// Device class tables uploaded by motif_init.
+struct DevTables {
+  const uint16_t* lut[6] = {};   // index k
+  const uint8_t* mult[6] = {};
+};
+const DevTables& dev_tables();
+
+// Grow-only device arena with a bump allocator.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  void reset() { used = 0; }
+  // Every region is carved before the kernels that use it are launched, so an
+  // undersized arena stops the process before any kernel could write past it.
+  template <class T>
+  T* take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    if (used + bytes > cap) {
+      std::fprintf(stderr, "motif: workspace sizing error (%zu + %zu > %zu)\n", used, bytes, cap);
+      std::abort();
+    }
+    T* p = reinterpret_cast<T*>(base + used);
+    used += bytes;
+    return p;
+  }
+};
+
+// Buffers of one census pipeline (one stream).
+struct Pipeline {
+  Arena arena;
+  int32_t* status = nullptr;       // device [kStatusWords]
+  int32_t* host_status = nullptr;  // pinned host copy
+  int num_cus = 0;
+};
+
+// Launch parameters used by the census kernels.
+struct Tuning {
+  int block = 256;
+  int grid_per_cu = 4;
+  int tile = 16;
+  int heavy = 0;
+};
+Tuning& tuning_for(int k);
+
+// Bytes the arena needs for a union graph of N vertices, M arcs, G graphs
+// (G > 1 includes the packing buffers of a batch).
+size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int num_cus);
+size_t build_bytes(int64_t N, int64_t M, int32_t G, bool batch);
+
+// Inputs of the build: either one graph or a packed batch.
+struct BuildInput {
+  const int32_t* out_off;
+  const int32_t* out_idx;
+  const int32_t* in_off;  // may be null
+  const int32_t* in_idx;  // may be null
+  int32_t n;
+  int64_t m;
+  const int32_t* gid = nullptr;     // batch only
+  int32_t ngraphs = 1;
+  const int32_t* has_in = nullptr;  // batch only: graph supplied an in-CSR
+};
+
+// Enqueue validation + G* + N+ build.  Returns the built view (device pointers
+// into the arena).  Does not wait.
+DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s);
+
+// Enqueue the census of k into acc[ngraphs * C] (accumulators, zeroed here)
+// and the exact division into out[ngraphs * C] (written only if every
+// remainder is zero).
+void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64_t* out,
+                    hipStream_t s);
+
+// Pack `count` device graphs into one union CSR inside the arena.
+// Host arrays voff/aoff are the prefix sums of n and m.
+BuildInput enqueue_pack(Pipeline& p, const motif_graph_t* graphs, int32_t count,
+                        const int64_t* voff, const int64_t* aoff, hipStream_t s);
+
+// Zero fill helper (a kernel, so it is safe inside captured graphs).
+void enqueue_zero(void* ptr, size_t bytes, hipStream_t s);
+
+// Device setup (class tables) for the current device; returns the device id.
+int32_t ensure_init(int* dev);
+int device_cus(int dev);
+
+// Validation + build + census on a pipeline whose arena is already sized
+// (host waits for the status word twice).  Used by every entry point.
+int32_t run_census_on(Pipeline& p, const BuildInput& in, int32_t k, uint64_t* hist, hipStream_t s);
+int32_t read_status(Pipeline& p, hipStream_t s);
+
+// Optional event timing of the build and of the census kernel (motif_profile_*):
+// no-ops unless profiling is enabled.  `what` is 0 = build, 1 = census kernel.
+void profile_mark(int k, int what, bool begin, hipStream_t s);
+
+}  // namespace motif

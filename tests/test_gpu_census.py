@@ -1,0 +1,271 @@
+"""GPU parity: the HIP census (through the C ABI) against the CPU oracle,
+bit-exact, on seeded inputs covering several tiles, ragged rows, hubs, both
+label-storage paths, the degenerate cases and the error paths."""
+import math
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1203_3415_amd as pm
+    pm.lib()
+    return pm
+
+
+def _dev(pm, off, idx):
+    return pm.to_device(np.asarray(off), np.asarray(idx))
+
+
+def gpu_census(pm, g, k, **kw):
+    off, idx = _dev(pm, g.out_off, g.out_idx)
+    return pm.census(off, idx, g.n, k, **kw)
+
+
+def assert_parity(pm, g, k, label):
+    print(f"[case] {label} n={g.n} m={g.m} k={k}", flush=True)
+    got = gpu_census(pm, g, k)
+    want = oracle.census(g, k)
+    if not np.array_equal(got, want):
+        bad = np.flatnonzero(got != want)
+        raise AssertionError(f"{label} k={k}: {len(bad)} classes differ, first {bad[:6].tolist()}: "
+                             f"gpu {got[bad[:6]].tolist()} oracle {want[bad[:6]].tolist()}")
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_small_random(pm, k):
+    rng = np.random.default_rng(10 + k)
+    for t in range(30 if k < 5 else 16):
+        n = int(rng.integers(2, 26))
+        g = gg.random_small(n, float(rng.uniform(0.05, 0.7)), float(rng.uniform(0, 1)), seed=500 * k + t)
+        assert_parity(pm, g, k, f"random_small#{t}")
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_structured(pm, k):
+    cases = {
+        "complete": gg.complete_digraph(9),
+        "transitive": gg.transitive_tournament(10),
+        "cycle": gg.directed_cycle(12),
+        "cycle_k": gg.directed_cycle(k),
+        "path": gg.directed_path(12),
+        "star": gg.star(4, 4, 5),
+        "empty": gg.from_arcs(10, []),
+        "n_lt_k": gg.complete_digraph(k - 1),
+        "one_arc": gg.from_arcs(5, [(3, 1)]),
+        "bidirected": gg.random_small(14, 0.3, 1.0, seed=3),
+        "dag": gg.from_arcs(15, [(i, j) for i in range(15) for j in range(i + 1, 15) if (i * 7 + j * 3) % 4 == 0]),
+        "isolated": gg.disjoint_union(gg.from_arcs(7, []), gg.random_small(9, 0.4, 0.3, seed=4), gg.from_arcs(5, [])),
+    }
+    for name, g in cases.items():
+        assert_parity(pm, g, k, name)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_gnm_n1000_m5500(pm, k):
+    # the paper-shaped small workload: G(n=1000, m=5000) + 10% reciprocated
+    assert_parity(pm, gg.gnm_reciprocal(1000, 5000, 0.1, seed=1), k, "gnm1000")
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_power_law_n2000(pm, k):
+    assert_parity(pm, gg.chung_lu(2000, 8000, 2.3, 2.3, 0.05, seed=3), k, "chung_lu2000")
+
+
+def test_power_law_k5(pm):
+    assert_parity(pm, gg.chung_lu(600, 2400, 2.2, 2.5, 0.1, seed=4), 5, "chung_lu600")
+
+
+def _star_expect(k, na, nb, nc):
+    C = oracle.N_CLASSES[k]
+    expect = np.zeros(C, np.uint64)
+    for i in range(k):
+        for j in range(k - i):
+            l = k - 1 - i - j
+            cnt = math.comb(na, i) * math.comb(nb, j) * math.comb(nc, l)
+            if not cnt:
+                continue
+            arcs, leaf = [], 1
+            for _ in range(i):
+                arcs += [(0, leaf), (leaf, 0)]; leaf += 1
+            for _ in range(j):
+                arcs.append((0, leaf)); leaf += 1
+            for _ in range(l):
+                arcs.append((leaf, 0)); leaf += 1
+            expect[oracle.class_of(k, arcs)] += cnt
+    return expect
+
+
+@pytest.mark.parametrize("k,sizes", [(3, (3000, 2000, 1500)), (4, (2500, 2000, 1500)), (5, (90, 70, 60))])
+def test_hub_star_closed_form(pm, k, sizes):
+    # a hub far above the LDS sort threshold; expected values by the multinomial
+    # closed form of the star (only sets containing the centre are connected)
+    g = gg.star(*sizes)
+    print(f"[case] star{sizes} k={k}", flush=True)
+    got = gpu_census(pm, g, k)
+    assert np.array_equal(got, _star_expect(k, *sizes))
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_global_label_path(pm, k):
+    # n above the LDS label capacity (131072 vertices at 4 bits, 65536 at 8 bits)
+    base = gg.chung_lu(3000, 12000 if k == 4 else 6000, 2.3, 2.3, 0.1, seed=21)
+    g = gg.relabel(gg.disjoint_union(base, gg.from_arcs(140000 - base.n, [])), seed=22)
+    assert_parity(pm, g, k, "global_labels")
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_unsorted_rows_and_in_csr(pm, k):
+    g = gg.chung_lu(800, 4000, 2.2, 2.2, 0.3, seed=31)
+    want = oracle.census(g, k)
+    rng = np.random.default_rng(5)
+    idx = g.out_idx.copy()
+    for v in range(g.n):
+        a, b = g.out_off[v], g.out_off[v + 1]
+        idx[a:b] = rng.permutation(idx[a:b])
+    off_d, idx_d = _dev(pm, g.out_off, idx)
+    in_off, in_idx = g.in_csr()
+    in_idx_shuf = in_idx.copy()
+    for v in range(g.n):
+        a, b = in_off[v], in_off[v + 1]
+        in_idx_shuf[a:b] = rng.permutation(in_idx_shuf[a:b])
+    io_d, ii_d = _dev(pm, in_off, in_idx_shuf)
+    assert np.array_equal(pm.census(off_d, idx_d, g.n, k), want)
+    assert np.array_equal(pm.census(off_d, idx_d, g.n, k, in_off=io_d, in_idx=ii_d), want)
+    # a wrong in-CSR: one in-arc replaced by a non-arc
+    bad = in_idx.copy()
+    v = int(np.argmax(np.diff(in_off)))
+    a = in_off[v]
+    present = set(bad[in_off[v]:in_off[v + 1]].tolist())
+    bad[a] = next(x for x in range(g.n) if x != v and x not in present)
+    bo_d, bi_d = _dev(pm, in_off, bad)
+    with pytest.raises(pm.MotifError) as e:
+        pm.census(off_d, idx_d, g.n, k, in_off=bo_d, in_idx=bi_d)
+    assert e.value.name == "ETRANSPOSE"
+    # a repeated in-arc (count right, one arc missing)
+    dup = in_idx.copy()
+    w = next(v for v in range(g.n) if in_off[v + 1] - in_off[v] >= 2)
+    dup[in_off[w] + 1] = dup[in_off[w]]
+    do_d, di_d = _dev(pm, in_off, dup)
+    with pytest.raises(pm.MotifError) as e:
+        pm.census(off_d, idx_d, g.n, k, in_off=do_d, in_idx=di_d)
+    assert e.value.name == "ETRANSPOSE"
+
+
+def _expect_error(pm, off, idx, n, k, name):
+    print(f"[case] error {name}", flush=True)
+    off_d, idx_d = _dev(pm, np.asarray(off, np.int32), np.asarray(idx, np.int32))
+    with pytest.raises(pm.MotifError) as e:
+        pm.census(off_d, idx_d, n, k)
+    assert e.value.name == name, e.value
+
+
+def test_errors(pm):
+    _expect_error(pm, [0, 1, 2, 2], [1, 1], 3, 3, "ESELFLOOP")
+    _expect_error(pm, [0, 2, 2, 2], [1, 1], 3, 3, "EDUP")
+    _expect_error(pm, [0, 1, 2, 2], [5, 0], 3, 3, "EINDEX")
+    _expect_error(pm, [0, 1, 2, 2], [-1, 0], 3, 3, "EINDEX")
+    _expect_error(pm, [0, 2, 1, 2], [1, 2], 3, 4, "EINVAL_SHAPE")
+    _expect_error(pm, [1, 1, 2, 2], [1, 2], 3, 4, "EINVAL_SHAPE")
+    _expect_error(pm, [0, 1, 2, 3], [1, 2], 3, 4, "EINVAL_SHAPE")
+    _expect_error(pm, [0, 1, 2, 2], [1, 0], 3, 6, "EINVAL_K")
+    # a repeated arc in a mid-size row (LDS sort) and in a big row (bitmap sort)
+    for deg in (100, 5000):
+        idx = list(range(1, deg + 1)) + [7]
+        _expect_error(pm, [0, deg + 1] + [deg + 1] * deg, idx, deg + 1, 4, "EDUP")
+    # histogram untouched on error
+    import torch
+    off_d, idx_d = _dev(pm, np.asarray([0, 1, 2, 2], np.int32), np.asarray([1, 1], np.int32))
+    out = torch.full((13,), 7, dtype=torch.int64, device="cuda")
+    with pytest.raises(pm.MotifError):
+        pm.census(off_d, idx_d, 3, 3, out=out)
+    assert bool((out == 7).all())
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_invariances(pm, k):
+    g = gg.chung_lu(400, 1600, 2.2, 2.4, 0.2, seed=41)
+    print(f"[case] invariances k={k}", flush=True)
+    h = gpu_census(pm, g, k)
+    assert np.array_equal(gpu_census(pm, gg.relabel(g, 9), k), h)
+    g2 = gg.gnm_reciprocal(300, 900, 0.3, seed=42)
+    h2 = gpu_census(pm, g2, k)
+    assert np.array_equal(gpu_census(pm, gg.disjoint_union(g, g2), k), h + h2)
+    # reversing every arc sends each class to the class of its transpose
+    C = len(h)
+    expect = np.zeros(C, np.uint64)
+    for c in range(C):
+        code = pm.class_code(k, c)
+        t = 0
+        for i in range(k):
+            for j in range(k):
+                if i != j and code >> (i * (k - 1) + (j if j < i else j - 1)) & 1:
+                    t |= 1 << (j * (k - 1) + (i if i < j else i - 1))
+        expect[pm.class_of_code(k, t)] += h[c]
+    assert np.array_equal(gpu_census(pm, gg.reverse(g), k), expect)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_batch_matches_alone(pm, k):
+    rng = np.random.default_rng(60 + k)
+    graphs = []
+    for t in range(14):
+        n = int(rng.integers(20, 400 if k < 5 else 150))
+        m = int(n * rng.uniform(1.5, 4.0))
+        graphs.append(gg.chung_lu(n, m, 2.3, 2.3, float(rng.uniform(0, 0.2)), seed=700 + t))
+    graphs.insert(3, gg.from_arcs(0, []))
+    graphs.insert(7, gg.from_arcs(12, []))
+    graphs.append(gg.complete_digraph(k))
+    dev = [(*_dev(pm, g.out_off, g.out_idx), g.n) for g in graphs]
+    print(f"[case] batch k={k} graphs={len(graphs)}", flush=True)
+    hb = pm.census_batch(dev, k)
+    hl = pm.census_batch_loop(dev, k)
+    for i, g in enumerate(graphs):
+        want = oracle.census(g, k)
+        assert np.array_equal(hb[i], want), f"batch graph {i}"
+        assert np.array_equal(hl[i], want), f"loop graph {i}"
+
+
+def test_batch_with_in_csr_and_errors(pm):
+    gs = [gg.chung_lu(200, 800, 2.3, 2.3, 0.1, seed=80 + t) for t in range(4)]
+    dev = []
+    for i, g in enumerate(gs):
+        o, x = _dev(pm, g.out_off, g.out_idx)
+        if i % 2 == 0:
+            io, ii = _dev(pm, *g.in_csr())
+            dev.append((o, x, g.n, io, ii))
+        else:
+            dev.append((o, x, g.n))
+    hb = pm.census_batch(dev, 4)
+    for i, g in enumerate(gs):
+        assert np.array_equal(hb[i], oracle.census(g, 4))
+    # one graph with a self-loop fails the whole batch
+    bad_off, bad_idx = _dev(pm, np.asarray([0, 1, 1], np.int32), np.asarray([0], np.int32))
+    with pytest.raises(pm.MotifError) as e:
+        pm.census_batch(dev + [(bad_off, bad_idx, 2)], 4)
+    assert e.value.name == "ESELFLOOP"
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_tuning_variants_agree(pm, k):
+    g = gg.chung_lu(700, 3000, 2.2, 2.3, 0.1, seed=90)
+    want = oracle.census(g, k)
+    saved = pm.get_tuning(k)
+    try:
+        blocks = (256, 512, 1024) if k == 4 else (512, 1024)
+        for block in blocks:
+            for tile in (1, 7, 64):
+                for gpc in (1, 3):
+                    pm.set_tuning(k, block=block, tile=tile, grid_per_cu=gpc)
+                    print(f"[case] tuning k={k} block={block} tile={tile} gpc={gpc}", flush=True)
+                    assert np.array_equal(gpu_census(pm, g, k), want)
+    finally:
+        pm.set_tuning(k, **saved)
