@@ -446,6 +446,10 @@ __global__ __launch_bounds__(BLOCK) void k5_kernel(DevGraph G, const uint16_t* _
         if (threadIdx.x < NL) cnt[threadIdx.x] = 0;
         __syncthreads();
       }
+      // Skipped triples read a-labels without a barrier: every wave must have
+      // left the triple loop before any wave clears them, or a late wave would
+      // see "not adjacent" for a skipped triangle and fall out of barrier step.
+      __syncthreads();
       for (int32_t i = threadIdx.x; i < da; i += BLOCK) lab.clear_bits(G.gs_idx[aa + i] & kIdMask, 3u << 2);
       __syncthreads();
     }
