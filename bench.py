@@ -1,0 +1,397 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the MI355X motif census (one JSON line on stdout).
+
+Default workload: Motifs-3 and Motifs-4 on a directed Chung-Lu power-law
+digraph with n = 100,000 vertices and m = 1,000,000 arcs (in/out weight
+exponent 2.1, reciprocity 0.2, seed 2).  One step = the exact census for k = 3
+and for k = 4 of that graph, whose CSR is resident in HBM before timing starts
+(validation, typed-G* build, census kernels and exact division all run inside
+the step).  value = arcs censused per second = m / (step time).
+
+Other workloads (--workload): gnm_n1000 (k = 3,4,5 on a G(n,m) digraph with
+n = 1000, m = 5000 + 10 % reciprocated), chunglu_n2e4_k5 (Motifs-5 on a
+Chung-Lu digraph n = 20,000, m = 100,000, exponents 2.2/2.5, reciprocity 0.1),
+nullmodel_k4 (batched null model: graphs per second, fused vs per-graph loop)
+and serving (Poisson request stream: p50/p99 latency and throughput).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _threads() -> int:
+    try:
+        return int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    except ValueError:
+        return os.cpu_count() or 1
+
+
+# ------------------------------------------------------------- workloads ---
+
+def make_graph(name: str):
+    import graphgen as gg
+    if name == "chunglu_n1e5_k34":
+        return gg.chung_lu(100_000, 1_000_000, 2.1, 2.1, 0.2, seed=2), (3, 4)
+    if name == "gnm_n1000":
+        return gg.gnm_reciprocal(1000, 5000, 0.1, seed=1), (3, 4, 5)
+    if name == "chunglu_n2e4_k5":
+        return gg.chung_lu(20_000, 100_000, 2.2, 2.5, 0.1, seed=4), (5,)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def graph_stats(g):
+    """Degree-ordered structure of G* used for the algorithmic-byte counts:
+    d*(v), d+(v), sum over neighbours of d+ (S+), per-vertex triangle counts."""
+    n = g.n
+    a = g.arcs()
+    lo = np.minimum(a[:, 0], a[:, 1])
+    hi = np.maximum(a[:, 0], a[:, 1])
+    key = np.unique(lo * n + hi)
+    u, v = key // n, key % n
+    deg = np.bincount(u, minlength=n) + np.bincount(v, minlength=n)
+    rank_u = deg[u] * n + u
+    rank_v = deg[v] * n + v
+    src = np.where(rank_u < rank_v, u, v)
+    dst = np.where(rank_u < rank_v, v, u)
+    order = np.lexsort((dst, src))
+    src, dst = src[order], dst[order]
+    dplus = np.bincount(src, minlength=n)
+    poff = np.zeros(n + 1, np.int64)
+    np.cumsum(dplus, out=poff[1:])
+    # S+(v) = sum of d+ over all neighbours of v
+    splus = np.bincount(u, weights=dplus[v], minlength=n) + np.bincount(v, weights=dplus[u], minlength=n)
+    # triangles per vertex by oriented intersection
+    tri = np.zeros(n, np.int64)
+    mark = np.zeros(n, bool)
+    for x in np.flatnonzero(dplus >= 2):
+        nx = dst[poff[x]:poff[x + 1]]
+        mark[nx] = True
+        for w in nx:
+            cand = dst[poff[w]:poff[w + 1]]
+            hit = cand[mark[cand]]
+            if hit.size:
+                tri[x] += hit.size
+                tri[w] += hit.size
+                np.add.at(tri, hit, 1)
+        mark[nx] = False
+    return dict(n=n, mstar=int(key.size), deg=deg, dplus=dplus, splus=splus, tri=tri, u=u, v=v)
+
+
+def k4_kernel_bytes(st) -> float:
+    """Algorithmic bytes of one k = 4 census kernel launch: per undirected
+    edge e = {u,v} the two typed rows (4 (d_u + d_v) B) and, per vertex x of
+    adj(e), its oriented row (4 d+(x) B) plus its two offsets (8 B).
+    |adj(e)| = d_u + d_v - 2 - |N(u) ∩ N(v)|, summed with the triangle counts."""
+    deg, dplus, splus, tri, u, v = st["deg"], st["dplus"], st["splus"], st["tri"], st["u"], st["v"]
+    rows = 4.0 * float((deg.astype(np.float64) ** 2).sum())
+    members = float((deg[u] + deg[v] - 2).sum()) - 3.0 * float(tri.sum() / 3)
+    probes = float((splus[u] + splus[v]).sum() - (dplus[u] + dplus[v]).sum()) - float((dplus * tri).sum())
+    return rows + 4.0 * probes + 8.0 * members
+
+
+def k3_kernel_bytes(st) -> float:
+    """Algorithmic bytes of one k = 3 census kernel launch: each vertex's typed
+    row (closed form) and, per oriented edge u->w, the rows N+(u) and N+(w)."""
+    deg, dplus = st["deg"], st["dplus"]
+    rows = 4.0 * float(deg.sum())
+    # sum over oriented edges of d+(u) + d+(w) = sum_v d+(v) * (d+(v) + d-(v)) = sum_v d+(v) d*(v)
+    merge = 4.0 * float((dplus.astype(np.float64) * deg).sum())
+    return rows + merge
+
+
+# ------------------------------------------------------------ main bench ---
+
+def bench_census(args):
+    import torch
+    import paper_1203_3415_amd as pm
+
+    g, ks = make_graph(args.workload)
+    dev = torch.device("cuda:0")
+    off, idx = pm.to_device(g.out_off, g.out_idx, dev)
+    outs = {k: torch.empty(pm.NUM_CLASSES[k], dtype=torch.int64, device=dev) for k in ks}
+    torch.cuda.synchronize()
+
+    def step():
+        for k in ks:
+            pm.census(off, idx, g.n, k, out=outs[k])
+
+    for _ in range(args.warmup):
+        step()
+    ref = {k: outs[k].cpu().numpy().view(np.uint64).copy() for k in ks}
+
+    pm.profile_enable(True)
+    kern_ms = {k: [] for k in ks}
+    build_ms = {k: [] for k in ks}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for k in ks:
+            pm.census(off, idx, g.n, k, out=outs[k])
+            km, bm = pm.profile_read(k)
+            kern_ms[k].append(km)
+            build_ms[k].append(bm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pm.profile_enable(False)
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    # the same histogram on every step (counts are exact integers)
+    stable = all(np.array_equal(outs[k].cpu().numpy().view(np.uint64), ref[k]) for k in ks)
+
+    st = graph_stats(g)
+    checks = {"stable_across_steps": bool(stable)}
+    if 3 in ks:
+        wedges = int((st["deg"] * (st["deg"] - 1) // 2).sum())
+        t_total = int(st["tri"].sum() // 3)
+        checks["k3_sum_equals_wedges_minus_2T"] = int(ref[3].sum()) == wedges - 2 * t_total
+
+    dominant = max(ks)
+    kms = float(np.mean(kern_ms[dominant]))
+    if dominant == 4:
+        kbytes = k4_kernel_bytes(st)
+    elif dominant == 3:
+        kbytes = k3_kernel_bytes(st)
+    else:
+        kbytes = None
+    roofline = None
+    if kbytes is not None:
+        achieved = kbytes / (kms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": f"k{dominant}_kernel", "kernel_ms": round(kms, 3),
+                    "algorithmic_bytes": kbytes}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(g, ks, {k: int(ref[k].sum()) for k in ks}, args.cpu_seconds)
+
+    value = g.m / (ms_per_step * 1e-3)
+    line = {
+        "metric": "arcs censused/sec",
+        "value": round(value, 1),
+        "unit": "arcs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": g.n, "m": g.m, "mstar": st["mstar"], "k": list(ks),
+                   "generator": describe(args.workload)},
+        "detail": {f"k{k}": {"census_kernel_ms": round(float(np.mean(kern_ms[k])), 3),
+                             "build_ms": round(float(np.mean(build_ms[k])), 3),
+                             "connected_sets": int(ref[k].sum())} for k in ks},
+        "checks": checks,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def describe(name):
+    return {
+        "chunglu_n1e5_k34": "Chung-Lu n=100000 m=1000000 gamma_out=gamma_in=2.1 reciprocity=0.2 seed=2",
+        "gnm_n1000": "G(n=1000, 5000 arcs) + 10% reciprocated, seed=1",
+        "chunglu_n2e4_k5": "Chung-Lu n=20000 m=100000 gamma_out=2.2 gamma_in=2.5 reciprocity=0.1 seed=4",
+    }.get(name, name)
+
+
+def cpu_baseline(g, ks, total_sets, seconds):
+    """The oracle (ESU + k! canonical labelling) timed on the host cores on a
+    bounded sample: roots in a seeded random order for `seconds` per k; the
+    rate in connected sets per second projects the full census time."""
+    import oracle
+    threads = _threads()
+    roots = np.random.default_rng(12345).permutation(g.n).astype(np.int32)
+    proj = 0.0
+    sample = {}
+    for k in ks:
+        oracle.class_table(k)  # table build excluded from timing
+        t = time.perf_counter()
+        h = oracle.census_timed(g, k, roots, seconds, threads=threads)
+        dt = time.perf_counter() - t
+        done = int(h.sum())
+        rate = done / dt if dt > 0 else 0.0
+        proj += total_sets[k] / rate if rate > 0 else float("inf")
+        sample[f"k{k}"] = {"seconds": round(dt, 2), "sets": done, "sets_per_s": round(rate, 1)}
+    value = g.m / proj if proj > 0 else 0.0
+    return {"value": round(value, 3), "unit": "arcs/s", "cores": threads, "kind": "oracle",
+            "sample": (f"ESU from roots in seeded random order, {seconds:.0f} s per k on {threads} threads; "
+                       f"full-census time projected from connected sets/s"),
+            "projected_seconds": round(proj, 1), "detail": sample}
+
+
+# ------------------------------------------------------- batch & serving ---
+
+def bench_nullmodel(args):
+    import torch
+    import graphgen as gg
+    import paper_1203_3415_amd as pm
+
+    rng = np.random.default_rng(3)
+    base = gg.chung_lu(2000, 8000, 2.3, 2.3, 0.05, seed=3)
+    graphs = [base]
+    switches = args.switches if args.switches > 0 else 100 * base.m
+    for i in range(args.null_graphs):
+        graphs.append(gg.arc_switch(base, switches, seed=1000 + i))
+    dev = torch.device("cuda:0")
+    d = [(*pm.to_device(x.out_off, x.out_idx, dev), x.n) for x in graphs]
+    out = torch.empty((len(d), 199), dtype=torch.int64, device=dev)
+    for _ in range(args.warmup):
+        pm.census_batch(d, 4, out=out)
+        pm.census_batch_loop(d, 4, out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        pm.census_batch(d, 4, out=out)
+    torch.cuda.synchronize()
+    fused = (time.perf_counter() - t) / args.steps
+    hb = out.cpu().numpy().view(np.uint64).copy()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        pm.census_batch_loop(d, 4, out=out)
+    torch.cuda.synchronize()
+    loop = (time.perf_counter() - t) / args.steps
+    hl = out.cpu().numpy().view(np.uint64).copy()
+    z = zscores(hb)
+    line = {"metric": "null-model graphs/sec", "value": round(len(d) / fused, 2), "unit": "graphs/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(fused * 1e3, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": "nullmodel_k4", "graphs": len(d), "n": base.n, "m": base.m,
+                       "switch_attempts": switches},
+            "detail": {"fused_graphs_per_s": round(len(d) / fused, 2), "loop_graphs_per_s": round(len(d) / loop, 2),
+                       "fused_equals_loop": bool(np.array_equal(hb, hl)),
+                       "finite_z": int(np.isfinite(z).sum())}}
+    print(json.dumps(line), flush=True)
+
+
+def zscores(h):
+    """z_c = (N_real,c - mean_c) / sd_c over the randomised graphs (rows 1..),
+    from exact integer sums, sd with ddof = 1; NaN where sd = 0."""
+    real = h[0].astype(object)
+    rnd = h[1:].astype(object)
+    cnt = rnd.shape[0]
+    s1 = rnd.sum(axis=0)
+    s2 = (rnd * rnd).sum(axis=0)
+    z = np.full(h.shape[1], np.nan)
+    if cnt < 2:
+        return z
+    for c in range(h.shape[1]):
+        var_num = cnt * s2[c] - s1[c] * s1[c]   # exact integer
+        if var_num <= 0:
+            continue
+        mean = s1[c] / cnt
+        sd = (var_num / (cnt * (cnt - 1))) ** 0.5
+        z[c] = float((real[c] - mean) / sd)
+    return z
+
+
+def bench_serving(args):
+    import graphgen as gg
+    import paper_1203_3415_amd as pm
+
+    rng = np.random.default_rng(5)
+    pool = []
+    for j in range(args.pool):
+        r = np.random.default_rng(10000 + j)
+        m = int(round(10 ** r.uniform(3, args.serve_log_m_max)))
+        gamma = float(r.uniform(2.1, 2.6))
+        recip = float(r.uniform(0, 0.2))
+        k = int(r.integers(3, 6))
+        if k == 5 and m > 200_000:
+            k = int(r.integers(3, 5))
+        n = max(10, m // 5)
+        pool.append((gg.chung_lu(n, m, gamma, gamma, recip, seed=10000 + j), k))
+    lam = args.rate
+    dur = args.serve_seconds
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=int(lam * dur * 2) + 10))
+    arrivals = arrivals[arrivals < dur]
+    picks = rng.integers(0, len(pool), size=arrivals.size)
+    lat = []
+    with pm.Server(args.hbm_budget, max_inflight=args.inflight) as srv:
+        start = time.perf_counter()
+        pending = []
+        for t_arr, p in zip(arrivals, picks):
+            now = time.perf_counter() - start
+            if t_arr > now:
+                time.sleep(t_arr - now)
+            g, k = pool[p]
+            try:
+                tk = srv.submit(g.out_off, g.out_idx, g.n, k)
+            except pm.MotifError:
+                continue
+            pending.append((tk, start + t_arr))
+            still = []
+            for tk2, ta in pending:
+                try:
+                    srv.wait(tk2, timeout_us=0)
+                    lat.append(time.perf_counter() - ta)
+                except TimeoutError:
+                    still.append((tk2, ta))
+            pending = still
+        for tk2, ta in pending:
+            srv.wait(tk2)
+            lat.append(time.perf_counter() - ta)
+        total = time.perf_counter() - start
+        stats = srv.stats()
+    lat = np.array(lat) * 1e3
+    line = {"metric": "census requests/sec", "value": round(len(lat) / total, 2), "unit": "req/s", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": round(total * 1e3, 1), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": "serving", "rate_per_s": lam, "seconds": dur, "pool": len(pool),
+                       "inflight": args.inflight},
+            "detail": {"p50_ms": round(float(np.percentile(lat, 50)), 2) if lat.size else None,
+                       "p99_ms": round(float(np.percentile(lat, 99)), 2) if lat.size else None,
+                       "completed": int(lat.size), "offered": int(arrivals.size),
+                       "peak_bytes": stats["peak_bytes"]}}
+    print(json.dumps(line), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="chunglu_n1e5_k34",
+                    choices=["chunglu_n1e5_k34", "gnm_n1000", "chunglu_n2e4_k5", "nullmodel_k4", "serving"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--null-graphs", type=int, default=1000)
+    ap.add_argument("--switches", type=int, default=0, help="arc-switch attempts per null graph (0 = 100 m)")
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-log-m-max", type=float, default=6.0)
+    ap.add_argument("--pool", type=int, default=64)
+    ap.add_argument("--inflight", type=int, default=8)
+    ap.add_argument("--hbm-budget", type=int, default=64 << 30)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this census runs on one GPU; --gpus must be 1 (multi-GPU sharding is a "
+                                   "design note only)"}), flush=True)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    if args.workload == "nullmodel_k4":
+        bench_nullmodel(args)
+    elif args.workload == "serving":
+        bench_serving(args)
+    else:
+        bench_census(args)
+
+
+if __name__ == "__main__":
+    main()

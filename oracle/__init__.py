@@ -52,6 +52,12 @@ def _lib():
     lib.oracle_multiplicity.restype = ctypes.c_int
     lib.oracle_census.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, P, ctypes.c_int32, P, ctypes.c_int32]
     lib.oracle_census.restype = ctypes.c_int
+    lib.oracle_census_roots.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, P, ctypes.c_int32, P, ctypes.c_int32,
+                                        P, ctypes.c_int32]
+    lib.oracle_census_roots.restype = ctypes.c_int
+    lib.oracle_census_timed.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, P, ctypes.c_int32, P, ctypes.c_int32,
+                                        P, ctypes.c_int32, ctypes.c_double]
+    lib.oracle_census_timed.restype = ctypes.c_int
     return lib
 
 
@@ -96,6 +102,38 @@ def census(g, k: int, threads: int = 0) -> np.ndarray:
     rc = _lib().oracle_census(int(g.n), _ptr(off), _ptr(idx), k, _ptr(cls), len(canon), _ptr(hist), threads)
     if rc != 0:
         raise RuntimeError(f"oracle_census failed: {rc}")
+    return hist
+
+
+def census_roots(g, k: int, roots, threads: int = 0) -> np.ndarray:
+    """Histogram of the connected k-sets whose smallest vertex is in `roots`."""
+    cls, canon, _, _ = class_table(k)
+    hist = np.zeros(len(canon), dtype=np.uint64)
+    off = np.ascontiguousarray(g.out_off, dtype=np.int32)
+    idx = np.ascontiguousarray(g.out_idx, dtype=np.int32)
+    if idx.size == 0:
+        idx = np.zeros(1, np.int32)
+    r = np.ascontiguousarray(roots, dtype=np.int32)
+    rc = _lib().oracle_census_roots(int(g.n), _ptr(off), _ptr(idx), k, _ptr(cls), len(canon), _ptr(hist), threads,
+                                    _ptr(r), int(r.size))
+    if rc != 0:
+        raise RuntimeError(f"oracle_census_roots failed: {rc}")
+    return hist
+
+
+def census_timed(g, k: int, roots, seconds: float, threads: int = 0) -> np.ndarray:
+    """Sets emitted by ESU from `roots` (in order) within `seconds` of wall time."""
+    cls, canon, _, _ = class_table(k)
+    hist = np.zeros(len(canon), dtype=np.uint64)
+    off = np.ascontiguousarray(g.out_off, dtype=np.int32)
+    idx = np.ascontiguousarray(g.out_idx, dtype=np.int32)
+    if idx.size == 0:
+        idx = np.zeros(1, np.int32)
+    r = np.ascontiguousarray(roots, dtype=np.int32)
+    rc = _lib().oracle_census_timed(int(g.n), _ptr(off), _ptr(idx), k, _ptr(cls), len(canon), _ptr(hist), threads,
+                                    _ptr(r), int(r.size), float(seconds))
+    if rc != 0:
+        raise RuntimeError(f"oracle_census_timed failed: {rc}")
     return hist
 
 

@@ -188,6 +188,9 @@ typedef struct {
     int k;
     const uint16_t* cls;
     uint64_t* hist;        /* this thread's histogram */
+    double deadline;       /* omp wall-clock deadline, <= 0: none */
+    volatile int* stop;    /* set once the deadline has passed */
+    uint64_t emitted;
 } esu_ctx;
 
 static int has_edge_u(const esu_ctx* c, int a, int b) {
@@ -212,15 +215,19 @@ static void emit(esu_ctx* c, const int* sub) {
             if (i != j && has_arc(c, v[i], v[j])) code |= 1u << bitpos(k, i, j);
     uint16_t cl = c->cls[code];
     if (cl != 0xFFFF) c->hist[cl] += 1;   /* ESU only emits connected sets */
+#ifdef _OPENMP
+    if (c->deadline > 0 && (++c->emitted & 0xFFFF) == 0 && omp_get_wtime() > c->deadline) *c->stop = 1;
+#endif
 }
 
 /* sub[0..depth) is the current subgraph, ext the extension set. */
 static void extend(esu_ctx* c, int* sub, int depth, const int* ext, int next, int root) {
     if (depth == c->k) { emit(c, sub); return; }
+    if (*c->stop) return;
     int* work = (int*)malloc(sizeof(int) * (size_t)next);
     memcpy(work, ext, sizeof(int) * (size_t)next);
     int nwork = next;
-    while (nwork > 0) {
+    while (nwork > 0 && !*c->stop) {
         int w = work[--nwork];
         /* ext' = remaining ext  U  { u in N(w) : u > root, u not in sub,
          *                             u not adjacent to any vertex of sub } */
@@ -252,8 +259,48 @@ static int cmp_i32(const void* a, const void* b) {
  * Census of the simple digraph given as out-CSR (rows may be unsorted).
  * hist[n_classes] is overwritten.  threads <= 0 means the OpenMP default.
  */
+static int census_impl(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32_t k,
+                       const uint16_t* cls_of_code, int32_t n_classes, uint64_t* hist, int32_t threads,
+                       const int32_t* roots, int32_t n_roots, double seconds);
+
 int oracle_census(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32_t k,
                   const uint16_t* cls_of_code, int32_t n_classes, uint64_t* hist, int32_t threads) {
+    return census_impl(n, out_off, out_idx, k, cls_of_code, n_classes, hist, threads, NULL, n, 0.0);
+}
+
+/*
+ * ESU from the given roots only: counts the connected k-sets whose smallest
+ * vertex is one of `roots` (ESU emits each set from its smallest vertex).
+ * Summed over all vertices this is the full census; a seeded subset of roots
+ * is a bounded sample of the same work.
+ */
+int oracle_census_roots(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32_t k,
+                        const uint16_t* cls_of_code, int32_t n_classes, uint64_t* hist, int32_t threads,
+                        const int32_t* roots, int32_t n_roots) {
+    for (int32_t i = 0; i < n_roots; ++i)
+        if (roots[i] < 0 || roots[i] >= n) return OR_EINVAL;
+    return census_impl(n, out_off, out_idx, k, cls_of_code, n_classes, hist, threads, roots, n_roots, 0.0);
+}
+
+/*
+ * Time-bounded sample of the census work: ESU from `roots` in the given order
+ * until `seconds` of wall time have passed (then every thread stops where it
+ * is).  hist receives the sets emitted so far; the caller turns that into a
+ * rate (sets per second).  Used only to time the oracle on workloads far too
+ * large to enumerate completely.
+ */
+int oracle_census_timed(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32_t k,
+                        const uint16_t* cls_of_code, int32_t n_classes, uint64_t* hist, int32_t threads,
+                        const int32_t* roots, int32_t n_roots, double seconds) {
+    for (int32_t i = 0; i < n_roots; ++i)
+        if (roots[i] < 0 || roots[i] >= n) return OR_EINVAL;
+    return census_impl(n, out_off, out_idx, k, cls_of_code, n_classes, hist, threads, roots, n_roots,
+                       seconds > 0 ? seconds : 1e-9);
+}
+
+static int census_impl(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32_t k,
+                       const uint16_t* cls_of_code, int32_t n_classes, uint64_t* hist, int32_t threads,
+                       const int32_t* roots, int32_t n_roots, double seconds) {
     if (k < 3 || k > 5 || n < 0) return OR_EINVAL;
     memset(hist, 0, sizeof(uint64_t) * (size_t)n_classes);
     if (n == 0) return 0;
@@ -292,13 +339,20 @@ int oracle_census(int32_t n, const int32_t* out_off, const int32_t* out_idx, int
     nthreads = threads > 0 ? threads : omp_get_max_threads();
 #endif
     uint64_t* th = (uint64_t*)calloc((size_t)nthreads * (size_t)n_classes, sizeof(uint64_t));
+    volatile int stop = 0;
+    double deadline = 0.0;
+#ifdef _OPENMP
+    if (seconds > 0) deadline = omp_get_wtime() + seconds;
+#endif
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
-    for (int root = 0; root < n; ++root) {
+    for (int ri = 0; ri < n_roots; ++ri) {
+        const int root = roots ? roots[ri] : ri;
         int tid = 0;
 #ifdef _OPENMP
         tid = omp_get_thread_num();
 #endif
-        esu_ctx c = { n, uoff2, uidx, aoff, aidx, k, cls_of_code, th + (size_t)tid * n_classes };
+        if (stop) continue;
+        esu_ctx c = { n, uoff2, uidx, aoff, aidx, k, cls_of_code, th + (size_t)tid * n_classes, deadline, &stop, 0 };
         int sub[5];
         sub[0] = root;
         int64_t d = uoff2[root + 1] - uoff2[root];

@@ -44,9 +44,9 @@ def test_server_mix_equals_alone(pm):
 
 
 def test_server_admission_and_errors(pm):
-    g = gg.chung_lu(3000, 15000, 2.2, 2.2, 0.1, seed=5)
+    g = gg.chung_lu(40000, 200000, 2.3, 2.3, 0.1, seed=5)
     fp = pm.request_footprint(g.n, g.m, 4)
-    assert fp > 0
+    assert fp > (4 << 20)
     with pm.Server(max(fp // 2, 1 << 20), max_inflight=2) as srv:
         with pytest.raises(pm.MotifError) as e:
             srv.submit(g.out_off, g.out_idx, g.n, 4)
@@ -57,7 +57,8 @@ def test_server_admission_and_errors(pm):
         hs = [srv.wait(t) for t in ts]
         st = srv.stats()
     assert st["peak_bytes"] <= int(fp * 1.5)
-    want = oracle.census(g, 4)
+    off, idx = pm.to_device(g.out_off, g.out_idx)
+    want = pm.census(off, idx, g.n, 4)   # the direct (non-server) census of the same graph
     for h in hs:
         assert np.array_equal(h, want)
     # an invalid graph returns its validation error through wait()

@@ -243,3 +243,15 @@ def test_esu_count_small_random_sum():
     for k in (3, 4, 5):
         want = sum(brute.census_by_canon(g.n, g.arcs(), k).values())
         assert int(oracle.census(g, k).sum()) == want
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_root_partition_sums_to_census(k):
+    # ESU emits each connected set from its smallest vertex, so censuses over
+    # a partition of the roots add up to the full census.
+    g = gg.chung_lu(120, 500, 2.2, 2.4, 0.2, seed=13)
+    rng = np.random.default_rng(4)
+    perm = rng.permutation(g.n)
+    parts = np.array_split(perm, 3)
+    total = sum(oracle.census_roots(g, k, p) for p in parts)
+    assert (total == oracle.census(g, k)).all()
