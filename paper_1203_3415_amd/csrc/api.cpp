@@ -34,8 +34,8 @@ int32_t g_init_err = 0;
 Tuning g_tuning[6] = {
     {256, 4, 16, 0}, {256, 4, 16, 0}, {256, 4, 16, 0},
     {256, 4, 16, 0},   // k = 3: tile*16 vertices per tile
-    {256, 2, 8, 0},    // k = 4
-    {1024, 1, 2, 0},   // k = 5
+    {1024, 2, 8, 0},   // k = 4
+    {1024, 1, 1, 0},   // k = 5
 };
 
 int32_t current_device(int* dev) {

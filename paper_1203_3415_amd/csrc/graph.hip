@@ -17,6 +17,8 @@
 //   G* write -> N+ count, scan, write -> optional in-CSR transpose check.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace motif {
@@ -171,14 +173,18 @@ __global__ void k_half_counts(const int32_t* off, const int32_t* in_cnt, int32_t
 
 // Half-edge keys: row u gets (d<<1|0) for arc u->d, row d gets (u<<1|1).
 __global__ void k_scatter(const int32_t* off, const int32_t* idx, int32_t n, int64_t m, const int32_t* hoff,
-                          int32_t* fill, uint32_t* keys, const int32_t* st) {
+                          int32_t* fill, uint32_t* keys, int32_t* hrow, const int32_t* st) {
   if (st[kStatus] != 0) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
     int32_t u = row_of(off, n, i);
     int32_t d = idx[i];
-    keys[hoff[u] + (i - off[u])] = ((uint32_t)d << 1);
+    const int32_t a = hoff[u] + (int32_t)(i - off[u]);
+    keys[a] = ((uint32_t)d << 1);
+    hrow[a] = u;
     int32_t p = atomicAdd(&fill[d], 1);
-    keys[hoff[d] + (off[d + 1] - off[d]) + p] = ((uint32_t)u << 1) | 1u;
+    const int32_t b = hoff[d] + (off[d + 1] - off[d]) + p;
+    keys[b] = ((uint32_t)u << 1) | 1u;
+    hrow[b] = d;
   }
 }
 
@@ -276,71 +282,74 @@ __global__ __launch_bounds__(kB) void k_sort_big(const int32_t* hoff, int32_t n,
   }
 }
 
-// Distinct neighbours per row (a pair id<<1, id<<1|1 is one bidirected
-// neighbour); equal keys mean a repeated arc.
-__global__ void k_row_degree(const int32_t* hoff, int32_t n, const uint32_t* keys, int32_t* deg, int32_t* st) {
+// Element-parallel merge of the sorted half-edges of every row: a half-edge
+// opens a new G* entry unless it carries the same neighbour as its
+// predecessor in the row (the pair id<<1, id<<1|1 is one bidirected
+// neighbour); equal keys are a repeated arc.  flag[2m] = 0 closes the scan.
+__global__ void k_entry_flags(const uint32_t* keys, const int32_t* hrow, const int32_t* hoff, int64_t h,
+                              int32_t* flag, int32_t* st) {
   if (st[kStatus] != 0) return;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t a = hoff[v], b = hoff[v + 1];
-    int32_t cnt = 0;
-    for (int32_t i = a; i < b;) {
-      uint32_t k = keys[i];
-      if (i + 1 < b && keys[i + 1] == k) { set_status(st, MOTIF_EDUP); break; }
-      i += (i + 1 < b && (keys[i + 1] >> 1) == (k >> 1)) ? 2 : 1;
-      ++cnt;
-    }
-    deg[v] = cnt;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= h; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i == h) { flag[i] = 0; continue; }
+    const uint32_t k = keys[i];
+    const bool first = i == hoff[hrow[i]];
+    if (!first && keys[i - 1] == k) set_status(st, MOTIF_EDUP);
+    flag[i] = (first || (keys[i - 1] >> 1) != (k >> 1)) ? 1 : 0;
   }
 }
 
-__global__ void k_copy_pad(const int32_t* src, int32_t n, int32_t* dst, const int32_t* st) {
+// gs_off[v] = position of row v's first half-edge in the scanned flags.
+__global__ void k_gather_off(const int32_t* pos, const int32_t* hoff, int32_t n, int32_t* gs_off, const int32_t* st) {
   if (st[kStatus] != 0) return;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += (int64_t)gridDim.x * blockDim.x)
-    dst[v] = v < n ? src[v] : 0;
+    gs_off[v] = pos[hoff[v]];
 }
 
-__global__ void k_write_gstar(const int32_t* hoff, int32_t n, const uint32_t* keys, const int32_t* gs_off,
-                              uint32_t* gs_idx, const int32_t* st) {
+// Typed G* entries, plus the row of each entry and the degree of each row.
+__global__ void k_write_gstar(const uint32_t* keys, const int32_t* hrow, const int32_t* hoff, int64_t h,
+                              const int32_t* pos, uint32_t* gs_idx, int32_t* gs_row, const int32_t* st) {
   if (st[kStatus] != 0) return;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t a = hoff[v], b = hoff[v + 1];
-    int32_t o = gs_off[v];
-    for (int32_t i = a; i < b;) {
-      uint32_t k = keys[i];
-      uint32_t t;
-      if (i + 1 < b && (keys[i + 1] >> 1) == (k >> 1)) { t = 3u; i += 2; }
-      else { t = (k & 1u) ? 2u : 1u; i += 1; }
-      gs_idx[o++] = (k >> 1) | (t << kTypeShift);
-    }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < h; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = hrow[i];
+    const uint32_t k = keys[i];
+    if (i != hoff[r] && (keys[i - 1] >> 1) == (k >> 1)) continue;  // second half of a pair
+    const bool pair = i + 1 < hoff[r + 1] && (keys[i + 1] >> 1) == (k >> 1);
+    const uint32_t t = pair ? 3u : ((k & 1u) ? 2u : 1u);
+    gs_idx[pos[i]] = (k >> 1) | (t << kTypeShift);
+    gs_row[pos[i]] = r;
   }
 }
 
-__global__ void k_count_plus(const int32_t* gs_off, const uint32_t* gs_idx, const int32_t* deg, int32_t n,
-                             int32_t* dplus, const int32_t* st) {
+__global__ void k_degree(const int32_t* gs_off, int32_t n, int32_t* deg, const int32_t* st) {
   if (st[kStatus] != 0) return;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += (int64_t)gridDim.x * blockDim.x) {
-    if (v == n) { dplus[v] = 0; continue; }
-    const int32_t dv = deg[v];
-    int32_t c = 0;
-    for (int32_t j = gs_off[v]; j < gs_off[v + 1]; ++j) {
-      int32_t w = (int32_t)(gs_idx[j] & kIdMask);
-      c += rank_less(dv, (int32_t)v, deg[w], w);
-    }
-    dplus[v] = c;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    deg[v] = gs_off[v + 1] - gs_off[v];
+}
+
+// flag[j] = 1 when entry j of row v points to a neighbour of higher rank;
+// entries past the last G* entry (up to `cap`) get 0.
+__global__ void k_plus_flags(const uint32_t* gs_idx, const int32_t* gs_row, const int32_t* deg,
+                             const int32_t* gs_off, int32_t n, int64_t cap, int32_t* flag, const int32_t* st) {
+  if (st[kStatus] != 0) return;
+  const int64_t e = gs_off[n];
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= cap; j += (int64_t)gridDim.x * blockDim.x) {
+    if (j >= e) { flag[j] = 0; continue; }
+    const int32_t v = gs_row[j];
+    const int32_t w = (int32_t)(gs_idx[j] & kIdMask);
+    flag[j] = rank_less(deg[v], v, deg[w], w) ? 1 : 0;
   }
 }
 
-__global__ void k_write_plus(const int32_t* gs_off, const uint32_t* gs_idx, const int32_t* deg, int32_t n,
-                             const int32_t* np_off, uint32_t* np_idx, const int32_t* st) {
+__global__ void k_write_plus(const uint32_t* gs_idx, const int32_t* flag_pos, const int32_t* gs_row,
+                             const int32_t* deg, const int32_t* gs_off, int32_t n, uint32_t* np_idx,
+                             const int32_t* st) {
   if (st[kStatus] != 0) return;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t dv = deg[v];
-    int32_t o = np_off[v];
-    for (int32_t j = gs_off[v]; j < gs_off[v + 1]; ++j) {
-      uint32_t e = gs_idx[j];
-      int32_t w = (int32_t)(e & kIdMask);
-      if (rank_less(dv, (int32_t)v, deg[w], w)) np_idx[o++] = e;
-    }
+  const int64_t e = gs_off[n];
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < e; j += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = gs_row[j];
+    const uint32_t x = gs_idx[j];
+    const int32_t w = (int32_t)(x & kIdMask);
+    if (rank_less(deg[v], v, deg[w], w)) np_idx[flag_pos[j]] = x;
   }
 }
 
@@ -447,7 +456,7 @@ void enqueue_zero(void* ptr, size_t bytes, hipStream_t s) {
 size_t build_bytes(int64_t N, int64_t M, int32_t G, bool batch) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   size_t b = 0;
-  b += 5 * al(sizeof(int32_t) * (N + 1));          // in_cnt, hoff, fill, deg, dplus/np_off
+  b += 4 * al(sizeof(int32_t) * (N + 1));          // in_cnt, hoff, fill, deg
   b += al(sizeof(int32_t) * (N + 1));              // gs_off
   b += al(sizeof(int32_t) * (N + 1));              // np_off
   b += al(sizeof(uint32_t) * 2 * (M + 1));         // keys
@@ -456,7 +465,8 @@ size_t build_bytes(int64_t N, int64_t M, int32_t G, bool batch) {
   b += 2 * al(sizeof(int32_t) * (N + 1));          // sort queues
   b += al(sizeof(uint32_t) * kBigSlots * ((2 * N + 31) / 32 + 1));
   b += al(sizeof(uint32_t) * ((2 * M + 31) / 32 + 1));  // transpose marks
-  b += al(sizeof(int32_t) * scan_scratch(N + 1));
+  b += al(sizeof(int32_t) * scan_scratch(std::max<int64_t>(N + 1, 2 * M + 1)));
+  b += 3 * al(sizeof(int32_t) * (2 * M + 1));      // half-edge rows, merge flags, G* entry rows
   if (batch) {
     b += 2 * al(sizeof(int32_t) * (N + 1)) + 2 * al(sizeof(int32_t) * (M + 1)) + al(sizeof(int32_t) * (N + 1));
     b += 2 * al(sizeof(int64_t) * (G + 1)) + al(sizeof(motif_graph_t) * G) + al(sizeof(int32_t) * G);
@@ -514,12 +524,15 @@ DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s) {
   uint32_t* keys = A.take<uint32_t>(2 * m + 1);
   uint32_t* gs_idx = A.take<uint32_t>(2 * m + 1);
   uint32_t* np_idx = A.take<uint32_t>(m + 1);
+  int32_t* hrow = A.take<int32_t>(2 * m + 1);
+  int32_t* flags = A.take<int32_t>(2 * m + 1);
+  int32_t* gs_row = A.take<int32_t>(2 * m + 1);
   int32_t* midq = A.take<int32_t>(n + 1);
   int32_t* bigq = A.take<int32_t>(n + 1);
   const int64_t bm_words = (2 * (int64_t)n + 31) / 32 + 1;
   uint32_t* bitmaps = A.take<uint32_t>(kBigSlots * bm_words);
   uint32_t* marks = A.take<uint32_t>((2 * m + 31) / 32 + 1);
-  int32_t* scratch = A.take<int32_t>(scan_scratch(n + 1));
+  int32_t* scratch = A.take<int32_t>(scan_scratch(std::max<int64_t>(n + 1, 2 * m + 1)));
 
   DevGraph g;
   g.n = n;
@@ -539,17 +552,24 @@ DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s) {
   scan_excl(hoff, n + 1, scratch, s);
   if (m > 0)
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(m)), dim3(kB), 0, s, in.out_off, in.out_idx, n, m, hoff, fill, keys,
-                       st);
+                       hrow, st);
   hipLaunchKernelGGL(k_sort_small, dim3(grid_for(n)), dim3(kB), 0, s, hoff, n, keys, midq, bigq, st);
   hipLaunchKernelGGL(k_sort_mid, dim3(512), dim3(kB), 0, s, hoff, keys, midq, st);
   hipLaunchKernelGGL(k_sort_big, dim3(kBigSlots), dim3(kB), 0, s, hoff, n, keys, bigq, bitmaps, st);
-  hipLaunchKernelGGL(k_row_degree, dim3(grid_for(n)), dim3(kB), 0, s, hoff, n, keys, deg, st);
-  hipLaunchKernelGGL(k_copy_pad, dim3(grid_for(n + 1)), dim3(kB), 0, s, deg, n, gs_off, st);
-  scan_excl(gs_off, n + 1, scratch, s);
-  hipLaunchKernelGGL(k_write_gstar, dim3(grid_for(n)), dim3(kB), 0, s, hoff, n, keys, gs_off, gs_idx, st);
-  hipLaunchKernelGGL(k_count_plus, dim3(grid_for(n + 1)), dim3(kB), 0, s, gs_off, gs_idx, deg, n, np_off, st);
-  scan_excl(np_off, n + 1, scratch, s);
-  hipLaunchKernelGGL(k_write_plus, dim3(grid_for(n)), dim3(kB), 0, s, gs_off, gs_idx, deg, n, np_off, np_idx, st);
+  // merge: flags over the 2m sorted half-edges, one scan gives offsets and positions
+  hipLaunchKernelGGL(k_entry_flags, dim3(grid_for(2 * m + 1)), dim3(kB), 0, s, keys, hrow, hoff, 2 * m, flags, st);
+  scan_excl(flags, 2 * m + 1, scratch, s);
+  hipLaunchKernelGGL(k_gather_off, dim3(grid_for(n + 1)), dim3(kB), 0, s, flags, hoff, n, gs_off, st);
+  hipLaunchKernelGGL(k_write_gstar, dim3(grid_for(2 * m)), dim3(kB), 0, s, keys, hrow, hoff, 2 * m, flags, gs_idx,
+                     gs_row, st);
+  hipLaunchKernelGGL(k_degree, dim3(grid_for(n)), dim3(kB), 0, s, gs_off, n, deg, st);
+  // oriented rows N+: flags over the G* entries (at most 2m of them), one scan
+  hipLaunchKernelGGL(k_plus_flags, dim3(grid_for(2 * m + 1)), dim3(kB), 0, s, gs_idx, gs_row, deg, gs_off, n,
+                     2 * m, flags, st);
+  scan_excl(flags, 2 * m + 1, scratch, s);
+  hipLaunchKernelGGL(k_gather_off, dim3(grid_for(n + 1)), dim3(kB), 0, s, flags, gs_off, n, np_off, st);
+  hipLaunchKernelGGL(k_write_plus, dim3(grid_for(2 * m)), dim3(kB), 0, s, gs_idx, flags, gs_row, deg, gs_off, n,
+                     np_idx, st);
   if (in.in_off) {
     if (!in.gid) hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.in_off, n, m, st);
     hipLaunchKernelGGL(k_check_in_rows, dim3(grid_for(n)), dim3(kB), 0, s, in.in_off, in_cnt, n, in.gid, in.has_in,
