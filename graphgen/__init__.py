@@ -12,6 +12,7 @@ from .core import (
     gnm_reciprocal,
     chung_lu,
     arc_switch,
+    arc_switch_many,
     directed_cycle,
     directed_path,
     complete_digraph,
@@ -24,7 +25,7 @@ from .core import (
 )
 
 __all__ = [
-    "Digraph", "from_arcs", "gnm_reciprocal", "chung_lu", "arc_switch",
+    "Digraph", "from_arcs", "gnm_reciprocal", "chung_lu", "arc_switch", "arc_switch_many",
     "directed_cycle", "directed_path", "complete_digraph", "transitive_tournament",
     "star", "disjoint_union", "relabel", "reverse", "random_small",
 ]

@@ -181,6 +181,47 @@ def arc_switch(g: Digraph, attempts: int, seed: int) -> Digraph:
     return from_arcs(n, np.stack([src, dst], axis=1))
 
 
+_SWITCH_LIB = None
+
+
+def _switch_lib():
+    """gcc-built helper for many randomisations (compiled on first use)."""
+    global _SWITCH_LIB
+    if _SWITCH_LIB is None:
+        import ctypes
+        import os
+        import subprocess
+        here = os.path.dirname(os.path.abspath(__file__))
+        src, lib = os.path.join(here, "switch.c"), os.path.join(here, "libswitch.so")
+        if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+            subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", lib + ".tmp", src])
+            os.replace(lib + ".tmp", lib)
+        L = ctypes.CDLL(lib)
+        P = ctypes.c_void_p
+        L.gg_arc_switch_many.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, ctypes.c_int64, P, ctypes.c_int32, P, P]
+        L.gg_arc_switch_many.restype = ctypes.c_int
+        _SWITCH_LIB = L
+    return _SWITCH_LIB
+
+
+def arc_switch_many(g: Digraph, attempts: int, seeds) -> list:
+    """Independent degree-preserving randomisations of g (one per seed), each
+    by `attempts` attempted arc switches (C helper, splitmix64 per seed)."""
+    import ctypes
+    a = g.arcs()
+    m = a.shape[0]
+    seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
+    if m < 2:
+        return [g for _ in seeds]
+    src = np.ascontiguousarray(a[:, 0], dtype=np.int32)
+    dst = np.ascontiguousarray(a[:, 1], dtype=np.int32)
+    out = np.empty((len(seeds), m), dtype=np.int32)
+    acc = np.zeros(len(seeds), dtype=np.int64)
+    P = lambda x: x.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    _switch_lib().gg_arc_switch_many(g.n, m, P(src), P(dst), int(attempts), P(seeds), len(seeds), P(out), P(acc))
+    return [from_arcs(g.n, np.stack([src, out[i]], axis=1)) for i in range(len(seeds))]
+
+
 def directed_cycle(n: int) -> Digraph:
     return from_arcs(n, [(i, (i + 1) % n) for i in range(n)] if n >= 2 else [])
 

@@ -147,6 +147,23 @@ int32_t motif_census_batch(const motif_graph_t* graphs, int32_t count, int32_t k
 int32_t motif_census_batch_loop(const motif_graph_t* graphs, int32_t count, int32_t k,
                                 uint64_t* hists, void* stream);
 
+/* Reusable fused batch ("plan") for repeated censuses of the same batch
+ * layout -- e.g. a null-model ensemble whose graphs are regenerated in place
+ * on the device between rounds.  create(): validates and censuses the batch
+ * once eagerly (on error returns NULL and sets *err), then captures the whole
+ * device sequence (pack, build, census, exact division) into a hipGraph on a
+ * private stream of the plan.  run(): orders itself after the work already
+ * enqueued on `stream`, replays that graph -- one launch -- and waits for the
+ * status word; it reads whatever the graph buffers hold at that moment, so
+ * new graphs of identical n and m per slot may be written in place between
+ * runs.  The descriptors are copied at create(); the device buffers they
+ * point to and `hists` must outlive the plan.  Not thread-safe per plan. */
+typedef struct motif_batch_plan motif_batch_plan_t;
+motif_batch_plan_t* motif_batch_plan_create(const motif_graph_t* graphs, int32_t count, int32_t k,
+                                            uint64_t* hists, void* stream, int32_t* err);
+int32_t motif_batch_plan_run(motif_batch_plan_t* plan);
+int32_t motif_batch_plan_destroy(motif_batch_plan_t* plan);
+
 /* ---- tuning ---------------------------------------------------------------- */
 
 /* Tunable launch parameters of the census kernels. */

@@ -13,6 +13,7 @@ from .binding import (  # noqa: F401
     census,
     census_batch,
     census_batch_loop,
+    BatchPlan,
     num_classes,
     class_code,
     class_multiplicity,
@@ -26,3 +27,4 @@ from .binding import (  # noqa: F401
     Server,
     request_footprint,
 )
+from .nullmodel import zscores  # noqa: F401,E402

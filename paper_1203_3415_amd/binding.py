@@ -80,6 +80,9 @@ def lib():
             "motif_get_tuning": ([I32, ctypes.POINTER(_Tuning)], I32),
             "motif_set_tuning": ([I32, ctypes.POINTER(_Tuning)], I32),
             "motif_autotune": ([P, I32, I32, P, P, ctypes.POINTER(_Tuning)], I32),
+            "motif_batch_plan_create": ([P, I32, I32, P, P, ctypes.POINTER(I32)], P),
+            "motif_batch_plan_run": ([P], I32),
+            "motif_batch_plan_destroy": ([P], I32),
             "motif_profile_enable": ([I32], I32),
             "motif_profile_read": ([I32, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)], I32),
             "motif_server_create": ([ctypes.c_size_t, I32], P),
@@ -215,6 +218,46 @@ def census_batch(graphs, k: int, stream=None, out=None, loop: bool = False):
 
 def census_batch_loop(graphs, k: int, stream=None, out=None):
     return census_batch(graphs, k, stream=stream, out=out, loop=True)
+
+
+class BatchPlan:
+    """Fused batched census captured once in a hipGraph and replayed.
+
+    The graph tensors must stay alive (and keep their shapes) while the plan
+    exists; their contents may change between runs."""
+
+    def __init__(self, graphs, k: int, stream=None, out=None):
+        torch = _torch()
+        C = NUM_CLASSES.get(k)
+        if C is None:
+            raise MotifError(-1, "BatchPlan")
+        self._graphs = list(graphs)  # keep the device tensors alive
+        arr = _graph_array(self._graphs)
+        dev = self._graphs[0][0].device
+        self.out = out if out is not None else torch.empty((len(self._graphs), C), dtype=torch.int64, device=dev)
+        self._stream = stream
+        err = ctypes.c_int32()
+        self._h = lib().motif_batch_plan_create(ctypes.cast(arr, ctypes.c_void_p), len(self._graphs), int(k),
+                                                _ptr(self.out), _stream_handle(stream), ctypes.byref(err))
+        if not self._h:
+            raise MotifError(err.value, "motif_batch_plan_create")
+
+    def run(self) -> None:
+        _check(lib().motif_batch_plan_run(self._h), "motif_batch_plan_run")
+
+    def hists(self) -> np.ndarray:
+        return self.out.cpu().numpy().view(np.uint64)
+
+    def close(self):
+        if self._h:
+            lib().motif_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def get_tuning(k: int) -> dict:

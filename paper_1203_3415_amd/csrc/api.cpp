@@ -432,6 +432,155 @@ int32_t motif_autotune(const motif_graph_t* graphs, int32_t count, int32_t k, ui
   return 0;
 }
 
+}  // extern "C"
+
+struct motif_batch_plan {
+  int dev = 0;
+  hipStream_t caller = nullptr;   // the caller's stream (may be the null stream)
+  hipStream_t stream = nullptr;   // private stream the graph is captured on
+  hipEvent_t ready = nullptr;
+  int32_t k = 0, count = 0;
+  Pipeline p;
+  motif_graph_t* graphs = nullptr;  // pinned copy of the descriptors
+  int64_t* voff = nullptr;          // pinned
+  int64_t* aoff = nullptr;          // pinned
+  uint64_t* hists = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// The whole batched census (status reset, pack, build, census, division) as
+// one stream-ordered sequence with no host interaction, so it can be captured.
+void enqueue_plan(motif_batch_plan* b) {
+  const int C = motif_num_classes(b->k);
+  b->p.arena.reset();
+  enqueue_zero(b->p.status, sizeof(int32_t) * kStatusWords, b->stream);
+  BuildInput in = enqueue_pack(b->p, b->graphs, b->count, b->voff, b->aoff, b->stream);
+  DevGraph g = enqueue_build(b->p, in, b->stream);
+  uint64_t* acc = b->p.arena.take<uint64_t>((size_t)b->count * C);
+  enqueue_census(b->p, g, b->k, acc, b->hists, b->stream);
+}
+
+void plan_free(motif_batch_plan* b) {
+  if (!b) return;
+  if (b->stream) hipStreamSynchronize(b->stream);
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->p.arena.base) hipFree(b->p.arena.base);
+  if (b->p.status) hipFree(b->p.status);
+  if (b->p.host_status) hipHostFree(b->p.host_status);
+  if (b->graphs) hipHostFree(b->graphs);
+  if (b->voff) hipHostFree(b->voff);
+  if (b->aoff) hipHostFree(b->aoff);
+  if (b->ready) hipEventDestroy(b->ready);
+  if (b->stream) hipStreamDestroy(b->stream);
+  delete b;
+}
+
+// Order the plan's private stream after everything already on the caller's.
+int32_t plan_join_caller(motif_batch_plan* b) {
+  if (hipEventRecord(b->ready, b->caller) != hipSuccess) return MOTIF_EDEVICE;
+  if (hipStreamWaitEvent(b->stream, b->ready, 0) != hipSuccess) return MOTIF_EDEVICE;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+motif_batch_plan_t* motif_batch_plan_create(const motif_graph_t* graphs, int32_t count, int32_t k, uint64_t* hists,
+                                            void* stream, int32_t* err) {
+  int32_t dummy;
+  if (!err) err = &dummy;
+  *err = 0;
+  if (motif_num_classes(k) < 0) { *err = MOTIF_EINVAL_K; return nullptr; }
+  if (count <= 0 || !graphs || !hists) { *err = MOTIF_EINVAL_ARG; return nullptr; }
+  int64_t N = 0, M = 0;
+  for (int32_t g = 0; g < count; ++g) {
+    const motif_graph_t& G = graphs[g];
+    if (!check_shape(G.n, G.m) || (G.n == 0 && G.m != 0)) { *err = MOTIF_EINVAL_SHAPE; return nullptr; }
+    if ((G.n > 0 && !G.out_off) || (G.m > 0 && !G.out_idx) || (G.in_off && G.m > 0 && !G.in_idx)) {
+      *err = MOTIF_EINVAL_ARG;
+      return nullptr;
+    }
+    N += G.n;
+    M += G.m;
+  }
+  if (N == 0 || N >= kMaxN || M >= kMaxN) { *err = N == 0 ? MOTIF_EINVAL_ARG : MOTIF_EINVAL_SHAPE; return nullptr; }
+  int dev;
+  if ((*err = ensure_init(&dev))) return nullptr;
+  motif_batch_plan* b = new motif_batch_plan();
+  b->dev = dev;
+  b->caller = (hipStream_t)stream;
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ready, hipEventDisableTiming) != hipSuccess) {
+    *err = MOTIF_EDEVICE;
+    plan_free(b);
+    return nullptr;
+  }
+  b->k = k;
+  b->count = count;
+  b->hists = hists;
+  b->p.num_cus = device_cus(dev);
+  const size_t bytes = pipeline_bytes(N, M, count, true, k, b->p.num_cus);
+  if (hipMalloc(&b->p.arena.base, bytes) != hipSuccess || hipMalloc(&b->p.status, kStatusWords * 4) != hipSuccess ||
+      hipHostMalloc(&b->p.host_status, kStatusWords * 4, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(&b->graphs, sizeof(motif_graph_t) * count, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(&b->voff, sizeof(int64_t) * (count + 1), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(&b->aoff, sizeof(int64_t) * (count + 1), hipHostMallocDefault) != hipSuccess) {
+    *err = MOTIF_ENOMEM;
+    plan_free(b);
+    return nullptr;
+  }
+  b->p.arena.cap = bytes;
+  std::memcpy(b->graphs, graphs, sizeof(motif_graph_t) * count);
+  b->voff[0] = b->aoff[0] = 0;
+  for (int32_t g = 0; g < count; ++g) {
+    b->voff[g + 1] = b->voff[g] + graphs[g].n;
+    b->aoff[g + 1] = b->aoff[g] + graphs[g].m;
+  }
+  // 1. eager run: validates the inputs and reports their error code
+  if ((*err = plan_join_caller(b))) {
+    plan_free(b);
+    return nullptr;
+  }
+  enqueue_plan(b);
+  if ((*err = read_status(b->p, b->stream))) {
+    plan_free(b);
+    return nullptr;
+  }
+  // 2. capture the same sequence (profiling events stay out of the graph)
+  const bool prof = g_prof.on;
+  g_prof.on = false;
+  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    enqueue_plan(b);
+    e = hipStreamEndCapture(b->stream, &b->graph);
+  }
+  g_prof.on = prof;
+  if (e != hipSuccess || hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+    *err = MOTIF_EDEVICE;
+    plan_free(b);
+    return nullptr;
+  }
+  return b;
+}
+
+int32_t motif_batch_plan_run(motif_batch_plan_t* b) {
+  if (!b) return MOTIF_EINVAL_ARG;
+  if (int32_t rc = plan_join_caller(b)) return rc;
+  if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return MOTIF_EDEVICE;
+  return read_status(b->p, b->stream);
+}
+
+int32_t motif_batch_plan_destroy(motif_batch_plan_t* b) {
+  if (!b) return MOTIF_EINVAL_ARG;
+  plan_free(b);
+  return 0;
+}
+
 int32_t motif_profile_enable(int32_t on) {
   g_prof.on = on != 0;
   for (bool& h : g_prof.have) h = false;

@@ -1,0 +1,88 @@
+"""GPU tests of the fused batch path: the hipGraph-captured plan replays,
+in-place regeneration between replays, and the autotuner."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1203_3415_amd as pm
+    pm.lib()
+    return pm
+
+
+def _ensemble(count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(count):
+        n = int(rng.integers(60, 400))
+        out.append(gg.chung_lu(n, int(n * rng.uniform(2, 4)), 2.3, 2.3, 0.05, seed=seed * 100 + t))
+    return out
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_plan_replays_match_eager(pm, k):
+    import torch
+    graphs = _ensemble(12 if k < 5 else 6, 40 + k)
+    dev = [(*pm.to_device(g.out_off, g.out_idx), g.n) for g in graphs]
+    eager = pm.census_batch(dev, k)
+    plan = pm.BatchPlan(dev, k)
+    assert np.array_equal(plan.hists(), eager)
+    other = gg.chung_lu(300, 1200, 2.2, 2.2, 0.1, seed=9)
+    oo, oi = pm.to_device(other.out_off, other.out_idx)
+    for r in range(3):
+        print(f"[case] plan replay k={k} round {r}", flush=True)
+        pm.census(oo, oi, other.n, 4)          # eager work between replays
+        torch.cuda.synchronize()
+        plan.out.fill_(0)
+        plan.run()
+        assert np.array_equal(plan.hists(), eager), f"replay {r}"
+    plan.close()
+
+
+def test_plan_sees_in_place_regeneration(pm):
+    import torch
+    base = gg.chung_lu(300, 1200, 2.3, 2.3, 0.05, seed=5)
+    first = gg.arc_switch_many(base, 20 * base.m, [1, 2, 3, 4])
+    second = gg.arc_switch_many(base, 20 * base.m, [5, 6, 7, 8])
+    dev = [(*pm.to_device(g.out_off, g.out_idx), g.n) for g in [base] + first]
+    plan = pm.BatchPlan(dev, 4)
+    for i, g in enumerate([base] + first):
+        assert np.array_equal(plan.hists()[i], oracle.census(g, 4))
+    # write new randomisations (same n and m per slot) into the same buffers
+    for (off_t, idx_t, _), g in zip(dev[1:], second):
+        off_t.copy_(torch.as_tensor(g.out_off, device=off_t.device))
+        idx_t.copy_(torch.as_tensor(g.out_idx, device=idx_t.device))
+    torch.cuda.synchronize()
+    plan.run()
+    for i, g in enumerate([base] + second):
+        assert np.array_equal(plan.hists()[i], oracle.census(g, 4)), i
+    plan.close()
+
+
+def test_plan_rejects_invalid_batch(pm):
+    off, idx = pm.to_device(np.array([0, 1, 1], np.int32), np.array([0], np.int32))
+    with pytest.raises(pm.MotifError) as e:
+        pm.BatchPlan([(off, idx, 2)], 3)
+    assert e.value.name == "ESELFLOOP"
+
+
+def test_autotune_keeps_results(pm):
+    graphs = _ensemble(10, 77)
+    dev = [(*pm.to_device(g.out_off, g.out_idx), g.n) for g in graphs]
+    saved = pm.get_tuning(4)
+    try:
+        best = pm.autotune(dev, 4)
+        assert best["block"] in (256, 512, 1024)
+        hb = pm.census_batch(dev, 4)
+        for i, g in enumerate(graphs):
+            assert np.array_equal(hb[i], oracle.census(g, 4))
+    finally:
+        pm.set_tuning(4, **saved)
