@@ -171,8 +171,9 @@ typedef struct motif_tuning {
   int32_t block;        /* threads per workgroup for the anchor kernels (64..1024)  */
   int32_t grid_per_cu;  /* persistent workgroups per compute unit (1..16)           */
   int32_t tile;         /* anchors per work-queue tile for light anchors (1..4096)  */
-  int32_t heavy;        /* adjacency size above which an anchor is "heavy" and is
-                           processed by a whole workgroup (0 = every anchor)        */
+  int32_t heavy;        /* census scheme for k = 4, 5: 1 = core reuse (neighbourhood
+                           of the highest-ranked anchor vertex scanned once per
+                           work unit), 2 = per-anchor scan; 0 = keep              */
 } motif_tuning_t;
 
 /* Read / override the parameters used for k (0 in a field = keep default). */

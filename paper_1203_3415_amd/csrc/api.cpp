@@ -32,10 +32,10 @@ std::map<int, DeviceState> g_dev;
 int32_t g_init_err = 0;
 
 Tuning g_tuning[6] = {
-    {256, 4, 16, 0}, {256, 4, 16, 0}, {256, 4, 16, 0},
-    {256, 4, 16, 0},   // k = 3: tile*16 vertices per tile
-    {1024, 2, 8, 0},   // k = 4
-    {1024, 1, 1, 0},   // k = 5
+    {256, 4, 16, 1}, {256, 4, 16, 1}, {256, 4, 16, 1},
+    {256, 4, 16, 1},    // k = 3: tile*16 vertices per tile
+    {1024, 2, 256, 1},  // k = 4: core reuse
+    {1024, 1, 1, 1},    // k = 5: core reuse
 };
 
 int32_t current_device(int* dev) {
@@ -182,7 +182,7 @@ int32_t run_census(const BuildInput& in, int32_t k, uint64_t* hist, hipStream_t 
   int32_t rc = ensure_init(&dev);
   if (rc) return rc;
   Pipeline* p = nullptr;
-  rc = get_pipeline(dev, s, pipeline_bytes(in.n, in.m, in.ngraphs, false, k, device_cus(dev)), &p);
+  rc = get_pipeline(dev, s, pipeline_bytes(in.n, in.m, in.ngraphs, false, k, device_cus(dev), in.n), &p);
   if (rc) return rc;
   return run_census_on(*p, in, k, hist, s);
 }
@@ -318,7 +318,9 @@ int32_t motif_census_batch(const motif_graph_t* graphs, int32_t count, int32_t k
   }
   // Graphs with n = 0 contribute no vertices; the pack kernel never sees them.
   Pipeline* p = nullptr;
-  rc = get_pipeline(dev, s, pipeline_bytes(voff[count], aoff[count], count, true, k, device_cus(dev)), &p);
+  int64_t maxn = 0;
+  for (int32_t g = 0; g < count; ++g) maxn = std::max<int64_t>(maxn, graphs[g].n);
+  rc = get_pipeline(dev, s, pipeline_bytes(voff[count], aoff[count], count, true, k, device_cus(dev), maxn), &p);
   if (rc) return rc;
   p->arena.reset();
   enqueue_zero(p->status, sizeof(int32_t) * kStatusWords, s);
@@ -353,7 +355,7 @@ int32_t motif_get_tuning(int32_t k, motif_tuning_t* out) {
   out->block = t.block;
   out->grid_per_cu = t.grid_per_cu;
   out->tile = t.tile;
-  out->heavy = t.heavy;
+  out->heavy = t.heavy == 1 ? 1 : 2;
   return 0;
 }
 
@@ -376,8 +378,9 @@ int32_t motif_set_tuning(int32_t k, const motif_tuning_t* in) {
     t.tile = in->tile;
   }
   if (in->heavy) {
-    if (in->heavy < 0) return MOTIF_EINVAL_ARG;
-    t.heavy = in->heavy;
+    // 1 = core-reuse scheme, 2 = per-anchor scan (k = 4, 5)
+    if (in->heavy < 1 || in->heavy > 2) return MOTIF_EINVAL_ARG;
+    t.heavy = in->heavy == 2 ? 0 : 1;
   }
   return 0;
 }
@@ -393,17 +396,19 @@ int32_t motif_autotune(const motif_graph_t* graphs, int32_t count, int32_t k, ui
     for (int tile : {4, 16, 64})
       for (int gpc : {2, 4, 8}) cands.push_back({256, gpc, tile, 0});
   } else if (k == 4) {
-    for (int block : {256, 512})
+    for (int block : {512, 1024})
       for (int gpc : {1, 2, 4})
-        for (int tile : {1, 8, 32}) cands.push_back({block, gpc, tile, 0});
+        for (int tile : {64, 256, 1024}) cands.push_back({block, gpc, tile, 0});
   } else {
     for (int block : {512, 1024})
-      for (int tile : {1, 2, 8}) cands.push_back({block, 1, tile, 0});
+      for (int tile : {1, 2, 4}) cands.push_back({block, 1, tile, 0});
   }
   const Tuning saved = tuning_for(k);
+  const int32_t scheme = saved.heavy == 1 ? 1 : 2;  // the scheme is kept, as reported by motif_get_tuning
+  for (auto& c : cands) c.heavy = scheme;
   std::vector<uint64_t> ref((size_t)count * C), cur((size_t)count * C);
   double best_ms = 1e300;
-  motif_tuning_t best_t{saved.block, saved.grid_per_cu, saved.tile, saved.heavy};
+  motif_tuning_t best_t{saved.block, saved.grid_per_cu, saved.tile, scheme};
   for (size_t i = 0; i < cands.size(); ++i) {
     Tuning& t = tuning_for(k);
     t.block = cands[i].block;
@@ -524,7 +529,9 @@ motif_batch_plan_t* motif_batch_plan_create(const motif_graph_t* graphs, int32_t
   b->count = count;
   b->hists = hists;
   b->p.num_cus = device_cus(dev);
-  const size_t bytes = pipeline_bytes(N, M, count, true, k, b->p.num_cus);
+  int64_t maxn = 0;
+  for (int32_t g = 0; g < count; ++g) maxn = std::max<int64_t>(maxn, graphs[g].n);
+  const size_t bytes = pipeline_bytes(N, M, count, true, k, b->p.num_cus, maxn);
   if (hipMalloc(&b->p.arena.base, bytes) != hipSuccess || hipMalloc(&b->p.status, kStatusWords * 4) != hipSuccess ||
       hipHostMalloc(&b->p.host_status, kStatusWords * 4, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(&b->graphs, sizeof(motif_graph_t) * count, hipHostMallocDefault) != hipSuccess ||

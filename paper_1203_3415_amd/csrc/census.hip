@@ -66,6 +66,8 @@ __device__ __forceinline__ uint32_t flip(uint32_t t) { return ((t & 1u) << 1) | 
 
 constexpr int num_classes(int k) { return k == 3 ? 13 : k == 4 ? 199 : 9364; }
 
+constexpr int kMaxHubs = 512;  // rows of the per-core W table in LDS
+
 using u64 = unsigned long long;
 constexpr u64 kMinusOne = ~0ull;
 
@@ -80,14 +82,22 @@ __device__ __forceinline__ void hist_flush(u64* hist, uint64_t* acc, int32_t g) 
   }
 }
 
-// Dense label array: BITS (4 or 8) bits per vertex in 32-bit words.
-template <int BITS>
+// Dense label array: BITS (4 or 8) bits per vertex in 32-bit words.  In LDS
+// (GLOBAL = false) plain loads see the LDS atomics of other waves after a
+// barrier.  In a private global slice (GLOBAL = true) the updates are device
+// atomics performed in L2, so reads also go to L2 (agent-scope atomic loads
+// bypass the per-CU L1, which those atomics do not update).
+template <int BITS, bool GLOBAL = false>
 struct Labels {
   uint32_t* w;
   static constexpr int kPer = 32 / BITS;
   static constexpr uint32_t kMask = (1u << BITS) - 1u;
+  __device__ __forceinline__ uint32_t word(uint32_t i) const {
+    if constexpr (GLOBAL) return __hip_atomic_load(&w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return w[i];
+  }
   __device__ __forceinline__ uint32_t get(uint32_t x) const {
-    return (w[x / kPer] >> ((x % kPer) * BITS)) & kMask;
+    return (word(x / kPer) >> ((x % kPer) * BITS)) & kMask;
   }
   __device__ __forceinline__ void set_bits(uint32_t x, uint32_t v) const {
     atomicOr(&w[x / kPer], v << ((x % kPer) * BITS));
@@ -95,8 +105,21 @@ struct Labels {
   __device__ __forceinline__ void clear_bits(uint32_t x, uint32_t v) const {
     atomicAnd(&w[x / kPer], ~(v << ((x % kPer) * BITS)));
   }
-  __device__ __forceinline__ void clear_all(uint32_t x) const { w[x / kPer] = 0u; }
+  __device__ __forceinline__ void clear_all(uint32_t x) const {
+    if constexpr (GLOBAL) __hip_atomic_store(&w[x / kPer], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else w[x / kPer] = 0u;
+  }
 };
+
+// Workgroup barrier.  With GLOBAL, first wait until every memory operation of
+// this wave has completed (global atomics included: the plain barrier only
+// waits for LDS traffic), so state kept in a private global slice is
+// consistent for all waves after it.
+template <bool GLOBAL>
+__device__ __forceinline__ void bar() {
+  if constexpr (GLOBAL) __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
 
 __device__ __forceinline__ int32_t find_row(const int32_t* off, int32_t lo, int32_t hi, int64_t j) {
   // last v in [lo, hi) with off[v] <= j
@@ -241,22 +264,22 @@ __global__ __launch_bounds__(BLOCK) void k4_kernel(DevGraph G, const uint16_t* _
   __shared__ int32_t sh_j0;
   __shared__ uint32_t lds_labels[LCAP > 0 ? LCAP / 4 : 1];
   if (st[kStatus] != 0) return;
-  Labels<4> lab{LCAP > 0 ? lds_labels : glabels + (int64_t)blockIdx.x * label_words};
+  Labels<4, LCAP == 0> lab{LCAP > 0 ? lds_labels : glabels + (int64_t)blockIdx.x * label_words};
   for (int i = threadIdx.x; i < 4096; i += BLOCK) lut[i] = lut_g[i];
   for (int i = threadIdx.x; i < C; i += BLOCK) hist[i] = 0;
   if (threadIdx.x < NL) cnt[threadIdx.x] = 0;
   if (LCAP > 0)
     for (int i = threadIdx.x; i < LCAP / 4; i += BLOCK) lds_labels[i] = 0u;
-  __syncthreads();
+  bar<LCAP == 0>();
 
   const int32_t n = G.n;
   const int32_t total = G.gs_off[n];
   int32_t cur_g = -1, u = 0;
   for (;;) {
     if (threadIdx.x == 0) sh_j0 = atomicAdd(queue, tile);
-    __syncthreads();
+    bar<LCAP == 0>();
     const int32_t j0 = sh_j0;
-    __syncthreads();
+    bar<LCAP == 0>();
     if (j0 >= total) break;
     const int32_t j1 = min(total, j0 + tile);
     u = find_row(G.gs_off, 0, n, j0);
@@ -269,7 +292,7 @@ __global__ __launch_bounds__(BLOCK) void k4_kernel(DevGraph G, const uint16_t* _
       if (g != cur_g) {
         hist_flush<C, BLOCK>(hist, acc, cur_g);
         cur_g = g;
-        __syncthreads();
+        bar<LCAP == 0>();
       }
       const uint32_t tuv = ev >> kTypeShift;
       const uint32_t base = ((tuv & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tuv & 2u) ? 1u << cbit<K>(1, 0) : 0u);
@@ -287,7 +310,7 @@ __global__ __launch_bounds__(BLOCK) void k4_kernel(DevGraph G, const uint16_t* _
           if ((int32_t)x != u) lab.set_bits(x, (e >> kTypeShift) << 2);
         }
       }
-      __syncthreads();
+      bar<LCAP == 0>();
       // 2. set sizes and edges inside adj(e)
       for (int32_t i = threadIdx.x; i < du + dv; i += BLOCK) {
         uint32_t x;
@@ -311,17 +334,17 @@ __global__ __launch_bounds__(BLOCK) void k4_kernel(DevGraph G, const uint16_t* _
           }
         }
       }
-      __syncthreads();
+      bar<LCAP == 0>();
       // 3. closed form over the 15 sets
       closed_form<K, NL, BLOCK>(hist, lut, cnt, nzl, &nz_count, base);
-      __syncthreads();
+      bar<LCAP == 0>();
       // 4. reset
       for (int32_t i = threadIdx.x; i < du + dv; i += BLOCK) {
         const uint32_t x = (i < du ? G.gs_idx[ua + i] : G.gs_idx[va + i - du]) & kIdMask;
         lab.clear_all(x);
       }
       if (threadIdx.x < NL) cnt[threadIdx.x] = 0;
-      __syncthreads();
+      bar<LCAP == 0>();
     }
   }
   hist_flush<C, BLOCK>(hist, acc, cur_g);
@@ -349,21 +372,21 @@ __global__ __launch_bounds__(BLOCK) void k5_kernel(DevGraph G, const uint16_t* _
   __shared__ int32_t sh_j0;
   __shared__ uint32_t lds_labels[LCAP > 0 ? LCAP / 4 : 1];
   if (st[kStatus] != 0) return;
-  Labels<8> lab{LCAP > 0 ? lds_labels : glabels + (int64_t)blockIdx.x * label_words};
+  Labels<8, LCAP == 0> lab{LCAP > 0 ? lds_labels : glabels + (int64_t)blockIdx.x * label_words};
   for (int i = threadIdx.x; i < C; i += BLOCK) hist[i] = 0;
   if (threadIdx.x < NL) cnt[threadIdx.x] = 0;
   if (LCAP > 0)
     for (int i = threadIdx.x; i < LCAP / 4; i += BLOCK) lds_labels[i] = 0u;
-  __syncthreads();
+  bar<LCAP == 0>();
 
   const int32_t n = G.n;
   const int32_t total = G.gs_off[n];
   int32_t cur_g = -1, b = 0, cur_b = -1;
   for (;;) {
     if (threadIdx.x == 0) sh_j0 = atomicAdd(queue, tile);
-    __syncthreads();
+    bar<LCAP == 0>();
     const int32_t j0 = sh_j0;
-    __syncthreads();
+    bar<LCAP == 0>();
     if (j0 >= total) break;
     const int32_t j1 = min(total, j0 + tile);
     b = find_row(G.gs_off, 0, n, j0);
@@ -376,7 +399,7 @@ __global__ __launch_bounds__(BLOCK) void k5_kernel(DevGraph G, const uint16_t* _
           for (int32_t i = G.gs_off[cur_b] + threadIdx.x; i < G.gs_off[cur_b + 1]; i += BLOCK)
             lab.clear_bits(G.gs_idx[i] & kIdMask, 3u);
         }
-        __syncthreads();
+        bar<LCAP == 0>();
         for (int32_t i = ba + threadIdx.x; i < bend; i += BLOCK) {
           const uint32_t e = G.gs_idx[i];
           lab.set_bits(e & kIdMask, e >> kTypeShift);
@@ -396,7 +419,7 @@ __global__ __launch_bounds__(BLOCK) void k5_kernel(DevGraph G, const uint16_t* _
         const uint32_t e = G.gs_idx[aa + i];
         lab.set_bits(e & kIdMask, (e >> kTypeShift) << 2);
       }
-      __syncthreads();
+      bar<LCAP == 0>();
       for (int32_t jc = j + 1; jc < bend; ++jc) {
         const uint32_t ec = G.gs_idx[jc];
         const int32_t c = (int32_t)(ec & kIdMask);
@@ -411,7 +434,7 @@ __global__ __launch_bounds__(BLOCK) void k5_kernel(DevGraph G, const uint16_t* _
           const uint32_t e = G.gs_idx[ca + i];
           lab.set_bits(e & kIdMask, (e >> kTypeShift) << 4);
         }
-        __syncthreads();
+        bar<LCAP == 0>();
         const int32_t db = bend - ba;
         for (int32_t i = threadIdx.x; i < db + da + dc; i += BLOCK) {
           uint32_t x;
@@ -439,27 +462,346 @@ __global__ __launch_bounds__(BLOCK) void k5_kernel(DevGraph G, const uint16_t* _
             }
           }
         }
-        __syncthreads();
+        bar<LCAP == 0>();
         closed_form<K, NL, BLOCK>(hist, lut, cnt, nzl, &nz_count, base);
-        __syncthreads();
+        bar<LCAP == 0>();
         for (int32_t i = threadIdx.x; i < dc; i += BLOCK) lab.clear_bits(G.gs_idx[ca + i] & kIdMask, 3u << 4);
         if (threadIdx.x < NL) cnt[threadIdx.x] = 0;
-        __syncthreads();
+        bar<LCAP == 0>();
       }
       // Skipped triples read a-labels without a barrier: every wave must have
       // left the triple loop before any wave clears them, or a late wave would
       // see "not adjacent" for a skipped triangle and fall out of barrier step.
-      __syncthreads();
+      bar<LCAP == 0>();
       for (int32_t i = threadIdx.x; i < da; i += BLOCK) lab.clear_bits(G.gs_idx[aa + i] & kIdMask, 3u << 2);
-      __syncthreads();
+      bar<LCAP == 0>();
     }
   }
   if (cur_b >= 0) {
     for (int32_t i = G.gs_off[cur_b] + threadIdx.x; i < G.gs_off[cur_b + 1]; i += BLOCK)
       lab.clear_bits(G.gs_idx[i] & kIdMask, 3u);
   }
-  __syncthreads();
+  bar<LCAP == 0>();
   hist_flush<C, BLOCK>(hist, acc, cur_g);
+}
+
+// ======================================================= core reuse ==
+//
+// The same sums as k4_kernel / k5_kernel, reorganised so that the
+// neighbourhood of the highest-ranked anchor vertex is scanned once per work
+// unit instead of once per anchor.  Core kappa = the higher-rank endpoint of
+// the anchor edge (k = 4) or the centre b of the connected triple (k = 5);
+// the other anchor vertices are the "sides".  Per core, once:
+//   M[tx][ty][r] = edges x -> y (N+ orientation) with both ends in N(kappa),
+//                  by the types of x, y towards kappa and the edge type r;
+//   W[q][tp][r]  = edges p -> q (N+ orientation, p in N(kappa)) for every q.
+// Per anchor, with R' = (sides and their neighbours) \ {kappa}, the edges
+// inside adj(anchor) are
+//   sum over M with core-only labels
+//   - the edges of M that touch R'   (scanned from R' or counted in W)
+//   + the same edges with their true labels when both ends are in adj(anchor),
+// where edges touching R' are found from the N+ row of their lower-rank end
+// when that end is in R', and otherwise counted in W[q] for q in R' (minus
+// the part already found from R').  The set sizes of the closed form for
+// core-only neighbours are the type counts of N(kappa) minus those in R'.
+//
+// W is a private global slice per workgroup, 9 uint32 per vertex of the
+// largest graph (indexed by the vertex's position in its graph).
+template <int K, int BLOCK, int LCAP>
+__global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* __restrict__ lut_g,
+                                                   uint64_t* __restrict__ acc, const int32_t* st,
+                                                   int32_t* __restrict__ queue, uint32_t* __restrict__ glabels,
+                                                   int64_t label_words, const int32_t* __restrict__ hub_id,
+                                                   uint32_t* __restrict__ wg, int64_t w_stride, int32_t tile) {
+  constexpr int C = K == 4 ? 199 : 9364, NL = K == 4 ? 16 : 64, LB = K == 4 ? 4 : 8;
+  constexpr int S1 = K - 2, S2 = K - 1;  // member slots
+  __shared__ u64 hist[C];
+  __shared__ uint16_t lut_lds[K == 4 ? 4096 : 1];
+  __shared__ int32_t cnt[NL], nzl[NL], nz_count;
+  __shared__ uint32_t Mc[27];
+  __shared__ uint32_t W[kMaxHubs * 9];
+  __shared__ int32_t ncore[4];
+  __shared__ int32_t sh_j0;
+  __shared__ uint32_t lds_labels[LCAP > 0 ? LCAP / 4 : 1];
+  if (st[kStatus] != 0) return;
+  Labels<LB, LCAP == 0> lab{LCAP > 0 ? lds_labels : glabels + (int64_t)blockIdx.x * label_words};
+  uint32_t* WG = wg + (int64_t)blockIdx.x * w_stride;  // 16 words per vertex of the largest graph
+  const uint16_t* lut = K == 4 ? lut_lds : lut_g;
+  if (K == 4)
+    for (int i = threadIdx.x; i < 4096; i += BLOCK) lut_lds[i] = lut_g[i];
+  for (int i = threadIdx.x; i < C; i += BLOCK) hist[i] = 0;
+  if (threadIdx.x < NL) cnt[threadIdx.x] = 0;
+  if (threadIdx.x < 27) Mc[threadIdx.x] = 0;
+  if (threadIdx.x < 4) ncore[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < kMaxHubs * 9; i += BLOCK) W[i] = 0u;
+  if (LCAP > 0)
+    for (int i = threadIdx.x; i < LCAP / 4; i += BLOCK) lds_labels[i] = 0u;
+  __syncthreads();
+
+  const int32_t n = G.n;
+  const int32_t total = G.gs_off[n];
+  int32_t cur_g = -1, row = 0, core = -1;
+  int64_t wbase = 0;  // first vertex of the core's graph
+  auto wrow = [&](int32_t q) { return WG + (int64_t)(q - wbase) * 16; };
+  // contribution of one edge between slots S1 (x) and S2 (y) of weight w
+  auto edge = [&](uint32_t base, uint32_t Lx, uint32_t Ly, uint32_t r, u64 w) {
+    const uint32_t c0 = base | slot_code<K, S1>(Lx) | slot_code<K, S2>(Ly);
+    atomicAdd(&hist[lut[c0 | rel_code<K>(r)]], w);
+    atomicAdd(&hist[lut[c0]], (u64)0 - w);
+  };
+  // per-core set-up (labels of N(core), type counts, M, W) and tear-down
+  auto core_setup = [&](int32_t c) {
+    const int32_t ca = G.gs_off[c], cb = G.gs_off[c + 1];
+    for (int32_t i = ca + threadIdx.x; i < cb; i += BLOCK) {
+      const uint32_t e = G.gs_idx[i];
+      lab.set_bits(e & kIdMask, e >> kTypeShift);
+      atomicAdd(&ncore[e >> kTypeShift], 1);
+    }
+    bar<LCAP == 0>();
+    for (int32_t i = ca + threadIdx.x; i < cb; i += BLOCK) {
+      const uint32_t ey = G.gs_idx[i];
+      const uint32_t y = ey & kIdMask, ty = ey >> kTypeShift;
+      for (int32_t p = G.np_off[y]; p < G.np_off[y + 1]; ++p) {
+        const uint32_t f = G.np_idx[p];
+        const int32_t x = (int32_t)(f & kIdMask);
+        if (x == c) continue;
+        const uint32_t r = f >> kTypeShift;
+        const int32_t h = hub_id[x];
+        if (h >= 0) atomicAdd(&W[h * 9 + (ty - 1) * 3 + (r - 1)], 1u);
+        else atomicAdd(&wrow(x)[(ty - 1) * 3 + (r - 1)], 1u);
+        const uint32_t tx = lab.get((uint32_t)x) & 3u;
+        if (tx) atomicAdd(&Mc[(ty - 1) * 9 + (tx - 1) * 3 + (r - 1)], 1u);
+      }
+    }
+    // W rows were built by L2 atomics: wait for them, then drop stale L1 lines
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  };
+  auto core_teardown = [&](int32_t c) {
+    bar<LCAP == 0>();
+    const int32_t ca = G.gs_off[c], cb = G.gs_off[c + 1];
+    for (int32_t i = ca + threadIdx.x; i < cb; i += BLOCK) {
+      const uint32_t y = G.gs_idx[i] & kIdMask;
+      lab.clear_bits(y, 3u);
+      for (int32_t p = G.np_off[y]; p < G.np_off[y + 1]; ++p) {
+        const int32_t x = (int32_t)(G.np_idx[p] & kIdMask);
+        if (x == c || hub_id[x] >= 0) continue;
+        uint4* w4 = reinterpret_cast<uint4*>(wrow(x));
+        w4[0] = make_uint4(0, 0, 0, 0);
+        w4[1] = make_uint4(0, 0, 0, 0);
+        w4[2] = make_uint4(0, 0, 0, 0);
+      }
+    }
+    for (int i = threadIdx.x; i < kMaxHubs * 9; i += BLOCK) W[i] = 0u;
+    __builtin_amdgcn_s_waitcnt(0);
+    if (threadIdx.x < 27) Mc[threadIdx.x] = 0;
+    if (threadIdx.x < 4) ncore[threadIdx.x] = 0;
+    bar<LCAP == 0>();
+  };
+
+  // One anchor: core c, sides s0 (and s1 for k = 5) whose labels are set.
+  auto anchor = [&](int32_t c, int32_t s0, int32_t s1, uint32_t base) {
+    const int32_t a0 = G.gs_off[s0], d0 = G.gs_off[s0 + 1] - a0;
+    const int32_t a1 = K == 5 ? G.gs_off[s1] : 0, d1 = K == 5 ? G.gs_off[s1 + 1] - a1 : 0;
+    const int32_t nsides = K == 5 ? 2 : 1;
+    auto is_side = [&](int32_t y) { return y == s0 || (K == 5 && y == s1); };
+    for (int32_t i = threadIdx.x; i < nsides + d0 + d1; i += BLOCK) {
+      int32_t q;
+      if (i < nsides) {
+        q = i == 0 ? s0 : s1;
+      } else if (i < nsides + d0) {
+        q = (int32_t)(G.gs_idx[a0 + i - nsides] & kIdMask);
+        if (q == c || is_side(q)) continue;
+      } else {
+        q = (int32_t)(G.gs_idx[a1 + i - nsides - d0] & kIdMask);
+        if (q == c || is_side(q) || ((lab.get((uint32_t)q) >> 2) & 3u)) continue;  // listed from s0's row
+      }
+      const uint32_t Lq = lab.get((uint32_t)q);
+      const bool mq = !is_side(q);  // R' vertices other than the sides are members
+      const uint32_t cq = Lq & 3u;
+      if (mq) atomicAdd(&cnt[Lq], 1);
+      for (int32_t p = G.np_off[q]; p < G.np_off[q + 1]; ++p) {
+        const uint32_t f = G.np_idx[p];
+        const int32_t y = (int32_t)(f & kIdMask);
+        if (y == c) continue;
+        const uint32_t Ly = lab.get((uint32_t)y);
+        const bool sy = is_side(y);
+        if (!Ly && !sy) continue;
+        const bool my = !sy;
+        const uint32_t r = f >> kTypeShift, cy = Ly & 3u;
+        if (cq && cy) edge(base, cq, cy, r, kMinusOne);
+        if (mq && my) edge(base, Lq, Ly, r, 1ull);
+        if (cq && (sy || (Ly >> 2))) {  // p = q is also counted in W[y]
+          if (cy) edge(base, cq, cy, r, 1ull);
+          if (my) edge(base, cq, Ly, r, kMinusOne);
+        }
+      }
+      // edges p -> q (p in N(core), p of lower rank than q): row W[q]
+      uint32_t wq[9];
+      const int32_t hq = hub_id[q];
+      if (hq >= 0) {
+#pragma unroll
+        for (int tr = 0; tr < 9; ++tr) wq[tr] = W[hq * 9 + tr];
+      } else {
+        const uint4* w4 = reinterpret_cast<const uint4*>(wrow(q));
+        const uint4 x0 = w4[0], x1 = w4[1], x2 = w4[2];
+        wq[0] = x0.x; wq[1] = x0.y; wq[2] = x0.z; wq[3] = x0.w;
+        wq[4] = x1.x; wq[5] = x1.y; wq[6] = x1.z; wq[7] = x1.w; wq[8] = x2.x;
+      }
+#pragma unroll
+      for (int tr = 0; tr < 9; ++tr) {
+        const uint32_t w = wq[tr];
+        if (!w) continue;
+        const uint32_t tp = (uint32_t)(tr / 3) + 1u, r = (uint32_t)(tr % 3) + 1u;
+        if (cq) edge(base, tp, cq, r, (u64)0 - (u64)w);
+        if (mq) edge(base, tp, Lq, r, (u64)w);
+      }
+    }
+    bar<LCAP == 0>();
+    // edges inside N(core) with core-only labels
+    if (threadIdx.x < 27) {
+      const uint32_t w = Mc[threadIdx.x];
+      if (w) {
+        const uint32_t tx = threadIdx.x / 9 + 1, ty = (threadIdx.x / 3) % 3 + 1, r = threadIdx.x % 3 + 1;
+        edge(base, tx, ty, r, (u64)w);
+      }
+    }
+    // sizes of the core-only sets: N(core) minus the sides minus R'
+    if (threadIdx.x < 3) {
+      const int32_t a = threadIdx.x + 1;
+      int32_t v = ncore[a];
+      for (int L = 4; L < NL; ++L)
+        if ((L & 3) == a) v -= cnt[L];
+      uint32_t t0 = 0, t1 = 0;
+      // the type of each side towards the core sits in its own label
+      t0 = lab.get((uint32_t)s0) & 3u;
+      if (K == 5) t1 = lab.get((uint32_t)s1) & 3u;
+      v -= (t0 == (uint32_t)a) + (K == 5 && t1 == (uint32_t)a);
+      cnt[a] = v;
+    }
+    bar<LCAP == 0>();
+    closed_form<K, NL, BLOCK>(hist, lut, cnt, nzl, &nz_count, base);
+    bar<LCAP == 0>();
+    if (threadIdx.x < NL) cnt[threadIdx.x] = 0;
+  };
+
+  for (;;) {
+    if (threadIdx.x == 0) sh_j0 = atomicAdd(queue, tile);
+    bar<LCAP == 0>();
+    const int32_t j0 = sh_j0;
+    bar<LCAP == 0>();
+    if (j0 >= total) break;
+    const int32_t j1 = min(total, j0 + tile);
+    row = find_row(G.gs_off, 0, n, j0);
+    for (int32_t j = j0; j < j1; ++j) {
+      while (G.gs_off[row + 1] <= j) ++row;
+      const int32_t c = row;
+      const int32_t rowa = G.gs_off[c], rowb = G.gs_off[c + 1];
+      const uint32_t ej = G.gs_idx[j];
+      const int32_t x = (int32_t)(ej & kIdMask);
+      bool unit;
+      if (K == 4) {  // anchor edge {c, x} owned by its higher-rank end
+        const int32_t dc = rowb - rowa, dx = G.gs_off[x + 1] - G.gs_off[x];
+        unit = dx < dc || (dx == dc && x < c);
+      } else {  // unit (b = c, a = x) with partners after x in c's row
+        unit = j + 1 < rowb;
+      }
+      if (!unit) continue;
+      if (c != core) {
+        if (core >= 0) core_teardown(core);
+        const int32_t g = G.gid ? G.gid[c] : 0;
+        if (g != cur_g) {
+          hist_flush<C, BLOCK>(hist, acc, cur_g);
+          cur_g = g;
+          bar<LCAP == 0>();
+        }
+        wbase = G.voff ? G.voff[g] : 0;
+        core = c;
+        core_setup(c);
+      }
+      const uint32_t tcx = ej >> kTypeShift;
+      // side labels of x (bits 2-3)
+      const int32_t xa = G.gs_off[x], xb = G.gs_off[x + 1];
+      for (int32_t i = xa + threadIdx.x; i < xb; i += BLOCK) {
+        const uint32_t e = G.gs_idx[i];
+        if ((int32_t)(e & kIdMask) != c) lab.set_bits(e & kIdMask, (e >> kTypeShift) << 2);
+      }
+      bar<LCAP == 0>();
+      if (K == 4) {
+        const uint32_t base = ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u);
+        anchor(c, x, -1, base);
+      } else {
+        for (int32_t jc = j + 1; jc < rowb; ++jc) {
+          const uint32_t ec = G.gs_idx[jc];
+          const int32_t c2 = (int32_t)(ec & kIdMask);
+          const uint32_t tbc = ec >> kTypeShift;
+          const uint32_t tac = (lab.get((uint32_t)c2) >> 2) & 3u;
+          if (tac && (c > x || c > c2)) continue;  // triangle: taken at its smallest id
+          const uint32_t base = ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u) |
+                                ((tbc & 1u) ? 1u << cbit<K>(0, 2) : 0u) | ((tbc & 2u) ? 1u << cbit<K>(2, 0) : 0u) |
+                                ((tac & 1u) ? 1u << cbit<K>(1, 2) : 0u) | ((tac & 2u) ? 1u << cbit<K>(2, 1) : 0u);
+          const int32_t ca2 = G.gs_off[c2], cb2 = G.gs_off[c2 + 1];
+          for (int32_t i = ca2 + threadIdx.x; i < cb2; i += BLOCK) {
+            const uint32_t e = G.gs_idx[i];
+            if ((int32_t)(e & kIdMask) != c) lab.set_bits(e & kIdMask, (e >> kTypeShift) << 4);
+          }
+          bar<LCAP == 0>();
+          anchor(c, x, c2, base);
+          for (int32_t i = ca2 + threadIdx.x; i < cb2; i += BLOCK) {
+            const uint32_t e = G.gs_idx[i];
+            if ((int32_t)(e & kIdMask) != c) lab.clear_bits(e & kIdMask, 3u << 4);
+          }
+          bar<LCAP == 0>();
+        }
+        // skipped triples read x's labels without a barrier (see k5_kernel)
+        bar<LCAP == 0>();
+      }
+      for (int32_t i = xa + threadIdx.x; i < xb; i += BLOCK) {
+        const uint32_t e = G.gs_idx[i];
+        if ((int32_t)(e & kIdMask) != c) lab.clear_bits(e & kIdMask, 3u << 2);
+      }
+      bar<LCAP == 0>();
+    }
+  }
+  if (core >= 0) core_teardown(core);
+  hist_flush<C, BLOCK>(hist, acc, cur_g);
+}
+
+// Hub slots for the core-reuse scheme: the vertices of largest degree get one
+// of kMaxHubs rows of the per-core W table; the threshold is the smallest
+// power of two whose degree bucket and all above hold at most kMaxHubs
+// vertices (and at least 32).  hs[0..31] = counts per floor(log2 d),
+// hs[32] = threshold, hs[33] = slot counter.  Which vertices get slots never
+// changes the result, only where the work goes.
+__global__ void k_degree_buckets(const int32_t* gs_off, int32_t n, int32_t* hs, const int32_t* st) {
+  if (st[kStatus] != 0) return;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t d = gs_off[v + 1] - gs_off[v];
+    if (d > 0) atomicAdd(&hs[31 - __clz(d)], 1);
+  }
+}
+
+__global__ void k_hub_threshold(int32_t* hs, const int32_t* st) {
+  if (st[kStatus] != 0 || threadIdx.x != 0) return;
+  int32_t cum = 0, b = 31;
+  while (b > 5 && cum + hs[b] <= kMaxHubs) cum += hs[b--];
+  hs[32] = 1 << (b + 1);
+  hs[33] = 0;
+}
+
+__global__ void k_assign_hubs(const int32_t* gs_off, int32_t n, int32_t* hs, int32_t* hub_id, const int32_t* st) {
+  if (st[kStatus] != 0) return;
+  const int32_t t = hs[32];
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t d = gs_off[v + 1] - gs_off[v];
+    int32_t h = -1;
+    if (d >= t) {
+      h = atomicAdd(&hs[33], 1);
+      if (h >= kMaxHubs) h = -1;
+    }
+    hub_id[v] = h;
+  }
 }
 
 // =========================================================== finalise ==
@@ -500,9 +842,12 @@ int grid_size(int k, int num_cus) {
 
 }  // namespace
 
-size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int num_cus) {
+size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int num_cus, int64_t maxn) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   size_t b = build_bytes(N, M, G, batch);
+  if ((k == 4 || k == 5) && tuning_for(k).heavy == 1)
+    b += al(sizeof(int32_t) * (N + 1)) + al(64 * sizeof(int32_t)) +
+         al(sizeof(uint32_t) * 16 * (size_t)(maxn > 0 ? maxn : N) * grid_size(k, num_cus));
   b += 2 * al(sizeof(uint64_t) * (size_t)G * num_classes(k));  // accumulators (+ output staging)
   b += al(64 * sizeof(int32_t));                               // queue counters
   const int cap = k == 4 ? label_cap_k4((int32_t)N) : k == 5 ? label_cap_k5((int32_t)N) : 1;
@@ -513,6 +858,9 @@ size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int nu
 #define LAUNCH_K4(BLOCK, CAP)                                                                                   \
   hipLaunchKernelGGL((k4_kernel<BLOCK, CAP>), dim3(grid), dim3(BLOCK), 0, s, g, T.lut[4], acc, p.status, queue, \
                      glabels, lw, t.tile)
+#define LAUNCH_KR(K, BLOCK, CAP)                                                                        \
+  hipLaunchKernelGGL((kr_kernel<K, BLOCK, CAP>), dim3(grid), dim3(BLOCK), 0, s, g, T.lut[K], acc, p.status, queue, \
+                     glabels, lw, hub_id, wg, ws, t.tile)
 #define LAUNCH_K5(BLOCK, CAP)                                                                                   \
   hipLaunchKernelGGL((k5_kernel<BLOCK, CAP>), dim3(grid), dim3(BLOCK), 0, s, g, T.lut[5], acc, p.status, queue, \
                      glabels, lw, t.tile)
@@ -531,33 +879,58 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
     if (k == 3) {
       const int tv = t.tile > 0 ? t.tile * 16 : 256;
       hipLaunchKernelGGL((k3_kernel<256>), dim3(grid), dim3(256), 0, s, g, T.lut[3], acc, p.status, tv);
-    } else if (k == 4) {
-      const int cap = label_cap_k4(g.n);
-      const int64_t lw = label_words(4, g.n);
-      uint32_t* glabels = nullptr;
-      if (cap == 0) {
-        glabels = p.arena.take<uint32_t>((size_t)lw * grid);
-        enqueue_zero(glabels, sizeof(uint32_t) * (size_t)lw * grid, s);
-      }
-      if (t.block == 512) {
-        if (cap == 8192) LAUNCH_K4(512, 8192); else if (cap == 65536) LAUNCH_K4(512, 65536); else LAUNCH_K4(512, 0);
-      } else if (t.block == 1024) {
-        if (cap == 8192) LAUNCH_K4(1024, 8192); else if (cap == 65536) LAUNCH_K4(1024, 65536); else LAUNCH_K4(1024, 0);
-      } else {
-        if (cap == 8192) LAUNCH_K4(256, 8192); else if (cap == 65536) LAUNCH_K4(256, 65536); else LAUNCH_K4(256, 0);
-      }
     } else {
-      const int cap = label_cap_k5(g.n);
-      const int64_t lw = label_words(5, g.n);
+      const bool reuse = t.heavy == 1;
+      const int cap = k == 4 ? label_cap_k4(g.n) : label_cap_k5(g.n);
+      const int64_t lw = label_words(k, g.n);
       uint32_t* glabels = nullptr;
       if (cap == 0) {
         glabels = p.arena.take<uint32_t>((size_t)lw * grid);
         enqueue_zero(glabels, sizeof(uint32_t) * (size_t)lw * grid, s);
       }
-      if (t.block == 512) {
-        if (cap == 16384) LAUNCH_K5(512, 16384); else if (cap == 65536) LAUNCH_K5(512, 65536); else LAUNCH_K5(512, 0);
+      int32_t* hub_id = nullptr;
+      uint32_t* wg = nullptr;
+      int64_t ws = 0;
+      if (reuse) {
+        ws = 16 * (int64_t)(g.max_graph_n > 0 ? g.max_graph_n : g.n);
+        wg = p.arena.take<uint32_t>((size_t)ws * grid);
+        enqueue_zero(wg, sizeof(uint32_t) * (size_t)ws * grid, s);
+        hub_id = p.arena.take<int32_t>(g.n + 1);
+        int32_t* hs = p.arena.take<int32_t>(64);
+        enqueue_zero(hs, 64 * sizeof(int32_t), s);
+        hipLaunchKernelGGL(k_degree_buckets, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.gs_off, g.n, hs, p.status);
+        hipLaunchKernelGGL(k_hub_threshold, dim3(1), dim3(64), 0, s, hs, p.status);
+        hipLaunchKernelGGL(k_assign_hubs, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.gs_off, g.n, hs, hub_id,
+                           p.status);
+      }
+      if (k == 4 && reuse) {
+        if (t.block == 512) {
+          if (cap == 8192) LAUNCH_KR(4, 512, 8192); else if (cap == 65536) LAUNCH_KR(4, 512, 65536); else LAUNCH_KR(4, 512, 0);
+        } else if (t.block == 1024) {
+          if (cap == 8192) LAUNCH_KR(4, 1024, 8192); else if (cap == 65536) LAUNCH_KR(4, 1024, 65536); else LAUNCH_KR(4, 1024, 0);
+        } else {
+          if (cap == 8192) LAUNCH_KR(4, 256, 8192); else if (cap == 65536) LAUNCH_KR(4, 256, 65536); else LAUNCH_KR(4, 256, 0);
+        }
+      } else if (k == 4) {
+        if (t.block == 512) {
+          if (cap == 8192) LAUNCH_K4(512, 8192); else if (cap == 65536) LAUNCH_K4(512, 65536); else LAUNCH_K4(512, 0);
+        } else if (t.block == 1024) {
+          if (cap == 8192) LAUNCH_K4(1024, 8192); else if (cap == 65536) LAUNCH_K4(1024, 65536); else LAUNCH_K4(1024, 0);
+        } else {
+          if (cap == 8192) LAUNCH_K4(256, 8192); else if (cap == 65536) LAUNCH_K4(256, 65536); else LAUNCH_K4(256, 0);
+        }
+      } else if (reuse) {
+        if (t.block == 512) {
+          if (cap == 16384) LAUNCH_KR(5, 512, 16384); else if (cap == 65536) LAUNCH_KR(5, 512, 65536); else LAUNCH_KR(5, 512, 0);
+        } else {
+          if (cap == 16384) LAUNCH_KR(5, 1024, 16384); else if (cap == 65536) LAUNCH_KR(5, 1024, 65536); else LAUNCH_KR(5, 1024, 0);
+        }
       } else {
-        if (cap == 16384) LAUNCH_K5(1024, 16384); else if (cap == 65536) LAUNCH_K5(1024, 65536); else LAUNCH_K5(1024, 0);
+        if (t.block == 512) {
+          if (cap == 16384) LAUNCH_K5(512, 16384); else if (cap == 65536) LAUNCH_K5(512, 65536); else LAUNCH_K5(512, 0);
+        } else {
+          if (cap == 16384) LAUNCH_K5(1024, 16384); else if (cap == 65536) LAUNCH_K5(1024, 65536); else LAUNCH_K5(1024, 0);
+        }
       }
     }
   }

@@ -507,6 +507,10 @@ BuildInput enqueue_pack(Pipeline& p, const motif_graph_t* graphs, int32_t count,
   in.gid = gid;
   in.ngraphs = count;
   in.has_in = has_in;
+  in.voff = dvoff;
+  int64_t mx = 0;
+  for (int32_t g = 0; g < count; ++g) mx = std::max<int64_t>(mx, voff[g + 1] - voff[g]);
+  in.max_graph_n = (int32_t)mx;
   return in;
 }
 
@@ -541,7 +545,9 @@ DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s) {
   g.np_off = np_off;
   g.np_idx = np_idx;
   g.gid = in.gid;
+  g.voff = in.voff;
   g.ngraphs = in.ngraphs;
+  g.max_graph_n = in.gid ? in.max_graph_n : n;
   if (n == 0) return g;
 
   enqueue_zero(in_cnt, sizeof(int32_t) * (n + 1), s);

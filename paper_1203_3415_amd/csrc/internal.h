@@ -37,7 +37,9 @@ struct DevGraph {
   const int32_t* np_off = nullptr;  // [n+1]
   const uint32_t* np_idx = nullptr; // [m*]  N+(v): neighbours of higher rank
   const int32_t* gid = nullptr;     // [n] graph of each vertex (batch) or null
+  const int64_t* voff = nullptr;    // [ngraphs+1] first vertex of each graph (batch) or null
   int32_t ngraphs = 1;
+  int32_t max_graph_n = 0;          // largest vertex count of one graph
 };
 
 // Device class tables uploaded by motif_init.
@@ -81,13 +83,13 @@ struct Tuning {
   int block = 256;
   int grid_per_cu = 4;
   int tile = 16;
-  int heavy = 0;
+  int heavy = 1;  // census scheme for k = 4, 5: 1 = core reuse, 0 = per-anchor scan
 };
 Tuning& tuning_for(int k);
 
 // Bytes the arena needs for a union graph of N vertices, M arcs, G graphs
 // (G > 1 includes the packing buffers of a batch).
-size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int num_cus);
+size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int num_cus, int64_t maxn);
 size_t build_bytes(int64_t N, int64_t M, int32_t G, bool batch);
 
 // Inputs of the build: either one graph or a packed batch.
@@ -101,6 +103,8 @@ struct BuildInput {
   const int32_t* gid = nullptr;     // batch only
   int32_t ngraphs = 1;
   const int32_t* has_in = nullptr;  // batch only: graph supplied an in-CSR
+  const int64_t* voff = nullptr;    // batch only: first vertex of each graph (device)
+  int32_t max_graph_n = 0;          // largest vertex count of one graph
 };
 
 // Enqueue validation + G* + N+ build.  Returns the built view (device pointers

@@ -80,7 +80,7 @@ class RangeAlloc {
 size_t request_bytes(int32_t n, int64_t m, int32_t k, int cus) {
   const int C = motif_num_classes(k);
   return al(sizeof(int32_t) * (size_t)(n + 1)) + al(sizeof(int32_t) * (size_t)(m + 1)) + al(sizeof(uint64_t) * C) +
-         al(pipeline_bytes(n, m, 1, false, k, cus));
+         al(pipeline_bytes(n, m, 1, false, k, cus, n));
 }
 
 }  // namespace

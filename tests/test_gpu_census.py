@@ -261,11 +261,50 @@ def test_tuning_variants_agree(pm, k):
     saved = pm.get_tuning(k)
     try:
         blocks = (256, 512, 1024) if k == 4 else (512, 1024)
-        for block in blocks:
-            for tile in (1, 7, 64):
-                for gpc in (1, 3):
-                    pm.set_tuning(k, block=block, tile=tile, grid_per_cu=gpc)
-                    print(f"[case] tuning k={k} block={block} tile={tile} gpc={gpc}", flush=True)
-                    assert np.array_equal(gpu_census(pm, g, k), want)
+        for scheme in (1, 2):
+            for block in blocks:
+                for tile in (1, 7, 64):
+                    for gpc in (1, 3):
+                        pm.set_tuning(k, block=block, tile=tile, grid_per_cu=gpc, heavy=scheme)
+                        print(f"[case] tuning k={k} scheme={scheme} block={block} tile={tile} gpc={gpc}", flush=True)
+                        assert np.array_equal(gpu_census(pm, g, k), want)
     finally:
         pm.set_tuning(k, **saved)
+
+
+@pytest.mark.parametrize("k", [4, 5])
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_both_schemes(pm, k, scheme):
+    # scheme 1: core reuse (default); scheme 2: per-anchor scan
+    saved = pm.get_tuning(k)
+    try:
+        pm.set_tuning(k, heavy=scheme)
+        rng = np.random.default_rng(200 + k)
+        for t in range(16 if k == 4 else 8):
+            n = int(rng.integers(3, 40 if k == 4 else 28))
+            g = gg.random_small(n, float(rng.uniform(0.05, 0.7)), float(rng.uniform(0, 1)), seed=900 * k + t)
+            assert_parity(pm, g, k, f"scheme{scheme} random#{t}")
+        assert_parity(pm, gg.chung_lu(700, 3000, 2.1, 2.2, 0.2, seed=91), k, f"scheme{scheme} chung_lu700")
+        sizes = (300, 250, 200) if k == 4 else (40, 30, 25)
+        g = gg.star(*sizes)
+        print(f"[case] scheme{scheme} star k={k}", flush=True)
+        assert np.array_equal(gpu_census(pm, g, k), _star_expect(k, *sizes))
+        base = gg.chung_lu(2500, 9000 if k == 4 else 5000, 2.3, 2.3, 0.1, seed=92)
+        big = gg.relabel(gg.disjoint_union(base, gg.from_arcs(140000 - base.n, [])), seed=93)
+        assert_parity(pm, big, k, f"scheme{scheme} global_labels")
+    finally:
+        pm.set_tuning(k, **saved)
+
+
+def test_schemes_agree_on_power_law(pm):
+    g = gg.chung_lu(20000, 100000, 2.1, 2.1, 0.2, seed=94)
+    off, idx = pm.to_device(g.out_off, g.out_idx)
+    saved = pm.get_tuning(4)
+    try:
+        pm.set_tuning(4, heavy=1)
+        a = pm.census(off, idx, g.n, 4)
+        pm.set_tuning(4, heavy=2)
+        b = pm.census(off, idx, g.n, 4)
+    finally:
+        pm.set_tuning(4, **saved)
+    assert np.array_equal(a, b)
