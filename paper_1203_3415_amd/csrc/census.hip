@@ -505,8 +505,15 @@ __global__ __launch_bounds__(BLOCK) void k5_kernel(DevGraph G, const uint16_t* _
 // the part already found from R').  The set sizes of the closed form for
 // core-only neighbours are the type counts of N(kappa) minus those in R'.
 //
-// W is a private global slice per workgroup, 9 uint32 per vertex of the
-// largest graph (indexed by the vertex's position in its graph).
+// W is a private global slice per workgroup, 16 uint32 per vertex of the
+// largest graph (indexed by the vertex's position in its graph), except for
+// the hub vertices, whose rows sit in LDS.
+//
+// Every scan of a list of N+ rows (the rows of N(kappa) at set-up and
+// tear-down, the rows of R' per anchor) is flattened: the rows of up to BLOCK
+// listed vertices are laid end to end and dealt out one entry per thread, so
+// the work of an anchor is spread over the whole workgroup whatever the row
+// lengths.
 template <int K, int BLOCK, int LCAP>
 __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* __restrict__ lut_g,
                                                    uint64_t* __restrict__ acc, const int32_t* st,
@@ -515,17 +522,22 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                                                    uint32_t* __restrict__ wg, int64_t w_stride, int32_t tile) {
   constexpr int C = K == 4 ? 199 : 9364, NL = K == 4 ? 16 : 64, LB = K == 4 ? 4 : 8;
   constexpr int S1 = K - 2, S2 = K - 1;  // member slots
+  // LDS rows of W: fewer where the k = 5 counters and labels leave no room
+  constexpr int HUBS = (K == 5 && LCAP == 65536) ? 256 : kMaxHubs;
+  constexpr bool GL = LCAP == 0;
   __shared__ u64 hist[C];
   __shared__ uint16_t lut_lds[K == 4 ? 4096 : 1];
   __shared__ int32_t cnt[NL], nzl[NL], nz_count;
   __shared__ uint32_t Mc[27];
-  __shared__ uint32_t W[kMaxHubs * 9];
+  __shared__ uint32_t W[HUBS * 9];
   __shared__ int32_t ncore[4];
   __shared__ int32_t sh_j0;
+  __shared__ u64 seg_ctr[2];  // (rows << 32) | entries of the chunk being laid out
+  __shared__ int32_t seg_v[BLOCK], seg_start[BLOCK];
   __shared__ uint32_t lds_labels[LCAP > 0 ? LCAP / 4 : 1];
   if (st[kStatus] != 0) return;
-  Labels<LB, LCAP == 0> lab{LCAP > 0 ? lds_labels : glabels + (int64_t)blockIdx.x * label_words};
-  uint32_t* WG = wg + (int64_t)blockIdx.x * w_stride;  // 16 words per vertex of the largest graph
+  Labels<LB, GL> lab{LCAP > 0 ? lds_labels : glabels + (int64_t)blockIdx.x * label_words};
+  uint32_t* WG = wg + (int64_t)blockIdx.x * w_stride;
   const uint16_t* lut = K == 4 ? lut_lds : lut_g;
   if (K == 4)
     for (int i = threadIdx.x; i < 4096; i += BLOCK) lut_lds[i] = lut_g[i];
@@ -533,71 +545,114 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   if (threadIdx.x < NL) cnt[threadIdx.x] = 0;
   if (threadIdx.x < 27) Mc[threadIdx.x] = 0;
   if (threadIdx.x < 4) ncore[threadIdx.x] = 0;
-  for (int i = threadIdx.x; i < kMaxHubs * 9; i += BLOCK) W[i] = 0u;
+  if (threadIdx.x < 2) seg_ctr[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < HUBS * 9; i += BLOCK) W[i] = 0u;
   if (LCAP > 0)
     for (int i = threadIdx.x; i < LCAP / 4; i += BLOCK) lds_labels[i] = 0u;
   __syncthreads();
 
   const int32_t n = G.n;
   const int32_t total = G.gs_off[n];
-  int32_t cur_g = -1, row = 0, core = -1;
+  int32_t cur_g = -1, row = 0, core = -1, par = 0;
   int64_t wbase = 0;  // first vertex of the core's graph
   auto wrow = [&](int32_t q) { return WG + (int64_t)(q - wbase) * 16; };
+  auto hub = [&](int32_t q) {
+    const int32_t h = hub_id[q];
+    return h < HUBS ? h : -1;
+  };
   // contribution of one edge between slots S1 (x) and S2 (y) of weight w
   auto edge = [&](uint32_t base, uint32_t Lx, uint32_t Ly, uint32_t r, u64 w) {
     const uint32_t c0 = base | slot_code<K, S1>(Lx) | slot_code<K, S2>(Ly);
     atomicAdd(&hist[lut[c0 | rel_code<K>(r)]], w);
     atomicAdd(&hist[lut[c0]], (u64)0 - w);
   };
+  // Flattened scan of the N+ rows of the vertices pick(0 .. items-1): pick
+  // returns a vertex (or -1) and does the per-vertex work, visit(v, f) handles
+  // one entry f of N+(v).  Uniform across the workgroup; ends with a barrier.
+  // seg_ctr alternates between two words so that one of them can be cleared
+  // while the other is read.
+  auto flat_rows = [&](int32_t items, auto&& pick, auto&& visit) {
+    for (int32_t i0 = 0; i0 < items; i0 += BLOCK) {
+      const int32_t i = i0 + (int32_t)threadIdx.x;
+      if (i < items) {
+        const int32_t v = pick(i);
+        if (v >= 0) {
+          const int32_t len = G.np_off[v + 1] - G.np_off[v];
+          if (len > 0) {  // |N+(v)| <= sqrt(2 |E*|), so BLOCK rows fit in 32 bits
+            const u64 old = atomicAdd(&seg_ctr[par], (1ull << 32) | (u64)len);
+            const int32_t sl = (int32_t)(old >> 32);
+            seg_v[sl] = v;
+            seg_start[sl] = (int32_t)(uint32_t)old;
+          }
+        }
+      }
+      bar<GL>();
+      const u64 ctr = seg_ctr[par];
+      const int32_t nseg = (int32_t)(ctr >> 32), tot = (int32_t)(uint32_t)ctr;
+      if (threadIdx.x == 0) seg_ctr[par ^ 1] = 0;
+      int32_t sl = 0;
+      for (int32_t j = threadIdx.x; j < tot; j += BLOCK) {
+        int32_t hi = nseg - 1;  // last row starting at or before j (starts increase with sl)
+        while (sl < hi) {
+          const int32_t mid = (sl + hi + 1) >> 1;
+          if (seg_start[mid] <= j) sl = mid; else hi = mid - 1;
+        }
+        const int32_t v = seg_v[sl];
+        visit(v, G.np_idx[G.np_off[v] + (j - seg_start[sl])]);
+      }
+      bar<GL>();
+      par ^= 1;
+    }
+  };
   // per-core set-up (labels of N(core), type counts, M, W) and tear-down
   auto core_setup = [&](int32_t c) {
-    const int32_t ca = G.gs_off[c], cb = G.gs_off[c + 1];
-    for (int32_t i = ca + threadIdx.x; i < cb; i += BLOCK) {
-      const uint32_t e = G.gs_idx[i];
+    const int32_t ca = G.gs_off[c], dcn = G.gs_off[c + 1] - ca;
+    for (int32_t i = threadIdx.x; i < dcn; i += BLOCK) {
+      const uint32_t e = G.gs_idx[ca + i];
       lab.set_bits(e & kIdMask, e >> kTypeShift);
       atomicAdd(&ncore[e >> kTypeShift], 1);
     }
-    bar<LCAP == 0>();
-    for (int32_t i = ca + threadIdx.x; i < cb; i += BLOCK) {
-      const uint32_t ey = G.gs_idx[i];
-      const uint32_t y = ey & kIdMask, ty = ey >> kTypeShift;
-      for (int32_t p = G.np_off[y]; p < G.np_off[y + 1]; ++p) {
-        const uint32_t f = G.np_idx[p];
-        const int32_t x = (int32_t)(f & kIdMask);
-        if (x == c) continue;
-        const uint32_t r = f >> kTypeShift;
-        const int32_t h = hub_id[x];
-        if (h >= 0) atomicAdd(&W[h * 9 + (ty - 1) * 3 + (r - 1)], 1u);
-        else atomicAdd(&wrow(x)[(ty - 1) * 3 + (r - 1)], 1u);
-        const uint32_t tx = lab.get((uint32_t)x) & 3u;
-        if (tx) atomicAdd(&Mc[(ty - 1) * 9 + (tx - 1) * 3 + (r - 1)], 1u);
-      }
-    }
+    bar<GL>();
+    flat_rows(
+        dcn, [&](int32_t i) { return (int32_t)(G.gs_idx[ca + i] & kIdMask); },
+        [&](int32_t y, uint32_t f) {
+          const int32_t x = (int32_t)(f & kIdMask);
+          if (x == c) return;
+          const uint32_t r = f >> kTypeShift, ty = lab.get((uint32_t)y) & 3u;
+          const int32_t h = hub(x);
+          if (h >= 0) atomicAdd(&W[h * 9 + (ty - 1) * 3 + (r - 1)], 1u);
+          else atomicAdd(&wrow(x)[(ty - 1) * 3 + (r - 1)], 1u);
+          const uint32_t tx = lab.get((uint32_t)x) & 3u;
+          if (tx) atomicAdd(&Mc[(ty - 1) * 9 + (tx - 1) * 3 + (r - 1)], 1u);
+        });
     // W rows were built by L2 atomics: wait for them, then drop stale L1 lines
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   };
   auto core_teardown = [&](int32_t c) {
-    bar<LCAP == 0>();
-    const int32_t ca = G.gs_off[c], cb = G.gs_off[c + 1];
-    for (int32_t i = ca + threadIdx.x; i < cb; i += BLOCK) {
-      const uint32_t y = G.gs_idx[i] & kIdMask;
-      lab.clear_bits(y, 3u);
-      for (int32_t p = G.np_off[y]; p < G.np_off[y + 1]; ++p) {
-        const int32_t x = (int32_t)(G.np_idx[p] & kIdMask);
-        if (x == c || hub_id[x] >= 0) continue;
-        uint4* w4 = reinterpret_cast<uint4*>(wrow(x));
-        w4[0] = make_uint4(0, 0, 0, 0);
-        w4[1] = make_uint4(0, 0, 0, 0);
-        w4[2] = make_uint4(0, 0, 0, 0);
-      }
-    }
-    for (int i = threadIdx.x; i < kMaxHubs * 9; i += BLOCK) W[i] = 0u;
+    bar<GL>();
+    const int32_t ca = G.gs_off[c], dcn = G.gs_off[c + 1] - ca;
+    flat_rows(
+        dcn,
+        [&](int32_t i) {
+          const int32_t y = (int32_t)(G.gs_idx[ca + i] & kIdMask);
+          lab.clear_bits((uint32_t)y, 3u);
+          return y;
+        },
+        [&](int32_t, uint32_t f) {
+          const int32_t x = (int32_t)(f & kIdMask);
+          if (x == c || hub(x) >= 0) return;
+          uint4* w4 = reinterpret_cast<uint4*>(wrow(x));
+          w4[0] = make_uint4(0, 0, 0, 0);
+          w4[1] = make_uint4(0, 0, 0, 0);
+          w4[2] = make_uint4(0, 0, 0, 0);
+        });
+    for (int i = threadIdx.x; i < HUBS * 9; i += BLOCK) W[i] = 0u;
     __builtin_amdgcn_s_waitcnt(0);
     if (threadIdx.x < 27) Mc[threadIdx.x] = 0;
     if (threadIdx.x < 4) ncore[threadIdx.x] = 0;
-    bar<LCAP == 0>();
+    bar<GL>();
   };
 
   // One anchor: core c, sides s0 (and s1 for k = 5) whose labels are set.
@@ -606,40 +661,26 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     const int32_t a1 = K == 5 ? G.gs_off[s1] : 0, d1 = K == 5 ? G.gs_off[s1 + 1] - a1 : 0;
     const int32_t nsides = K == 5 ? 2 : 1;
     auto is_side = [&](int32_t y) { return y == s0 || (K == 5 && y == s1); };
-    for (int32_t i = threadIdx.x; i < nsides + d0 + d1; i += BLOCK) {
+    // list position -> vertex q of R' (each once); the O(1) part per q:
+    // set sizes and the edges p -> q counted in W[q]
+    auto pick = [&](int32_t i) -> int32_t {
       int32_t q;
       if (i < nsides) {
         q = i == 0 ? s0 : s1;
       } else if (i < nsides + d0) {
         q = (int32_t)(G.gs_idx[a0 + i - nsides] & kIdMask);
-        if (q == c || is_side(q)) continue;
+        if (q == c || is_side(q)) return -1;
       } else {
         q = (int32_t)(G.gs_idx[a1 + i - nsides - d0] & kIdMask);
-        if (q == c || is_side(q) || ((lab.get((uint32_t)q) >> 2) & 3u)) continue;  // listed from s0's row
+        if (q == c || is_side(q) || ((lab.get((uint32_t)q) >> 2) & 3u)) return -1;  // listed from s0's row
       }
       const uint32_t Lq = lab.get((uint32_t)q);
       const bool mq = !is_side(q);  // R' vertices other than the sides are members
       const uint32_t cq = Lq & 3u;
       if (mq) atomicAdd(&cnt[Lq], 1);
-      for (int32_t p = G.np_off[q]; p < G.np_off[q + 1]; ++p) {
-        const uint32_t f = G.np_idx[p];
-        const int32_t y = (int32_t)(f & kIdMask);
-        if (y == c) continue;
-        const uint32_t Ly = lab.get((uint32_t)y);
-        const bool sy = is_side(y);
-        if (!Ly && !sy) continue;
-        const bool my = !sy;
-        const uint32_t r = f >> kTypeShift, cy = Ly & 3u;
-        if (cq && cy) edge(base, cq, cy, r, kMinusOne);
-        if (mq && my) edge(base, Lq, Ly, r, 1ull);
-        if (cq && (sy || (Ly >> 2))) {  // p = q is also counted in W[y]
-          if (cy) edge(base, cq, cy, r, 1ull);
-          if (my) edge(base, cq, Ly, r, kMinusOne);
-        }
-      }
       // edges p -> q (p in N(core), p of lower rank than q): row W[q]
       uint32_t wq[9];
-      const int32_t hq = hub_id[q];
+      const int32_t hq = hub(q);
       if (hq >= 0) {
 #pragma unroll
         for (int tr = 0; tr < 9; ++tr) wq[tr] = W[hq * 9 + tr];
@@ -657,8 +698,26 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
         if (cq) edge(base, tp, cq, r, (u64)0 - (u64)w);
         if (mq) edge(base, tp, Lq, r, (u64)w);
       }
-    }
-    bar<LCAP == 0>();
+      return q;
+    };
+    // one edge q -> y of N+(q) with q in R'
+    auto visit = [&](int32_t q, uint32_t f) {
+      const int32_t y = (int32_t)(f & kIdMask);
+      if (y == c) return;
+      const uint32_t Ly = lab.get((uint32_t)y);
+      const bool sy = is_side(y);
+      if (!Ly && !sy) return;
+      const uint32_t Lq = lab.get((uint32_t)q);
+      const bool mq = !is_side(q), my = !sy;
+      const uint32_t r = f >> kTypeShift, cq = Lq & 3u, cy = Ly & 3u;
+      if (cq && cy) edge(base, cq, cy, r, kMinusOne);
+      if (mq && my) edge(base, Lq, Ly, r, 1ull);
+      if (cq && (sy || (Ly >> 2))) {  // p = q is also counted in W[y]
+        if (cy) edge(base, cq, cy, r, 1ull);
+        if (my) edge(base, cq, Ly, r, kMinusOne);
+      }
+    };
+    flat_rows(nsides + d0 + d1, pick, visit);
     // edges inside N(core) with core-only labels
     if (threadIdx.x < 27) {
       const uint32_t w = Mc[threadIdx.x];
@@ -673,24 +732,23 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       int32_t v = ncore[a];
       for (int L = 4; L < NL; ++L)
         if ((L & 3) == a) v -= cnt[L];
-      uint32_t t0 = 0, t1 = 0;
       // the type of each side towards the core sits in its own label
-      t0 = lab.get((uint32_t)s0) & 3u;
-      if (K == 5) t1 = lab.get((uint32_t)s1) & 3u;
+      const uint32_t t0 = lab.get((uint32_t)s0) & 3u;
+      const uint32_t t1 = K == 5 ? lab.get((uint32_t)s1) & 3u : 0u;
       v -= (t0 == (uint32_t)a) + (K == 5 && t1 == (uint32_t)a);
       cnt[a] = v;
     }
-    bar<LCAP == 0>();
+    bar<GL>();
     closed_form<K, NL, BLOCK>(hist, lut, cnt, nzl, &nz_count, base);
-    bar<LCAP == 0>();
+    bar<GL>();
     if (threadIdx.x < NL) cnt[threadIdx.x] = 0;
   };
 
   for (;;) {
     if (threadIdx.x == 0) sh_j0 = atomicAdd(queue, tile);
-    bar<LCAP == 0>();
+    bar<GL>();
     const int32_t j0 = sh_j0;
-    bar<LCAP == 0>();
+    bar<GL>();
     if (j0 >= total) break;
     const int32_t j1 = min(total, j0 + tile);
     row = find_row(G.gs_off, 0, n, j0);
@@ -714,7 +772,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
         if (g != cur_g) {
           hist_flush<C, BLOCK>(hist, acc, cur_g);
           cur_g = g;
-          bar<LCAP == 0>();
+          bar<GL>();
         }
         wbase = G.voff ? G.voff[g] : 0;
         core = c;
@@ -727,7 +785,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
         const uint32_t e = G.gs_idx[i];
         if ((int32_t)(e & kIdMask) != c) lab.set_bits(e & kIdMask, (e >> kTypeShift) << 2);
       }
-      bar<LCAP == 0>();
+      bar<GL>();
       if (K == 4) {
         const uint32_t base = ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u);
         anchor(c, x, -1, base);
@@ -746,22 +804,22 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
             const uint32_t e = G.gs_idx[i];
             if ((int32_t)(e & kIdMask) != c) lab.set_bits(e & kIdMask, (e >> kTypeShift) << 4);
           }
-          bar<LCAP == 0>();
+          bar<GL>();
           anchor(c, x, c2, base);
           for (int32_t i = ca2 + threadIdx.x; i < cb2; i += BLOCK) {
             const uint32_t e = G.gs_idx[i];
             if ((int32_t)(e & kIdMask) != c) lab.clear_bits(e & kIdMask, 3u << 4);
           }
-          bar<LCAP == 0>();
+          bar<GL>();
         }
         // skipped triples read x's labels without a barrier (see k5_kernel)
-        bar<LCAP == 0>();
+        bar<GL>();
       }
       for (int32_t i = xa + threadIdx.x; i < xb; i += BLOCK) {
         const uint32_t e = G.gs_idx[i];
         if ((int32_t)(e & kIdMask) != c) lab.clear_bits(e & kIdMask, 3u << 2);
       }
-      bar<LCAP == 0>();
+      bar<GL>();
     }
   }
   if (core >= 0) core_teardown(core);
