@@ -34,7 +34,7 @@ int32_t g_init_err = 0;
 Tuning g_tuning[6] = {
     {256, 4, 16, 1}, {256, 4, 16, 1}, {256, 4, 16, 1},
     {256, 4, 16, 1},    // k = 3: tile*16 vertices per tile
-    {1024, 1, 256, 1},  // k = 4: core reuse
+    {1024, 1, 16, 1},   // k = 4: core reuse (tile = cost tiles per workgroup)
     {1024, 1, 1, 1},    // k = 5: core reuse
 };
 
@@ -398,7 +398,7 @@ int32_t motif_autotune(const motif_graph_t* graphs, int32_t count, int32_t k, ui
   } else if (k == 4) {
     for (int block : {512, 1024})
       for (int gpc : {1, 2, 4})
-        for (int tile : {64, 256, 1024}) cands.push_back({block, gpc, tile, 0});
+        for (int tile : {8, 16, 32}) cands.push_back({block, gpc, tile, 0});
   } else {
     for (int block : {512, 1024})
       for (int tile : {1, 2, 4}) cands.push_back({block, 1, tile, 0});

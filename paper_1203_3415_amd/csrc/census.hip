@@ -67,6 +67,28 @@ __device__ __forceinline__ uint32_t flip(uint32_t t) { return ((t & 1u) << 1) | 
 constexpr int num_classes(int k) { return k == 3 ? 13 : k == 4 ? 199 : 9364; }
 
 constexpr int kMaxHubs = 512;  // rows of the per-core W table in LDS
+constexpr int kMaxBig = 16;          // cores whose W / M tables are built once per call
+constexpr int kBigMinDeg = 256;      // ... among vertices of at least this degree
+constexpr int64_t kBigBytes = 256ll << 20;  // ... within this many bytes of tables
+constexpr int kBigRow = 12;          // words per W row of a big core (9 used, 16-byte aligned)
+constexpr int kUnroll = 4;         // N+ entries per lane and pass of the flattened scans
+constexpr int kLightDeg = 256;  // k = 4 anchors whose side has at most this degree run on one wave
+constexpr int kWaveHashBits = 9;
+constexpr int kWaveHash = 1 << kWaveHashBits;  // slots of the wave-private hash of N(side): load <= 1/2
+constexpr uint32_t kEmptySlot = ~0u;
+
+__device__ __forceinline__ uint32_t hash_slot(int32_t y) {
+  return ((uint32_t)y * 2654435761u) >> (32 - kWaveHashBits);  // Fibonacci hashing
+}
+
+// Ordering point for LDS traffic inside one wave: LDS operations of a wave
+// complete in issue order, so only the compiler has to be kept from moving
+// accesses across it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 using u64 = unsigned long long;
 constexpr u64 kMinusOne = ~0ull;
@@ -519,7 +541,11 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                                                    uint64_t* __restrict__ acc, const int32_t* st,
                                                    int32_t* __restrict__ queue, uint32_t* __restrict__ glabels,
                                                    int64_t label_words, const int32_t* __restrict__ hub_id,
-                                                   uint32_t* __restrict__ wg, int64_t w_stride, int32_t tile) {
+                                                   uint32_t* __restrict__ wg, int64_t w_stride, int32_t tile,
+                                                   const int32_t* __restrict__ cpre,
+                                                   const int32_t* __restrict__ big_id,
+                                                   const uint32_t* __restrict__ wbig, int64_t wbig_stride,
+                                                   const uint32_t* __restrict__ mbig) {
   constexpr int C = K == 4 ? 199 : 9364, NL = K == 4 ? 16 : 64, LB = K == 4 ? 4 : 8;
   constexpr int S1 = K - 2, S2 = K - 1;  // member slots
   // LDS rows of W: fewer where the k = 5 counters and labels leave no room
@@ -531,9 +557,13 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   __shared__ uint32_t Mc[27];
   __shared__ uint32_t W[HUBS * 9];
   __shared__ int32_t ncore[4];
-  __shared__ int32_t sh_j0;
+  __shared__ int32_t sh_j0, sh_j1;
   __shared__ u64 seg_ctr[2];  // (rows << 32) | entries of the chunk being laid out
-  __shared__ int32_t seg_v[BLOCK], seg_start[BLOCK];
+  __shared__ int32_t seg_v[BLOCK], seg_start[BLOCK], seg_base[BLOCK];
+  constexpr int NW = BLOCK / 64, WAVE_LDS = K == 4 ? NW : 1;
+  __shared__ uint32_t wh[WAVE_LDS * kWaveHash];  // k = 4 light anchors: per-wave hash of N(side)
+  __shared__ int32_t wcnt[WAVE_LDS * NL];        // per-wave set sizes
+  __shared__ int32_t unit_list[K == 4 ? BLOCK : 1], unit_ctr[3];
   __shared__ uint32_t lds_labels[LCAP > 0 ? LCAP / 4 : 1];
   if (st[kStatus] != 0) return;
   Labels<LB, GL> lab{LCAP > 0 ? lds_labels : glabels + (int64_t)blockIdx.x * label_words};
@@ -547,6 +577,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   if (threadIdx.x < 4) ncore[threadIdx.x] = 0;
   if (threadIdx.x < 2) seg_ctr[threadIdx.x] = 0;
   for (int i = threadIdx.x; i < HUBS * 9; i += BLOCK) W[i] = 0u;
+  for (int i = threadIdx.x; i < WAVE_LDS * kWaveHash; i += BLOCK) wh[i] = kEmptySlot;
+  for (int i = threadIdx.x; i < WAVE_LDS * NL; i += BLOCK) wcnt[i] = 0;
   if (LCAP > 0)
     for (int i = threadIdx.x; i < LCAP / 4; i += BLOCK) lds_labels[i] = 0u;
   __syncthreads();
@@ -554,11 +586,32 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   const int32_t n = G.n;
   const int32_t total = G.gs_off[n];
   int32_t cur_g = -1, row = 0, core = -1, par = 0;
+  int32_t cbig = -1;  // slot of the current core among the precomputed big cores, or -1
   int64_t wbase = 0;  // first vertex of the core's graph
   auto wrow = [&](int32_t q) { return WG + (int64_t)(q - wbase) * 16; };
   auto hub = [&](int32_t q) {
     const int32_t h = hub_id[q];
     return h < HUBS ? h : -1;
+  };
+  // W row of q for the current core: precomputed table of a big core, LDS
+  // row of a hub, or the workgroup's global row
+  struct Row9 {
+    uint32_t v[9];
+  };
+  auto load_w = [&](int32_t q) {
+    Row9 w;
+    const int32_t hq = cbig >= 0 ? -1 : hub(q);
+    if (hq >= 0) {
+#pragma unroll
+      for (int tr = 0; tr < 9; ++tr) w.v[tr] = W[hq * 9 + tr];
+    } else {
+      const uint4* w4 = reinterpret_cast<const uint4*>(
+          cbig >= 0 ? wbig + cbig * wbig_stride + (int64_t)(q - wbase) * kBigRow : wrow(q));
+      const uint4 x0 = w4[0], x1 = w4[1], x2 = w4[2];
+      w.v[0] = x0.x; w.v[1] = x0.y; w.v[2] = x0.z; w.v[3] = x0.w;
+      w.v[4] = x1.x; w.v[5] = x1.y; w.v[6] = x1.z; w.v[7] = x1.w; w.v[8] = x2.x;
+    }
+    return w;
   };
   // contribution of one edge between slots S1 (x) and S2 (y) of weight w
   auto edge = [&](uint32_t base, uint32_t Lx, uint32_t Ly, uint32_t r, u64 w) {
@@ -583,6 +636,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
             const int32_t sl = (int32_t)(old >> 32);
             seg_v[sl] = v;
             seg_start[sl] = (int32_t)(uint32_t)old;
+            seg_base[sl] = G.np_off[v] - (int32_t)(uint32_t)old;  // entry j of the layout is np_idx[seg_base + j]
           }
         }
       }
@@ -591,14 +645,27 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       const int32_t nseg = (int32_t)(ctr >> 32), tot = (int32_t)(uint32_t)ctr;
       if (threadIdx.x == 0) seg_ctr[par ^ 1] = 0;
       int32_t sl = 0;
-      for (int32_t j = threadIdx.x; j < tot; j += BLOCK) {
-        int32_t hi = nseg - 1;  // last row starting at or before j (starts increase with sl)
-        while (sl < hi) {
-          const int32_t mid = (sl + hi + 1) >> 1;
-          if (seg_start[mid] <= j) sl = mid; else hi = mid - 1;
+      // kUnroll entries per thread and pass, their loads issued together
+      for (int32_t jb = threadIdx.x; jb < tot; jb += kUnroll * BLOCK) {
+        int32_t vv[kUnroll];
+        uint32_t ff[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int32_t j = jb + u * BLOCK;
+          vv[u] = -1;
+          if (j < tot) {
+            int32_t hi = nseg - 1;  // last row starting at or before j (starts increase with sl)
+            while (sl < hi) {
+              const int32_t mid = (sl + hi + 1) >> 1;
+              if (seg_start[mid] <= j) sl = mid; else hi = mid - 1;
+            }
+            vv[u] = seg_v[sl];
+            ff[u] = G.np_idx[seg_base[sl] + j];
+          }
         }
-        const int32_t v = seg_v[sl];
-        visit(v, G.np_idx[G.np_off[v] + (j - seg_start[sl])]);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          if (vv[u] >= 0) visit(vv[u], ff[u]);
       }
       bar<GL>();
       par ^= 1;
@@ -607,10 +674,16 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   // per-core set-up (labels of N(core), type counts, M, W) and tear-down
   auto core_setup = [&](int32_t c) {
     const int32_t ca = G.gs_off[c], dcn = G.gs_off[c + 1] - ca;
+    cbig = big_id ? big_id[c] : -1;
     for (int32_t i = threadIdx.x; i < dcn; i += BLOCK) {
       const uint32_t e = G.gs_idx[ca + i];
       lab.set_bits(e & kIdMask, e >> kTypeShift);
       atomicAdd(&ncore[e >> kTypeShift], 1);
+    }
+    if (cbig >= 0) {  // W and M were built once for this core (k_core_tables)
+      if (threadIdx.x < 27) Mc[threadIdx.x] = mbig[cbig * 32 + threadIdx.x];
+      bar<GL>();
+      return;
     }
     bar<GL>();
     flat_rows(
@@ -633,6 +706,14 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   auto core_teardown = [&](int32_t c) {
     bar<GL>();
     const int32_t ca = G.gs_off[c], dcn = G.gs_off[c + 1] - ca;
+    if (cbig >= 0) {
+      for (int32_t i = threadIdx.x; i < dcn; i += BLOCK) lab.clear_bits(G.gs_idx[ca + i] & kIdMask, 3u);
+      if (threadIdx.x < 27) Mc[threadIdx.x] = 0;
+      if (threadIdx.x < 4) ncore[threadIdx.x] = 0;
+      bar<GL>();
+      cbig = -1;
+      return;
+    }
     flat_rows(
         dcn,
         [&](int32_t i) {
@@ -679,20 +760,10 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       const uint32_t cq = Lq & 3u;
       if (mq) atomicAdd(&cnt[Lq], 1);
       // edges p -> q (p in N(core), p of lower rank than q): row W[q]
-      uint32_t wq[9];
-      const int32_t hq = hub(q);
-      if (hq >= 0) {
-#pragma unroll
-        for (int tr = 0; tr < 9; ++tr) wq[tr] = W[hq * 9 + tr];
-      } else {
-        const uint4* w4 = reinterpret_cast<const uint4*>(wrow(q));
-        const uint4 x0 = w4[0], x1 = w4[1], x2 = w4[2];
-        wq[0] = x0.x; wq[1] = x0.y; wq[2] = x0.z; wq[3] = x0.w;
-        wq[4] = x1.x; wq[5] = x1.y; wq[6] = x1.z; wq[7] = x1.w; wq[8] = x2.x;
-      }
+      const Row9 wq = load_w(q);
 #pragma unroll
       for (int tr = 0; tr < 9; ++tr) {
-        const uint32_t w = wq[tr];
+        const uint32_t w = wq.v[tr];
         if (!w) continue;
         const uint32_t tp = (uint32_t)(tr / 3) + 1u, r = (uint32_t)(tr % 3) + 1u;
         if (cq) edge(base, tp, cq, r, (u64)0 - (u64)w);
@@ -743,6 +814,251 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     bar<GL>();
     if (threadIdx.x < NL) cnt[threadIdx.x] = 0;
   };
+
+  // Light k = 4 anchor {c, s} (d*(s) <= kLightDeg) on one wave.  The types
+  // of N(s) towards s sit in a wave-private hash table instead of the dense
+  // labels (which then hold only the core's types), so the waves of the
+  // workgroup take different anchors of the same core at the same time with
+  // no workgroup barrier.  Entry i of s's row stands for R' member i, the
+  // entry of c standing for s itself, and R' is taken 64 members at a time:
+  // one lane per member, their N+ rows laid end to end over the wave.  Same
+  // sums as anchor().
+  auto wave_anchor4 = [&](int32_t c, int32_t s, uint32_t base) {
+    const int32_t lane = (int32_t)(threadIdx.x & 63u);
+    uint32_t* H = wh + (threadIdx.x >> 6) * kWaveHash;
+    int32_t* cn = wcnt + (threadIdx.x >> 6) * NL;
+    const int32_t a0 = G.gs_off[s], d0 = G.gs_off[s + 1] - a0;
+    const uint32_t Ls = lab.get((uint32_t)s) & 3u;
+    for (int32_t i = lane; i < d0; i += 64) {
+      const uint32_t e = G.gs_idx[a0 + i];
+      const int32_t q = (int32_t)(e & kIdMask);
+      if (q == c) continue;
+      uint32_t h = hash_slot(q);
+      const uint32_t ent = ((uint32_t)q << 2) | (e >> kTypeShift);  // q < 2^30 - 1: never kEmptySlot
+      while (atomicCAS(&H[h], kEmptySlot, ent) != kEmptySlot) h = (h + 1) & (kWaveHash - 1);
+    }
+    wave_sync();  // hash table complete
+    for (int32_t i0 = 0; i0 < d0; i0 += 64) {
+      const int32_t i = i0 + lane;
+      int32_t q = -1;
+      uint32_t Lq = 0;
+      int32_t len = 0, rb = 0;
+      if (i < d0) {
+        const uint32_t e = G.gs_idx[a0 + i];
+        q = (int32_t)(e & kIdMask);
+        bool mq = true;
+        if (q == c) {
+          q = s;
+          Lq = Ls;
+          mq = false;
+        } else {
+          Lq = (lab.get((uint32_t)q) & 3u) | ((e >> kTypeShift) << 2);
+          atomicAdd(&cn[Lq], 1);
+        }
+        const uint32_t cq = Lq & 3u;
+        const Row9 wq = load_w(q);
+#pragma unroll
+        for (int tr = 0; tr < 9; ++tr) {
+          const uint32_t w = wq.v[tr];
+          if (!w) continue;
+          const uint32_t tp = (uint32_t)(tr / 3) + 1u, r = (uint32_t)(tr % 3) + 1u;
+          if (cq) edge(base, tp, cq, r, (u64)0 - (u64)w);
+          if (mq) edge(base, tp, Lq, r, (u64)w);
+        }
+        rb = G.np_off[q];
+        len = G.np_off[q + 1] - rb;
+      }
+      int32_t inc = len;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int32_t t = __shfl_up(inc, d);
+        if (lane >= d) inc += t;
+      }
+      const int32_t tot = __shfl(inc, 63);
+      const int32_t rs = rb - (inc - len);  // flat entry j of this lane's row is np_idx[rs + j]
+      for (int32_t jb = 0; jb < tot; jb += 64 * kUnroll) {
+        int32_t sqs[kUnroll];
+        uint32_t sLs[kUnroll], fs[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int32_t j = jb + u * 64 + lane;
+          int32_t sl = 0;  // number of lanes whose rows end at or before j
+#pragma unroll
+          for (int st2 = 32; st2; st2 >>= 1)
+            if (__shfl(inc, sl + st2 - 1) <= j) sl += st2;
+          sqs[u] = __shfl(q, sl);
+          sLs[u] = (uint32_t)__shfl((int32_t)Lq, sl);
+          const int32_t srs = __shfl(rs, sl);
+          fs[u] = j < tot ? G.np_idx[srs + j] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int32_t j = jb + u * 64 + lane;
+          if (j >= tot) continue;
+          const int32_t sq = sqs[u];
+          const uint32_t sL = sLs[u], f = fs[u];
+          const int32_t y = (int32_t)(f & kIdMask);
+          if (y != c) {
+            const bool sy = y == s;
+            uint32_t Ly = lab.get((uint32_t)y) & 3u;
+            if (!sy) {
+              uint32_t h = hash_slot(y);
+              for (;;) {
+                const uint32_t e = H[h];
+                if (e == kEmptySlot) break;
+                if ((e >> 2) == (uint32_t)y) {
+                  Ly |= (e & 3u) << 2;
+                  break;
+                }
+                h = (h + 1) & (kWaveHash - 1);
+              }
+            }
+            if (Ly || sy) {
+              const bool mq = sq != s, my = !sy;
+              const uint32_t r = f >> kTypeShift, cq = sL & 3u, cy = Ly & 3u;
+              if (cq && cy) edge(base, cq, cy, r, kMinusOne);
+              if (mq && my) edge(base, sL, Ly, r, 1ull);
+              if (cq && (sy || (Ly >> 2))) {  // p = sq is also counted in W[y]
+                if (cy) edge(base, cq, cy, r, 1ull);
+                if (my) edge(base, cq, Ly, r, kMinusOne);
+              }
+            }
+          }
+        }
+      }
+    }
+    // edges inside N(core) with core-only labels
+    if (lane < 27) {
+      const uint32_t w = Mc[lane];
+      if (w) edge(base, (uint32_t)lane / 9 + 1, ((uint32_t)lane / 3) % 3 + 1, (uint32_t)lane % 3 + 1, (u64)w);
+    }
+    wave_sync();
+    // sizes of the core-only sets: N(core) minus s minus R'
+    if (lane >= 1 && lane <= 3) {
+      int32_t v = ncore[lane];
+      for (int L = 4; L < NL; ++L)
+        if ((L & 3) == lane) v -= cn[L];
+      v -= (int32_t)(Ls == (uint32_t)lane);
+      cn[lane] = v;
+    }
+    wave_sync();
+    for (int32_t pq = lane; pq < NL * NL; pq += 64) {
+      const int32_t La = pq / NL, Lb = pq % NL;
+      if (La == 0 || La > Lb) continue;
+      const u64 na = (u64)cn[La], nb = (u64)cn[Lb];
+      const u64 w = La == Lb ? na * (na - (na > 0)) / 2 : na * nb;
+      if (w) atomicAdd(&hist[lut[base | slot_code<K, K - 2>((uint32_t)La) | slot_code<K, K - 1>((uint32_t)Lb)]], w);
+    }
+    wave_sync();
+    if (lane < NL) cn[lane] = 0;
+    for (int32_t i = lane; i < kWaveHash; i += 64) H[i] = kEmptySlot;
+    wave_sync();
+  };
+  // A unit of a new core: flush the histogram on a graph change and set up
+  // the core's tables (the previous core's are torn down first).
+  auto enter_core = [&](int32_t c) {
+    if (c == core) return;
+    if (core >= 0) core_teardown(core);
+    const int32_t g = G.gid ? G.gid[c] : 0;
+    if (g != cur_g) {
+      hist_flush<C, BLOCK>(hist, acc, cur_g);
+      cur_g = g;
+      bar<GL>();
+    }
+    wbase = G.voff ? G.voff[g] : 0;
+    core = c;
+    core_setup(c);
+  };
+
+  if constexpr (K == 4) {
+    // Tiles of G* entries cut by estimated cost: cpre is the exclusive prefix
+    // sum of a per-entry cost (k_unit_cost4), and a tile is the run of
+    // entries whose prefix falls in one cost interval of the queue, about
+    // `tile` tiles per workgroup.  Within a tile, the entries of one core
+    // row are sorted into heavy units (whole workgroup, one after another)
+    // and light units (one wave each).
+    const int32_t tot_cost = cpre[total];
+    const int64_t parts = (int64_t)gridDim.x * (tile > 0 ? tile : 1);
+    const int32_t tc = (int32_t)max((int64_t)1, ((int64_t)tot_cost + parts - 1) / parts);
+    auto first_at = [&](int64_t key) {  // first entry whose cost prefix is >= key
+      int32_t lo = 0, hi = total;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if ((int64_t)cpre[mid] < key) lo = mid + 1; else hi = mid;
+      }
+      return lo;
+    };
+    for (;;) {
+      if (threadIdx.x == 0) {
+        const int32_t c0 = atomicAdd(queue, tc);
+        sh_j0 = c0 >= tot_cost ? -1 : first_at(c0);
+        sh_j1 = c0 >= tot_cost ? -1 : first_at((int64_t)c0 + tc);
+      }
+      bar<GL>();
+      const int32_t j0 = sh_j0, j1 = sh_j1;
+      bar<GL>();
+      if (j0 < 0) break;
+      if (j0 >= j1) continue;
+      row = find_row(G.gs_off, 0, n, j0);
+      for (int32_t js = j0; js < j1;) {
+        while (G.gs_off[row + 1] <= js) ++row;
+        const int32_t c = row;
+        const int32_t rowa = G.gs_off[c], rowb = G.gs_off[c + 1];
+        const int32_t je = min(min(j1, rowb), js + BLOCK);
+        if (threadIdx.x < 3) unit_ctr[threadIdx.x] = 0;
+        bar<GL>();
+        {
+          const int32_t j = js + (int32_t)threadIdx.x;
+          if (j < je) {
+            const int32_t x = (int32_t)(G.gs_idx[j] & kIdMask);
+            const int32_t dc = rowb - rowa, dx = G.gs_off[x + 1] - G.gs_off[x];
+            if (dx < dc || (dx == dc && x < c)) {  // anchor edge {c, x} owned by its higher-rank end
+              if (dx > kLightDeg) unit_list[atomicAdd(&unit_ctr[0], 1)] = j;
+              else unit_list[BLOCK - 1 - atomicAdd(&unit_ctr[1], 1)] = j;
+            }
+          }
+        }
+        bar<GL>();
+        const int32_t nheavy = unit_ctr[0], nlight = unit_ctr[1];
+        if (nheavy + nlight > 0) {
+          enter_core(c);
+          for (int32_t u = 0; u < nheavy; ++u) {
+            const int32_t j = unit_list[u];
+            const uint32_t ej = G.gs_idx[j];
+            const int32_t x = (int32_t)(ej & kIdMask);
+            const uint32_t tcx = ej >> kTypeShift;
+            const int32_t xa = G.gs_off[x], xb = G.gs_off[x + 1];
+            for (int32_t i = xa + threadIdx.x; i < xb; i += BLOCK) {
+              const uint32_t e = G.gs_idx[i];
+              if ((int32_t)(e & kIdMask) != c) lab.set_bits(e & kIdMask, (e >> kTypeShift) << 2);
+            }
+            bar<GL>();
+            anchor(c, x, -1, ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u));
+            for (int32_t i = xa + threadIdx.x; i < xb; i += BLOCK) {
+              const uint32_t e = G.gs_idx[i];
+              if ((int32_t)(e & kIdMask) != c) lab.clear_bits(e & kIdMask, 3u << 2);
+            }
+            bar<GL>();
+          }
+          for (;;) {  // light units are handed to the waves one at a time
+            int32_t u = 0;
+            if ((threadIdx.x & 63u) == 0) u = atomicAdd(&unit_ctr[2], 1);
+            u = __shfl(u, 0);
+            if (u >= nlight) break;
+            const uint32_t ej = G.gs_idx[unit_list[BLOCK - 1 - u]];
+            const uint32_t tcx = ej >> kTypeShift;
+            wave_anchor4(c, (int32_t)(ej & kIdMask),
+                         ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u));
+          }
+          bar<GL>();
+        }
+        js = je;
+      }
+    }
+    if (core >= 0) core_teardown(core);
+    hist_flush<C, BLOCK>(hist, acc, cur_g);
+    return;
+  }
 
   for (;;) {
     if (threadIdx.x == 0) sh_j0 = atomicAdd(queue, tile);
@@ -826,6 +1142,26 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   hist_flush<C, BLOCK>(hist, acc, cur_g);
 }
 
+// Per-entry cost estimate of the k = 4 core-reuse kernel, for cutting its
+// work queue into tiles of similar cost: 1 for an entry that is not a unit,
+// else a fixed part (larger for a heavy unit, which takes the whole
+// workgroup) plus a quarter of the side's degree.  Clamped to cmax so that
+// the prefix sum stays below 2^30; any positive costs give a correct tiling.
+__global__ void k_unit_cost4(DevGraph G, int32_t cmax, int32_t* cost, const int32_t* st) {
+  if (st[kStatus] != 0) return;
+  const int32_t total = G.gs_off[G.n];
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < G.gs_cap; j += (int64_t)gridDim.x * blockDim.x) {
+    int32_t c = 0;
+    if (j < total) {
+      const int32_t r = G.gs_row[j], x = (int32_t)(G.gs_idx[j] & kIdMask);
+      const int32_t dr = G.gs_off[r + 1] - G.gs_off[r], dx = G.gs_off[x + 1] - G.gs_off[x];
+      c = 1;
+      if (dx < dr || (dx == dr && x < r)) c = min(cmax, (dx > kLightDeg ? 40 : 4) + (dx >> 2));
+    }
+    cost[j] = c;
+  }
+}
+
 // Hub slots for the core-reuse scheme: the vertices of largest degree get one
 // of kMaxHubs rows of the per-core W table; the threshold is the smallest
 // power of two whose degree bucket and all above hold at most kMaxHubs
@@ -840,17 +1176,26 @@ __global__ void k_degree_buckets(const int32_t* gs_off, int32_t n, int32_t* hs, 
   }
 }
 
-__global__ void k_hub_threshold(int32_t* hs, const int32_t* st) {
+//
+// The same buckets choose the big cores (at most nbig, degree >= kBigMinDeg):
+// hs[34] = their threshold, hs[35] = their slot counter.
+__global__ void k_hub_threshold(int32_t* hs, int32_t nbig, const int32_t* st) {
   if (st[kStatus] != 0 || threadIdx.x != 0) return;
-  int32_t cum = 0, b = 31;
+  int32_t cum = 0, b = 30;
   while (b > 5 && cum + hs[b] <= kMaxHubs) cum += hs[b--];
   hs[32] = 1 << (b + 1);
   hs[33] = 0;
+  cum = 0;
+  b = 30;
+  while ((1 << b) >= kBigMinDeg && cum + hs[b] <= nbig) cum += hs[b--];
+  hs[34] = b == 30 ? 0x7fffffff : 1 << (b + 1);
+  hs[35] = 0;
 }
 
-__global__ void k_assign_hubs(const int32_t* gs_off, int32_t n, int32_t* hs, int32_t* hub_id, const int32_t* st) {
+__global__ void k_assign_hubs(const int32_t* gs_off, int32_t n, int32_t* hs, int32_t* hub_id, int32_t nbig,
+                              int32_t* big_id, int32_t* big_list, const int32_t* st) {
   if (st[kStatus] != 0) return;
-  const int32_t t = hs[32];
+  const int32_t t = hs[32], tb = hs[34];
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const int32_t d = gs_off[v + 1] - gs_off[v];
     int32_t h = -1;
@@ -859,7 +1204,66 @@ __global__ void k_assign_hubs(const int32_t* gs_off, int32_t n, int32_t* hs, int
       if (h >= kMaxHubs) h = -1;
     }
     hub_id[v] = h;
+    if (big_id) {
+      int32_t b = -1;
+      if (d >= tb) {
+        b = atomicAdd(&hs[35], 1);
+        if (b >= nbig) b = -1;
+        else big_list[b] = (int32_t)v;
+      }
+      big_id[v] = b;
+    }
   }
+}
+
+// Types of the neighbours of each big core, 2 bits per vertex of its graph.
+__global__ void k_big_labels(DevGraph G, const int32_t* hs, const int32_t* big_list, uint32_t* lbig, int64_t lstride,
+                             const int32_t* st) {
+  if (st[kStatus] != 0 || (int32_t)blockIdx.y >= min(hs[35], kMaxBig)) return;
+  const int32_t c = big_list[blockIdx.y];
+  const int64_t wbase = G.voff ? G.voff[G.gid[c]] : 0;
+  uint32_t* L = lbig + blockIdx.y * lstride;
+  for (int32_t i = G.gs_off[c] + blockIdx.x * blockDim.x + threadIdx.x; i < G.gs_off[c + 1];
+       i += gridDim.x * blockDim.x) {
+    const uint32_t e = G.gs_idx[i];
+    const int64_t x = (int64_t)(e & kIdMask) - wbase;
+    atomicOr(&L[x >> 4], (e >> kTypeShift) << (2 * (x & 15)));
+  }
+}
+
+// W rows and M counts of each big core (the per-core set-up of the core-reuse
+// kernel, done once): thread (entry y of the core's row, lane s of 4) takes
+// every fourth entry of N+(y).
+__global__ __launch_bounds__(256) void k_core_tables(DevGraph G, const int32_t* hs, const int32_t* big_list,
+                                                     const uint32_t* lbig, int64_t lstride, uint32_t* wbig,
+                                                     int64_t wstride, uint32_t* mbig, const int32_t* st) {
+  __shared__ uint32_t M[27];
+  if (st[kStatus] != 0 || (int32_t)blockIdx.y >= min(hs[35], kMaxBig)) return;
+  if (threadIdx.x < 27) M[threadIdx.x] = 0;
+  __syncthreads();
+  const int32_t b = blockIdx.y, c = big_list[b];
+  const int64_t wbase = G.voff ? G.voff[G.gid[c]] : 0;
+  const uint32_t* L = lbig + b * lstride;
+  uint32_t* Wb = wbig + b * wstride;
+  const int32_t ca = G.gs_off[c], dc = G.gs_off[c + 1] - ca;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 4 * (int64_t)dc;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t ey = G.gs_idx[ca + (int32_t)(t >> 2)];
+    const int32_t y = (int32_t)(ey & kIdMask);
+    const uint32_t ty = ey >> kTypeShift;
+    for (int32_t p = G.np_off[y] + (int32_t)(t & 3); p < G.np_off[y + 1]; p += 4) {
+      const uint32_t f = G.np_idx[p];
+      const int32_t x = (int32_t)(f & kIdMask);
+      if (x == c) continue;
+      const uint32_t r = f >> kTypeShift;
+      const int64_t xl = (int64_t)x - wbase;
+      atomicAdd(&Wb[xl * kBigRow + (ty - 1) * 3 + (r - 1)], 1u);
+      const uint32_t tx = (L[xl >> 4] >> (2 * (xl & 15))) & 3u;
+      if (tx) atomicAdd(&M[(ty - 1) * 9 + (tx - 1) * 3 + (r - 1)], 1u);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 27 && M[threadIdx.x]) atomicAdd(&mbig[b * 32 + threadIdx.x], M[threadIdx.x]);
 }
 
 // =========================================================== finalise ==
@@ -893,6 +1297,13 @@ int label_cap_k5(int32_t n) {
 }
 int64_t label_words(int k, int32_t n) { return k == 4 ? ((int64_t)n + 7) / 8 : ((int64_t)n + 3) / 4; }
 
+// Number of big-core table slots for graphs of at most maxn vertices.
+int big_slots(int64_t maxn) {
+  const int64_t per = (int64_t)kBigRow * 4 * (maxn > 0 ? maxn : 1);
+  return (int)std::min<int64_t>(kMaxBig, kBigBytes / per);
+}
+int64_t big_label_words(int64_t maxn) { return ((maxn > 0 ? maxn : 1) + 15) / 16; }
+
 int grid_size(int k, int num_cus) {
   const Tuning& t = tuning_for(k);
   return num_cus * t.grid_per_cu;
@@ -906,6 +1317,15 @@ size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int nu
   if ((k == 4 || k == 5) && tuning_for(k).heavy == 1)
     b += al(sizeof(int32_t) * (N + 1)) + al(64 * sizeof(int32_t)) +
          al(sizeof(uint32_t) * 16 * (size_t)(maxn > 0 ? maxn : N) * grid_size(k, num_cus));
+  if (k == 4 && tuning_for(k).heavy == 1) {  // cost prefix of the G* entries and its scan scratch
+    b += al(sizeof(int32_t) * (2 * M + 1)) + al(sizeof(int32_t) * (size_t)scan_scratch(2 * M + 1));
+    const int64_t mn = maxn > 0 ? maxn : N;
+    const int nb = big_slots(mn);
+    if (nb > 0)  // big-core ids, list, labels, W rows, M counts
+      b += al(sizeof(int32_t) * (N + 1)) + al(sizeof(int32_t) * kMaxBig) +
+           al(sizeof(uint32_t) * (size_t)nb * big_label_words(mn)) + al(sizeof(uint32_t) * (size_t)nb * kBigRow * mn) +
+           al(sizeof(uint32_t) * 32 * kMaxBig);
+  }
   b += 2 * al(sizeof(uint64_t) * (size_t)G * num_classes(k));  // accumulators (+ output staging)
   b += al(64 * sizeof(int32_t));                               // queue counters
   const int cap = k == 4 ? label_cap_k4((int32_t)N) : k == 5 ? label_cap_k5((int32_t)N) : 1;
@@ -918,7 +1338,7 @@ size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int nu
                      glabels, lw, t.tile)
 #define LAUNCH_KR(K, BLOCK, CAP)                                                                        \
   hipLaunchKernelGGL((kr_kernel<K, BLOCK, CAP>), dim3(grid), dim3(BLOCK), 0, s, g, T.lut[K], acc, p.status, queue, \
-                     glabels, lw, hub_id, wg, ws, t.tile)
+                     glabels, lw, hub_id, wg, ws, t.tile, cpre, big_id, wbig, wbig_stride, mbig)
 #define LAUNCH_K5(BLOCK, CAP)                                                                                   \
   hipLaunchKernelGGL((k5_kernel<BLOCK, CAP>), dim3(grid), dim3(BLOCK), 0, s, g, T.lut[5], acc, p.status, queue, \
                      glabels, lw, t.tile)
@@ -949,6 +1369,21 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
       int32_t* hub_id = nullptr;
       uint32_t* wg = nullptr;
       int64_t ws = 0;
+      const int64_t maxn = g.max_graph_n > 0 ? g.max_graph_n : g.n;
+      const int nbig = (reuse && k == 4) ? big_slots(maxn) : 0;
+      int32_t *big_id = nullptr, *big_list = nullptr;
+      uint32_t *lbig = nullptr, *wbig = nullptr, *mbig = nullptr;
+      const int64_t lstride = big_label_words(maxn), wbig_stride = (int64_t)kBigRow * maxn;
+      if (nbig > 0) {
+        big_id = p.arena.take<int32_t>(g.n + 1);
+        big_list = p.arena.take<int32_t>(kMaxBig);
+        lbig = p.arena.take<uint32_t>((size_t)nbig * lstride);
+        wbig = p.arena.take<uint32_t>((size_t)nbig * wbig_stride);
+        mbig = p.arena.take<uint32_t>(32 * kMaxBig);
+        enqueue_zero(lbig, sizeof(uint32_t) * (size_t)nbig * lstride, s);
+        enqueue_zero(wbig, sizeof(uint32_t) * (size_t)nbig * wbig_stride, s);
+        enqueue_zero(mbig, sizeof(uint32_t) * 32 * kMaxBig, s);
+      }
       if (reuse) {
         ws = 16 * (int64_t)(g.max_graph_n > 0 ? g.max_graph_n : g.n);
         wg = p.arena.take<uint32_t>((size_t)ws * grid);
@@ -957,9 +1392,23 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
         int32_t* hs = p.arena.take<int32_t>(64);
         enqueue_zero(hs, 64 * sizeof(int32_t), s);
         hipLaunchKernelGGL(k_degree_buckets, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.gs_off, g.n, hs, p.status);
-        hipLaunchKernelGGL(k_hub_threshold, dim3(1), dim3(64), 0, s, hs, p.status);
+        hipLaunchKernelGGL(k_hub_threshold, dim3(1), dim3(64), 0, s, hs, nbig, p.status);
         hipLaunchKernelGGL(k_assign_hubs, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.gs_off, g.n, hs, hub_id,
-                           p.status);
+                           nbig, big_id, big_list, p.status);
+        if (nbig > 0) {
+          hipLaunchKernelGGL(k_big_labels, dim3(16, nbig), dim3(256), 0, s, g, hs, big_list, lbig, lstride, p.status);
+          hipLaunchKernelGGL(k_core_tables, dim3(64, nbig), dim3(256), 0, s, g, hs, big_list, lbig, lstride, wbig,
+                             wbig_stride, mbig, p.status);
+        }
+      }
+      const int32_t* cpre = nullptr;
+      if (reuse && k == 4) {
+        int32_t* cost = p.arena.take<int32_t>((size_t)g.gs_cap);
+        int32_t* scr = p.arena.take<int32_t>((size_t)scan_scratch(g.gs_cap));
+        const int32_t cmax = (int32_t)std::max<int64_t>(2, std::min<int64_t>(1 << 16, (int64_t(1) << 30) / g.gs_cap));
+        hipLaunchKernelGGL(k_unit_cost4, dim3(blocks_for(g.gs_cap, 256)), dim3(256), 0, s, g, cmax, cost, p.status);
+        scan_excl(cost, g.gs_cap, scr, s);
+        cpre = cost;
       }
       if (k == 4 && reuse) {
         if (t.block == 512) {

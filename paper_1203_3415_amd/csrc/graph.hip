@@ -109,6 +109,8 @@ __global__ __launch_bounds__(kB) void k_scan_add(int32_t* data, int64_t len, con
     if (base + i < len) data[base + i] += add;
 }
 
+}  // namespace
+
 // In-place exclusive scan of data[0..len); scratch needs scan_scratch(len) ints.
 void scan_excl(int32_t* data, int64_t len, int32_t* scratch, hipStream_t s) {
   if (len <= 0) return;
@@ -129,6 +131,8 @@ int64_t scan_scratch(int64_t len) {
   }
   return total;
 }
+
+namespace {
 
 unsigned grid_for(int64_t items, int block = kB) {
   int64_t g = (items + block - 1) / block;
@@ -548,6 +552,8 @@ DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s) {
   g.voff = in.voff;
   g.ngraphs = in.ngraphs;
   g.max_graph_n = in.gid ? in.max_graph_n : n;
+  g.gs_row = gs_row;
+  g.gs_cap = 2 * m + 1;
   if (n == 0) return g;
 
   enqueue_zero(in_cnt, sizeof(int32_t) * (n + 1), s);

@@ -40,6 +40,8 @@ struct DevGraph {
   const int64_t* voff = nullptr;    // [ngraphs+1] first vertex of each graph (batch) or null
   int32_t ngraphs = 1;
   int32_t max_graph_n = 0;          // largest vertex count of one graph
+  const int32_t* gs_row = nullptr;  // [2m*] row (vertex) of each G* entry
+  int64_t gs_cap = 0;               // 2m + 1 >= entries of G* + 1
 };
 
 // Device class tables uploaded by motif_init.
@@ -124,6 +126,11 @@ BuildInput enqueue_pack(Pipeline& p, const motif_graph_t* graphs, int32_t count,
 
 // Zero fill helper (a kernel, so it is safe inside captured graphs).
 void enqueue_zero(void* ptr, size_t bytes, hipStream_t s);
+
+// In-place exclusive scan of int32 data[0..len) on the device; `scratch`
+// holds scan_scratch(len) ints.
+void scan_excl(int32_t* data, int64_t len, int32_t* scratch, hipStream_t s);
+int64_t scan_scratch(int64_t len);
 
 // Device setup (class tables) for the current device; returns the device id.
 int32_t ensure_init(int* dev);
