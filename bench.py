@@ -100,6 +100,53 @@ def k4_kernel_bytes(st) -> float:
     return rows + 4.0 * probes + 8.0 * members
 
 
+def _core_side(st):
+    """Per undirected edge: the core (higher rank (d*, id)) and the side."""
+    deg, u, v, n = st["deg"], st["u"], st["v"], st["n"]
+    ru = deg[u].astype(np.int64) * n + u
+    rv = deg[v].astype(np.int64) * n + v
+    return np.where(ru > rv, u, v), np.where(ru > rv, v, u)
+
+
+def kr4_kernel_bytes(st) -> float:
+    """Algorithmic bytes of one launch of the k = 4 core-reuse kernel.
+    Per core c (once): its typed row (4 d_c), the offsets (8 B) and N+ row
+    (4 d+(y)) of every y in N(c), and one 4-byte W update per N+ entry:
+    12 d_c + 8 S+(c).  Per anchor {c, s}: the side's row (4 d_s) and, for
+    each of the d_s members q of R' = {s} u N(s) \ {c}, its offsets and W
+    row (44 B) and its N+ row (4 d+(q)): 48 d_s + 4 (S+(s) - d+(c) + d+(s))."""
+    deg = st["deg"].astype(np.float64)
+    dplus = st["dplus"].astype(np.float64)
+    splus = st["splus"]
+    c, s = _core_side(st)
+    anchor = 48.0 * deg[s] + 4.0 * (splus[s] - dplus[c] + dplus[s])
+    cores = np.unique(c)
+    return float(anchor.sum()) + float((12.0 * deg[cores] + 8.0 * splus[cores]).sum())
+
+
+def kr5_kernel_bytes(st) -> float:
+    """Algorithmic bytes of one launch of the k = 5 core-reuse kernel.  Per
+    centre c (once): 12 d_c + 8 S+(c) as for k = 4.  Per connected triple
+    (x, c, c2): the two side rows, 4 (d_x + d_c2), and per member q of
+    N(x) u N(c2) its offsets and W row (44 B) and N+ row (4 d+(q)); the
+    union is the sum over both rows minus the common neighbours, counted
+    through the co-degrees t(c, q): sum over c != q of C(t, 2) g(q)."""
+    import scipy.sparse as sp
+    n, u, v = st["n"], st["u"], st["v"]
+    deg = st["deg"].astype(np.float64)
+    dplus = st["dplus"].astype(np.float64)
+    A = sp.csr_matrix((np.ones(2 * len(u)), (np.r_[u, v], np.r_[v, u])), shape=(n, n))
+    gq = 44.0 + 4.0 * dplus
+    f = 4.0 * deg + A @ gq
+    pairs = float(((deg - 1.0) * (A @ f)).sum())
+    A2 = (A @ A).tocoo()
+    off = A2.row != A2.col
+    t = A2.data[off]
+    inter = float((t * (t - 1.0) / 2.0 * gq[A2.col[off]]).sum())
+    core = float((12.0 * deg + 8.0 * st["splus"])[deg >= 2].sum())
+    return pairs - inter + core
+
+
 def k3_kernel_bytes(st) -> float:
     """Algorithmic bytes of one k = 3 census kernel launch: each vertex's typed
     row (closed form) and, per oriented edge u->w, the rows N+(u) and N+(w)."""
@@ -157,19 +204,19 @@ def bench_census(args):
 
     dominant = max(ks)
     kms = float(np.mean(kern_ms[dominant]))
-    if dominant == 4:
-        kbytes = k4_kernel_bytes(st)
-    elif dominant == 3:
-        kbytes = k3_kernel_bytes(st)
-    else:
-        kbytes = None
+    kname = kernel_name(dominant, pm.get_tuning(dominant)["heavy"] if dominant > 3 else 0)
+    kbytes = {"k3_kernel": k3_kernel_bytes, "k4_kernel": k4_kernel_bytes, "kr_kernel<4>": kr4_kernel_bytes,
+              "kr_kernel<5>": kr5_kernel_bytes}.get(kname, lambda _: None)(st)
     roofline = None
     if kbytes is not None:
         achieved = kbytes / (kms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": f"k{dominant}_kernel", "kernel_ms": round(kms, 3),
-                    "algorithmic_bytes": kbytes}
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(kname, args.workload),
+                    "kernel": kname, "kernel_ms": round(kms, 3), "algorithmic_bytes": kbytes}
+    if args.calibration_copy_mib > 0:  # a copy of known size for the counter runs
+        a = torch.empty(args.calibration_copy_mib << 18, dtype=torch.float32, device=dev)
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
 
     cpu = None
     if not args.no_cpu:
@@ -199,6 +246,75 @@ def bench_census(args):
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def kernel_name(k: int, scheme: int) -> str:
+    if k == 3:
+        return "k3_kernel"
+    return f"kr_kernel<{k}>" if scheme == 1 else f"k{k}_kernel"
+
+
+TRAFFIC_DIR = os.path.join(ROOT, "profiles")
+CENSUS_SRC = os.path.join(ROOT, "paper_1203_3415_amd", "csrc", "census.hip")
+
+
+def _src_digest() -> str:
+    import hashlib
+    with open(CENSUS_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _traffic_file(kname: str, workload: str) -> str:
+    safe = kname.replace("<", "").replace(">", "")
+    return os.path.join(TRAFFIC_DIR, f"traffic_{safe}_{workload}.json")
+
+
+def stored_traffic(kname: str, workload: str):
+    """HBM bytes per launch from the committed counter runs, or None when
+    there are none or the census kernels changed since they were taken."""
+    path = _traffic_file(kname, workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    return rec["bytes_per_launch"] if rec.get("census_src_sha256") == _src_digest() else None
+
+
+def traffic_from_counters(fetch_csv: str, write_csv: str, kname: str, workload: str, copy_mib: int):
+    """Turn a FETCH_SIZE run and a WRITE_SIZE run (rocprofv3 --pmc, csv) of
+    `bench.py --calibration-copy-mib N` into bytes per launch of the kernel:
+    each counter is scaled by what it reads for the copy of N MiB (which
+    reads and writes exactly N MiB), then averaged over the kernel's
+    dispatches.  Writes the record next to the other profile summaries."""
+    import csv
+    stem = kname.split("<")[0]
+    kk = kname[len(stem):]  # "<4>" or ""
+
+    def load(path, counter):
+        per = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            key = (r["Kernel_Name"], r["Dispatch_Id"])
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"]) * 1024.0  # KiB -> bytes
+        kern = [v for (name, _), v in per.items() if f"{stem}<{kk[1:-1]}," in name] if kk else \
+            [v for (name, _), v in per.items() if f"{stem}<" in name]
+        copies = [v for (name, _), v in per.items() if "copyBuffer" in name or "copy" in name.lower()]
+        return kern, max(copies) if copies else None
+
+    kf, cf = load(fetch_csv, "FETCH_SIZE")
+    kw, cw = load(write_csv, "WRITE_SIZE")
+    ref = float(copy_mib << 20)
+    sf, sw = ref / cf, ref / cw
+    rec = {"kernel": kname, "workload": workload, "dispatches": [len(kf), len(kw)],
+           "fetch_bytes_raw": float(np.mean(kf)), "write_bytes_raw": float(np.mean(kw)),
+           "copy_mib": copy_mib, "fetch_scale": sf, "write_scale": sw,
+           "bytes_per_launch": float(np.mean(kf)) * sf + float(np.mean(kw)) * sw,
+           "census_src_sha256": _src_digest()}
+    os.makedirs(TRAFFIC_DIR, exist_ok=True)
+    with open(_traffic_file(kname, workload), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
 
 
 def describe(name):
@@ -412,7 +528,16 @@ def main():
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--inflight", type=int, default=8)
     ap.add_argument("--hbm-budget", type=int, default=64 << 30)
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="after the timed steps, copy this many MiB on the device (reference for HBM counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU: turn two rocprofv3 --pmc csv files into the stored traffic record")
+    ap.add_argument("--kernel", default="kr_kernel<4>", help="kernel of --traffic-from")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.kernel, args.workload,
+                              args.calibration_copy_mib)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this census runs on one GPU; --gpus must be 1 (multi-GPU sharding is a "
                                    "design note only)"}), flush=True)

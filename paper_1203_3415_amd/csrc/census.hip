@@ -1352,10 +1352,12 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
   enqueue_zero(queue, 64 * sizeof(int32_t), s);
   const Tuning& t = tuning_for(k);
   const int grid = grid_size(k, p.num_cus);
-  profile_mark(k, 1, true, s);
+  bool marked = false;  // the profiling events bracket the main census kernel only
   if (g.n > 0) {
     if (k == 3) {
       const int tv = t.tile > 0 ? t.tile * 16 : 256;
+      profile_mark(k, 1, true, s);
+      marked = true;
       hipLaunchKernelGGL((k3_kernel<256>), dim3(grid), dim3(256), 0, s, g, T.lut[3], acc, p.status, tv);
     } else {
       const bool reuse = t.heavy == 1;
@@ -1410,6 +1412,8 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
         scan_excl(cost, g.gs_cap, scr, s);
         cpre = cost;
       }
+      profile_mark(k, 1, true, s);
+      marked = true;
       if (k == 4 && reuse) {
         if (t.block == 512) {
           if (cap == 8192) LAUNCH_KR(4, 512, 8192); else if (cap == 65536) LAUNCH_KR(4, 512, 65536); else LAUNCH_KR(4, 512, 0);
@@ -1441,6 +1445,7 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
       }
     }
   }
+  if (!marked) profile_mark(k, 1, true, s);
   profile_mark(k, 1, false, s);
   hipLaunchKernelGGL(k_div_check, dim3(blocks_for(total, 256)), dim3(256), 0, s, acc, T.mult[k], C, total, p.status);
   hipLaunchKernelGGL(k_div_write, dim3(blocks_for(total, 256)), dim3(256), 0, s, acc, T.mult[k], C, total, out,
