@@ -148,13 +148,13 @@ def kr5_kernel_bytes(st) -> float:
 
 
 def k3_kernel_bytes(st) -> float:
-    """Algorithmic bytes of one k = 3 census kernel launch: each vertex's typed
-    row (closed form) and, per oriented edge u->w, the rows N+(u) and N+(w)."""
-    deg, dplus = st["deg"], st["dplus"]
-    rows = 4.0 * float(deg.sum())
-    # sum over oriented edges of d+(u) + d+(w) = sum_v d+(v) * (d+(v) + d-(v)) = sum_v d+(v) d*(v)
-    merge = 4.0 * float((dplus.astype(np.float64) * deg).sum())
-    return rows + merge
+    """Algorithmic bytes of one k = 3 census kernel launch: every typed G*
+    entry with its row index (8 B, type counts), and per vertex u its row
+    N+(u) (4 d+(u)) plus, for each w in N+(u), the offsets and row N+(w)
+    (8 + 4 d+(w)); w is reached from its d*(w) - d+(w) lower-ranked
+    neighbours."""
+    deg, dplus = st["deg"].astype(np.float64), st["dplus"].astype(np.float64)
+    return float(8.0 * deg.sum() + 4.0 * dplus.sum() + ((deg - dplus) * (8.0 + 4.0 * dplus)).sum())
 
 
 # ------------------------------------------------------------ main bench ---

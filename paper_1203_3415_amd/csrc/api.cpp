@@ -33,7 +33,7 @@ int32_t g_init_err = 0;
 
 Tuning g_tuning[6] = {
     {256, 4, 16, 1}, {256, 4, 16, 1}, {256, 4, 16, 1},
-    {256, 4, 16, 1},    // k = 3: tile*16 vertices per tile
+    {256, 4, 16, 1},    // k = 3: tile*16 vertices per tile (at most 1024)
     {1024, 1, 16, 1},   // k = 4: core reuse (tile = cost tiles per workgroup)
     {1024, 1, 1, 1},    // k = 5: core reuse
 };

@@ -159,19 +159,45 @@ __device__ __forceinline__ int32_t find_row(const int32_t* off, int32_t lo, int3
 // six pair counts n_a n_b, n_a n_c, n_b n_c, C(n_a,2), C(n_b,2), C(n_c,2)
 // (Figure "star").  Edges between two neighbours of v are exactly the
 // triangles at v (Algorithm "alternative"), listed once each as
-// u -> w -> x in rank order: N+(u) ∩ N+(w).  For each corner the pair of the
-// other two corners leaves its open class, and the triangle class gains one
-// occurrence per corner (the division by 3 removes the repetition).
+// u -> w -> x in rank order: x in N+(u) and in N+(w).  For each corner the
+// pair of the other two corners leaves its open class, and the triangle class
+// gains one occurrence per corner (the division by 3 removes the repetition).
+//
+// Work unit = a tile of consecutive vertices (of one graph).  The type counts
+// of the tile's rows are summed by the whole workgroup (one G* entry per
+// thread, so a hub's row is spread over the workgroup), then each vertex's
+// closed form is added.  Triangles: one wave per vertex u of the tile; N+(u)
+// goes into a wave-private LDS hash (vertex -> type), the N+ rows of its
+// members are laid end to end over the lanes and every entry x is looked up.
+// A u with more than kTriHash / 2 higher-ranked neighbours takes the same
+// rows with a binary search of N+(u) instead of the hash.
+constexpr int kTriHashBits = 10;
+constexpr int kTriHash = 1 << kTriHashBits;
+constexpr int kTriTileMax = 1024;  // vertices per k = 3 tile
+
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k3_kernel(DevGraph G, const uint16_t* __restrict__ lut_g,
                                                    uint64_t* __restrict__ acc, const int32_t* st, int32_t tv) {
-  constexpr int K = 3, C = 13;
+  constexpr int K = 3, C = 13, NW = BLOCK / 64;
   __shared__ u64 hist[C];
   __shared__ uint16_t lut[64];
+  __shared__ int32_t tcnt[3 * kTriTileMax];
+  __shared__ uint32_t th[NW * kTriHash];
   if (st[kStatus] != 0) return;
   for (int i = threadIdx.x; i < 64; i += BLOCK) lut[i] = lut_g[i];
   for (int i = threadIdx.x; i < C; i += BLOCK) hist[i] = 0;
+  for (int i = threadIdx.x; i < 3 * kTriTileMax; i += BLOCK) tcnt[i] = 0;
+  for (int i = threadIdx.x; i < NW * kTriHash; i += BLOCK) th[i] = kEmptySlot;
   __syncthreads();
+  const int32_t lane = (int32_t)(threadIdx.x & 63u);
+  uint32_t* H = th + (threadIdx.x >> 6) * kTriHash;
+  auto tri = [&](uint32_t tuw, uint32_t tux, uint32_t twx) {
+    const uint32_t full = slot_code<K, 1>(tuw) | slot_code<K, 2>(tux) | rel_code<K>(twx);
+    atomicAdd(&hist[lut[full]], 3ull);
+    atomicAdd(&hist[lut[slot_code<K, 1>(tuw) | slot_code<K, 2>(tux)]], kMinusOne);
+    atomicAdd(&hist[lut[slot_code<K, 1>(flip(tuw)) | slot_code<K, 2>(twx)]], kMinusOne);
+    atomicAdd(&hist[lut[slot_code<K, 1>(flip(tux)) | slot_code<K, 2>(flip(twx))]], kMinusOne);
+  };
   const int32_t n = G.n;
   const int32_t ntiles = (n + tv - 1) / tv;
   int32_t cur_g = -1;
@@ -195,15 +221,14 @@ __global__ __launch_bounds__(BLOCK) void k3_kernel(DevGraph G, const uint16_t* _
         cur_g = g;
         __syncthreads();
       }
-      // closed form at every vertex of [v0, end)
+      // type counts of the rows of [v0, end), one entry per thread
+      for (int32_t j = G.gs_off[v0] + threadIdx.x; j < G.gs_off[end]; j += BLOCK)
+        atomicAdd(&tcnt[3 * (G.gs_row[j] - v0) + (int32_t)(G.gs_idx[j] >> kTypeShift) - 1], 1);
+      __syncthreads();
       for (int32_t v = v0 + threadIdx.x; v < end; v += BLOCK) {
-        u64 na = 0, nb = 0, nc = 0;
-        for (int32_t j = G.gs_off[v]; j < G.gs_off[v + 1]; ++j) {
-          const uint32_t ty = G.gs_idx[j] >> kTypeShift;
-          na += ty == 3u;
-          nb += ty == 1u;
-          nc += ty == 2u;
-        }
+        int32_t* tc = tcnt + 3 * (v - v0);
+        const u64 nb = (u64)tc[0], nc = (u64)tc[1], na = (u64)tc[2];  // types 1 = B, 2 = C, 3 = A
+        tc[0] = tc[1] = tc[2] = 0;
         const u64 w[6] = {na * nb, na * nc, nb * nc, na * (na - (na > 0)) / 2, nb * (nb - (nb > 0)) / 2,
                           nc * (nc - (nc > 0)) / 2};
         const uint32_t ta[6] = {3, 3, 1, 3, 1, 2};
@@ -212,32 +237,88 @@ __global__ __launch_bounds__(BLOCK) void k3_kernel(DevGraph G, const uint16_t* _
         for (int q = 0; q < 6; ++q)
           if (w[q]) atomicAdd(&hist[lut[slot_code<K, 1>(ta[q]) | slot_code<K, 2>(tb[q])]], w[q]);
       }
-      // triangles through the oriented edges leaving [v0, end)
-      const int32_t j0 = G.np_off[v0], j1 = G.np_off[end];
-      for (int32_t j = j0 + threadIdx.x; j < j1; j += BLOCK) {
-        const int32_t u = find_row(G.np_off, v0, end, j);
-        const uint32_t e = G.np_idx[j];
-        const int32_t w = (int32_t)(e & kIdMask);
-        const uint32_t tuw = e >> kTypeShift;
-        const int32_t ua = G.np_off[u], ub = G.np_off[u + 1];
-        for (int32_t p = G.np_off[w]; p < G.np_off[w + 1]; ++p) {
-          const uint32_t f = G.np_idx[p];
-          const int32_t x = (int32_t)(f & kIdMask);
-          int32_t lo = ua, hi = ub;
-          while (lo < hi) {
-            int32_t mid = (lo + hi) >> 1;
-            if ((int32_t)(G.np_idx[mid] & kIdMask) < x) lo = mid + 1; else hi = mid;
+      // triangles u -> w -> x with u in [v0, end), one wave per u
+      for (int32_t u = v0 + (int32_t)(threadIdx.x >> 6); u < end; u += NW) {
+        const int32_t ua = G.np_off[u], du = G.np_off[u + 1] - ua;
+        if (du < 2) continue;
+        const bool hashed = du <= kTriHash / 2;
+        if (hashed) {
+          for (int32_t i = lane; i < du; i += 64) {
+            const uint32_t e = G.np_idx[ua + i];
+            uint32_t h = ((e & kIdMask) * 2654435761u) >> (32 - kTriHashBits);
+            const uint32_t ent = ((e & kIdMask) << 2) | (e >> kTypeShift);  // id < 2^30 - 1: never kEmptySlot
+            while (atomicCAS(&H[h], kEmptySlot, ent) != kEmptySlot) h = (h + 1) & (kTriHash - 1);
           }
-          if (lo < ub && (int32_t)(G.np_idx[lo] & kIdMask) == x) {
-            const uint32_t tux = G.np_idx[lo] >> kTypeShift, twx = f >> kTypeShift;
-            const uint32_t full = slot_code<K, 1>(tuw) | slot_code<K, 2>(tux) | rel_code<K>(twx);
-            atomicAdd(&hist[lut[full]], 3ull);
-            atomicAdd(&hist[lut[slot_code<K, 1>(tuw) | slot_code<K, 2>(tux)]], kMinusOne);
-            atomicAdd(&hist[lut[slot_code<K, 1>(flip(tuw)) | slot_code<K, 2>(twx)]], kMinusOne);
-            atomicAdd(&hist[lut[slot_code<K, 1>(flip(tux)) | slot_code<K, 2>(flip(twx))]], kMinusOne);
+          wave_sync();
+        }
+        for (int32_t i0 = 0; i0 < du; i0 += 64) {
+          // lanes take members w of N+(u); their rows are laid end to end
+          const int32_t i = i0 + lane;
+          int32_t len = 0, rb = 0;
+          uint32_t tuw = 0;
+          if (i < du) {
+            const uint32_t e = G.np_idx[ua + i];
+            const int32_t w = (int32_t)(e & kIdMask);
+            tuw = e >> kTypeShift;
+            rb = G.np_off[w];
+            len = G.np_off[w + 1] - rb;
+          }
+          int32_t inc = len;
+#pragma unroll
+          for (int d = 1; d < 64; d <<= 1) {
+            const int32_t tt = __shfl_up(inc, d);
+            if (lane >= d) inc += tt;
+          }
+          const int32_t tot = __shfl(inc, 63);
+          const int32_t rs = rb - (inc - len);
+          for (int32_t jb = 0; jb < tot; jb += 64 * kUnroll) {
+            uint32_t fs[kUnroll], ts[kUnroll];
+#pragma unroll
+            for (int uu = 0; uu < kUnroll; ++uu) {
+              const int32_t j = jb + uu * 64 + lane;
+              int32_t sl = 0;
+#pragma unroll
+              for (int st2 = 32; st2; st2 >>= 1)
+                if (__shfl(inc, sl + st2 - 1) <= j) sl += st2;
+              ts[uu] = (uint32_t)__shfl((int32_t)tuw, sl);
+              const int32_t srs = __shfl(rs, sl);
+              fs[uu] = j < tot ? G.np_idx[srs + j] : 0u;
+            }
+#pragma unroll
+            for (int uu = 0; uu < kUnroll; ++uu) {
+              if (jb + uu * 64 + lane >= tot) continue;
+              const uint32_t f = fs[uu], x = f & kIdMask;
+              uint32_t tux = 0;
+              if (hashed) {
+                uint32_t h = (x * 2654435761u) >> (32 - kTriHashBits);
+                for (;;) {
+                  const uint32_t e = H[h];
+                  if (e == kEmptySlot) break;
+                  if ((e >> 2) == x) {
+                    tux = e & 3u;
+                    break;
+                  }
+                  h = (h + 1) & (kTriHash - 1);
+                }
+              } else {
+                int32_t lo = ua, hi = ua + du;
+                while (lo < hi) {
+                  const int32_t mid = (lo + hi) >> 1;
+                  if ((G.np_idx[mid] & kIdMask) < x) lo = mid + 1; else hi = mid;
+                }
+                if (lo < ua + du && (G.np_idx[lo] & kIdMask) == x) tux = G.np_idx[lo] >> kTypeShift;
+              }
+              if (tux) tri(ts[uu], tux, f >> kTypeShift);
+            }
           }
         }
+        if (hashed) {
+          wave_sync();
+          for (int32_t i = lane; i < kTriHash; i += 64) H[i] = kEmptySlot;
+          wave_sync();
+        }
       }
+      __syncthreads();
       v0 = end;
     }
   }
@@ -1169,11 +1250,16 @@ __global__ void k_unit_cost4(DevGraph G, int32_t cmax, int32_t* cost, const int3
 // hs[32] = threshold, hs[33] = slot counter.  Which vertices get slots never
 // changes the result, only where the work goes.
 __global__ void k_degree_buckets(const int32_t* gs_off, int32_t n, int32_t* hs, const int32_t* st) {
+  __shared__ int32_t b[32];
   if (st[kStatus] != 0) return;
+  if (threadIdx.x < 32) b[threadIdx.x] = 0;
+  __syncthreads();
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const int32_t d = gs_off[v + 1] - gs_off[v];
-    if (d > 0) atomicAdd(&hs[31 - __clz(d)], 1);
+    if (d > 0) atomicAdd(&b[31 - __clz(d)], 1);
   }
+  __syncthreads();
+  if (threadIdx.x < 32 && b[threadIdx.x]) atomicAdd(&hs[threadIdx.x], b[threadIdx.x]);
 }
 
 //
@@ -1355,7 +1441,7 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
   bool marked = false;  // the profiling events bracket the main census kernel only
   if (g.n > 0) {
     if (k == 3) {
-      const int tv = t.tile > 0 ? t.tile * 16 : 256;
+      const int tv = std::min(kTriTileMax, t.tile > 0 ? t.tile * 16 : 256);
       profile_mark(k, 1, true, s);
       marked = true;
       hipLaunchKernelGGL((k3_kernel<256>), dim3(grid), dim3(256), 0, s, g, T.lut[3], acc, p.status, tv);
