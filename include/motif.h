@@ -129,6 +129,17 @@ int32_t motif_census(const int32_t* out_off, const int32_t* out_idx, const int32
                      const int32_t* in_idx, int32_t n, int64_t m, int32_t k, uint64_t* hist,
                      void* stream);
 
+/* Census of one graph for several sizes: ks[0..nk) are distinct values of
+ * {3, 4, 5} and hists[i] (device, motif_num_classes(ks[i]) uint64) receives
+ * exactly what motif_census(..., ks[i], hists[i], ...) would write.  The
+ * validation and the G* / N+ build run once and are shared (the paper's
+ * motif profiles use several sizes of one network, Section "Results and
+ * Discussion").  `g` holds device pointers; errors as for motif_census():
+ * on any error no histogram is written, except that a self-check failure
+ * (MOTIF_EINTERNAL) of a later size leaves the earlier sizes written. */
+int32_t motif_census_multi(const motif_graph_t* g, int32_t nk, const int32_t* ks, uint64_t* const* hists,
+                           void* stream);
+
 /* Census of `count` graphs in one fused pass: the graphs are packed into one
  * disjoint union on the device, built once, and censused by one persistent
  * kernel that pulls anchor tiles from a device work queue; each tile's counts

@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     lib_path,
     census,
     census_batch,
+    census_multi,
     census_batch_loop,
     BatchPlan,
     num_classes,

@@ -76,6 +76,7 @@ def lib():
             "motif_strerror": ([I32], ctypes.c_char_p),
             "motif_census": ([P, P, P, P, I32, I64, I32, P, P], I32),
             "motif_census_batch": ([P, I32, I32, P, P], I32),
+            "motif_census_multi": ([P, I32, P, P, P], I32),
             "motif_census_batch_loop": ([P, I32, I32, P, P], I32),
             "motif_get_tuning": ([I32, ctypes.POINTER(_Tuning)], I32),
             "motif_set_tuning": ([I32, ctypes.POINTER(_Tuning)], I32),
@@ -179,6 +180,31 @@ def census(out_off, out_idx, n: int, k: int, in_off=None, in_idx=None, stream=No
     if out is not None:
         return out
     return hist.cpu().numpy().view(np.uint64)
+
+
+def census_multi(out_off, out_idx, n: int, ks, in_off=None, in_idx=None, stream=None, outs=None):
+    """Census of one graph for several sizes ks (distinct values of 3, 4, 5)
+    over one shared G* build.  Returns a list of numpy uint64 [C_k] (or fills
+    `outs`, int64 CUDA tensors of C_k entries each, and returns them)."""
+    torch = _torch()
+    ks = [int(k) for k in ks]
+    if any(k not in NUM_CLASSES for k in ks):
+        raise MotifError(-1, "census_multi")
+    g = _graph_array([(out_off, out_idx, n) + ((in_off, in_idx) if in_off is not None else ())])
+    hists = outs if outs is not None else [torch.empty(NUM_CLASSES[k], dtype=torch.int64, device=out_off.device)
+                                           for k in ks]
+    for h, k in zip(hists, ks):
+        if not (torch.is_tensor(h) and h.is_cuda and h.dtype == torch.int64 and h.is_contiguous()
+                and h.numel() == NUM_CLASSES[k]):
+            raise TypeError("outs must be contiguous int64 CUDA tensors of C_k entries")
+    karr = (ctypes.c_int32 * len(ks))(*ks)
+    parr = (ctypes.c_void_p * len(ks))(*[h.data_ptr() for h in hists])
+    rc = lib().motif_census_multi(ctypes.cast(g, ctypes.c_void_p), len(ks), ctypes.cast(karr, ctypes.c_void_p),
+                                  ctypes.cast(parr, ctypes.c_void_p), _stream_handle(stream))
+    _check(rc, "motif_census_multi")
+    if outs is not None:
+        return outs
+    return [h.cpu().numpy().view(np.uint64) for h in hists]
 
 
 def _graph_array(graphs):

@@ -177,6 +177,24 @@ int32_t run_census_on(Pipeline& p, const BuildInput& in, int32_t k, uint64_t* hi
   return read_status(p, s);
 }
 
+int32_t run_census_multi_on(Pipeline& p, const BuildInput& in, int32_t nk, const int32_t* ks, uint64_t* const* hists,
+                            hipStream_t s) {
+  p.arena.reset();
+  enqueue_zero(p.status, sizeof(int32_t) * kStatusWords, s);
+  for (int32_t i = 0; i < nk; ++i) profile_mark(ks[i], 0, true, s);  // the shared build, seen by every k
+  DevGraph g = enqueue_build(p, in, s);
+  for (int32_t i = 0; i < nk; ++i) profile_mark(ks[i], 0, false, s);
+  int32_t rc = read_status(p, s);
+  if (rc) return rc;
+  const size_t built = p.arena.mark();
+  for (int32_t i = 0; i < nk; ++i) {
+    uint64_t* acc = p.arena.take<uint64_t>((size_t)in.ngraphs * motif_num_classes(ks[i]));
+    enqueue_census(p, g, ks[i], acc, hists[i], s);
+    p.arena.rewind(built);  // the next census reuses this region after these kernels
+  }
+  return read_status(p, s);
+}
+
 int32_t run_census(const BuildInput& in, int32_t k, uint64_t* hist, hipStream_t s) {
   int dev;
   int32_t rc = ensure_init(&dev);
@@ -290,6 +308,43 @@ int32_t motif_census(const int32_t* out_off, const int32_t* out_idx, const int32
   in.n = n;
   in.m = m;
   return run_census(in, k, hist, s);
+}
+
+int32_t motif_census_multi(const motif_graph_t* g, int32_t nk, const int32_t* ks, uint64_t* const* hists,
+                           void* stream) {
+  if (!g || !ks || !hists || nk < 1 || nk > 3) return MOTIF_EINVAL_ARG;
+  bool seen[6] = {};
+  for (int32_t i = 0; i < nk; ++i) {
+    if (motif_num_classes(ks[i]) < 0) return MOTIF_EINVAL_K;
+    if (seen[ks[i]] || !hists[i]) return MOTIF_EINVAL_ARG;
+    seen[ks[i]] = true;
+  }
+  if (!check_shape(g->n, g->m)) return MOTIF_EINVAL_SHAPE;
+  if (!g->out_off || (g->m > 0 && !g->out_idx)) return MOTIF_EINVAL_ARG;
+  if (g->in_off && g->m > 0 && !g->in_idx) return MOTIF_EINVAL_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  int dev;
+  int32_t rc = ensure_init(&dev);
+  if (rc) return rc;
+  if (g->n == 0) {
+    if (g->m != 0) return MOTIF_EINVAL_SHAPE;
+    for (int32_t i = 0; i < nk; ++i) enqueue_zero(hists[i], sizeof(uint64_t) * motif_num_classes(ks[i]), s);
+    return hipStreamSynchronize(s) == hipSuccess ? 0 : MOTIF_EDEVICE;
+  }
+  BuildInput in{};
+  in.out_off = g->out_off;
+  in.out_idx = g->out_idx;
+  in.in_off = g->in_off;
+  in.in_idx = g->in_off ? g->in_idx : nullptr;
+  in.n = g->n;
+  in.m = g->m;
+  size_t bytes = 0;
+  for (int32_t i = 0; i < nk; ++i)
+    bytes = std::max(bytes, pipeline_bytes(in.n, in.m, 1, false, ks[i], device_cus(dev), in.n));
+  Pipeline* p = nullptr;
+  rc = get_pipeline(dev, s, bytes, &p);
+  if (rc) return rc;
+  return run_census_multi_on(*p, in, nk, ks, hists, s);
 }
 
 int32_t motif_census_batch(const motif_graph_t* graphs, int32_t count, int32_t k, uint64_t* hists, void* stream) {

@@ -76,6 +76,9 @@ constexpr int kLightDeg = 256;  // k = 4 anchors whose side has at most this deg
 constexpr int kWaveHashBits = 9;
 constexpr int kWaveHash = 1 << kWaveHashBits;  // slots of the wave-private hash of N(side): load <= 1/2
 constexpr uint32_t kEmptySlot = ~0u;
+constexpr int kSoloDeg = 64;        // k = 4 anchors whose core has at most this degree run alone on one wave
+constexpr int kSoloHashBits = 8;
+constexpr int kSoloHash = 1 << kSoloHashBits;  // keys of the solo hash of N(c) u N(s): load < 1/2
 
 __device__ __forceinline__ uint32_t hash_slot(int32_t y) {
   return ((uint32_t)y * 2654435761u) >> (32 - kWaveHashBits);  // Fibonacci hashing
@@ -1035,17 +1038,115 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     for (int32_t i = lane; i < kWaveHash; i += 64) H[i] = kEmptySlot;
     wave_sync();
   };
+  // Solo k = 4 anchor {c, s} with d*(c) <= kSoloDeg on one wave: the plain
+  // per-anchor method (as in k4_kernel) with the labels of N(c) u N(s) in a
+  // wave-private hash (keys, then complemented label bits, in the wave's
+  // table), so small cores need no workgroup set-up at all.  Members are the
+  // hash entries; each member's N+ row is scanned and every labelled
+  // neighbour is an inner edge; then the closed form over the 15 sets.
+  auto wave_solo4 = [&](int32_t c, int32_t s, uint32_t base) {
+    const int32_t lane = (int32_t)(threadIdx.x & 63u);
+    uint32_t* key = wh + (threadIdx.x >> 6) * kWaveHash;
+    uint32_t* nlab = key + kSoloHash;
+    int32_t* cn = wcnt + (threadIdx.x >> 6) * NL;
+    auto slot = [](uint32_t x) { return (x * 2654435761u) >> (32 - kSoloHashBits); };
+    auto insert = [&](uint32_t x, uint32_t bits) {
+      uint32_t h = slot(x);
+      for (;;) {
+        const uint32_t old = atomicCAS(&key[h], kEmptySlot, x);
+        if (old == kEmptySlot || old == x) {
+          atomicAnd(&nlab[h], ~bits);
+          return;
+        }
+        h = (h + 1) & (kSoloHash - 1);
+      }
+    };
+    const int32_t ca = G.gs_off[c], dc = G.gs_off[c + 1] - ca;  // dc <= kSoloDeg <= 64
+    if (lane < dc) {
+      const uint32_t e = G.gs_idx[ca + lane];
+      if ((int32_t)(e & kIdMask) != s) insert(e & kIdMask, e >> kTypeShift);
+    }
+    wave_sync();
+    const int32_t sa = G.gs_off[s], ds = G.gs_off[s + 1] - sa;  // ds <= dc
+    if (lane < ds) {
+      const uint32_t e = G.gs_idx[sa + lane];
+      if ((int32_t)(e & kIdMask) != c) insert(e & kIdMask, (e >> kTypeShift) << 2);
+    }
+    wave_sync();
+    for (int32_t i0 = 0; i0 < kSoloHash; i0 += 64) {
+      const uint32_t xk = key[i0 + lane];
+      uint32_t Lx = 0;
+      int32_t len = 0, rb = 0;
+      if (xk != kEmptySlot) {
+        Lx = ~nlab[i0 + lane];
+        atomicAdd(&cn[Lx], 1);
+        rb = G.np_off[xk];
+        len = G.np_off[xk + 1] - rb;
+      }
+      int32_t inc = len;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int32_t t = __shfl_up(inc, d);
+        if (lane >= d) inc += t;
+      }
+      const int32_t tot = __shfl(inc, 63);
+      const int32_t rs = rb - (inc - len);
+      for (int32_t jb = 0; jb < tot; jb += 64 * kUnroll) {
+        uint32_t sLs[kUnroll], fs[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int32_t j = jb + u * 64 + lane;
+          int32_t sl = 0;
+#pragma unroll
+          for (int st2 = 32; st2; st2 >>= 1)
+            if (__shfl(inc, sl + st2 - 1) <= j) sl += st2;
+          sLs[u] = (uint32_t)__shfl((int32_t)Lx, sl);
+          const int32_t srs = __shfl(rs, sl);
+          fs[u] = j < tot ? G.np_idx[srs + j] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (jb + u * 64 + lane >= tot) continue;
+          const uint32_t f = fs[u], y = f & kIdMask;
+          uint32_t h = slot(y);
+          for (;;) {
+            const uint32_t kk = key[h];
+            if (kk == kEmptySlot) break;
+            if (kk == y) {
+              edge(base, sLs[u], ~nlab[h], f >> kTypeShift, 1ull);
+              break;
+            }
+            h = (h + 1) & (kSoloHash - 1);
+          }
+        }
+      }
+    }
+    wave_sync();
+    for (int32_t pq = lane; pq < NL * NL; pq += 64) {
+      const int32_t La = pq / NL, Lb = pq % NL;
+      if (La == 0 || La > Lb) continue;
+      const u64 na = (u64)cn[La], nb = (u64)cn[Lb];
+      const u64 w = La == Lb ? na * (na - (na > 0)) / 2 : na * nb;
+      if (w) atomicAdd(&hist[lut[base | slot_code<K, K - 2>((uint32_t)La) | slot_code<K, K - 1>((uint32_t)Lb)]], w);
+    }
+    wave_sync();
+    if (lane < NL) cn[lane] = 0;
+    for (int32_t i = lane; i < kWaveHash; i += 64) key[i] = kEmptySlot;
+    wave_sync();
+  };
   // A unit of a new core: flush the histogram on a graph change and set up
   // the core's tables (the previous core's are torn down first).
+  // The graph is checked even for the current core: the small-core pass of a
+  // tile may have moved the histogram to another graph in between.
   auto enter_core = [&](int32_t c) {
-    if (c == core) return;
-    if (core >= 0) core_teardown(core);
     const int32_t g = G.gid ? G.gid[c] : 0;
     if (g != cur_g) {
       hist_flush<C, BLOCK>(hist, acc, cur_g);
       cur_g = g;
       bar<GL>();
     }
+    if (c == core) return;
+    if (core >= 0) core_teardown(core);
     wbase = G.voff ? G.voff[g] : 0;
     core = c;
     core_setup(c);
@@ -1080,11 +1181,55 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       bar<GL>();
       if (j0 < 0) break;
       if (j0 >= j1) continue;
+      // units of small cores: one wave each, no core set-up, in chunks of
+      // BLOCK entries of one graph
+      for (int32_t jc = j0; jc < j1;) {
+        int32_t jce = min(j1, jc + BLOCK);
+        const int32_t g = G.gid ? G.gid[G.gs_row[jc]] : 0;
+        if (G.gid) jce = min(jce, G.gs_off[(int32_t)G.voff[g + 1]]);
+        if (g != cur_g) {
+          hist_flush<C, BLOCK>(hist, acc, cur_g);
+          cur_g = g;
+        }
+        if (threadIdx.x < 2) unit_ctr[threadIdx.x] = 0;
+        bar<GL>();
+        {
+          const int32_t j = jc + (int32_t)threadIdx.x;
+          if (j < jce) {
+            const int32_t c = G.gs_row[j];
+            const int32_t dc = G.gs_off[c + 1] - G.gs_off[c];
+            if (dc <= kSoloDeg) {
+              const int32_t x = (int32_t)(G.gs_idx[j] & kIdMask), dx = G.gs_off[x + 1] - G.gs_off[x];
+              if (dx < dc || (dx == dc && x < c)) unit_list[atomicAdd(&unit_ctr[0], 1)] = j;
+            }
+          }
+        }
+        bar<GL>();
+        const int32_t nsolo = unit_ctr[0];
+        for (;;) {
+          int32_t u = 0;
+          if ((threadIdx.x & 63u) == 0) u = atomicAdd(&unit_ctr[1], 1);
+          u = __shfl(u, 0);
+          if (u >= nsolo) break;
+          const int32_t j = unit_list[u];
+          const uint32_t ej = G.gs_idx[j];
+          const uint32_t tcx = ej >> kTypeShift;
+          wave_solo4(G.gs_row[j], (int32_t)(ej & kIdMask),
+                     ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u));
+        }
+        bar<GL>();
+        jc = jce;
+      }
+      // units of the other cores, one core row at a time
       row = find_row(G.gs_off, 0, n, j0);
       for (int32_t js = j0; js < j1;) {
         while (G.gs_off[row + 1] <= js) ++row;
         const int32_t c = row;
         const int32_t rowa = G.gs_off[c], rowb = G.gs_off[c + 1];
+        if (rowb - rowa <= kSoloDeg) {  // taken above
+          js = min(j1, rowb);
+          continue;
+        }
         const int32_t je = min(min(j1, rowb), js + BLOCK);
         if (threadIdx.x < 3) unit_ctr[threadIdx.x] = 0;
         bar<GL>();

@@ -57,6 +57,10 @@ struct Arena {
   size_t cap = 0;
   size_t used = 0;
   void reset() { used = 0; }
+  // Regions taken after a mark can be given back once the kernels that use
+  // them are enqueued: later work on the same stream runs after them.
+  size_t mark() const { return used; }
+  void rewind(size_t m) { used = m; }
   // Every region is carved before the kernels that use it are launched, so an
   // undersized arena stops the process before any kernel could write past it.
   template <class T>
@@ -139,6 +143,9 @@ int device_cus(int dev);
 // Validation + build + census on a pipeline whose arena is already sized
 // (host waits for the status word twice).  Used by every entry point.
 int32_t run_census_on(Pipeline& p, const BuildInput& in, int32_t k, uint64_t* hist, hipStream_t s);
+// Same for several k over one build; hists[i] receives the census of ks[i].
+int32_t run_census_multi_on(Pipeline& p, const BuildInput& in, int32_t nk, const int32_t* ks, uint64_t* const* hists,
+                            hipStream_t s);
 int32_t read_status(Pipeline& p, hipStream_t s);
 
 // Optional event timing of the build and of the census kernel (motif_profile_*):

@@ -308,3 +308,23 @@ def test_schemes_agree_on_power_law(pm):
     finally:
         pm.set_tuning(4, **saved)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.gpu
+def test_census_multi_matches_single(pm):
+    """One shared build for k = 3, 4, 5 gives what three separate calls give,
+    in any order of ks; the errors match motif_census."""
+    g = gg.chung_lu(1500, 7000, 2.2, 2.4, 0.15, seed=21)
+    off, idx = pm.to_device(g.out_off, g.out_idx)
+    singles = {k: pm.census(off, idx, g.n, k) for k in (3, 4, 5)}
+    for ks in ((3, 4, 5), (5, 3), (4,)):
+        outs = pm.census_multi(off, idx, g.n, ks)
+        for k, h in zip(ks, outs):
+            assert np.array_equal(h, singles[k]), (ks, k)
+    assert np.array_equal(singles[3], oracle.census(g, 3))
+    bad_off, bad_idx = pm.to_device(np.array([0, 1, 1], np.int32), np.array([0], np.int32))
+    with pytest.raises(pm.MotifError) as e:
+        pm.census_multi(bad_off, bad_idx, 2, (3, 4))
+    assert e.value.name == "ESELFLOOP"
+    with pytest.raises(pm.MotifError):
+        pm.census_multi(off, idx, g.n, (3, 3))
