@@ -383,6 +383,8 @@ def bench_nullmodel(args):
         gen_s = time.perf_counter() - t
         d = [(*pm.to_device(x.out_off, x.out_idx, dev), x.n) for x in graphs]
         out = torch.empty((len(d), 199), dtype=torch.int64, device=dev)
+        print(f"[nullmodel] {mode}: {len(d)} graphs generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
+        tuned = pm.autotune(d, 4) if args.autotune else pm.get_tuning(4)
         for _ in range(args.warmup):
             pm.census_batch(d, 4, out=out)
         timings = {}
@@ -392,6 +394,7 @@ def bench_nullmodel(args):
             pm.census_batch(d, 4, out=out)
         torch.cuda.synchronize()
         timings["fused"] = (time.perf_counter() - t) / args.steps
+        print(f"[nullmodel] {mode}: fused {timings['fused'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
         hb = out.cpu().numpy().view(np.uint64).copy()
         plan = pm.BatchPlan(d, 4)
         plan.run()
@@ -401,6 +404,7 @@ def bench_nullmodel(args):
             plan.run()
         torch.cuda.synchronize()
         timings["graph_replay"] = (time.perf_counter() - t) / args.steps
+        print(f"[nullmodel] {mode}: graph replay {timings['graph_replay'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
         hp = plan.hists().copy()
         plan.close()
         pm.census_batch_loop(d, 4, out=out)
@@ -410,6 +414,7 @@ def bench_nullmodel(args):
             pm.census_batch_loop(d, 4, out=out)
         torch.cuda.synchronize()
         timings["loop"] = (time.perf_counter() - t) / args.steps
+        print(f"[nullmodel] {mode}: loop {timings['loop'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
         hl = out.cpu().numpy().view(np.uint64).copy()
         z = pm.zscores(hb)
         report[mode] = {
@@ -417,6 +422,7 @@ def bench_nullmodel(args):
             "graphs_per_s": {kk: round(len(d) / v, 1) for kk, v in timings.items()},
             "ms": {kk: round(v * 1e3, 2) for kk, v in timings.items()},
             "identical_fused_replay_loop": bool(np.array_equal(hb, hl) and np.array_equal(hb, hp)),
+            "tuning": tuned,
             "finite_z": int(np.isfinite(z).sum()),
         }
         del d, out
@@ -521,6 +527,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--null-graphs", type=int, default=1000)
     ap.add_argument("--switch-per-arc", type=int, default=100, help="arc-switch attempts per arc of each null graph")
+    ap.add_argument("--autotune", action="store_true", help="null model: autotune on each ensemble first")
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--max-outstanding", type=int, default=64)

@@ -195,8 +195,9 @@ int32_t motif_get_tuning(int32_t k, motif_tuning_t* out);
 int32_t motif_set_tuning(int32_t k, const motif_tuning_t* in);
 
 /* Autotuner: times the fused batch census of `graphs` (device pointers, as for
- * motif_census_batch) under a small grid of candidate tunings, keeps the
- * fastest for k (it is then used by every later call) and writes it to *best.
+ * motif_census_batch) under a small grid of candidate tunings -- block,
+ * grid, tile and, for k = 4 and 5, the census scheme -- keeps the fastest
+ * for k (it is then used by every later call) and writes it to *best.
  * `hists` is scratch output (count * C uint64, device).  Every candidate's
  * histograms are checked equal to the first candidate's; a mismatch returns
  * MOTIF_EINTERNAL. */

@@ -34,7 +34,7 @@ int32_t g_init_err = 0;
 Tuning g_tuning[6] = {
     {256, 4, 16, 1}, {256, 4, 16, 1}, {256, 4, 16, 1},
     {256, 4, 16, 1},    // k = 3: tile*16 vertices per tile (at most 1024)
-    {1024, 1, 16, 1},   // k = 4: core reuse (tile = cost tiles per workgroup)
+    {1024, 1, 8, 1},    // k = 4: core reuse (tile = cost tiles per workgroup)
     {1024, 1, 1, 1},    // k = 5: core reuse
 };
 
@@ -450,36 +450,42 @@ int32_t motif_autotune(const motif_graph_t* graphs, int32_t count, int32_t k, ui
   if (k == 3) {
     for (int tile : {4, 16, 64})
       for (int gpc : {2, 4, 8}) cands.push_back({256, gpc, tile, 0});
-  } else if (k == 4) {
+  } else if (k == 4) {  // both schemes: core reuse (1) and per-anchor scan (2)
     for (int block : {512, 1024})
-      for (int gpc : {1, 2, 4})
-        for (int tile : {8, 16, 32}) cands.push_back({block, gpc, tile, 0});
+      for (int gpc : {1, 2})
+        for (int tile : {4, 8, 16}) cands.push_back({block, gpc, tile, 1});
+    for (int block : {256, 512})
+      for (int gpc : {2, 4})
+        for (int tile : {8, 32}) cands.push_back({block, gpc, tile, 2});
   } else {
     for (int block : {512, 1024})
-      for (int tile : {1, 2, 4}) cands.push_back({block, 1, tile, 0});
+      for (int tile : {1, 2, 4}) cands.push_back({block, 1, tile, 1});
+    for (int tile : {1, 4}) cands.push_back({1024, 1, tile, 2});
   }
   const Tuning saved = tuning_for(k);
-  const int32_t scheme = saved.heavy == 1 ? 1 : 2;  // the scheme is kept, as reported by motif_get_tuning
-  for (auto& c : cands) c.heavy = scheme;
   std::vector<uint64_t> ref((size_t)count * C), cur((size_t)count * C);
   double best_ms = 1e300;
-  motif_tuning_t best_t{saved.block, saved.grid_per_cu, saved.tile, scheme};
+  motif_tuning_t best_t{saved.block, saved.grid_per_cu, saved.tile, saved.heavy == 1 ? 1 : 2};
   for (size_t i = 0; i < cands.size(); ++i) {
     Tuning& t = tuning_for(k);
     t.block = cands[i].block;
     t.grid_per_cu = cands[i].grid_per_cu;
     t.tile = cands[i].tile;
+    if (k > 3) t.heavy = cands[i].heavy == 1 ? 1 : 0;
+    auto tw = std::chrono::steady_clock::now();
     int32_t rc = motif_census_batch(graphs, count, k, hists, stream);  // warm-up
     if (rc) { tuning_for(k) = saved; return rc; }
     auto t0 = std::chrono::steady_clock::now();
-    rc = motif_census_batch(graphs, count, k, hists, stream);
+    // a candidate whose warm-up is 4x slower than the best so far is not timed
+    const bool slow = std::chrono::duration<double, std::milli>(t0 - tw).count() > 4.0 * best_ms;
+    if (!slow) rc = motif_census_batch(graphs, count, k, hists, stream);
     auto t1 = std::chrono::steady_clock::now();
     if (rc) { tuning_for(k) = saved; return rc; }
     hipMemcpyAsync(i == 0 ? ref.data() : cur.data(), hists, sizeof(uint64_t) * ref.size(), hipMemcpyDeviceToHost, s);
     hipStreamSynchronize(s);
     if (i > 0 && cur != ref) { tuning_for(k) = saved; return MOTIF_EINTERNAL; }
     const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    if (ms < best_ms) {
+    if (!slow && ms < best_ms) {
       best_ms = ms;
       best_t = cands[i];
     }
@@ -488,6 +494,7 @@ int32_t motif_autotune(const motif_graph_t* graphs, int32_t count, int32_t k, ui
   t.block = best_t.block;
   t.grid_per_cu = best_t.grid_per_cu;
   t.tile = best_t.tile;
+  if (k > 3) t.heavy = best_t.heavy == 1 ? 1 : 0;
   if (best) *best = best_t;
   return 0;
 }

@@ -67,9 +67,9 @@ __device__ __forceinline__ uint32_t flip(uint32_t t) { return ((t & 1u) << 1) | 
 constexpr int num_classes(int k) { return k == 3 ? 13 : k == 4 ? 199 : 9364; }
 
 constexpr int kMaxHubs = 512;  // rows of the per-core W table in LDS
-constexpr int kMaxBig = 16;          // cores whose W / M tables are built once per call
+constexpr int kMaxBig = 64;          // cores whose W / M tables are built once per call
 constexpr int kBigMinDeg = 256;      // ... among vertices of at least this degree
-constexpr int64_t kBigBytes = 256ll << 20;  // ... within this many bytes of tables
+constexpr int64_t kBigBytes = 512ll << 20;  // ... within this many bytes of tables
 constexpr int kBigRow = 12;          // words per W row of a big core (9 used, 16-byte aligned)
 constexpr int kUnroll = 4;         // N+ entries per lane and pass of the flattened scans
 constexpr int kLightDeg = 256;  // k = 4 anchors whose side has at most this degree run on one wave
@@ -1170,11 +1170,18 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       }
       return lo;
     };
+    // The last quarter of the cost is cut four times finer (second counter),
+    // so the tiles still running at the end are small.
+    const int32_t split = tot_cost - tot_cost / 4, tc_end = max(1, tc / 4);
     for (;;) {
       if (threadIdx.x == 0) {
-        const int32_t c0 = atomicAdd(queue, tc);
+        int32_t c0 = atomicAdd(&queue[0], tc), c1 = min(split, c0 + tc);
+        if (c0 >= split) {
+          c0 = split + atomicAdd(&queue[1], tc_end);
+          c1 = min(tot_cost, c0 + tc_end);
+        }
         sh_j0 = c0 >= tot_cost ? -1 : first_at(c0);
-        sh_j1 = c0 >= tot_cost ? -1 : first_at((int64_t)c0 + tc);
+        sh_j1 = c0 >= tot_cost ? -1 : first_at(c1);
       }
       bar<GL>();
       const int32_t j0 = sh_j0, j1 = sh_j1;
