@@ -76,6 +76,9 @@ constexpr int kLightDeg = 256;  // k = 4 anchors whose side has at most this deg
 constexpr int kWaveHashBits = 9;
 constexpr int kWaveHash = 1 << kWaveHashBits;  // slots of the wave-private hash of N(side): load <= 1/2
 constexpr uint32_t kEmptySlot = ~0u;
+constexpr int kWave5HashBits = 7;
+constexpr int kWave5Hash = 1 << kWave5HashBits;  // slots of each k = 5 side hash (<= 64 entries)
+constexpr int kLight5 = 64;         // k = 5 triples whose two sides have at most this degree run on one wave
 constexpr int kSoloDeg = 64;        // k = 4 anchors whose core has at most this degree run alone on one wave
 constexpr int kSoloHashBits = 8;
 constexpr int kSoloHash = 1 << kSoloHashBits;  // keys of the solo hash of N(c) u N(s): load < 1/2
@@ -633,7 +636,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   constexpr int C = K == 4 ? 199 : 9364, NL = K == 4 ? 16 : 64, LB = K == 4 ? 4 : 8;
   constexpr int S1 = K - 2, S2 = K - 1;  // member slots
   // LDS rows of W: fewer where the k = 5 counters and labels leave no room
-  constexpr int HUBS = (K == 5 && LCAP == 65536) ? 256 : kMaxHubs;
+  constexpr int HUBS = (K == 5 && LCAP == 32768) ? 256 : kMaxHubs;
   constexpr bool GL = LCAP == 0;
   __shared__ u64 hist[C];
   __shared__ uint16_t lut_lds[K == 4 ? 4096 : 1];
@@ -644,10 +647,11 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   __shared__ int32_t sh_j0, sh_j1;
   __shared__ u64 seg_ctr[2];  // (rows << 32) | entries of the chunk being laid out
   __shared__ int32_t seg_v[BLOCK], seg_start[BLOCK], seg_base[BLOCK];
-  constexpr int NW = BLOCK / 64, WAVE_LDS = K == 4 ? NW : 1;
-  __shared__ uint32_t wh[WAVE_LDS * kWaveHash];  // k = 4 light anchors: per-wave hash of N(side)
-  __shared__ int32_t wcnt[WAVE_LDS * NL];        // per-wave set sizes
-  __shared__ int32_t unit_list[K == 4 ? BLOCK : 1], unit_ctr[3];
+  constexpr int NW = BLOCK / 64;
+  constexpr int WH = K == 4 ? kWaveHash : 2 * kWave5Hash;  // per-wave hash words
+  __shared__ uint32_t wh[NW * WH];  // light anchors: per-wave hashes of the sides' neighbourhoods
+  __shared__ int32_t wcnt[NW * NL];  // per-wave set sizes
+  __shared__ int32_t unit_list[BLOCK], unit_ctr[3];
   __shared__ uint32_t lds_labels[LCAP > 0 ? LCAP / 4 : 1];
   if (st[kStatus] != 0) return;
   Labels<LB, GL> lab{LCAP > 0 ? lds_labels : glabels + (int64_t)blockIdx.x * label_words};
@@ -661,8 +665,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   if (threadIdx.x < 4) ncore[threadIdx.x] = 0;
   if (threadIdx.x < 2) seg_ctr[threadIdx.x] = 0;
   for (int i = threadIdx.x; i < HUBS * 9; i += BLOCK) W[i] = 0u;
-  for (int i = threadIdx.x; i < WAVE_LDS * kWaveHash; i += BLOCK) wh[i] = kEmptySlot;
-  for (int i = threadIdx.x; i < WAVE_LDS * NL; i += BLOCK) wcnt[i] = 0;
+  for (int i = threadIdx.x; i < NW * WH; i += BLOCK) wh[i] = kEmptySlot;
+  for (int i = threadIdx.x; i < NW * NL; i += BLOCK) wcnt[i] = 0;
   if (LCAP > 0)
     for (int i = threadIdx.x; i < LCAP / 4; i += BLOCK) lds_labels[i] = 0u;
   __syncthreads();
@@ -909,7 +913,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   // sums as anchor().
   auto wave_anchor4 = [&](int32_t c, int32_t s, uint32_t base) {
     const int32_t lane = (int32_t)(threadIdx.x & 63u);
-    uint32_t* H = wh + (threadIdx.x >> 6) * kWaveHash;
+    uint32_t* H = wh + (threadIdx.x >> 6) * WH;
     int32_t* cn = wcnt + (threadIdx.x >> 6) * NL;
     const int32_t a0 = G.gs_off[s], d0 = G.gs_off[s + 1] - a0;
     const uint32_t Ls = lab.get((uint32_t)s) & 3u;
@@ -1035,7 +1039,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     }
     wave_sync();
     if (lane < NL) cn[lane] = 0;
-    for (int32_t i = lane; i < kWaveHash; i += 64) H[i] = kEmptySlot;
+    for (int32_t i = lane; i < WH; i += 64) H[i] = kEmptySlot;
     wave_sync();
   };
   // Solo k = 4 anchor {c, s} with d*(c) <= kSoloDeg on one wave: the plain
@@ -1046,7 +1050,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   // neighbour is an inner edge; then the closed form over the 15 sets.
   auto wave_solo4 = [&](int32_t c, int32_t s, uint32_t base) {
     const int32_t lane = (int32_t)(threadIdx.x & 63u);
-    uint32_t* key = wh + (threadIdx.x >> 6) * kWaveHash;
+    uint32_t* key = wh + (threadIdx.x >> 6) * WH;
     uint32_t* nlab = key + kSoloHash;
     int32_t* cn = wcnt + (threadIdx.x >> 6) * NL;
     auto slot = [](uint32_t x) { return (x * 2654435761u) >> (32 - kSoloHashBits); };
@@ -1131,11 +1135,178 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     }
     wave_sync();
     if (lane < NL) cn[lane] = 0;
-    for (int32_t i = lane; i < kWaveHash; i += 64) key[i] = kEmptySlot;
+    for (int32_t i = lane; i < WH; i += 64) key[i] = kEmptySlot;
     wave_sync();
   };
   // A unit of a new core: flush the histogram on a graph change and set up
   // the core's tables (the previous core's are torn down first).
+  // k = 5: a triple (b = core, a, c) whose sides both have degree <= kLight5
+  // runs on one wave.  The types of N(a) towards a and of N(c) towards c sit
+  // in two wave-private hashes (HA, built once per unit and wave, and HC);
+  // the dense labels give only the types towards the core.  R' = {a, c} u
+  // N(a) u N(c) \ {b} is taken 64 members at a time, their N+ rows laid end
+  // to end over the lanes.  Same sums as anchor().
+  auto h5_slot = [](uint32_t y) { return (y * 2654435761u) >> (32 - kWave5HashBits); };
+  auto h5_insert = [&](uint32_t* T, uint32_t y, uint32_t t) {
+    uint32_t h = h5_slot(y);
+    while (atomicCAS(&T[h], kEmptySlot, (y << 2) | t) != kEmptySlot) h = (h + 1) & (kWave5Hash - 1);
+  };
+  auto h5_type = [&](const uint32_t* T, uint32_t y) -> uint32_t {
+    uint32_t h = h5_slot(y);
+    for (;;) {
+      const uint32_t e = T[h];
+      if (e == kEmptySlot) return 0u;
+      if ((e >> 2) == y) return e & 3u;
+      h = (h + 1) & (kWave5Hash - 1);
+    }
+  };
+  // HA := N(a) \ {b}, types towards a
+  auto wave_side5 = [&](int32_t b, int32_t a) {
+    const int32_t lane = (int32_t)(threadIdx.x & 63u);
+    uint32_t* HA = wh + (threadIdx.x >> 6) * WH;
+    const int32_t aa = G.gs_off[a], da = G.gs_off[a + 1] - aa;  // da <= kLight5 <= 64
+    if (lane < da) {
+      const uint32_t e = G.gs_idx[aa + lane];
+      if ((int32_t)(e & kIdMask) != b) h5_insert(HA, e & kIdMask, e >> kTypeShift);
+    }
+    wave_sync();
+  };
+  auto wave_side5_clear = [&]() {
+    uint32_t* HA = wh + (threadIdx.x >> 6) * WH;
+    for (int32_t i = (int32_t)(threadIdx.x & 63u); i < kWave5Hash; i += 64) HA[i] = kEmptySlot;
+    wave_sync();
+  };
+  auto wave_triple5 = [&](int32_t b, int32_t a, int32_t c2, uint32_t base) {
+    const int32_t lane = (int32_t)(threadIdx.x & 63u);
+    const uint32_t* HA = wh + (threadIdx.x >> 6) * WH;
+    uint32_t* HC = wh + (threadIdx.x >> 6) * WH + kWave5Hash;
+    int32_t* cn = wcnt + (threadIdx.x >> 6) * NL;
+    const int32_t aa = G.gs_off[a], da = G.gs_off[a + 1] - aa;
+    const int32_t ca2 = G.gs_off[c2], dc2 = G.gs_off[c2 + 1] - ca2;  // both <= 64
+    if (lane < dc2) {
+      const uint32_t e = G.gs_idx[ca2 + lane];
+      if ((int32_t)(e & kIdMask) != b) h5_insert(HC, e & kIdMask, e >> kTypeShift);
+    }
+    wave_sync();
+    auto is_side = [&](int32_t y) { return y == a || y == c2; };
+    const int32_t items = 2 + da + dc2;
+    for (int32_t i0 = 0; i0 < items; i0 += 64) {
+      const int32_t i = i0 + lane;
+      int32_t q = -1;
+      uint32_t Lq = 0;
+      int32_t len = 0, rb = 0;
+      if (i < items) {
+        if (i < 2) {
+          q = i == 0 ? a : c2;
+          Lq = lab.get((uint32_t)q) & 3u;
+        } else if (i < 2 + da) {
+          const uint32_t e = G.gs_idx[aa + i - 2];
+          q = (int32_t)(e & kIdMask);
+          if (q == b || is_side(q)) q = -1;
+          else Lq = (lab.get((uint32_t)q) & 3u) | ((e >> kTypeShift) << 2) | (h5_type(HC, (uint32_t)q) << 4);
+        } else {
+          const uint32_t e = G.gs_idx[ca2 + i - 2 - da];
+          q = (int32_t)(e & kIdMask);
+          if (q == b || is_side(q) || h5_type(HA, (uint32_t)q)) q = -1;  // members of N(a) are listed above
+          else Lq = (lab.get((uint32_t)q) & 3u) | ((e >> kTypeShift) << 4);
+        }
+        if (q >= 0) {
+          const bool mq = !is_side(q);
+          const uint32_t cq = Lq & 3u;
+          if (mq) atomicAdd(&cn[Lq], 1);
+          const Row9 wq = load_w(q);
+#pragma unroll
+          for (int tr = 0; tr < 9; ++tr) {
+            const uint32_t w = wq.v[tr];
+            if (!w) continue;
+            const uint32_t tp = (uint32_t)(tr / 3) + 1u, r = (uint32_t)(tr % 3) + 1u;
+            if (cq) edge(base, tp, cq, r, (u64)0 - (u64)w);
+            if (mq) edge(base, tp, Lq, r, (u64)w);
+          }
+          rb = G.np_off[q];
+          len = G.np_off[q + 1] - rb;
+        }
+      }
+      int32_t inc = len;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int32_t t = __shfl_up(inc, d);
+        if (lane >= d) inc += t;
+      }
+      const int32_t tot = __shfl(inc, 63);
+      const int32_t rs = rb - (inc - len);
+      for (int32_t jb = 0; jb < tot; jb += 64 * kUnroll) {
+        int32_t sqs[kUnroll];
+        uint32_t sLs[kUnroll], fs[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int32_t j = jb + u * 64 + lane;
+          int32_t sl = 0;
+#pragma unroll
+          for (int st2 = 32; st2; st2 >>= 1)
+            if (__shfl(inc, sl + st2 - 1) <= j) sl += st2;
+          sqs[u] = __shfl(q, sl);
+          sLs[u] = (uint32_t)__shfl((int32_t)Lq, sl);
+          const int32_t srs = __shfl(rs, sl);
+          fs[u] = j < tot ? G.np_idx[srs + j] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (jb + u * 64 + lane >= tot) continue;
+          const uint32_t f = fs[u];
+          const int32_t y = (int32_t)(f & kIdMask);
+          if (y == b) continue;
+          const bool sy = is_side(y);
+          uint32_t Ly = lab.get((uint32_t)y) & 3u;
+          if (!sy) Ly |= (h5_type(HA, (uint32_t)y) << 2) | (h5_type(HC, (uint32_t)y) << 4);
+          if (!Ly && !sy) continue;
+          const int32_t sq = sqs[u];
+          const uint32_t sL = sLs[u];
+          const bool mq = !is_side(sq), my = !sy;
+          const uint32_t r = f >> kTypeShift, cq = sL & 3u, cy = Ly & 3u;
+          if (cq && cy) edge(base, cq, cy, r, kMinusOne);
+          if (mq && my) edge(base, sL, Ly, r, 1ull);
+          if (cq && (sy || (Ly >> 2))) {  // p = sq is also counted in W[y]
+            if (cy) edge(base, cq, cy, r, 1ull);
+            if (my) edge(base, cq, Ly, r, kMinusOne);
+          }
+        }
+      }
+    }
+    // edges inside N(core) with core-only labels
+    if (lane < 27) {
+      const uint32_t w = Mc[lane];
+      if (w) edge(base, (uint32_t)lane / 9 + 1, ((uint32_t)lane / 3) % 3 + 1, (uint32_t)lane % 3 + 1, (u64)w);
+    }
+    wave_sync();
+    // sizes of the core-only sets: N(core) minus the sides minus R'
+    if (lane >= 1 && lane <= 3) {
+      int32_t v = ncore[lane];
+      for (int L = 4; L < NL; ++L)
+        if ((L & 3) == lane) v -= cn[L];
+      v -= (int32_t)((lab.get((uint32_t)a) & 3u) == (uint32_t)lane) + (int32_t)((lab.get((uint32_t)c2) & 3u) == (uint32_t)lane);
+      cn[lane] = v;
+    }
+    wave_sync();
+    // closed form over the non-empty sets (NL = 64 labels, one per lane)
+    const int32_t myc = lane < NL ? cn[lane] : 0;
+    const unsigned long long nzm = __ballot(lane > 0 && myc != 0);
+    const int32_t nz = __popcll(nzm);
+    if (lane > 0 && myc != 0) HC[__popcll(nzm & ((1ull << lane) - 1ull))] = (uint32_t)lane;  // HC is free now
+    wave_sync();
+    for (int32_t pq = lane; pq < nz * nz; pq += 64) {
+      const int32_t ia = pq / nz, ib = pq - ia * nz;
+      if (ia > ib) continue;
+      const uint32_t La = HC[ia], Lb = HC[ib];
+      const u64 na = (u64)cn[La], nb = (u64)cn[Lb];
+      const u64 w = ia == ib ? na * (na - 1) / 2 : na * nb;
+      if (w) atomicAdd(&hist[lut[base | slot_code<K, K - 2>(La) | slot_code<K, K - 1>(Lb)]], w);
+    }
+    wave_sync();
+    if (lane < NL) cn[lane] = 0;
+    for (int32_t i = lane; i < kWave5Hash; i += 64) HC[i] = kEmptySlot;
+    wave_sync();
+  };
   // The graph is checked even for the current core: the small-core pass of a
   // tile may have moved the histogram to another graph in between.
   auto enter_core = [&](int32_t c) {
@@ -1339,30 +1510,73 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
         const uint32_t base = ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u);
         anchor(c, x, -1, base);
       } else {
-        for (int32_t jc = j + 1; jc < rowb; ++jc) {
-          const uint32_t ec = G.gs_idx[jc];
-          const int32_t c2 = (int32_t)(ec & kIdMask);
-          const uint32_t tbc = ec >> kTypeShift;
-          const uint32_t tac = (lab.get((uint32_t)c2) >> 2) & 3u;
-          if (tac && (c > x || c > c2)) continue;  // triangle: taken at its smallest id
-          const uint32_t base = ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u) |
-                                ((tbc & 1u) ? 1u << cbit<K>(0, 2) : 0u) | ((tbc & 2u) ? 1u << cbit<K>(2, 0) : 0u) |
-                                ((tac & 1u) ? 1u << cbit<K>(1, 2) : 0u) | ((tac & 2u) ? 1u << cbit<K>(2, 1) : 0u);
-          const int32_t ca2 = G.gs_off[c2], cb2 = G.gs_off[c2 + 1];
-          for (int32_t i = ca2 + threadIdx.x; i < cb2; i += BLOCK) {
-            const uint32_t e = G.gs_idx[i];
-            if ((int32_t)(e & kIdMask) != c) lab.set_bits(e & kIdMask, (e >> kTypeShift) << 4);
+        // partners c2 after x in c's row, BLOCK at a time: light triples (both
+        // sides of degree <= kLight5) one per wave, the others on the workgroup
+        const bool xlight = xb - xa <= kLight5;
+        for (int32_t jc0 = j + 1; jc0 < rowb; jc0 += BLOCK) {
+          const int32_t jce = min(rowb, jc0 + BLOCK);
+          if (threadIdx.x < 3) unit_ctr[threadIdx.x] = 0;
+          bar<GL>();
+          {
+            const int32_t jc = jc0 + (int32_t)threadIdx.x;
+            if (jc < jce) {
+              const int32_t c2 = (int32_t)(G.gs_idx[jc] & kIdMask);
+              if (xlight && G.gs_off[c2 + 1] - G.gs_off[c2] <= kLight5)
+                unit_list[BLOCK - 1 - atomicAdd(&unit_ctr[1], 1)] = jc;
+              else
+                unit_list[atomicAdd(&unit_ctr[0], 1)] = jc;
+            }
           }
           bar<GL>();
-          anchor(c, x, c2, base);
-          for (int32_t i = ca2 + threadIdx.x; i < cb2; i += BLOCK) {
-            const uint32_t e = G.gs_idx[i];
-            if ((int32_t)(e & kIdMask) != c) lab.clear_bits(e & kIdMask, 3u << 4);
+          const int32_t nheavy = unit_ctr[0], nlight = unit_ctr[1];
+          for (int32_t u = 0; u < nheavy; ++u) {
+            const uint32_t ec = G.gs_idx[unit_list[u]];
+            const int32_t c2 = (int32_t)(ec & kIdMask);
+            const uint32_t tbc = ec >> kTypeShift;
+            const uint32_t tac = (lab.get((uint32_t)c2) >> 2) & 3u;
+            if (tac && (c > x || c > c2)) continue;  // triangle: taken at its smallest id
+            const uint32_t base = ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u) |
+                                  ((tbc & 1u) ? 1u << cbit<K>(0, 2) : 0u) | ((tbc & 2u) ? 1u << cbit<K>(2, 0) : 0u) |
+                                  ((tac & 1u) ? 1u << cbit<K>(1, 2) : 0u) | ((tac & 2u) ? 1u << cbit<K>(2, 1) : 0u);
+            const int32_t ca2 = G.gs_off[c2], cb2 = G.gs_off[c2 + 1];
+            for (int32_t i = ca2 + threadIdx.x; i < cb2; i += BLOCK) {
+              const uint32_t e = G.gs_idx[i];
+              if ((int32_t)(e & kIdMask) != c) lab.set_bits(e & kIdMask, (e >> kTypeShift) << 4);
+            }
+            bar<GL>();
+            anchor(c, x, c2, base);
+            for (int32_t i = ca2 + threadIdx.x; i < cb2; i += BLOCK) {
+              const uint32_t e = G.gs_idx[i];
+              if ((int32_t)(e & kIdMask) != c) lab.clear_bits(e & kIdMask, 3u << 4);
+            }
+            bar<GL>();
           }
+          if (nlight > 0) {
+            bool have_side = false;
+            for (;;) {  // light triples are handed to the waves one at a time
+              int32_t u = 0;
+              if ((threadIdx.x & 63u) == 0) u = atomicAdd(&unit_ctr[2], 1);
+              u = __shfl(u, 0);
+              if (u >= nlight) break;
+              if (!have_side) {
+                wave_side5(c, x);
+                have_side = true;
+              }
+              const uint32_t ec = G.gs_idx[unit_list[BLOCK - 1 - u]];
+              const int32_t c2 = (int32_t)(ec & kIdMask);
+              const uint32_t tbc = ec >> kTypeShift;
+              const uint32_t tac = h5_type(wh + (threadIdx.x >> 6) * WH, (uint32_t)c2);
+              if (tac && (c > x || c > c2)) continue;  // triangle: taken at its smallest id
+              const uint32_t base = ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u) |
+                                    ((tbc & 1u) ? 1u << cbit<K>(0, 2) : 0u) | ((tbc & 2u) ? 1u << cbit<K>(2, 0) : 0u) |
+                                    ((tac & 1u) ? 1u << cbit<K>(1, 2) : 0u) | ((tac & 2u) ? 1u << cbit<K>(2, 1) : 0u);
+              wave_triple5(c, x, c2, base);
+            }
+            if (have_side) wave_side5_clear();
+          }
+          // skipped triples read x's labels without a barrier (see k5_kernel)
           bar<GL>();
         }
-        // skipped triples read x's labels without a barrier (see k5_kernel)
-        bar<GL>();
       }
       for (int32_t i = xa + threadIdx.x; i < xb; i += BLOCK) {
         const uint32_t e = G.gs_idx[i];
@@ -1531,7 +1745,7 @@ int label_cap_k4(int32_t n) {
 }
 int label_cap_k5(int32_t n) {
   const int64_t bytes = ((int64_t)n + 3) / 4 * 4;
-  return bytes <= 16384 ? 16384 : bytes <= 65536 ? 65536 : 0;
+  return bytes <= 16384 ? 16384 : bytes <= 32768 ? 32768 : 0;
 }
 int64_t label_words(int k, int32_t n) { return k == 4 ? ((int64_t)n + 7) / 8 : ((int64_t)n + 3) / 4; }
 
@@ -1670,15 +1884,15 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
         }
       } else if (reuse) {
         if (t.block == 512) {
-          if (cap == 16384) LAUNCH_KR(5, 512, 16384); else if (cap == 65536) LAUNCH_KR(5, 512, 65536); else LAUNCH_KR(5, 512, 0);
+          if (cap == 16384) LAUNCH_KR(5, 512, 16384); else if (cap == 32768) LAUNCH_KR(5, 512, 32768); else LAUNCH_KR(5, 512, 0);
         } else {
-          if (cap == 16384) LAUNCH_KR(5, 1024, 16384); else if (cap == 65536) LAUNCH_KR(5, 1024, 65536); else LAUNCH_KR(5, 1024, 0);
+          if (cap == 16384) LAUNCH_KR(5, 1024, 16384); else if (cap == 32768) LAUNCH_KR(5, 1024, 32768); else LAUNCH_KR(5, 1024, 0);
         }
       } else {
         if (t.block == 512) {
-          if (cap == 16384) LAUNCH_K5(512, 16384); else if (cap == 65536) LAUNCH_K5(512, 65536); else LAUNCH_K5(512, 0);
+          if (cap == 16384) LAUNCH_K5(512, 16384); else if (cap == 32768) LAUNCH_K5(512, 32768); else LAUNCH_K5(512, 0);
         } else {
-          if (cap == 16384) LAUNCH_K5(1024, 16384); else if (cap == 65536) LAUNCH_K5(1024, 65536); else LAUNCH_K5(1024, 0);
+          if (cap == 16384) LAUNCH_K5(1024, 16384); else if (cap == 32768) LAUNCH_K5(1024, 32768); else LAUNCH_K5(1024, 0);
         }
       }
     }
