@@ -71,7 +71,9 @@ constexpr int kMaxBig = 64;          // cores whose W / M tables are built once 
 constexpr int kBigMinDeg = 256;      // ... among vertices of at least this degree
 constexpr int64_t kBigBytes = 512ll << 20;  // ... within this many bytes of tables
 constexpr int kBigRow = 12;          // words per W row of a big core (9 used, 16-byte aligned)
-constexpr int kUnroll = 4;         // N+ entries per lane and pass of the flattened scans
+constexpr int kUnroll = 4;
+constexpr int kBucketShift = 6;     // the row-scan layout records the row at every 64th entry ...
+constexpr int kBuckets = 1024;      // ... for layouts of up to 64 K entries (else plain binary search)         // N+ entries per lane and pass of the flattened scans
 constexpr int kLightDeg = 256;  // k = 4 anchors whose side has at most this degree run on one wave
 constexpr int kWaveHashBits = 9;
 constexpr int kWaveHash = 1 << kWaveHashBits;  // slots of the wave-private hash of N(side): load <= 1/2
@@ -646,7 +648,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   __shared__ int32_t ncore[4];
   __shared__ int32_t sh_j0, sh_j1;
   __shared__ u64 seg_ctr[2];  // (rows << 32) | entries of the chunk being laid out
-  __shared__ int32_t seg_v[BLOCK], seg_start[BLOCK], seg_base[BLOCK];
+  __shared__ int32_t seg_v[BLOCK], seg_start[BLOCK], seg_base[BLOCK], seg_at[kBuckets];
   constexpr int NW = BLOCK / 64;
   constexpr int WH = K == 4 ? kWaveHash : 2 * kWave5Hash;  // per-wave hash words
   __shared__ uint32_t wh[NW * WH];  // light anchors: per-wave hashes of the sides' neighbourhoods
@@ -722,9 +724,14 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
           if (len > 0) {  // |N+(v)| <= sqrt(2 |E*|), so BLOCK rows fit in 32 bits
             const u64 old = atomicAdd(&seg_ctr[par], (1ull << 32) | (u64)len);
             const int32_t sl = (int32_t)(old >> 32);
+            const int32_t start = (int32_t)(uint32_t)old;
             seg_v[sl] = v;
-            seg_start[sl] = (int32_t)(uint32_t)old;
-            seg_base[sl] = G.np_off[v] - (int32_t)(uint32_t)old;  // entry j of the layout is np_idx[seg_base + j]
+            seg_start[sl] = start;
+            seg_base[sl] = G.np_off[v] - start;  // entry j of the layout is np_idx[seg_base + j]
+            // this row holds the bucket boundaries b * 64 in [start, start + len)
+            for (int32_t b = (start + (1 << kBucketShift) - 1) >> kBucketShift;
+                 b <= (start + len - 1) >> kBucketShift && b < kBuckets; ++b)
+              seg_at[b] = sl;
           }
         }
       }
@@ -732,7 +739,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       const u64 ctr = seg_ctr[par];
       const int32_t nseg = (int32_t)(ctr >> 32), tot = (int32_t)(uint32_t)ctr;
       if (threadIdx.x == 0) seg_ctr[par ^ 1] = 0;
-      int32_t sl = 0;
+      const int32_t last_b = (tot - 1) >> kBucketShift;
+      const bool bucketed = last_b < kBuckets;
       // kUnroll entries per thread and pass, their loads issued together
       for (int32_t jb = threadIdx.x; jb < tot; jb += kUnroll * BLOCK) {
         int32_t vv[kUnroll];
@@ -742,13 +750,16 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
           const int32_t j = jb + u * BLOCK;
           vv[u] = -1;
           if (j < tot) {
-            int32_t hi = nseg - 1;  // last row starting at or before j (starts increase with sl)
-            while (sl < hi) {
-              const int32_t mid = (sl + hi + 1) >> 1;
-              if (seg_start[mid] <= j) sl = mid; else hi = mid - 1;
+            // the row of j lies between the rows of the bucket boundaries around j
+            const int32_t b = j >> kBucketShift;
+            int32_t lo = bucketed ? seg_at[b] : 0;
+            int32_t hi = bucketed && b < last_b ? seg_at[b + 1] : nseg - 1;
+            while (lo < hi) {
+              const int32_t mid = (lo + hi + 1) >> 1;
+              if (seg_start[mid] <= j) lo = mid; else hi = mid - 1;
             }
-            vv[u] = seg_v[sl];
-            ff[u] = G.np_idx[seg_base[sl] + j];
+            vv[u] = seg_v[lo];
+            ff[u] = G.np_idx[seg_base[lo] + j];
           }
         }
 #pragma unroll
