@@ -101,6 +101,7 @@ int32_t get_pipeline(int dev, hipStream_t s, size_t bytes, Pipeline** out) {
   if (p->arena.cap < bytes) {
     if (p->arena.base) {
       hipStreamSynchronize(s);
+      if (p->side) hipStreamSynchronize(p->side);
       hipFree(p->arena.base);
       p->arena.base = nullptr;
       p->arena.cap = 0;
@@ -163,6 +164,9 @@ void profile_mark(int k, int what, bool begin, hipStream_t s) {
 }
 
 // One census on a sized pipeline: build + status wait + census + status wait.
+// The census is enqueued right behind the build, with no host wait in
+// between: every census kernel returns at once when the build has set the
+// status word, and the exact division writes nothing then.
 int32_t run_census_on(Pipeline& p, const BuildInput& in, int32_t k, uint64_t* hist, hipStream_t s) {
   const int C = motif_num_classes(k);
   p.arena.reset();
@@ -170,13 +174,15 @@ int32_t run_census_on(Pipeline& p, const BuildInput& in, int32_t k, uint64_t* hi
   profile_mark(k, 0, true, s);
   DevGraph g = enqueue_build(p, in, s);
   profile_mark(k, 0, false, s);
-  int32_t rc = read_status(p, s);
-  if (rc) return rc;
   uint64_t* acc = p.arena.take<uint64_t>((size_t)in.ngraphs * C);
   enqueue_census(p, g, k, acc, hist, s);
   return read_status(p, s);
 }
 
+// Several sizes over one build.  The largest size runs on the caller's
+// stream; the others follow each other on the pipeline's second stream,
+// forked after the build, so their workgroups fill the compute units that the
+// largest census leaves idle at its end.  Each census has its own workspace.
 int32_t run_census_multi_on(Pipeline& p, const BuildInput& in, int32_t nk, const int32_t* ks, uint64_t* const* hists,
                             hipStream_t s) {
   p.arena.reset();
@@ -184,14 +190,25 @@ int32_t run_census_multi_on(Pipeline& p, const BuildInput& in, int32_t nk, const
   for (int32_t i = 0; i < nk; ++i) profile_mark(ks[i], 0, true, s);  // the shared build, seen by every k
   DevGraph g = enqueue_build(p, in, s);
   for (int32_t i = 0; i < nk; ++i) profile_mark(ks[i], 0, false, s);
-  int32_t rc = read_status(p, s);
-  if (rc) return rc;
-  const size_t built = p.arena.mark();
-  for (int32_t i = 0; i < nk; ++i) {
-    uint64_t* acc = p.arena.take<uint64_t>((size_t)in.ngraphs * motif_num_classes(ks[i]));
-    enqueue_census(p, g, ks[i], acc, hists[i], s);
-    p.arena.rewind(built);  // the next census reuses this region after these kernels
+  int32_t top = 0;
+  for (int32_t i = 1; i < nk; ++i)
+    if (ks[i] > ks[top]) top = i;
+  if (nk > 1) {
+    if (!p.side && hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) != hipSuccess) return MOTIF_EDEVICE;
+    if (!p.ev_fork && hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming) != hipSuccess) return MOTIF_EDEVICE;
+    if (!p.ev_join && hipEventCreateWithFlags(&p.ev_join, hipEventDisableTiming) != hipSuccess) return MOTIF_EDEVICE;
+    if (hipEventRecord(p.ev_fork, s) != hipSuccess || hipStreamWaitEvent(p.side, p.ev_fork, 0) != hipSuccess)
+      return MOTIF_EDEVICE;
   }
+  uint64_t* acc = p.arena.take<uint64_t>((size_t)in.ngraphs * motif_num_classes(ks[top]));
+  enqueue_census(p, g, ks[top], acc, hists[top], s);
+  for (int32_t i = 0; i < nk; ++i) {
+    if (i == top) continue;
+    uint64_t* a = p.arena.take<uint64_t>((size_t)in.ngraphs * motif_num_classes(ks[i]));
+    enqueue_census(p, g, ks[i], a, hists[i], p.side);
+  }
+  if (nk > 1 && (hipEventRecord(p.ev_join, p.side) != hipSuccess || hipStreamWaitEvent(s, p.ev_join, 0) != hipSuccess))
+    return MOTIF_EDEVICE;
   return read_status(p, s);
 }
 
@@ -223,6 +240,9 @@ int32_t motif_shutdown(void) {
     hipDeviceSynchronize();
     for (void* ptr : kv.second.owned) hipFree(ptr);
     for (auto& pp : kv.second.pipes) {
+      if (pp.second->side) hipStreamDestroy(pp.second->side);
+      if (pp.second->ev_fork) hipEventDestroy(pp.second->ev_fork);
+      if (pp.second->ev_join) hipEventDestroy(pp.second->ev_join);
       if (pp.second->arena.base) hipFree(pp.second->arena.base);
       if (pp.second->status) hipFree(pp.second->status);
       if (pp.second->host_status) hipHostFree(pp.second->host_status);
@@ -338,9 +358,10 @@ int32_t motif_census_multi(const motif_graph_t* g, int32_t nk, const int32_t* ks
   in.in_idx = g->in_off ? g->in_idx : nullptr;
   in.n = g->n;
   in.m = g->m;
-  size_t bytes = 0;
-  for (int32_t i = 0; i < nk; ++i)
-    bytes = std::max(bytes, pipeline_bytes(in.n, in.m, 1, false, ks[i], device_cus(dev), in.n));
+  // one build plus the workspace of every size (the censuses may run at once)
+  const size_t build = build_bytes(in.n, in.m, 1, false);
+  size_t bytes = build;
+  for (int32_t i = 0; i < nk; ++i) bytes += pipeline_bytes(in.n, in.m, 1, false, ks[i], device_cus(dev), in.n) - build;
   Pipeline* p = nullptr;
   rc = get_pipeline(dev, s, bytes, &p);
   if (rc) return rc;

@@ -82,6 +82,10 @@ struct Pipeline {
   int32_t* status = nullptr;       // device [kStatusWords]
   int32_t* host_status = nullptr;  // pinned host copy
   int num_cus = 0;
+  // second stream for the smaller sizes of a multi-size census, forked after
+  // the shared build and joined before the status is read (default priority)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 // Launch parameters used by the census kernels.
