@@ -1780,8 +1780,9 @@ size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int nu
   if ((k == 4 || k == 5) && tuning_for(k).heavy == 1)
     b += al(sizeof(int32_t) * (N + 1)) + al(64 * sizeof(int32_t)) +
          al(sizeof(uint32_t) * 16 * (size_t)(maxn > 0 ? maxn : N) * grid_size(k, num_cus));
-  if (k == 4 && tuning_for(k).heavy == 1) {  // cost prefix of the G* entries and its scan scratch
+  if (k == 4 && tuning_for(k).heavy == 1)  // cost prefix of the G* entries and its scan scratch
     b += al(sizeof(int32_t) * (2 * M + 1)) + al(sizeof(int32_t) * (size_t)scan_scratch(2 * M + 1));
+  if ((k == 4 || k == 5) && tuning_for(k).heavy == 1) {
     const int64_t mn = maxn > 0 ? maxn : N;
     const int nb = big_slots(mn);
     if (nb > 0)  // big-core ids, list, labels, W rows, M counts
@@ -1835,7 +1836,7 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
       uint32_t* wg = nullptr;
       int64_t ws = 0;
       const int64_t maxn = g.max_graph_n > 0 ? g.max_graph_n : g.n;
-      const int nbig = (reuse && k == 4) ? big_slots(maxn) : 0;
+      const int nbig = reuse ? big_slots(maxn) : 0;
       int32_t *big_id = nullptr, *big_list = nullptr;
       uint32_t *lbig = nullptr, *wbig = nullptr, *mbig = nullptr;
       const int64_t lstride = big_label_words(maxn), wbig_stride = (int64_t)kBigRow * maxn;
