@@ -78,9 +78,10 @@ constexpr int kLightDeg = 256;  // k = 4 anchors whose side has at most this deg
 constexpr int kWaveHashBits = 9;
 constexpr int kWaveHash = 1 << kWaveHashBits;  // slots of the wave-private hash of N(side): load <= 1/2
 constexpr uint32_t kEmptySlot = ~0u;
-constexpr int kWave5HashBits = 7;
-constexpr int kWave5Hash = 1 << kWave5HashBits;  // slots of each k = 5 side hash (<= 64 entries)
-constexpr int kLight5 = 64;         // k = 5 triples whose two sides have at most this degree run on one wave
+constexpr int kWave5HashBits = 8;
+constexpr int kWave5Hash = 1 << kWave5HashBits;  // slots of the k = 5 hash of N(c) (<= 128 entries)
+constexpr int kLight5A = 256;       // k = 5 triples with sides a and c of degree at most these
+constexpr int kLight5C = 128;       // ... run on one wave
 constexpr int kSoloDeg = 64;        // k = 4 anchors whose core has at most this degree run alone on one wave
 constexpr int kSoloHashBits = 8;
 constexpr int kSoloHash = 1 << kSoloHashBits;  // keys of the solo hash of N(c) u N(s): load < 1/2
@@ -339,11 +340,13 @@ __global__ __launch_bounds__(BLOCK) void k3_kernel(DevGraph G, const uint16_t* _
 template <int K, int NL, int BLOCK>
 __device__ __forceinline__ void closed_form(u64* hist, const uint16_t* lut, const int32_t* cnt, int32_t* nzl,
                                             int32_t* nz_count, uint32_t base) {
-  if (threadIdx.x == 0) {
-    int32_t z = 0;
-    for (int L = 1; L < NL; ++L)
-      if (cnt[L]) nzl[z++] = L;
-    *nz_count = z;
+  static_assert(NL <= 64, "one label per lane of the first wave");
+  if (threadIdx.x < 64) {  // the non-empty sets, compacted by a ballot of the first wave
+    const int32_t lane = (int32_t)threadIdx.x;
+    const bool nz = lane > 0 && lane < NL && cnt[lane] != 0;
+    const unsigned long long m = __ballot(nz);
+    if (nz) nzl[__popcll(m & ((1ull << lane) - 1ull))] = lane;
+    if (lane == 0) *nz_count = __popcll(m);
   }
   __syncthreads();
   const int32_t z = *nz_count;
@@ -650,7 +653,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   __shared__ u64 seg_ctr[2];  // (rows << 32) | entries of the chunk being laid out
   __shared__ int32_t seg_v[BLOCK], seg_start[BLOCK], seg_base[BLOCK], seg_at[kBuckets];
   constexpr int NW = BLOCK / 64;
-  constexpr int WH = K == 4 ? kWaveHash : 2 * kWave5Hash;  // per-wave hash words
+  constexpr int WH = K == 4 ? kWaveHash : kWave5Hash;  // per-wave hash words
   __shared__ uint32_t wh[NW * WH];  // light anchors: per-wave hashes of the sides' neighbourhoods
   __shared__ int32_t wcnt[NW * NL];  // per-wave set sizes
   __shared__ int32_t unit_list[BLOCK], unit_ctr[3];
@@ -900,8 +903,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     if (threadIdx.x < 3) {
       const int32_t a = threadIdx.x + 1;
       int32_t v = ncore[a];
-      for (int L = 4; L < NL; ++L)
-        if ((L & 3) == a) v -= cnt[L];
+      for (int L = 4 + a; L < NL; L += 4) v -= cnt[L];
       // the type of each side towards the core sits in its own label
       const uint32_t t0 = lab.get((uint32_t)s0) & 3u;
       const uint32_t t1 = K == 5 ? lab.get((uint32_t)s1) & 3u : 0u;
@@ -1035,8 +1037,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     // sizes of the core-only sets: N(core) minus s minus R'
     if (lane >= 1 && lane <= 3) {
       int32_t v = ncore[lane];
-      for (int L = 4; L < NL; ++L)
-        if ((L & 3) == lane) v -= cn[L];
+      for (int L = 4 + lane; L < NL; L += 4) v -= cn[L];
       v -= (int32_t)(Ls == (uint32_t)lane);
       cn[lane] = v;
     }
@@ -1151,12 +1152,12 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   };
   // A unit of a new core: flush the histogram on a graph change and set up
   // the core's tables (the previous core's are torn down first).
-  // k = 5: a triple (b = core, a, c) whose sides both have degree <= kLight5
-  // runs on one wave.  The types of N(a) towards a and of N(c) towards c sit
-  // in two wave-private hashes (HA, built once per unit and wave, and HC);
-  // the dense labels give only the types towards the core.  R' = {a, c} u
-  // N(a) u N(c) \ {b} is taken 64 members at a time, their N+ rows laid end
-  // to end over the lanes.  Same sums as anchor().
+  // k = 5: a triple (b = core, a, c) with d*(a) <= kLight5A and d*(c) <=
+  // kLight5C runs on one wave.  The types towards b and towards a come from
+  // the dense labels (a's are set for the whole unit), those of N(c) towards
+  // c from a wave-private hash HC.  R' = {a, c} u N(a) u N(c) \ {b} is taken
+  // 64 members at a time, their N+ rows laid end to end over the lanes.
+  // Same sums as anchor().
   auto h5_slot = [](uint32_t y) { return (y * 2654435761u) >> (32 - kWave5HashBits); };
   auto h5_insert = [&](uint32_t* T, uint32_t y, uint32_t t) {
     uint32_t h = h5_slot(y);
@@ -1171,31 +1172,14 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       h = (h + 1) & (kWave5Hash - 1);
     }
   };
-  // HA := N(a) \ {b}, types towards a
-  auto wave_side5 = [&](int32_t b, int32_t a) {
-    const int32_t lane = (int32_t)(threadIdx.x & 63u);
-    uint32_t* HA = wh + (threadIdx.x >> 6) * WH;
-    const int32_t aa = G.gs_off[a], da = G.gs_off[a + 1] - aa;  // da <= kLight5 <= 64
-    if (lane < da) {
-      const uint32_t e = G.gs_idx[aa + lane];
-      if ((int32_t)(e & kIdMask) != b) h5_insert(HA, e & kIdMask, e >> kTypeShift);
-    }
-    wave_sync();
-  };
-  auto wave_side5_clear = [&]() {
-    uint32_t* HA = wh + (threadIdx.x >> 6) * WH;
-    for (int32_t i = (int32_t)(threadIdx.x & 63u); i < kWave5Hash; i += 64) HA[i] = kEmptySlot;
-    wave_sync();
-  };
   auto wave_triple5 = [&](int32_t b, int32_t a, int32_t c2, uint32_t base) {
     const int32_t lane = (int32_t)(threadIdx.x & 63u);
-    const uint32_t* HA = wh + (threadIdx.x >> 6) * WH;
-    uint32_t* HC = wh + (threadIdx.x >> 6) * WH + kWave5Hash;
+    uint32_t* HC = wh + (threadIdx.x >> 6) * WH;
     int32_t* cn = wcnt + (threadIdx.x >> 6) * NL;
-    const int32_t aa = G.gs_off[a], da = G.gs_off[a + 1] - aa;
-    const int32_t ca2 = G.gs_off[c2], dc2 = G.gs_off[c2 + 1] - ca2;  // both <= 64
-    if (lane < dc2) {
-      const uint32_t e = G.gs_idx[ca2 + lane];
+    const int32_t aa = G.gs_off[a], da = G.gs_off[a + 1] - aa;     // <= kLight5A
+    const int32_t ca2 = G.gs_off[c2], dc2 = G.gs_off[c2 + 1] - ca2;  // <= kLight5C
+    for (int32_t i = lane; i < dc2; i += 64) {
+      const uint32_t e = G.gs_idx[ca2 + i];
       if ((int32_t)(e & kIdMask) != b) h5_insert(HC, e & kIdMask, e >> kTypeShift);
     }
     wave_sync();
@@ -1214,12 +1198,13 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
           const uint32_t e = G.gs_idx[aa + i - 2];
           q = (int32_t)(e & kIdMask);
           if (q == b || is_side(q)) q = -1;
-          else Lq = (lab.get((uint32_t)q) & 3u) | ((e >> kTypeShift) << 2) | (h5_type(HC, (uint32_t)q) << 4);
+          else Lq = (lab.get((uint32_t)q) & 15u) | (h5_type(HC, (uint32_t)q) << 4);
         } else {
           const uint32_t e = G.gs_idx[ca2 + i - 2 - da];
           q = (int32_t)(e & kIdMask);
-          if (q == b || is_side(q) || h5_type(HA, (uint32_t)q)) q = -1;  // members of N(a) are listed above
-          else Lq = (lab.get((uint32_t)q) & 3u) | ((e >> kTypeShift) << 4);
+          const uint32_t Lx = lab.get((uint32_t)q);
+          if (q == b || is_side(q) || ((Lx >> 2) & 3u)) q = -1;  // members of N(a) are listed above
+          else Lq = (Lx & 3u) | ((e >> kTypeShift) << 4);
         }
         if (q >= 0) {
           const bool mq = !is_side(q);
@@ -1268,8 +1253,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
           const int32_t y = (int32_t)(f & kIdMask);
           if (y == b) continue;
           const bool sy = is_side(y);
-          uint32_t Ly = lab.get((uint32_t)y) & 3u;
-          if (!sy) Ly |= (h5_type(HA, (uint32_t)y) << 2) | (h5_type(HC, (uint32_t)y) << 4);
+          uint32_t Ly = lab.get((uint32_t)y) & (sy ? 3u : 15u);
+          if (!sy) Ly |= h5_type(HC, (uint32_t)y) << 4;
           if (!Ly && !sy) continue;
           const int32_t sq = sqs[u];
           const uint32_t sL = sLs[u];
@@ -1293,8 +1278,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     // sizes of the core-only sets: N(core) minus the sides minus R'
     if (lane >= 1 && lane <= 3) {
       int32_t v = ncore[lane];
-      for (int L = 4; L < NL; ++L)
-        if ((L & 3) == lane) v -= cn[L];
+      for (int L = 4 + lane; L < NL; L += 4) v -= cn[L];
       v -= (int32_t)((lab.get((uint32_t)a) & 3u) == (uint32_t)lane) + (int32_t)((lab.get((uint32_t)c2) & 3u) == (uint32_t)lane);
       cn[lane] = v;
     }
@@ -1521,9 +1505,10 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
         const uint32_t base = ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u);
         anchor(c, x, -1, base);
       } else {
-        // partners c2 after x in c's row, BLOCK at a time: light triples (both
-        // sides of degree <= kLight5) one per wave, the others on the workgroup
-        const bool xlight = xb - xa <= kLight5;
+        // partners c2 after x in c's row, BLOCK at a time: light triples
+        // (d*(x) <= kLight5A, d*(c2) <= kLight5C) one per wave, the others on
+        // the workgroup; x's types stay in the dense labels for both
+        const bool xlight = xb - xa <= kLight5A;
         for (int32_t jc0 = j + 1; jc0 < rowb; jc0 += BLOCK) {
           const int32_t jce = min(rowb, jc0 + BLOCK);
           if (threadIdx.x < 3) unit_ctr[threadIdx.x] = 0;
@@ -1532,7 +1517,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
             const int32_t jc = jc0 + (int32_t)threadIdx.x;
             if (jc < jce) {
               const int32_t c2 = (int32_t)(G.gs_idx[jc] & kIdMask);
-              if (xlight && G.gs_off[c2 + 1] - G.gs_off[c2] <= kLight5)
+              if (xlight && G.gs_off[c2 + 1] - G.gs_off[c2] <= kLight5C)
                 unit_list[BLOCK - 1 - atomicAdd(&unit_ctr[1], 1)] = jc;
               else
                 unit_list[atomicAdd(&unit_ctr[0], 1)] = jc;
@@ -1563,27 +1548,21 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
             bar<GL>();
           }
           if (nlight > 0) {
-            bool have_side = false;
             for (;;) {  // light triples are handed to the waves one at a time
               int32_t u = 0;
               if ((threadIdx.x & 63u) == 0) u = atomicAdd(&unit_ctr[2], 1);
               u = __shfl(u, 0);
               if (u >= nlight) break;
-              if (!have_side) {
-                wave_side5(c, x);
-                have_side = true;
-              }
               const uint32_t ec = G.gs_idx[unit_list[BLOCK - 1 - u]];
               const int32_t c2 = (int32_t)(ec & kIdMask);
               const uint32_t tbc = ec >> kTypeShift;
-              const uint32_t tac = h5_type(wh + (threadIdx.x >> 6) * WH, (uint32_t)c2);
+              const uint32_t tac = (lab.get((uint32_t)c2) >> 2) & 3u;
               if (tac && (c > x || c > c2)) continue;  // triangle: taken at its smallest id
               const uint32_t base = ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u) |
                                     ((tbc & 1u) ? 1u << cbit<K>(0, 2) : 0u) | ((tbc & 2u) ? 1u << cbit<K>(2, 0) : 0u) |
                                     ((tac & 1u) ? 1u << cbit<K>(1, 2) : 0u) | ((tac & 2u) ? 1u << cbit<K>(2, 1) : 0u);
               wave_triple5(c, x, c2, base);
             }
-            if (have_side) wave_side5_clear();
           }
           // skipped triples read x's labels without a barrier (see k5_kernel)
           bar<GL>();
