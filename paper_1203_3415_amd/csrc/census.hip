@@ -80,8 +80,7 @@ constexpr int kWaveHash = 1 << kWaveHashBits;  // slots of the wave-private hash
 constexpr uint32_t kEmptySlot = ~0u;
 constexpr int kWave5HashBits = 8;
 constexpr int kWave5Hash = 1 << kWave5HashBits;  // slots of the k = 5 hash of N(c) (<= 128 entries)
-constexpr int kLight5A = 256;       // k = 5 triples with sides a and c of degree at most these
-constexpr int kLight5C = 128;       // ... run on one wave
+constexpr int kLight5C = 128;       // k = 5 triples whose side c has at most this degree run on one wave
 constexpr int kSoloDeg = 64;        // k = 4 anchors whose core has at most this degree run alone on one wave
 constexpr int kSoloHashBits = 8;
 constexpr int kSoloHash = 1 << kSoloHashBits;  // keys of the solo hash of N(c) u N(s): load < 1/2
@@ -1152,8 +1151,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   };
   // A unit of a new core: flush the histogram on a graph change and set up
   // the core's tables (the previous core's are torn down first).
-  // k = 5: a triple (b = core, a, c) with d*(a) <= kLight5A and d*(c) <=
-  // kLight5C runs on one wave.  The types towards b and towards a come from
+  // k = 5: a triple (b = core, a, c) with d*(c) <= kLight5C runs on one
+  // wave.  The types towards b and towards a come from
   // the dense labels (a's are set for the whole unit), those of N(c) towards
   // c from a wave-private hash HC.  R' = {a, c} u N(a) u N(c) \ {b} is taken
   // 64 members at a time, their N+ rows laid end to end over the lanes.
@@ -1176,7 +1175,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     const int32_t lane = (int32_t)(threadIdx.x & 63u);
     uint32_t* HC = wh + (threadIdx.x >> 6) * WH;
     int32_t* cn = wcnt + (threadIdx.x >> 6) * NL;
-    const int32_t aa = G.gs_off[a], da = G.gs_off[a + 1] - aa;     // <= kLight5A
+    const int32_t aa = G.gs_off[a], da = G.gs_off[a + 1] - aa;
     const int32_t ca2 = G.gs_off[c2], dc2 = G.gs_off[c2 + 1] - ca2;  // <= kLight5C
     for (int32_t i = lane; i < dc2; i += 64) {
       const uint32_t e = G.gs_idx[ca2 + i];
@@ -1506,9 +1505,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
         anchor(c, x, -1, base);
       } else {
         // partners c2 after x in c's row, BLOCK at a time: light triples
-        // (d*(x) <= kLight5A, d*(c2) <= kLight5C) one per wave, the others on
-        // the workgroup; x's types stay in the dense labels for both
-        const bool xlight = xb - xa <= kLight5A;
+        // (d*(c2) <= kLight5C) one per wave, the others on the workgroup;
+        // x's types stay in the dense labels for both
         for (int32_t jc0 = j + 1; jc0 < rowb; jc0 += BLOCK) {
           const int32_t jce = min(rowb, jc0 + BLOCK);
           if (threadIdx.x < 3) unit_ctr[threadIdx.x] = 0;
@@ -1517,7 +1515,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
             const int32_t jc = jc0 + (int32_t)threadIdx.x;
             if (jc < jce) {
               const int32_t c2 = (int32_t)(G.gs_idx[jc] & kIdMask);
-              if (xlight && G.gs_off[c2 + 1] - G.gs_off[c2] <= kLight5C)
+              if (G.gs_off[c2 + 1] - G.gs_off[c2] <= kLight5C)
                 unit_list[BLOCK - 1 - atomicAdd(&unit_ctr[1], 1)] = jc;
               else
                 unit_list[atomicAdd(&unit_ctr[0], 1)] = jc;
