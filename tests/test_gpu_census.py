@@ -328,3 +328,27 @@ def test_census_multi_matches_single(pm):
     assert e.value.name == "ESELFLOOP"
     with pytest.raises(pm.MotifError):
         pm.census_multi(off, idx, g.n, (3, 3))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("k,n", [(3, 400), (4, 400), (5, 60)])
+def test_dense_closed_forms(pm, k, n):
+    """Complete digraph and transitive tournament: every k-set induces the
+    same class, C(n, k) times.  At n = 400 every k = 4 anchor is heavy and a
+    flattened row layout holds more than 64 K entries (the unbucketed row
+    search); at k = 5 every triple runs on the wave path."""
+    full = (1 << (k * (k - 1))) - 1
+    want = math.comb(n, k)
+    cases = {"complete": (gg.complete_digraph(n), full)}
+    # transitive tournament: arc i -> j for i < j, i.e. slot i has arcs to every later slot
+    tt = 0
+    for i in range(k):
+        for j in range(i + 1, k):
+            tt |= 1 << (i * (k - 1) + (j - 1))
+    cases["transitive"] = (gg.transitive_tournament(n), tt)
+    for name, (g, code) in cases.items():
+        print(f"[case] dense {name} n={n} k={k}", flush=True)
+        h = gpu_census(pm, g, k)
+        cls = pm.class_of_code(k, code)
+        assert int(h[cls]) == want, name
+        assert int(h.sum()) == want, name
