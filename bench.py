@@ -259,9 +259,13 @@ CENSUS_SRC = os.path.join(ROOT, "paper_1203_3415_amd", "csrc", "census.hip")
 
 
 def _src_digest() -> str:
+    """SHA-256 of the census source with comments and blank lines removed, so
+    that the stored traffic stays valid across comment edits only."""
     import hashlib
-    with open(CENSUS_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    import re
+    with open(CENSUS_SRC) as f:
+        code = [re.sub(r"//.*$", "", line).rstrip() for line in f]
+    return hashlib.sha256("\n".join(x for x in code if x).encode()).hexdigest()
 
 
 def _traffic_file(kname: str, workload: str) -> str:

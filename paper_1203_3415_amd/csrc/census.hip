@@ -27,6 +27,11 @@
 // graph with 64-bit global atomics, so the result does not depend on the
 // schedule.  Counters wrap modulo 2^64; the intermediate "negative" values of
 // the edge moves cancel exactly.
+//
+// k4_kernel and k5_kernel follow this per anchor.  The default kernels for
+// k = 4, 5 (kr_kernel) compute the same sums with the neighbourhood of the
+// highest-ranked anchor vertex scanned once for all of its anchors, and run
+// small anchors on single waves with their labels in LDS hashes.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -1149,14 +1154,12 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     for (int32_t i = lane; i < WH; i += 64) key[i] = kEmptySlot;
     wave_sync();
   };
-  // A unit of a new core: flush the histogram on a graph change and set up
-  // the core's tables (the previous core's are torn down first).
   // k = 5: a triple (b = core, a, c) with d*(c) <= kLight5C runs on one
-  // wave.  The types towards b and towards a come from
-  // the dense labels (a's are set for the whole unit), those of N(c) towards
-  // c from a wave-private hash HC.  R' = {a, c} u N(a) u N(c) \ {b} is taken
-  // 64 members at a time, their N+ rows laid end to end over the lanes.
-  // Same sums as anchor().
+  // wave.  The types towards b and towards a come from the dense labels (a's
+  // are set for the whole unit), those of N(c) towards c from a
+  // wave-private hash HC.  R' = {a, c} u N(a) u N(c) \ {b} is taken 64
+  // members at a time, their N+ rows laid end to end over the lanes.  Same
+  // sums as anchor().
   auto h5_slot = [](uint32_t y) { return (y * 2654435761u) >> (32 - kWave5HashBits); };
   auto h5_insert = [&](uint32_t* T, uint32_t y, uint32_t t) {
     uint32_t h = h5_slot(y);
@@ -1301,8 +1304,10 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     for (int32_t i = lane; i < kWave5Hash; i += 64) HC[i] = kEmptySlot;
     wave_sync();
   };
-  // The graph is checked even for the current core: the small-core pass of a
-  // tile may have moved the histogram to another graph in between.
+  // A unit of a new core: flush the histogram on a graph change and set up
+  // the core's tables (the previous core's are torn down first).  The graph
+  // is checked even for the current core: the small-core pass of a tile may
+  // have moved the histogram to another graph in between.
   auto enter_core = [&](int32_t c) {
     const int32_t g = G.gid ? G.gid[c] : 0;
     if (g != cur_g) {
