@@ -645,7 +645,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   constexpr int C = K == 4 ? 199 : 9364, NL = K == 4 ? 16 : 64, LB = K == 4 ? 4 : 8;
   constexpr int S1 = K - 2, S2 = K - 1;  // member slots
   // LDS rows of W: fewer where the k = 5 counters and labels leave no room
-  constexpr int HUBS = (K == 5 && LCAP == 32768) ? 256 : kMaxHubs;
+  constexpr int HUBS = (K == 5 && LCAP == 32768) ? 256 : (K == 4 && LCAP == 65536) ? 384 : kMaxHubs;
   constexpr bool GL = LCAP == 0;
   __shared__ u64 hist[C];
   __shared__ uint16_t lut_lds[K == 4 ? 4096 : 1];
@@ -660,6 +660,10 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   constexpr int WH = K == 4 ? kWaveHash : kWave5Hash;  // per-wave hash words
   __shared__ uint32_t wh[NW * WH];  // light anchors: per-wave hashes of the sides' neighbourhoods
   __shared__ int32_t wcnt[NW * NL];  // per-wave set sizes
+  // k = 4: the no-edge half of every edge move, per label pair (min, max),
+  // summed for the current anchor and added in its closed form (per wave for
+  // the wave paths, one table for the workgroup path)
+  __shared__ uint32_t wE[K == 4 ? NW * NL * NL : 1], bE[K == 4 ? NL * NL : 1];
   __shared__ int32_t unit_list[BLOCK], unit_ctr[3];
   __shared__ uint32_t lds_labels[LCAP > 0 ? LCAP / 4 : 1];
   if (st[kStatus] != 0) return;
@@ -676,6 +680,10 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   for (int i = threadIdx.x; i < HUBS * 9; i += BLOCK) W[i] = 0u;
   for (int i = threadIdx.x; i < NW * WH; i += BLOCK) wh[i] = kEmptySlot;
   for (int i = threadIdx.x; i < NW * NL; i += BLOCK) wcnt[i] = 0;
+  if (K == 4) {
+    for (int i = threadIdx.x; i < NW * NL * NL; i += BLOCK) wE[i] = 0u;
+    for (int i = threadIdx.x; i < NL * NL; i += BLOCK) bE[i] = 0u;
+  }
   if (LCAP > 0)
     for (int i = threadIdx.x; i < LCAP / 4; i += BLOCK) lds_labels[i] = 0u;
   __syncthreads();
@@ -715,6 +723,22 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     const uint32_t c0 = base | slot_code<K, S1>(Lx) | slot_code<K, S2>(Ly);
     atomicAdd(&hist[lut[c0 | rel_code<K>(r)]], w);
     atomicAdd(&hist[lut[c0]], (u64)0 - w);
+  };
+  // k = 4: the same move with its no-edge half kept in E (the class of a
+  // member pair without an edge does not depend on which member is in which
+  // slot); per anchor and pair the sum stays far inside int32, so 32-bit
+  // wrapping counters are exact after sign extension
+  auto edge4 = [&](uint32_t* E, uint32_t base, uint32_t Lx, uint32_t Ly, uint32_t r, u64 w) {
+    atomicAdd(&hist[lut[base | slot_code<K, S1>(Lx) | slot_code<K, S2>(Ly) | rel_code<K>(r)]], w);
+    atomicAdd(&E[min(Lx, Ly) * NL + max(Lx, Ly)], (uint32_t)((u64)0 - w));
+  };
+  // closed form of one pair (La <= Lb) plus its deferred no-edge moves
+  auto pair_total = [&](const int32_t* cntv, uint32_t* E, int32_t La, int32_t Lb) -> u64 {
+    const u64 na = (u64)cntv[La], nb = (u64)cntv[Lb];
+    const u64 w = La == Lb ? na * (na - (na > 0)) / 2 : na * nb;
+    const uint32_t e = E[La * NL + Lb];
+    E[La * NL + Lb] = 0u;
+    return w + (u64)(int64_t)(int32_t)e;
   };
   // Flattened scan of the N+ rows of the vertices pick(0 .. items-1): pick
   // returns a vertex (or -1) and does the per-vertex work, visit(v, f) handles
@@ -844,6 +868,10 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
 
   // One anchor: core c, sides s0 (and s1 for k = 5) whose labels are set.
   auto anchor = [&](int32_t c, int32_t s0, int32_t s1, uint32_t base) {
+    auto EDGE = [&](uint32_t bs, uint32_t Lx, uint32_t Ly, uint32_t r, u64 w) {
+      if constexpr (K == 4) edge4(bE, bs, Lx, Ly, r, w);
+      else edge(bs, Lx, Ly, r, w);
+    };
     const int32_t a0 = G.gs_off[s0], d0 = G.gs_off[s0 + 1] - a0;
     const int32_t a1 = K == 5 ? G.gs_off[s1] : 0, d1 = K == 5 ? G.gs_off[s1 + 1] - a1 : 0;
     const int32_t nsides = K == 5 ? 2 : 1;
@@ -872,8 +900,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
         const uint32_t w = wq.v[tr];
         if (!w) continue;
         const uint32_t tp = (uint32_t)(tr / 3) + 1u, r = (uint32_t)(tr % 3) + 1u;
-        if (cq) edge(base, tp, cq, r, (u64)0 - (u64)w);
-        if (mq) edge(base, tp, Lq, r, (u64)w);
+        if (cq) EDGE(base, tp, cq, r, (u64)0 - (u64)w);
+        if (mq) EDGE(base, tp, Lq, r, (u64)w);
       }
       return q;
     };
@@ -887,11 +915,11 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       const uint32_t Lq = lab.get((uint32_t)q);
       const bool mq = !is_side(q), my = !sy;
       const uint32_t r = f >> kTypeShift, cq = Lq & 3u, cy = Ly & 3u;
-      if (cq && cy) edge(base, cq, cy, r, kMinusOne);
-      if (mq && my) edge(base, Lq, Ly, r, 1ull);
+      if (cq && cy) EDGE(base, cq, cy, r, kMinusOne);
+      if (mq && my) EDGE(base, Lq, Ly, r, 1ull);
       if (cq && (sy || (Ly >> 2))) {  // p = q is also counted in W[y]
-        if (cy) edge(base, cq, cy, r, 1ull);
-        if (my) edge(base, cq, Ly, r, kMinusOne);
+        if (cy) EDGE(base, cq, cy, r, 1ull);
+        if (my) EDGE(base, cq, Ly, r, kMinusOne);
       }
     };
     flat_rows(nsides + d0 + d1, pick, visit);
@@ -900,7 +928,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       const uint32_t w = Mc[threadIdx.x];
       if (w) {
         const uint32_t tx = threadIdx.x / 9 + 1, ty = (threadIdx.x / 3) % 3 + 1, r = threadIdx.x % 3 + 1;
-        edge(base, tx, ty, r, (u64)w);
+        EDGE(base, tx, ty, r, (u64)w);
       }
     }
     // sizes of the core-only sets: N(core) minus the sides minus R'
@@ -915,7 +943,16 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       cnt[a] = v;
     }
     bar<GL>();
-    closed_form<K, NL, BLOCK>(hist, lut, cnt, nzl, &nz_count, base);
+    if constexpr (K == 4) {  // every pair once: some deferred moves sit on empty sets
+      for (int32_t t = threadIdx.x; t < NL * NL; t += BLOCK) {
+        const int32_t La = t / NL, Lb = t % NL;
+        if (La == 0 || La > Lb) continue;
+        const u64 w = pair_total(cnt, bE, La, Lb);
+        if (w) atomicAdd(&hist[lut[base | slot_code<K, K - 2>((uint32_t)La) | slot_code<K, K - 1>((uint32_t)Lb)]], w);
+      }
+    } else {
+      closed_form<K, NL, BLOCK>(hist, lut, cnt, nzl, &nz_count, base);
+    }
     bar<GL>();
     if (threadIdx.x < NL) cnt[threadIdx.x] = 0;
   };
@@ -932,6 +969,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     const int32_t lane = (int32_t)(threadIdx.x & 63u);
     uint32_t* H = wh + (threadIdx.x >> 6) * WH;
     int32_t* cn = wcnt + (threadIdx.x >> 6) * NL;
+    uint32_t* E = wE + (threadIdx.x >> 6) * NL * NL;
     const int32_t a0 = G.gs_off[s], d0 = G.gs_off[s + 1] - a0;
     const uint32_t Ls = lab.get((uint32_t)s) & 3u;
     for (int32_t i = lane; i < d0; i += 64) {
@@ -967,8 +1005,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
           const uint32_t w = wq.v[tr];
           if (!w) continue;
           const uint32_t tp = (uint32_t)(tr / 3) + 1u, r = (uint32_t)(tr % 3) + 1u;
-          if (cq) edge(base, tp, cq, r, (u64)0 - (u64)w);
-          if (mq) edge(base, tp, Lq, r, (u64)w);
+          if (cq) edge4(E, base, tp, cq, r, (u64)0 - (u64)w);
+          if (mq) edge4(E, base, tp, Lq, r, (u64)w);
         }
         rb = G.np_off[q];
         len = G.np_off[q + 1] - rb;
@@ -1021,11 +1059,11 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
             if (Ly || sy) {
               const bool mq = sq != s, my = !sy;
               const uint32_t r = f >> kTypeShift, cq = sL & 3u, cy = Ly & 3u;
-              if (cq && cy) edge(base, cq, cy, r, kMinusOne);
-              if (mq && my) edge(base, sL, Ly, r, 1ull);
+              if (cq && cy) edge4(E, base, cq, cy, r, kMinusOne);
+              if (mq && my) edge4(E, base, sL, Ly, r, 1ull);
               if (cq && (sy || (Ly >> 2))) {  // p = sq is also counted in W[y]
-                if (cy) edge(base, cq, cy, r, 1ull);
-                if (my) edge(base, cq, Ly, r, kMinusOne);
+                if (cy) edge4(E, base, cq, cy, r, 1ull);
+                if (my) edge4(E, base, cq, Ly, r, kMinusOne);
               }
             }
           }
@@ -1035,7 +1073,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     // edges inside N(core) with core-only labels
     if (lane < 27) {
       const uint32_t w = Mc[lane];
-      if (w) edge(base, (uint32_t)lane / 9 + 1, ((uint32_t)lane / 3) % 3 + 1, (uint32_t)lane % 3 + 1, (u64)w);
+      if (w) edge4(E, base, (uint32_t)lane / 9 + 1, ((uint32_t)lane / 3) % 3 + 1, (uint32_t)lane % 3 + 1, (u64)w);
     }
     wave_sync();
     // sizes of the core-only sets: N(core) minus s minus R'
@@ -1049,8 +1087,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     for (int32_t pq = lane; pq < NL * NL; pq += 64) {
       const int32_t La = pq / NL, Lb = pq % NL;
       if (La == 0 || La > Lb) continue;
-      const u64 na = (u64)cn[La], nb = (u64)cn[Lb];
-      const u64 w = La == Lb ? na * (na - (na > 0)) / 2 : na * nb;
+      const u64 w = pair_total(cn, E, La, Lb);
       if (w) atomicAdd(&hist[lut[base | slot_code<K, K - 2>((uint32_t)La) | slot_code<K, K - 1>((uint32_t)Lb)]], w);
     }
     wave_sync();
@@ -1069,6 +1106,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     uint32_t* key = wh + (threadIdx.x >> 6) * WH;
     uint32_t* nlab = key + kSoloHash;
     int32_t* cn = wcnt + (threadIdx.x >> 6) * NL;
+    uint32_t* E = wE + (threadIdx.x >> 6) * NL * NL;
     auto slot = [](uint32_t x) { return (x * 2654435761u) >> (32 - kSoloHashBits); };
     auto insert = [&](uint32_t x, uint32_t bits) {
       uint32_t h = slot(x);
@@ -1133,7 +1171,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
             const uint32_t kk = key[h];
             if (kk == kEmptySlot) break;
             if (kk == y) {
-              edge(base, sLs[u], ~nlab[h], f >> kTypeShift, 1ull);
+              edge4(E, base, sLs[u], ~nlab[h], f >> kTypeShift, 1ull);
               break;
             }
             h = (h + 1) & (kSoloHash - 1);
@@ -1145,8 +1183,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     for (int32_t pq = lane; pq < NL * NL; pq += 64) {
       const int32_t La = pq / NL, Lb = pq % NL;
       if (La == 0 || La > Lb) continue;
-      const u64 na = (u64)cn[La], nb = (u64)cn[Lb];
-      const u64 w = La == Lb ? na * (na - (na > 0)) / 2 : na * nb;
+      const u64 w = pair_total(cn, E, La, Lb);
       if (w) atomicAdd(&hist[lut[base | slot_code<K, K - 2>((uint32_t)La) | slot_code<K, K - 1>((uint32_t)Lb)]], w);
     }
     wave_sync();
