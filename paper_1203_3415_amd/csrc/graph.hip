@@ -44,6 +44,10 @@ __device__ __forceinline__ int32_t row_of(const int32_t* off, int32_t n, int64_t
   return lo;
 }
 
+// Arcs are taken kArcsPerThread consecutive ones per thread: one binary
+// search for the row of the first, then a forward walk over the offsets.
+constexpr int kArcsPerThread = 8;
+
 __device__ __forceinline__ bool rank_less(int32_t dv, int32_t v, int32_t dw, int32_t w) {
   return dv < dw || (dv == dw && v < w);
 }
@@ -156,12 +160,17 @@ __global__ void k_check_offsets(const int32_t* off, int32_t n, int64_t m, int32_
 __global__ void k_count_in(const int32_t* off, const int32_t* idx, int32_t n, int64_t m, int32_t* in_cnt,
                            int32_t* st) {
   if (st[kStatus] != 0) return;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    int32_t d = idx[i];
-    if (d < 0 || d >= n) { set_status(st, MOTIF_EINDEX); continue; }
-    int32_t u = row_of(off, n, i);
-    if (d == u) { set_status(st, MOTIF_ESELFLOOP); continue; }
-    atomicAdd(&in_cnt[d], 1);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t * kArcsPerThread < m;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i0 = t * kArcsPerThread, i1 = min(m, i0 + kArcsPerThread);
+    int32_t u = row_of(off, n, i0);
+    for (int64_t i = i0; i < i1; ++i) {
+      while (u < n - 1 && off[u + 1] <= i) ++u;  // bounded even if the offsets were not valid
+      const int32_t d = idx[i];
+      if (d < 0 || d >= n) { set_status(st, MOTIF_EINDEX); continue; }
+      if (d == u) { set_status(st, MOTIF_ESELFLOOP); continue; }
+      atomicAdd(&in_cnt[d], 1);
+    }
   }
 }
 
@@ -179,16 +188,21 @@ __global__ void k_half_counts(const int32_t* off, const int32_t* in_cnt, int32_t
 __global__ void k_scatter(const int32_t* off, const int32_t* idx, int32_t n, int64_t m, const int32_t* hoff,
                           int32_t* fill, uint32_t* keys, int32_t* hrow, const int32_t* st) {
   if (st[kStatus] != 0) return;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    int32_t u = row_of(off, n, i);
-    int32_t d = idx[i];
-    const int32_t a = hoff[u] + (int32_t)(i - off[u]);
-    keys[a] = ((uint32_t)d << 1);
-    hrow[a] = u;
-    int32_t p = atomicAdd(&fill[d], 1);
-    const int32_t b = hoff[d] + (off[d + 1] - off[d]) + p;
-    keys[b] = ((uint32_t)u << 1) | 1u;
-    hrow[b] = d;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t * kArcsPerThread < m;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i0 = t * kArcsPerThread, i1 = min(m, i0 + kArcsPerThread);
+    int32_t u = row_of(off, n, i0);
+    for (int64_t i = i0; i < i1; ++i) {
+      while (u < n - 1 && off[u + 1] <= i) ++u;
+      const int32_t d = idx[i];
+      const int32_t a = hoff[u] + (int32_t)(i - off[u]);
+      keys[a] = ((uint32_t)d << 1);
+      hrow[a] = u;
+      const int32_t p = atomicAdd(&fill[d], 1);
+      const int32_t b = hoff[d] + (off[d + 1] - off[d]) + p;
+      keys[b] = ((uint32_t)u << 1) | 1u;
+      hrow[b] = d;
+    }
   }
 }
 
@@ -559,11 +573,13 @@ DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s) {
   enqueue_zero(in_cnt, sizeof(int32_t) * (n + 1), s);
   if (!in.gid) hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.out_off, n, m, st);
   if (m > 0)
-    hipLaunchKernelGGL(k_count_in, dim3(grid_for(m)), dim3(kB), 0, s, in.out_off, in.out_idx, n, m, in_cnt, st);
+    hipLaunchKernelGGL(k_count_in, dim3(grid_for((m + kArcsPerThread - 1) / kArcsPerThread)), dim3(kB), 0, s,
+                       in.out_off, in.out_idx, n, m, in_cnt, st);
   hipLaunchKernelGGL(k_half_counts, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.out_off, in_cnt, n, hoff, fill, st);
   scan_excl(hoff, n + 1, scratch, s);
   if (m > 0)
-    hipLaunchKernelGGL(k_scatter, dim3(grid_for(m)), dim3(kB), 0, s, in.out_off, in.out_idx, n, m, hoff, fill, keys,
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for((m + kArcsPerThread - 1) / kArcsPerThread)), dim3(kB), 0, s,
+                       in.out_off, in.out_idx, n, m, hoff, fill, keys,
                        hrow, st);
   hipLaunchKernelGGL(k_sort_small, dim3(grid_for(n)), dim3(kB), 0, s, hoff, n, keys, midq, bigq, st);
   hipLaunchKernelGGL(k_sort_mid, dim3(512), dim3(kB), 0, s, hoff, keys, midq, st);
