@@ -59,6 +59,11 @@ __global__ void k_zero(uint32_t* p, size_t words) {
     p[i] = 0u;
 }
 
+__global__ void k_zero16(uint4* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 // Exclusive block scan of one value per thread (wave64 shuffles + LDS).
 __device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* sh, int32_t* total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -468,6 +473,13 @@ __global__ void k_pack_arcs(const motif_graph_t* gs, int32_t count, const int64_
 void enqueue_zero(void* ptr, size_t bytes, hipStream_t s) {
   size_t words = (bytes + 3) / 4;
   if (!words) return;
+  if (((uintptr_t)ptr & 15u) == 0 && words >= 1024) {  // 16-byte stores for the bulk
+    const size_t n16 = words / 4;
+    hipLaunchKernelGGL(k_zero16, dim3(grid_for((int64_t)n16)), dim3(kB), 0, s, (uint4*)ptr, n16);
+    words -= n16 * 4;
+    if (!words) return;
+    ptr = (uint32_t*)ptr + n16 * 4;
+  }
   hipLaunchKernelGGL(k_zero, dim3(grid_for((int64_t)words)), dim3(kB), 0, s, (uint32_t*)ptr, words);
 }
 
