@@ -134,9 +134,12 @@ int32_t motif_census(const int32_t* out_off, const int32_t* out_idx, const int32
  * exactly what motif_census(..., ks[i], hists[i], ...) would write.  The
  * validation and the G* / N+ build run once and are shared (the paper's
  * motif profiles use several sizes of one network, Section "Results and
- * Discussion").  `g` holds device pointers; errors as for motif_census():
- * on any error no histogram is written, except that a self-check failure
- * (MOTIF_EINTERNAL) of a later size leaves the earlier sizes written. */
+ * Discussion").  The largest size runs on `stream`, the others on a second
+ * stream owned by the library, forked after the build; both are joined
+ * before the call returns, so on return the work on `stream` includes all
+ * of it.  `g` holds device pointers; errors as for motif_census(): on any
+ * validation error no histogram is written; a self-check failure
+ * (MOTIF_EINTERNAL) of one size may leave the other sizes written. */
 int32_t motif_census_multi(const motif_graph_t* g, int32_t nk, const int32_t* ks, uint64_t* const* hists,
                            void* stream);
 

@@ -28,7 +28,7 @@ namespace {
 constexpr int kB = 256;           // threads per block for streaming kernels
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kB * kScanItems;
-constexpr int kSmallRow = 32;     // rows up to this length: sorted by one thread
+constexpr int kSmallRow = 64;     // rows up to this length: sorted by one thread, in registers
 constexpr int kMidRow = 4096;     // rows up to this length: LDS bitonic sort
 constexpr int kBigSlots = 32;     // concurrent bitmap sorts
 
@@ -162,20 +162,54 @@ __global__ void k_check_offsets(const int32_t* off, int32_t n, int64_t m, int32_
 }
 
 // Every arc: index range, self-loop, in-degree count.
-__global__ void k_count_in(const int32_t* off, const int32_t* idx, int32_t n, int64_t m, int32_t* in_cnt,
-                           int32_t* st) {
+// Per-block aggregation of arc targets: a block takes kArcsPerBlock
+// consecutive arcs, counts them per target in an LDS hash (kAggSlots keys, at
+// most half full), and touches each target's global counter once.  Hubs with
+// thousands of in-arcs then see one atomic per block instead of one per arc.
+constexpr int kArcsPerBlock = kB * kArcsPerThread;
+constexpr int kAggSlots = 2 * kArcsPerBlock;
+constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;
+
+__device__ __forceinline__ int32_t agg_insert(uint32_t* keys, uint32_t d) {
+  uint32_t h = (d * 2654435761u) & (kAggSlots - 1);
+  for (;;) {
+    const uint32_t old = atomicCAS(&keys[h], kAggEmpty, d);
+    if (old == kAggEmpty || old == d) return (int32_t)h;
+    h = (h + 1) & (kAggSlots - 1);
+  }
+}
+
+__global__ __launch_bounds__(kB) void k_count_in(const int32_t* off, const int32_t* idx, int32_t n, int64_t m,
+                                                 int32_t* in_cnt, int32_t* st) {
+  __shared__ uint32_t akey[kAggSlots];
+  __shared__ int32_t acnt[kAggSlots];
   if (st[kStatus] != 0) return;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t * kArcsPerThread < m;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i0 = t * kArcsPerThread, i1 = min(m, i0 + kArcsPerThread);
-    int32_t u = row_of(off, n, i0);
-    for (int64_t i = i0; i < i1; ++i) {
-      while (u < n - 1 && off[u + 1] <= i) ++u;  // bounded even if the offsets were not valid
-      const int32_t d = idx[i];
-      if (d < 0 || d >= n) { set_status(st, MOTIF_EINDEX); continue; }
-      if (d == u) { set_status(st, MOTIF_ESELFLOOP); continue; }
-      atomicAdd(&in_cnt[d], 1);
+  for (int i = threadIdx.x; i < kAggSlots; i += kB) {
+    akey[i] = kAggEmpty;
+    acnt[i] = 0;
+  }
+  __syncthreads();
+  for (int64_t b0 = (int64_t)blockIdx.x * kArcsPerBlock; b0 < m; b0 += (int64_t)gridDim.x * kArcsPerBlock) {
+    const int64_t i0 = b0 + (int64_t)threadIdx.x * kArcsPerThread, i1 = min(m, i0 + kArcsPerThread);
+    if (i0 < m) {
+      int32_t u = row_of(off, n, i0);
+      for (int64_t i = i0; i < i1; ++i) {
+        while (u < n - 1 && off[u + 1] <= i) ++u;  // bounded even if the offsets were not valid
+        const int32_t d = idx[i];
+        if (d < 0 || d >= n) { set_status(st, MOTIF_EINDEX); continue; }
+        if (d == u) { set_status(st, MOTIF_ESELFLOOP); continue; }
+        atomicAdd(&acnt[agg_insert(akey, (uint32_t)d)], 1);
+      }
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAggSlots; i += kB) {
+      if (akey[i] != kAggEmpty) {
+        atomicAdd(&in_cnt[akey[i]], acnt[i]);
+        akey[i] = kAggEmpty;
+        acnt[i] = 0;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -190,42 +224,102 @@ __global__ void k_half_counts(const int32_t* off, const int32_t* in_cnt, int32_t
 }
 
 // Half-edge keys: row u gets (d<<1|0) for arc u->d, row d gets (u<<1|1).
-__global__ void k_scatter(const int32_t* off, const int32_t* idx, int32_t n, int64_t m, const int32_t* hoff,
-                          int32_t* fill, uint32_t* keys, int32_t* hrow, const int32_t* st) {
+// Half-edge scatter with the same per-block aggregation: each arc takes a
+// local rank among the block's arcs to its target, one global atomic per
+// (block, target) reserves the range, and the arc's slot is base + rank (the
+// order inside a row is arbitrary; rows are sorted next).
+__global__ __launch_bounds__(kB) void k_scatter(const int32_t* off, const int32_t* idx, int32_t n, int64_t m,
+                                                const int32_t* hoff, int32_t* fill, uint32_t* keys, int32_t* hrow,
+                                                const int32_t* st) {
+  __shared__ uint32_t akey[kAggSlots];
+  __shared__ int32_t acnt[kAggSlots];
   if (st[kStatus] != 0) return;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t * kArcsPerThread < m;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i0 = t * kArcsPerThread, i1 = min(m, i0 + kArcsPerThread);
-    int32_t u = row_of(off, n, i0);
-    for (int64_t i = i0; i < i1; ++i) {
-      while (u < n - 1 && off[u + 1] <= i) ++u;
-      const int32_t d = idx[i];
-      const int32_t a = hoff[u] + (int32_t)(i - off[u]);
-      keys[a] = ((uint32_t)d << 1);
-      hrow[a] = u;
-      const int32_t p = atomicAdd(&fill[d], 1);
-      const int32_t b = hoff[d] + (off[d + 1] - off[d]) + p;
-      keys[b] = ((uint32_t)u << 1) | 1u;
-      hrow[b] = d;
+  for (int i = threadIdx.x; i < kAggSlots; i += kB) {
+    akey[i] = kAggEmpty;
+    acnt[i] = 0;
+  }
+  __syncthreads();
+  for (int64_t b0 = (int64_t)blockIdx.x * kArcsPerBlock; b0 < m; b0 += (int64_t)gridDim.x * kArcsPerBlock) {
+    const int64_t i0 = b0 + (int64_t)threadIdx.x * kArcsPerThread, i1 = min(m, i0 + kArcsPerThread);
+    int32_t slot[kArcsPerThread], rank[kArcsPerThread];
+    int32_t u0 = 0;
+    if (i0 < m) {
+      int32_t u = u0 = row_of(off, n, i0);
+#pragma unroll
+      for (int t = 0; t < kArcsPerThread; ++t) {
+        const int64_t i = i0 + t;
+        slot[t] = -1;
+        if (i < i1) {
+          while (u < n - 1 && off[u + 1] <= i) ++u;
+          const int32_t d = idx[i];
+          const int32_t a = hoff[u] + (int32_t)(i - off[u]);
+          keys[a] = ((uint32_t)d << 1);
+          hrow[a] = u;
+          slot[t] = agg_insert(akey, (uint32_t)d);
+          rank[t] = atomicAdd(&acnt[slot[t]], 1);
+        }
+      }
     }
+    __syncthreads();
+    // reserve each target's range once; acnt becomes the range base
+    for (int i = threadIdx.x; i < kAggSlots; i += kB)
+      if (akey[i] != kAggEmpty) acnt[i] = atomicAdd(&fill[akey[i]], acnt[i]);
+    __syncthreads();
+    if (i0 < m) {
+      int32_t u = u0;
+#pragma unroll
+      for (int t = 0; t < kArcsPerThread; ++t) {
+        const int64_t i = i0 + t;
+        if (i < i1) {
+          while (u < n - 1 && off[u + 1] <= i) ++u;
+          const int32_t d = (int32_t)akey[slot[t]];
+          const int32_t b = hoff[d] + (off[d + 1] - off[d]) + acnt[slot[t]] + rank[t];
+          keys[b] = ((uint32_t)u << 1) | 1u;
+          hrow[b] = d;
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAggSlots; i += kB) {
+      akey[i] = kAggEmpty;
+      acnt[i] = 0;
+    }
+    __syncthreads();
   }
 }
 
 // Small rows sorted by their own thread; longer rows queued.
-__global__ void k_sort_small(const int32_t* hoff, int32_t n, uint32_t* keys, int32_t* midq, int32_t* bigq,
+__global__ __launch_bounds__(kB) void k_sort_small(const int32_t* hoff, int32_t n, uint32_t* keys, int32_t* midq,
+                                                   int32_t* bigq,
                              int32_t* st) {
   if (st[kStatus] != 0) return;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const int32_t a = hoff[v], len = hoff[v + 1] - a;
     if (len <= 1) continue;
     if (len <= kSmallRow) {
+      // bitonic network over kSmallRow registers (padding keys sort last);
+      // every index is a compile-time constant once the loops are unrolled
       uint32_t* r = keys + a;
-      for (int i = 1; i < len; ++i) {
-        uint32_t t = r[i];
-        int j = i - 1;
-        while (j >= 0 && r[j] > t) { r[j + 1] = r[j]; --j; }
-        r[j + 1] = t;
-      }
+      uint32_t x[kSmallRow];
+#pragma unroll
+      for (int i = 0; i < kSmallRow; ++i) x[i] = i < len ? r[i] : 0xFFFFFFFFu;
+#pragma unroll
+      for (int k = 2; k <= kSmallRow; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+          for (int i = 0; i < kSmallRow; ++i) {
+            const int ij = i ^ j;
+            if (ij > i) {
+              const uint32_t lo = min(x[i], x[ij]), hi = max(x[i], x[ij]);
+              const bool up = (i & k) == 0;
+              x[i] = up ? lo : hi;
+              x[ij] = up ? hi : lo;
+            }
+          }
+#pragma unroll
+      for (int i = 0; i < kSmallRow; ++i)
+        if (i < len) r[i] = x[i];
     } else if (len <= kMidRow) {
       midq[atomicAdd(&st[kMidCount], 1)] = (int32_t)v;
     } else {
@@ -586,7 +680,7 @@ DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s) {
   if (!in.gid) hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.out_off, n, m, st);
   if (m > 0)
     hipLaunchKernelGGL(k_count_in, dim3(grid_for((m + kArcsPerThread - 1) / kArcsPerThread)), dim3(kB), 0, s,
-                       in.out_off, in.out_idx, n, m, in_cnt, st);
+                       in.out_off, in.out_idx, n, m, in_cnt, st);  // grid_for caps at 65536 blocks
   hipLaunchKernelGGL(k_half_counts, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.out_off, in_cnt, n, hoff, fill, st);
   scan_excl(hoff, n + 1, scratch, s);
   if (m > 0)
