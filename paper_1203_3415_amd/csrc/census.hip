@@ -1882,7 +1882,7 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
                            nbig, big_id, big_list, p.status);
         if (nbig > 0) {
           hipLaunchKernelGGL(k_big_labels, dim3(16, nbig), dim3(256), 0, s, g, hs, big_list, lbig, lstride, p.status);
-          hipLaunchKernelGGL(k_core_tables, dim3(256, nbig), dim3(256), 0, s, g, hs, big_list, lbig, lstride, wbig,
+          hipLaunchKernelGGL(k_core_tables, dim3(64, nbig), dim3(256), 0, s, g, hs, big_list, lbig, lstride, wbig,
                              wbig_stride, mbig, p.status);
         }
       }
