@@ -83,9 +83,13 @@ constexpr int kLightDeg = 256;  // k = 4 anchors whose side has at most this deg
 constexpr int kWaveHashBits = 9;
 constexpr int kWaveHash = 1 << kWaveHashBits;  // slots of the wave-private hash of N(side): load <= 1/2
 constexpr uint32_t kEmptySlot = ~0u;
-constexpr int kWave5HashBits = 8;
-constexpr int kWave5Hash = 1 << kWave5HashBits;  // slots of the k = 5 hash of N(c) (<= 128 entries)
-constexpr int kLight5C = 128;       // k = 5 triples whose side c has at most this degree run on one wave
+constexpr int kLight5C = 128;       // k = 5 triples whose side c has at most this degree are light
+constexpr int kNP5 = 32;            // light partners c per sub-chunk of a k = 5 unit (2 type bits each in 64)
+constexpr int kT5Bits = 10;
+constexpr int kT5 = 1 << kT5Bits;   // slots of the merged table of the sub-chunk's N(c) ...
+constexpr int kT5Load = 768;        // ... holding at most this many keys (sum of d*(c) + 1)
+constexpr uint32_t kInT5 = 64u;     // label bit 6: the vertex is a key of that table
+constexpr int kU5 = 16 * 48;        // per-unit move counters: (x label, y label, r), labels of 4 bits
 constexpr int kSoloDeg = 64;        // k = 4 anchors whose core has at most this degree run alone on one wave
 constexpr int kSoloHashBits = 8;
 constexpr int kSoloHash = 1 << kSoloHashBits;  // keys of the solo hash of N(c) u N(s): load < 1/2
@@ -645,7 +649,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   constexpr int C = K == 4 ? 199 : 9364, NL = K == 4 ? 16 : 64, LB = K == 4 ? 4 : 8;
   constexpr int S1 = K - 2, S2 = K - 1;  // member slots
   // LDS rows of W: fewer where the k = 5 counters and labels leave no room
-  constexpr int HUBS = (K == 5 && LCAP == 32768) ? 256 : (K == 4 && LCAP == 65536) ? 384 : kMaxHubs;
+  constexpr int HUBS = (K == 5 && LCAP == 32768) ? 224 : (K == 4 && LCAP == 65536) ? 384 : kMaxHubs;
   constexpr bool GL = LCAP == 0;
   __shared__ u64 hist[C];
   __shared__ uint16_t lut_lds[K == 4 ? 4096 : 1];
@@ -657,9 +661,22 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   __shared__ u64 seg_ctr[2];  // (rows << 32) | entries of the chunk being laid out
   __shared__ int32_t seg_v[BLOCK], seg_start[BLOCK], seg_base[BLOCK], seg_at[kBuckets];
   constexpr int NW = BLOCK / 64;
-  constexpr int WH = K == 4 ? kWaveHash : kWave5Hash;  // per-wave hash words
-  __shared__ uint32_t wh[NW * WH];  // light anchors: per-wave hashes of the sides' neighbourhoods
-  __shared__ int32_t wcnt[NW * NL];  // per-wave set sizes
+  constexpr int WH = K == 4 ? kWaveHash : 0;  // per-wave hash words
+  constexpr int NCN = K == 4 ? NW : kNP5;     // set-size rows: one per wave (k = 4), per light partner (k = 5)
+  __shared__ uint32_t wh[K == 4 ? NW * WH : 1];  // light anchors: per-wave hashes of the sides' neighbourhoods
+  __shared__ int32_t wcnt[NCN * NL];
+  // k = 5 light partners of one unit: merged table of their neighbourhoods
+  // (vertex -> 2 type bits per partner, partner index + 1 of the vertex
+  // itself), per-unit move counters, the a-part set sizes, the partners
+  constexpr int T5 = K == 5 ? kT5 : 1, P5 = K == 5 ? kNP5 : 1;
+  __shared__ uint32_t tkey[T5];
+  __shared__ u64 ttyp[T5];
+  __shared__ uint8_t tpid[T5];
+  __shared__ uint32_t U5[K == 5 ? kU5 : 1];
+  __shared__ int32_t cnU[16];
+  __shared__ int32_t p5_v[P5], p5_off[P5], p5_dc[P5], p5_ctl[5];
+  __shared__ uint16_t tlist[K == 5 ? kT5Load : 1];  // slots of the table's keys
+  __shared__ uint32_t p5_base[P5], p5_db[P5];
   // k = 4: the no-edge half of every edge move, per label pair (min, max),
   // summed for the current anchor and added in its closed form (per wave for
   // the wave paths, one table for the workgroup path)
@@ -679,7 +696,16 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   if (threadIdx.x < 2) seg_ctr[threadIdx.x] = 0;
   for (int i = threadIdx.x; i < HUBS * 9; i += BLOCK) W[i] = 0u;
   for (int i = threadIdx.x; i < NW * WH; i += BLOCK) wh[i] = kEmptySlot;
-  for (int i = threadIdx.x; i < NW * NL; i += BLOCK) wcnt[i] = 0;
+  for (int i = threadIdx.x; i < NCN * NL; i += BLOCK) wcnt[i] = 0;
+  if (K == 5) {
+    for (int i = threadIdx.x; i < T5; i += BLOCK) {
+      tkey[i] = kEmptySlot;
+      ttyp[i] = 0ull;
+      tpid[i] = 0;
+    }
+    for (int i = threadIdx.x; i < kU5; i += BLOCK) U5[i] = 0u;
+    if (threadIdx.x < 16) cnU[threadIdx.x] = 0;
+  }
   if (K == 4) {
     for (int i = threadIdx.x; i < NW * NL * NL; i += BLOCK) wE[i] = 0u;
     for (int i = threadIdx.x; i < NL * NL; i += BLOCK) bE[i] = 0u;
@@ -690,6 +716,9 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
 
   const int32_t n = G.n;
   const int32_t total = G.gs_off[n];
+  // the per-unit move counters of the k = 5 light path are 32-bit and stay
+  // within 3 |E*| in magnitude: exact while |E*| < 2^29
+  const bool fact5 = total < (1 << 30);
   int32_t cur_g = -1, row = 0, core = -1, par = 0;
   int32_t cbig = -1;  // slot of the current core among the precomputed big cores, or -1
   int64_t wbase = 0;  // first vertex of the core's graph
@@ -1191,128 +1220,209 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     for (int32_t i = lane; i < WH; i += 64) key[i] = kEmptySlot;
     wave_sync();
   };
-  // k = 5: a triple (b = core, a, c) with d*(c) <= kLight5C runs on one
-  // wave.  The types towards b and towards a come from the dense labels (a's
-  // are set for the whole unit), those of N(c) towards c from a
-  // wave-private hash HC.  R' = {a, c} u N(a) u N(c) \ {b} is taken 64
-  // members at a time, their N+ rows laid end to end over the lanes.  Same
-  // sums as anchor().
-  auto h5_slot = [](uint32_t y) { return (y * 2654435761u) >> (32 - kWave5HashBits); };
-  auto h5_insert = [&](uint32_t* T, uint32_t y, uint32_t t) {
-    uint32_t h = h5_slot(y);
-    while (atomicCAS(&T[h], kEmptySlot, (y << 2) | t) != kEmptySlot) h = (h + 1) & (kWave5Hash - 1);
+  // ---- k = 5, light partners: the side-a part shared by a unit's triples --
+  //
+  // For a unit (b = core, a) the triples (b; a, c) with a light partner c
+  // share most of their sums: the members of N(a), their W rows and their N+
+  // rows carry the same labels in every triple except where they meet N[c].
+  // A sub-chunk of up to kNP5 light partners is therefore done as
+  //   U  = the sums of {a} u N(a) \ {b} with every partner absent (labels of
+  //        b and a only), kept without the base code as counters per
+  //        (label x, label y, r) and added once per distinct base;
+  //   plus, per partner c, the difference to its own triple: items and edges
+  //        that meet N[c] (a member of N(c), an edge into N(c) or into c)
+  //        are moved to their labels in the triple, and c itself, when it is
+  //        in N(a), leaves the a-part and becomes a side;
+  //   plus the part of each triple outside N[a]: c and its neighbours
+  //        outside N[a], each vertex taken once for all the partners it
+  //        belongs to;
+  //   plus the closed form of each triple (one wave per partner).
+  // Both parts share one flattened scan.  The partners' neighbourhoods sit in
+  // one LDS table (key -> 2 type bits per partner, partner index + 1 of the
+  // vertex itself); label bit 6 marks its keys, so vertices outside every
+  // N(c) cost no lookup.  The sums equal those of anchor() for each triple.
+  auto u5i = [](uint32_t X, uint32_t Y, uint32_t r) { return X * 48u + Y * 3u + (r - 1u); };
+  auto t5_slot = [](uint32_t v) { return (v * 2654435761u) >> (32 - kT5Bits); };
+  auto t5_insert = [&](uint32_t v) -> uint32_t {  // at most kT5Load < kT5 keys: a slot is always found
+    uint32_t h = t5_slot(v);
+    for (int i = 0; i < kT5; ++i) {
+      const uint32_t old = atomicCAS(&tkey[h], kEmptySlot, v);
+      if (old == kEmptySlot) tlist[atomicAdd(&p5_ctl[4], 1)] = (uint16_t)h;
+      if (old == kEmptySlot || old == v) return h;
+      h = (h + 1) & (kT5 - 1);
+    }
+    return kT5;
   };
-  auto h5_type = [&](const uint32_t* T, uint32_t y) -> uint32_t {
-    uint32_t h = h5_slot(y);
-    for (;;) {
-      const uint32_t e = T[h];
-      if (e == kEmptySlot) return 0u;
-      if ((e >> 2) == y) return e & 3u;
-      h = (h + 1) & (kWave5Hash - 1);
+  auto t5_find = [&](uint32_t v) -> uint32_t {  // v carries label bit 6, so it is a key
+    uint32_t h = t5_slot(v);
+    for (int i = 0; i < kT5; ++i) {
+      if (tkey[h] == v) return h;
+      h = (h + 1) & (kT5 - 1);
+    }
+    return kT5;
+  };
+  // moves of one edge q -> y (r = type of y relative to q, sign s): the edge
+  // terms of anchor() with the pair that cancels when y is in R' left out
+  auto emove = [&](uint32_t base, uint32_t Lq, bool mq, uint32_t Ly, bool sy, uint32_t r, u64 s) {
+    const bool it = sy || (Ly >> 2);
+    const uint32_t cq = Lq & 3u, cy = Ly & 3u;
+    if (cq && cy && !it) edge(base, cq, cy, r, (u64)0 - s);
+    if (mq && !sy) edge(base, Lq, Ly, r, s);
+    if (cq && it && !sy) edge(base, cq, Ly, r, (u64)0 - s);
+  };
+  auto umove = [&](uint32_t Lq, bool mq, uint32_t Ly, bool sy, uint32_t r) {
+    const bool it = sy || (Ly >> 2);
+    const uint32_t cq = Lq & 3u, cy = Ly & 3u;
+    if (cq && cy && !it) atomicAdd(&U5[u5i(cq, cy, r)], ~0u);
+    if (mq && !sy) atomicAdd(&U5[u5i(Lq, Ly, r)], 1u);
+    if (cq && it && !sy) atomicAdd(&U5[u5i(cq, Ly, r)], ~0u);
+  };
+  auto pairs2 = [](u64 t) { return (t | (t >> 1)) & 0x5555555555555555ull; };  // bit 2p: partner p present
+  auto t5_get = [&](uint32_t v, uint32_t lv, u64& t, int32_t& pv) {
+    t = 0ull;
+    pv = -1;
+    if (lv & kInT5) {
+      const uint32_t h = t5_find(v);
+      if (h < kT5) {
+        t = ttyp[h];
+        pv = (int32_t)tpid[h] - 1;
+      }
     }
   };
-  auto wave_triple5 = [&](int32_t b, int32_t a, int32_t c2, uint32_t base) {
+  // labels of an N+ entry y for partner p: side flag and label in the triple
+  auto ylab = [&](int32_t y, int32_t a, uint32_t ly, u64 ty, int32_t py, int32_t p, bool& syT) -> uint32_t {
+    syT = y == a || py == p;
+    return syT ? (ly & 3u) : ((ly & 15u) | (((uint32_t)(ty >> (2 * p)) & 3u) << 4));
+  };
+  // a-part item i of {a} u N(a) \ {b}: set size and W row, into U and into
+  // the per-partner differences
+  auto u5_pick = [&](int32_t b, int32_t a, int32_t aa, int32_t i) -> int32_t {
+    int32_t q = a;
+    if (i > 0) {
+      q = (int32_t)(G.gs_idx[aa + i - 1] & kIdMask);
+      if (q == b) return -1;
+    }
+    const bool mq = i > 0;
+    const uint32_t lq = lab.get((uint32_t)q);
+    const uint32_t Lq = lq & (mq ? 15u : 3u), cq = Lq & 3u;
+    u64 tq;
+    int32_t pq;
+    t5_get((uint32_t)q, lq, tq, pq);
+    if (mq) atomicAdd(&cnU[Lq], 1);
+    if (pq >= 0) atomicAdd(&wcnt[pq * NL + Lq], -1);  // partner q: a side of its own triple
+    u64 cm = mq ? pairs2(tq) : 0ull;
+    if (pq >= 0) cm &= ~(1ull << (2 * pq));
+    for (u64 m = cm; m; m &= m - 1ull) {
+      const int32_t p = __builtin_ctzll(m) >> 1;
+      atomicAdd(&wcnt[p * NL + Lq], -1);
+      atomicAdd(&wcnt[p * NL + (Lq | (((uint32_t)(tq >> (2 * p)) & 3u) << 4))], 1);
+    }
+    const Row9 wq = load_w(q);
+#pragma unroll
+    for (int tr = 0; tr < 9; ++tr) {
+      const uint32_t w = wq.v[tr];
+      if (!w) continue;
+      const uint32_t tp = (uint32_t)(tr / 3) + 1u, r = (uint32_t)(tr % 3) + 1u;
+      if (cq) atomicAdd(&U5[u5i(tp, cq, r)], (uint32_t)0 - w);
+      if (mq) atomicAdd(&U5[u5i(tp, Lq, r)], w);
+      if (pq >= 0) edge(p5_base[pq], tp, Lq, r, (u64)0 - w);  // minus the member, the side's term stays
+      for (u64 m = cm; m; m &= m - 1ull) {
+        const int32_t p = __builtin_ctzll(m) >> 1;
+        const uint32_t bp = p5_base[p];
+        edge(bp, tp, Lq | (((uint32_t)(tq >> (2 * p)) & 3u) << 4), r, (u64)w);
+        edge(bp, tp, Lq, r, (u64)0 - w);
+      }
+    }
+    return q;
+  };
+  // c-part item k (a key of the partner table outside N[a]): a partner as a
+  // side, and a member of the neighbourhoods of the partners it is in
+  auto c5_pick = [&](int32_t a, int32_t k) -> int32_t {
+    const uint32_t h = tlist[k];
+    const int32_t q = (int32_t)tkey[h];
+    const uint32_t lq = lab.get((uint32_t)q);
+    if (q == a || ((lq >> 2) & 3u)) return -1;  // in the a-part
+    const u64 tq = ttyp[h];
+    const int32_t pq = (int32_t)tpid[h] - 1;
+    const uint32_t cq = lq & 3u;
+    const u64 cm = pairs2(tq);
+    for (u64 m = cm; m; m &= m - 1ull) {
+      const int32_t p = __builtin_ctzll(m) >> 1;
+      atomicAdd(&wcnt[p * NL + (cq | (((uint32_t)(tq >> (2 * p)) & 3u) << 4))], 1);
+    }
+    const Row9 wq = load_w(q);
+#pragma unroll
+    for (int tr = 0; tr < 9; ++tr) {
+      const uint32_t w = wq.v[tr];
+      if (!w) continue;
+      const uint32_t tp = (uint32_t)(tr / 3) + 1u, r = (uint32_t)(tr % 3) + 1u;
+      if (pq >= 0 && cq) edge(p5_base[pq], tp, cq, r, (u64)0 - w);
+      for (u64 m = cm; m; m &= m - 1ull) {
+        const int32_t p = __builtin_ctzll(m) >> 1;
+        const uint32_t bp = p5_base[p];
+        if (cq) edge(bp, tp, cq, r, (u64)0 - w);
+        edge(bp, tp, cq | (((uint32_t)(tq >> (2 * p)) & 3u) << 4), r, (u64)w);
+      }
+    }
+    return q;
+  };
+  // entry (y, r) of N+(q) for an item q of either part
+  auto s5_visit = [&](int32_t b, int32_t a, int32_t q, uint32_t f) {
+    const int32_t y = (int32_t)(f & kIdMask);
+    if (y == b) return;
+    const uint32_t r = f >> kTypeShift;
+    const uint32_t lq = lab.get((uint32_t)q), ly = lab.get((uint32_t)y);
+    u64 tq, ty;
+    int32_t pq, py;
+    t5_get((uint32_t)q, lq, tq, pq);
+    t5_get((uint32_t)y, ly, ty, py);
+    if (q != a && !((lq >> 2) & 3u)) {  // c-part: q is outside N[a]
+      const uint32_t cq = lq & 3u;
+      if (pq >= 0) {
+        bool syT;
+        const uint32_t LyT = ylab(y, a, ly, ty, py, pq, syT);
+        if (syT || LyT) emove(p5_base[pq], cq, false, LyT, syT, r, 1ull);
+      }
+      for (u64 m = pairs2(tq); m; m &= m - 1ull) {
+        const int32_t p = __builtin_ctzll(m) >> 1;
+        bool syT;
+        const uint32_t LyT = ylab(y, a, ly, ty, py, p, syT);
+        if (syT || LyT) emove(p5_base[p], cq | (((uint32_t)(tq >> (2 * p)) & 3u) << 4), true, LyT, syT, r, 1ull);
+      }
+      return;
+    }
+    const bool mq = q != a, syU = y == a;
+    const uint32_t Lq = lq & (mq ? 15u : 3u), LyU = ly & (syU ? 3u : 15u);
+    const bool inU = syU || LyU;
+    if (inU) umove(Lq, mq, LyU, syU, r);
+    if (!((lq | ly) & kInT5)) return;
+    if (pq >= 0) {  // partner q: its member edge leaves, its side edge comes in
+      if (inU) emove(p5_base[pq], Lq, mq, LyU, syU, r, kMinusOne);
+      bool syT;
+      const uint32_t LyT = ylab(y, a, ly, ty, py, pq, syT);
+      if (syT || LyT) emove(p5_base[pq], Lq & 3u, false, LyT, syT, r, 1ull);
+    }
+    u64 cm = pairs2((mq ? tq : 0ull) | ty);
+    if (py >= 0) cm |= 1ull << (2 * py);
+    if (pq >= 0) cm &= ~(1ull << (2 * pq));
+    for (u64 m = cm; m; m &= m - 1ull) {
+      const int32_t p = __builtin_ctzll(m) >> 1;
+      const uint32_t bp = p5_base[p];
+      const uint32_t LT = mq ? (Lq | (((uint32_t)(tq >> (2 * p)) & 3u) << 4)) : Lq;
+      bool syT;
+      const uint32_t LyT = ylab(y, a, ly, ty, py, p, syT);
+      if (syT || LyT) emove(bp, LT, mq, LyT, syT, r, 1ull);
+      if (inU) emove(bp, Lq, mq, LyU, syU, r, kMinusOne);
+    }
+  };
+  // closed form of light partner p on one wave: its set sizes are the a-part
+  // sizes plus its own differences; then the non-empty sets of the 63
+  auto close5 = [&](int32_t p, int32_t a) {
     const int32_t lane = (int32_t)(threadIdx.x & 63u);
-    uint32_t* HC = wh + (threadIdx.x >> 6) * WH;
-    int32_t* cn = wcnt + (threadIdx.x >> 6) * NL;
-    const int32_t aa = G.gs_off[a], da = G.gs_off[a + 1] - aa;
-    const int32_t ca2 = G.gs_off[c2], dc2 = G.gs_off[c2 + 1] - ca2;  // <= kLight5C
-    for (int32_t i = lane; i < dc2; i += 64) {
-      const uint32_t e = G.gs_idx[ca2 + i];
-      if ((int32_t)(e & kIdMask) != b) h5_insert(HC, e & kIdMask, e >> kTypeShift);
-    }
-    wave_sync();
-    auto is_side = [&](int32_t y) { return y == a || y == c2; };
-    const int32_t items = 2 + da + dc2;
-    for (int32_t i0 = 0; i0 < items; i0 += 64) {
-      const int32_t i = i0 + lane;
-      int32_t q = -1;
-      uint32_t Lq = 0;
-      int32_t len = 0, rb = 0;
-      if (i < items) {
-        if (i < 2) {
-          q = i == 0 ? a : c2;
-          Lq = lab.get((uint32_t)q) & 3u;
-        } else if (i < 2 + da) {
-          const uint32_t e = G.gs_idx[aa + i - 2];
-          q = (int32_t)(e & kIdMask);
-          if (q == b || is_side(q)) q = -1;
-          else Lq = (lab.get((uint32_t)q) & 15u) | (h5_type(HC, (uint32_t)q) << 4);
-        } else {
-          const uint32_t e = G.gs_idx[ca2 + i - 2 - da];
-          q = (int32_t)(e & kIdMask);
-          const uint32_t Lx = lab.get((uint32_t)q);
-          if (q == b || is_side(q) || ((Lx >> 2) & 3u)) q = -1;  // members of N(a) are listed above
-          else Lq = (Lx & 3u) | ((e >> kTypeShift) << 4);
-        }
-        if (q >= 0) {
-          const bool mq = !is_side(q);
-          const uint32_t cq = Lq & 3u;
-          if (mq) atomicAdd(&cn[Lq], 1);
-          const Row9 wq = load_w(q);
-#pragma unroll
-          for (int tr = 0; tr < 9; ++tr) {
-            const uint32_t w = wq.v[tr];
-            if (!w) continue;
-            const uint32_t tp = (uint32_t)(tr / 3) + 1u, r = (uint32_t)(tr % 3) + 1u;
-            if (cq) edge(base, tp, cq, r, (u64)0 - (u64)w);
-            if (mq) edge(base, tp, Lq, r, (u64)w);
-          }
-          rb = G.np_off[q];
-          len = G.np_off[q + 1] - rb;
-        }
-      }
-      int32_t inc = len;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const int32_t t = __shfl_up(inc, d);
-        if (lane >= d) inc += t;
-      }
-      const int32_t tot = __shfl(inc, 63);
-      const int32_t rs = rb - (inc - len);
-      for (int32_t jb = 0; jb < tot; jb += 64 * kUnroll) {
-        int32_t sqs[kUnroll];
-        uint32_t sLs[kUnroll], fs[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int32_t j = jb + u * 64 + lane;
-          int32_t sl = 0;
-#pragma unroll
-          for (int st2 = 32; st2; st2 >>= 1)
-            if (__shfl(inc, sl + st2 - 1) <= j) sl += st2;
-          sqs[u] = __shfl(q, sl);
-          sLs[u] = (uint32_t)__shfl((int32_t)Lq, sl);
-          const int32_t srs = __shfl(rs, sl);
-          fs[u] = j < tot ? G.np_idx[srs + j] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          if (jb + u * 64 + lane >= tot) continue;
-          const uint32_t f = fs[u];
-          const int32_t y = (int32_t)(f & kIdMask);
-          if (y == b) continue;
-          const bool sy = is_side(y);
-          uint32_t Ly = lab.get((uint32_t)y) & (sy ? 3u : 15u);
-          if (!sy) Ly |= h5_type(HC, (uint32_t)y) << 4;
-          if (!Ly && !sy) continue;
-          const int32_t sq = sqs[u];
-          const uint32_t sL = sLs[u];
-          const bool mq = !is_side(sq), my = !sy;
-          const uint32_t r = f >> kTypeShift, cq = sL & 3u, cy = Ly & 3u;
-          if (cq && cy) edge(base, cq, cy, r, kMinusOne);
-          if (mq && my) edge(base, sL, Ly, r, 1ull);
-          if (cq && (sy || (Ly >> 2))) {  // p = sq is also counted in W[y]
-            if (cy) edge(base, cq, cy, r, 1ull);
-            if (my) edge(base, cq, Ly, r, kMinusOne);
-          }
-        }
-      }
-    }
-    // edges inside N(core) with core-only labels
-    if (lane < 27) {
-      const uint32_t w = Mc[lane];
-      if (w) edge(base, (uint32_t)lane / 9 + 1, ((uint32_t)lane / 3) % 3 + 1, (uint32_t)lane % 3 + 1, (u64)w);
-    }
+    const int32_t c2 = p5_v[p];
+    const uint32_t base = p5_base[p];
+    int32_t* cn = wcnt + p * NL;
+    if (lane < 16) cn[lane] += cnU[lane];
     wave_sync();
     // sizes of the core-only sets: N(core) minus the sides minus R'
     if (lane >= 1 && lane <= 3) {
@@ -1322,23 +1432,29 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       cn[lane] = v;
     }
     wave_sync();
-    // closed form over the non-empty sets (NL = 64 labels, one per lane)
-    const int32_t myc = lane < NL ? cn[lane] : 0;
-    const unsigned long long nzm = __ballot(lane > 0 && myc != 0);
+    // the non-empty sets (NL = 64 labels, one per lane) compacted to the low
+    // lanes by a lane permutation
+    const int32_t myc = cn[lane];
+    const bool nzb = lane > 0 && myc != 0;
+    const unsigned long long nzm = __ballot(nzb);
     const int32_t nz = __popcll(nzm);
-    if (lane > 0 && myc != 0) HC[__popcll(nzm & ((1ull << lane) - 1ull))] = (uint32_t)lane;  // HC is free now
-    wave_sync();
-    for (int32_t pq = lane; pq < nz * nz; pq += 64) {
+    const int32_t pos = __popcll(nzm & ((1ull << lane) - 1ull));
+    const int32_t dst = nzb ? pos : nz + (lane - pos);
+    const int32_t lbl = __builtin_amdgcn_ds_permute(dst * 4, lane);
+    const int32_t cnt_c = __builtin_amdgcn_ds_permute(dst * 4, myc);
+    for (int32_t pq0 = 0; pq0 < nz * nz; pq0 += 64) {
+      const int32_t pq = pq0 + lane;
       const int32_t ia = pq / nz, ib = pq - ia * nz;
-      if (ia > ib) continue;
-      const uint32_t La = HC[ia], Lb = HC[ib];
-      const u64 na = (u64)cn[La], nb = (u64)cn[Lb];
-      const u64 w = ia == ib ? na * (na - 1) / 2 : na * nb;
-      if (w) atomicAdd(&hist[lut[base | slot_code<K, K - 2>(La) | slot_code<K, K - 1>(Lb)]], w);
+      const int32_t sa = min(ia, 63), sb = min(ib, 63);
+      const uint32_t La = (uint32_t)__shfl(lbl, sa), Lb = (uint32_t)__shfl(lbl, sb);
+      const u64 na = (u64)(int64_t)__shfl(cnt_c, sa), nb = (u64)(int64_t)__shfl(cnt_c, sb);
+      if (pq < nz * nz && ia <= ib) {
+        const u64 w = ia == ib ? na * (na - 1) / 2 : na * nb;
+        if (w) atomicAdd(&hist[lut[base | slot_code<K, K - 2>(La) | slot_code<K, K - 1>(Lb)]], w);
+      }
     }
     wave_sync();
-    if (lane < NL) cn[lane] = 0;
-    for (int32_t i = lane; i < kWave5Hash; i += 64) HC[i] = kEmptySlot;
+    cn[lane] = 0;
     wave_sync();
   };
   // A unit of a new core: flush the histogram on a graph change and set up
@@ -1518,8 +1634,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       if (K == 4) {  // anchor edge {c, x} owned by its higher-rank end
         const int32_t dc = rowb - rowa, dx = G.gs_off[x + 1] - G.gs_off[x];
         unit = dx < dc || (dx == dc && x < c);
-      } else {  // unit (b = c, a = x) with partners after x in c's row
-        unit = j + 1 < rowb;
+      } else {  // unit (b = c, a = x) with the neighbours of b of lower rank than x as partners
+        unit = rowb - rowa >= 2;
       }
       if (!unit) continue;
       if (c != core) {
@@ -1546,10 +1662,14 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
         const uint32_t base = ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u);
         anchor(c, x, -1, base);
       } else {
-        // partners c2 after x in c's row, BLOCK at a time: light triples
-        // (d*(c2) <= kLight5C) one per wave, the others on the workgroup;
-        // x's types stay in the dense labels for both
-        for (int32_t jc0 = j + 1; jc0 < rowb; jc0 += BLOCK) {
+        // partners: the neighbours c2 of b of lower rank (d*, id) than x, so
+        // that of the two sides of a triple the heavier one is shared by the
+        // unit and the lighter one is done per triple.  Scanned BLOCK at a
+        // time: light partners (d*(c2) <= kLight5C) in sub-chunks, the
+        // others on the workgroup one by one; x's types stay in the dense
+        // labels for both
+        const int32_t dx = xb - xa;
+        for (int32_t jc0 = rowa; jc0 < rowb; jc0 += BLOCK) {
           const int32_t jce = min(rowb, jc0 + BLOCK);
           if (threadIdx.x < 3) unit_ctr[threadIdx.x] = 0;
           bar<GL>();
@@ -1557,10 +1677,13 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
             const int32_t jc = jc0 + (int32_t)threadIdx.x;
             if (jc < jce) {
               const int32_t c2 = (int32_t)(G.gs_idx[jc] & kIdMask);
-              if (G.gs_off[c2 + 1] - G.gs_off[c2] <= kLight5C)
-                unit_list[BLOCK - 1 - atomicAdd(&unit_ctr[1], 1)] = jc;
-              else
-                unit_list[atomicAdd(&unit_ctr[0], 1)] = jc;
+              const int32_t d2 = G.gs_off[c2 + 1] - G.gs_off[c2];
+              if (d2 < dx || (d2 == dx && c2 < x)) {
+                if (fact5 && d2 <= kLight5C)
+                  unit_list[BLOCK - 1 - atomicAdd(&unit_ctr[1], 1)] = jc;
+                else
+                  unit_list[atomicAdd(&unit_ctr[0], 1)] = jc;
+              }
             }
           }
           bar<GL>();
@@ -1588,20 +1711,134 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
             bar<GL>();
           }
           if (nlight > 0) {
-            for (;;) {  // light triples are handed to the waves one at a time
-              int32_t u = 0;
-              if ((threadIdx.x & 63u) == 0) u = atomicAdd(&unit_ctr[2], 1);
-              u = __shfl(u, 0);
-              if (u >= nlight) break;
-              const uint32_t ec = G.gs_idx[unit_list[BLOCK - 1 - u]];
-              const int32_t c2 = (int32_t)(ec & kIdMask);
-              const uint32_t tbc = ec >> kTypeShift;
-              const uint32_t tac = (lab.get((uint32_t)c2) >> 2) & 3u;
-              if (tac && (c > x || c > c2)) continue;  // triangle: taken at its smallest id
-              const uint32_t base = ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u) |
-                                    ((tbc & 1u) ? 1u << cbit<K>(0, 2) : 0u) | ((tbc & 2u) ? 1u << cbit<K>(2, 0) : 0u) |
-                                    ((tac & 1u) ? 1u << cbit<K>(1, 2) : 0u) | ((tac & 2u) ? 1u << cbit<K>(2, 1) : 0u);
-              wave_triple5(c, x, c2, base);
+            // light partners, up to kNP5 at a time with at most kT5Load keys
+            // in the merged table; triangles not taken here are dropped
+            for (int32_t u0 = 0; u0 < nlight;) {
+              if (threadIdx.x < 64) {
+                const int32_t lane = (int32_t)threadIdx.x, u = u0 + lane;
+                const bool in = lane < kNP5 && u < nlight;
+                int32_t c2 = -1, cost = 0;
+                uint32_t base = 0;
+                if (in) {
+                  const uint32_t ec = G.gs_idx[unit_list[BLOCK - 1 - u]];
+                  c2 = (int32_t)(ec & kIdMask);
+                  const uint32_t tbc = ec >> kTypeShift;
+                  const uint32_t tac = (lab.get((uint32_t)c2) >> 2) & 3u;
+                  if (tac && (c > x || c > c2)) {
+                    c2 = -1;  // triangle: taken at its smallest id
+                  } else {
+                    cost = G.gs_off[c2 + 1] - G.gs_off[c2] + 1;
+                    base = ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u) |
+                           ((tbc & 1u) ? 1u << cbit<K>(0, 2) : 0u) | ((tbc & 2u) ? 1u << cbit<K>(2, 0) : 0u) |
+                           ((tac & 1u) ? 1u << cbit<K>(1, 2) : 0u) | ((tac & 2u) ? 1u << cbit<K>(2, 1) : 0u);
+                  }
+                }
+                int32_t inc = cost;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                  const int32_t t = __shfl_up(inc, d);
+                  if (lane >= d) inc += t;
+                }
+                // a prefix of the lanes: lane 0 always fits (cost <= kLight5C + 1)
+                const bool take = in && inc <= kT5Load;
+                const int32_t ntake = __popcll(__ballot(take));
+                const bool act = take && c2 >= 0;
+                const unsigned long long am = __ballot(act);
+                if (act) {
+                  const int32_t k = __popcll(am & ((1ull << lane) - 1ull));
+                  p5_v[k] = c2;
+                  p5_base[k] = base;
+                  p5_off[k] = inc - cost;
+                }
+                const int32_t tot = __shfl(inc, ntake - 1);
+                if (lane == 0) {
+                  p5_ctl[0] = __popcll(am);
+                  p5_ctl[1] = u0 + ntake;
+                  p5_ctl[2] = tot;
+                  p5_ctl[3] = 0;
+                  p5_ctl[4] = 0;
+                }
+              }
+              bar<GL>();
+              const int32_t np = p5_ctl[0], tot = p5_ctl[2];
+              u0 = p5_ctl[1];
+              if (np == 0) {
+                bar<GL>();
+                continue;
+              }
+              // merged table: partner k's row at [p5_off[k] + 1, ...), k itself at p5_off[k]
+              for (int32_t t = threadIdx.x; t < tot; t += BLOCK) {
+                int32_t lo = 0, hi = np - 1;
+                while (lo < hi) {
+                  const int32_t mid = (lo + hi + 1) >> 1;
+                  if (p5_off[mid] <= t) lo = mid; else hi = mid - 1;
+                }
+                const int32_t c2 = p5_v[lo], kk = t - p5_off[lo];
+                if (kk == 0) {
+                  const uint32_t h = t5_insert((uint32_t)c2);
+                  if (h < kT5) tpid[h] = (uint8_t)(lo + 1);
+                  lab.set_bits((uint32_t)c2, kInT5);
+                } else {
+                  const uint32_t e = G.gs_idx[G.gs_off[c2] + kk - 1];
+                  const uint32_t v = e & kIdMask;
+                  if ((int32_t)v != c) {
+                    const uint32_t h = t5_insert(v);
+                    if (h < kT5) atomicOr(&ttyp[h], (u64)(e >> kTypeShift) << (2 * lo));
+                    lab.set_bits(v, kInT5);
+                  }
+                }
+              }
+              // distinct base codes of the sub-chunk with their multiplicities
+              if ((int32_t)threadIdx.x < np) {
+                const uint32_t bs = p5_base[threadIdx.x];
+                bool first = true;
+                int32_t nb = 0;
+                for (int32_t k = 0; k < np; ++k) {
+                  const bool same = p5_base[k] == bs;
+                  nb += same;
+                  first = first && !(same && k < (int32_t)threadIdx.x);
+                }
+                if (first) {
+                  const int32_t d = atomicAdd(&p5_ctl[3], 1);
+                  p5_db[d] = bs;
+                  p5_dc[d] = nb;
+                }
+              }
+              // edges inside N(core): the same for every triple of the unit
+              if (threadIdx.x < 27) {
+                const uint32_t w = Mc[threadIdx.x];
+                if (w) U5[u5i(threadIdx.x / 9 + 1, (threadIdx.x / 3) % 3 + 1, threadIdx.x % 3 + 1)] += w;
+              }
+              bar<GL>();
+              {
+                const int32_t na = 1 + (xb - xa);
+                flat_rows(
+                    na + p5_ctl[4],
+                    [&](int32_t i) { return i < na ? u5_pick(c, x, xa, i) : c5_pick(x, i - na); },
+                    [&](int32_t q, uint32_t f) { s5_visit(c, x, q, f); });
+              }
+              {
+                const int32_t nd = p5_ctl[3];
+                for (int32_t t = threadIdx.x; t < kU5; t += BLOCK) {
+                  const uint32_t w = U5[t];
+                  if (!w) continue;
+                  U5[t] = 0u;
+                  const uint32_t X = (uint32_t)t / 48u, Y = ((uint32_t)t / 3u) % 16u, r = (uint32_t)t % 3u + 1u;
+                  const u64 w64 = (u64)(int64_t)(int32_t)w;
+                  for (int32_t d = 0; d < nd; ++d) edge(p5_db[d], X, Y, r, w64 * (u64)p5_dc[d]);
+                }
+              }
+              for (int32_t p = (int32_t)(threadIdx.x >> 6); p < np; p += NW) close5(p, x);
+              bar<GL>();
+              for (int32_t k = threadIdx.x; k < p5_ctl[4]; k += BLOCK) {
+                const uint32_t h = tlist[k];
+                lab.clear_bits(tkey[h], kInT5);
+                tkey[h] = kEmptySlot;
+                ttyp[h] = 0ull;
+                tpid[h] = 0;
+              }
+              if (threadIdx.x < 16) cnU[threadIdx.x] = 0;
+              bar<GL>();
             }
           }
           // skipped triples read x's labels without a barrier (see k5_kernel)
