@@ -1263,12 +1263,30 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   };
   // moves of one edge q -> y (r = type of y relative to q, sign s): the edge
   // terms of anchor() with the pair that cancels when y is in R' left out
+  // (the table reads of all three terms are issued before their counters)
   auto emove = [&](uint32_t base, uint32_t Lq, bool mq, uint32_t Ly, bool sy, uint32_t r, u64 s) {
     const bool it = sy || (Ly >> 2);
     const uint32_t cq = Lq & 3u, cy = Ly & 3u;
-    if (cq && cy && !it) edge(base, cq, cy, r, (u64)0 - s);
-    if (mq && !sy) edge(base, Lq, Ly, r, s);
-    if (cq && it && !sy) edge(base, cq, Ly, r, (u64)0 - s);
+    const bool e1 = cq && cy && !it, e2 = mq && !sy, e3 = cq && it && !sy;
+    const uint32_t rc = rel_code<K>(r);
+    const uint32_t b1 = base | slot_code<K, S1>(cq) | slot_code<K, S2>(cy);
+    const uint32_t b2 = base | slot_code<K, S1>(Lq) | slot_code<K, S2>(Ly);
+    const uint32_t b3 = base | slot_code<K, S1>(cq) | slot_code<K, S2>(Ly);
+    const uint32_t k1a = e1 ? lut[b1 | rc] : 0u, k1b = e1 ? lut[b1] : 0u;
+    const uint32_t k2a = e2 ? lut[b2 | rc] : 0u, k2b = e2 ? lut[b2] : 0u;
+    const uint32_t k3a = e3 ? lut[b3 | rc] : 0u, k3b = e3 ? lut[b3] : 0u;
+    if (e1) {
+      atomicAdd(&hist[k1a], (u64)0 - s);
+      atomicAdd(&hist[k1b], s);
+    }
+    if (e2) {
+      atomicAdd(&hist[k2a], s);
+      atomicAdd(&hist[k2b], (u64)0 - s);
+    }
+    if (e3) {
+      atomicAdd(&hist[k3a], (u64)0 - s);
+      atomicAdd(&hist[k3b], s);
+    }
   };
   auto umove = [&](uint32_t Lq, bool mq, uint32_t Ly, bool sy, uint32_t r) {
     const bool it = sy || (Ly >> 2);
@@ -1303,20 +1321,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       if (q == b) return -1;
     }
     const bool mq = i > 0;
-    const uint32_t lq = lab.get((uint32_t)q);
-    const uint32_t Lq = lq & (mq ? 15u : 3u), cq = Lq & 3u;
-    u64 tq;
-    int32_t pq;
-    t5_get((uint32_t)q, lq, tq, pq);
+    const uint32_t Lq = lab.get((uint32_t)q) & (mq ? 15u : 3u), cq = Lq & 3u;
     if (mq) atomicAdd(&cnU[Lq], 1);
-    if (pq >= 0) atomicAdd(&wcnt[pq * NL + Lq], -1);  // partner q: a side of its own triple
-    u64 cm = mq ? pairs2(tq) : 0ull;
-    if (pq >= 0) cm &= ~(1ull << (2 * pq));
-    for (u64 m = cm; m; m &= m - 1ull) {
-      const int32_t p = __builtin_ctzll(m) >> 1;
-      atomicAdd(&wcnt[p * NL + Lq], -1);
-      atomicAdd(&wcnt[p * NL + (Lq | (((uint32_t)(tq >> (2 * p)) & 3u) << 4))], 1);
-    }
     const Row9 wq = load_w(q);
 #pragma unroll
     for (int tr = 0; tr < 9; ++tr) {
@@ -1325,46 +1331,65 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       const uint32_t tp = (uint32_t)(tr / 3) + 1u, r = (uint32_t)(tr % 3) + 1u;
       if (cq) atomicAdd(&U5[u5i(tp, cq, r)], (uint32_t)0 - w);
       if (mq) atomicAdd(&U5[u5i(tp, Lq, r)], w);
-      if (pq >= 0) edge(p5_base[pq], tp, Lq, r, (u64)0 - w);  // minus the member, the side's term stays
-      for (u64 m = cm; m; m &= m - 1ull) {
-        const int32_t p = __builtin_ctzll(m) >> 1;
-        const uint32_t bp = p5_base[p];
-        edge(bp, tp, Lq | (((uint32_t)(tq >> (2 * p)) & 3u) << 4), r, (u64)w);
-        edge(bp, tp, Lq, r, (u64)0 - w);
-      }
     }
     return q;
   };
-  // c-part item k (a key of the partner table outside N[a]): a partner as a
-  // side, and a member of the neighbourhoods of the partners it is in
-  auto c5_pick = [&](int32_t a, int32_t k) -> int32_t {
-    const uint32_t h = tlist[k];
-    const int32_t q = (int32_t)tkey[h];
-    const uint32_t lq = lab.get((uint32_t)q);
-    if (q == a || ((lq >> 2) & 3u)) return -1;  // in the a-part
-    const u64 tq = ttyp[h];
-    const int32_t pq = (int32_t)tpid[h] - 1;
-    const uint32_t cq = lq & 3u;
-    const u64 cm = pairs2(tq);
-    for (u64 m = cm; m; m &= m - 1ull) {
-      const int32_t p = __builtin_ctzll(m) >> 1;
-      atomicAdd(&wcnt[p * NL + (cq | (((uint32_t)(tq >> (2 * p)) & 3u) << 4))], 1);
+  // per-partner part of a table entry, one thread per (vertex v, partner p)
+  // pair: set sizes and W row of v in p's triple minus what U holds for it.
+  // self: v is the partner itself (a side), else v in N(p) with type tv.
+  auto pair5 = [&](int32_t a, int32_t p, int32_t v, bool self, uint32_t tv) {
+    if (v == a) return;  // a side in every triple, as in U
+    const uint32_t lv = lab.get((uint32_t)v);
+    const bool ina = (lv >> 2) & 3u;  // in N(a): an item of U
+    const uint32_t LU = lv & 15u, cv = lv & 3u;
+    const uint32_t LT = cv | (tv << 4) | (ina ? (lv & 12u) : 0u);
+    int32_t* cn = wcnt + p * NL;
+    if (self) {
+      if (ina) atomicAdd(&cn[LU], -1);
+    } else {
+      if (ina) atomicAdd(&cn[LU], -1);
+      atomicAdd(&cn[LT], 1);
     }
-    const Row9 wq = load_w(q);
+    const uint32_t bp = p5_base[p];
+    const Row9 wv = load_w(v);
+    // self: side of its own triple; when in N(a), its member terms in U
+    // leave.  Else a member with label LT instead of LU (or of nothing).
+    const bool plus = !self, minus = ina || cv;
+    const uint32_t Lm = ina ? LU : cv;
+    // table reads of one type tp (three r) first, then the counters
 #pragma unroll
-    for (int tr = 0; tr < 9; ++tr) {
-      const uint32_t w = wq.v[tr];
-      if (!w) continue;
-      const uint32_t tp = (uint32_t)(tr / 3) + 1u, r = (uint32_t)(tr % 3) + 1u;
-      if (pq >= 0 && cq) edge(p5_base[pq], tp, cq, r, (u64)0 - w);
-      for (u64 m = cm; m; m &= m - 1ull) {
-        const int32_t p = __builtin_ctzll(m) >> 1;
-        const uint32_t bp = p5_base[p];
-        if (cq) edge(bp, tp, cq, r, (u64)0 - w);
-        edge(bp, tp, cq | (((uint32_t)(tq >> (2 * p)) & 3u) << 4), r, (u64)w);
+    for (int t3 = 0; t3 < 3; ++t3) {
+      const uint32_t bt = bp | slot_code<K, S1>((uint32_t)t3 + 1u);
+      const uint32_t cpl = bt | slot_code<K, S2>(LT), cmi = bt | slot_code<K, S2>(Lm);
+      uint32_t kp[3][2], km[3][2];
+#pragma unroll
+      for (int r3 = 0; r3 < 3; ++r3) {
+        const uint32_t rc = rel_code<K>((uint32_t)r3 + 1u);
+        const bool on = wv.v[t3 * 3 + r3] != 0u;
+        kp[r3][0] = on && plus ? lut[cpl | rc] : 0u;
+        kp[r3][1] = on && plus ? lut[cpl] : 0u;
+        km[r3][0] = on && minus ? lut[cmi | rc] : 0u;
+        km[r3][1] = on && minus ? lut[cmi] : 0u;
+      }
+#pragma unroll
+      for (int r3 = 0; r3 < 3; ++r3) {
+        const u64 w = wv.v[t3 * 3 + r3];
+        if (!w) continue;
+        if (plus) {
+          atomicAdd(&hist[kp[r3][0]], w);
+          atomicAdd(&hist[kp[r3][1]], (u64)0 - w);
+        }
+        if (minus) {
+          atomicAdd(&hist[km[r3][0]], (u64)0 - w);
+          atomicAdd(&hist[km[r3][1]], w);
+        }
       }
     }
-    return q;
+  };
+  // c-part item k: a key of the partner table outside N[a]
+  auto c5_pick = [&](int32_t a, int32_t k) -> int32_t {
+    const int32_t q = (int32_t)tkey[tlist[k]];
+    return q == a || ((lab.get((uint32_t)q) >> 2) & 3u) ? -1 : q;
   };
   // entry (y, r) of N+(q) for an item q of either part
   auto s5_visit = [&](int32_t b, int32_t a, int32_t q, uint32_t f) {
@@ -1778,6 +1803,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                   const uint32_t h = t5_insert((uint32_t)c2);
                   if (h < kT5) tpid[h] = (uint8_t)(lo + 1);
                   lab.set_bits((uint32_t)c2, kInT5);
+                  pair5(x, lo, c2, true, 0u);
                 } else {
                   const uint32_t e = G.gs_idx[G.gs_off[c2] + kk - 1];
                   const uint32_t v = e & kIdMask;
@@ -1785,6 +1811,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                     const uint32_t h = t5_insert(v);
                     if (h < kT5) atomicOr(&ttyp[h], (u64)(e >> kTypeShift) << (2 * lo));
                     lab.set_bits(v, kInT5);
+                    pair5(x, lo, (int32_t)v, false, e >> kTypeShift);
                   }
                 }
               }
@@ -1825,7 +1852,23 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                   U5[t] = 0u;
                   const uint32_t X = (uint32_t)t / 48u, Y = ((uint32_t)t / 3u) % 16u, r = (uint32_t)t % 3u + 1u;
                   const u64 w64 = (u64)(int64_t)(int32_t)w;
-                  for (int32_t d = 0; d < nd; ++d) edge(p5_db[d], X, Y, r, w64 * (u64)p5_dc[d]);
+                  const uint32_t sx = slot_code<K, S1>(X) | slot_code<K, S2>(Y), rc = rel_code<K>(r);
+                  for (int32_t d0 = 0; d0 < nd; d0 += 4) {  // table reads of 4 bases, then the counters
+                    uint32_t kf[4], kn[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                      const uint32_t c0 = p5_db[min(d0 + u, nd - 1)] | sx;
+                      kf[u] = lut[c0 | rc];
+                      kn[u] = lut[c0];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                      if (d0 + u >= nd) break;
+                      const u64 wd = w64 * (u64)p5_dc[d0 + u];
+                      atomicAdd(&hist[kf[u]], wd);
+                      atomicAdd(&hist[kn[u]], (u64)0 - wd);
+                    }
+                  }
                 }
               }
               for (int32_t p = (int32_t)(threadIdx.x >> 6); p < np; p += NW) close5(p, x);
