@@ -774,8 +774,16 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   // one entry f of N+(v).  Uniform across the workgroup; ends with a barrier.
   // seg_ctr alternates between two words so that one of them can be cleared
   // while the other is read.
-  auto flat_rows = [&](int32_t items, auto&& pick, auto&& visit) {
+  // pre() runs once on every thread before the first rows are laid out
+  // (independent work that can share the first pass's latency).
+  auto flat_rows_pre = [&](int32_t items, auto&& pre, auto&& pick, auto&& visit) {
+    if (items <= 0) {
+      pre();
+      bar<GL>();
+      return;
+    }
     for (int32_t i0 = 0; i0 < items; i0 += BLOCK) {
+      if (i0 == 0) pre();
       const int32_t i = i0 + (int32_t)threadIdx.x;
       if (i < items) {
         const int32_t v = pick(i);
@@ -830,6 +838,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       par ^= 1;
     }
   };
+  auto flat_rows = [&](int32_t items, auto&& pick, auto&& visit) { flat_rows_pre(items, [] {}, pick, visit); };
   // per-core set-up (labels of N(core), type counts, M, W) and tear-down
   auto core_setup = [&](int32_t c) {
     const int32_t ca = G.gs_off[c], dcn = G.gs_off[c + 1] - ca;
@@ -1803,7 +1812,6 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                   const uint32_t h = t5_insert((uint32_t)c2);
                   if (h < kT5) tpid[h] = (uint8_t)(lo + 1);
                   lab.set_bits((uint32_t)c2, kInT5);
-                  pair5(x, lo, c2, true, 0u);
                 } else {
                   const uint32_t e = G.gs_idx[G.gs_off[c2] + kk - 1];
                   const uint32_t v = e & kIdMask;
@@ -1811,7 +1819,6 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                     const uint32_t h = t5_insert(v);
                     if (h < kT5) atomicOr(&ttyp[h], (u64)(e >> kTypeShift) << (2 * lo));
                     lab.set_bits(v, kInT5);
-                    pair5(x, lo, (int32_t)v, false, e >> kTypeShift);
                   }
                 }
               }
@@ -1839,8 +1846,28 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
               bar<GL>();
               {
                 const int32_t na = 1 + (xb - xa);
-                flat_rows(
-                    na + p5_ctl[4],
+                // the per-(vertex, partner) pairs of the table share the
+                // latency of the first layout pass: they go to the last
+                // threads, whose waves have no item when the items and the
+                // pairs fit in one pass together
+                auto pairs = [&] {
+                  for (int32_t t = BLOCK - 1 - (int32_t)threadIdx.x; t < tot; t += BLOCK) {
+                    int32_t lo = 0, hi = np - 1;
+                    while (lo < hi) {
+                      const int32_t mid = (lo + hi + 1) >> 1;
+                      if (p5_off[mid] <= t) lo = mid; else hi = mid - 1;
+                    }
+                    const int32_t c2 = p5_v[lo], kk = t - p5_off[lo];
+                    if (kk == 0) {
+                      pair5(x, lo, c2, true, 0u);
+                    } else {
+                      const uint32_t e = G.gs_idx[G.gs_off[c2] + kk - 1];
+                      if ((int32_t)(e & kIdMask) != c) pair5(x, lo, (int32_t)(e & kIdMask), false, e >> kTypeShift);
+                    }
+                  }
+                };
+                flat_rows_pre(
+                    na + p5_ctl[4], pairs,
                     [&](int32_t i) { return i < na ? u5_pick(c, x, xa, i) : c5_pick(x, i - na); },
                     [&](int32_t q, uint32_t f) { s5_visit(c, x, q, f); });
               }
