@@ -131,7 +131,11 @@ def kr5_kernel_bytes(st) -> float:
     (x, c, c2): the two side rows, 4 (d_x + d_c2), and per member q of
     N(x) u N(c2) its offsets and W row (44 B) and N+ row (4 d+(q)); the
     union is the sum over both rows minus the common neighbours, counted
-    through the co-degrees t(c, q): sum over c != q of C(t, 2) g(q)."""
+    through the co-degrees t(c, q): sum over c != q of C(t, 2) g(q).
+    Light triples (lighter side of degree <= 128) read the heavier side's
+    part f(x) = 4 d_x + sum g(q) once per sub-chunk of at most 32 partners
+    (and 768 table keys) instead of once per triple; the sub-chunks of a
+    unit are counted as ceil(max(n_l / 32, sum(d + 1) / 768))."""
     import scipy.sparse as sp
     n, u, v = st["n"], st["u"], st["v"]
     deg = st["deg"].astype(np.float64)
@@ -145,7 +149,20 @@ def kr5_kernel_bytes(st) -> float:
     t = A2.data[off]
     inter = float((t * (t - 1.0) / 2.0 * gq[A2.col[off]]).sum())
     core = float((12.0 * deg + 8.0 * st["splus"])[deg >= 2].sum())
-    return pairs - inter + core
+    # units (c, x): light partners are the neighbours of c of lower rank
+    src, dst = np.r_[u, v], np.r_[v, u]
+    key = deg * n + np.arange(n)  # rank (d*, id)
+    order = np.lexsort((key[dst], src))
+    cs, xs = src[order], dst[order]
+    light = (deg[xs] <= 128).astype(np.float64)
+    cl = np.cumsum(light) - light  # light entries before each position
+    cd = np.cumsum(light * (deg[xs] + 1.0)) - light * (deg[xs] + 1.0)
+    start = np.searchsorted(cs, cs, side="left")
+    nl = cl - cl[start]
+    sd = cd - cd[start]
+    nsub = np.where(nl > 0, np.ceil(np.maximum(nl / 32.0, sd / 768.0)), 0.0)
+    shared = float(((nl - nsub) * f[xs]).sum())
+    return pairs - inter + core - shared
 
 
 def k3_kernel_bytes(st) -> float:

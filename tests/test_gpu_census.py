@@ -310,6 +310,52 @@ def test_schemes_agree_on_power_law(pm):
     assert np.array_equal(a, b)
 
 
+def _partner_fan(n_part=60, d_part=30, d_a=40, seed=5):
+    """Centre 0 with a heavier side 1 and many light partners (of lower rank)
+    whose neighbourhoods overlap N(1), each other and side 1 itself; random
+    arc types.  Each unit (0, 1) has its light partners split over several
+    sub-chunks, by count and by the size of their merged neighbourhoods."""
+    rng = np.random.default_rng(seed)
+    arcs = set()
+
+    def link(x, y):
+        t = int(rng.integers(1, 4))
+        if t & 1:
+            arcs.add((x, y))
+        if t & 2:
+            arcs.add((y, x))
+
+    parts = list(range(2, 2 + n_part))
+    na = list(range(2 + n_part, 2 + n_part + d_a))
+    nxt = 2 + n_part + d_a
+    link(0, 1)
+    for q in na:
+        link(1, q)
+    for c in parts:
+        link(0, c)
+        nb = set(rng.choice(na, size=int(rng.integers(2, 8)), replace=False).tolist())
+        nb.update(rng.choice(parts, size=int(rng.integers(0, 4)), replace=False).tolist())
+        if rng.random() < 0.3:
+            nb.add(1)
+        nb.discard(c)
+        while len(nb) < d_part - 1:
+            nb.add(nxt)
+            nxt += 1
+        for q in nb:
+            link(c, q)
+    return gg.from_arcs(nxt, sorted((x, y) for x, y in arcs if x != y))
+
+
+@pytest.mark.gpu
+def test_k5_light_subchunks(pm):
+    """The factored k = 5 path where it splits: one unit's light partners in
+    several sub-chunks, partners inside N(a), adjacent to a (triangles) and
+    to each other; also relabelled, so the triangles' centres move."""
+    g = _partner_fan()
+    assert_parity(pm, g, 5, "partner fan")
+    assert_parity(pm, gg.relabel(g, seed=6), 5, "partner fan relabelled")
+
+
 @pytest.mark.gpu
 def test_census_multi_matches_single(pm):
     """One shared build for k = 3, 4, 5 gives what three separate calls give,
