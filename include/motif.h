@@ -185,9 +185,9 @@ typedef struct motif_tuning {
   int32_t block;        /* threads per workgroup for the anchor kernels (64..1024)  */
   int32_t grid_per_cu;  /* persistent workgroups per compute unit (1..16)           */
   int32_t tile;         /* work-queue granularity (1..4096): G* entries per tile,
-                           except for the k = 4 core-reuse scheme, where the
-                           queue is cut by estimated cost into about `tile`
-                           tiles per workgroup                                  */
+                           except for the k = 4 and k = 5 core-reuse schemes,
+                           where the queue is cut by estimated cost into about
+                           `tile` tiles per workgroup                           */
   int32_t heavy;        /* census scheme for k = 4, 5: 1 = core reuse (neighbourhood
                            of the highest-ranked anchor vertex scanned once per
                            work unit), 2 = per-anchor scan; 0 = keep              */

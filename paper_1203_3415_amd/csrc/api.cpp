@@ -35,7 +35,7 @@ Tuning g_tuning[6] = {
     {256, 4, 16, 1}, {256, 4, 16, 1}, {256, 4, 16, 1},
     {256, 4, 16, 1},    // k = 3: tile*16 vertices per tile (at most 1024)
     {1024, 1, 8, 1},    // k = 4: core reuse (tile = cost tiles per workgroup)
-    {1024, 1, 1, 1},    // k = 5: core reuse
+    {1024, 1, 64, 1},   // k = 5: core reuse (tile = cost tiles per workgroup)
 };
 
 int32_t current_device(int* dev) {
@@ -480,7 +480,7 @@ int32_t motif_autotune(const motif_graph_t* graphs, int32_t count, int32_t k, ui
         for (int tile : {8, 32}) cands.push_back({block, gpc, tile, 2});
   } else {
     for (int block : {512, 1024})
-      for (int tile : {1, 2, 4}) cands.push_back({block, 1, tile, 1});
+      for (int tile : {16, 64, 256}) cands.push_back({block, 1, tile, 1});
     for (int tile : {1, 4}) cands.push_back({1024, 1, tile, 2});
   }
   const Tuning saved = tuning_for(k);

@@ -1650,13 +1650,36 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     return;
   }
 
+  // Tiles of units cut by estimated cost (k_unit_cost5) as for k = 4, about
+  // `tile` per workgroup, the last quarter four times finer: the units of a
+  // light core stay together (one core set-up), a heavy core's are spread.
+  const int32_t tot_cost = cpre[total];
+  const int64_t parts = (int64_t)gridDim.x * (tile > 0 ? tile : 1);
+  const int32_t tc = (int32_t)max((int64_t)1, ((int64_t)tot_cost + parts - 1) / parts);
+  const int32_t split = tot_cost - tot_cost / 4, tc_end = max(1, tc / 4);
   for (;;) {
-    if (threadIdx.x == 0) sh_j0 = atomicAdd(queue, tile);
+    if (threadIdx.x == 0) {
+      int32_t c0 = atomicAdd(&queue[0], tc), c1 = min(split, c0 + tc);
+      if (c0 >= split) {
+        c0 = split + atomicAdd(&queue[1], tc_end);
+        c1 = min(tot_cost, c0 + tc_end);
+      }
+      auto first_at = [&](int64_t key) {  // first entry whose cost prefix is >= key
+        int32_t lo = 0, hi = total;
+        while (lo < hi) {
+          const int32_t mid = (lo + hi) >> 1;
+          if ((int64_t)cpre[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+      };
+      sh_j0 = c0 >= tot_cost ? -1 : first_at(c0);
+      sh_j1 = c0 >= tot_cost ? -1 : first_at(c1);
+    }
     bar<GL>();
-    const int32_t j0 = sh_j0;
+    const int32_t j0 = sh_j0, j1 = sh_j1;
     bar<GL>();
-    if (j0 >= total) break;
-    const int32_t j1 = min(total, j0 + tile);
+    if (j0 < 0) break;
+    if (j0 >= j1) continue;
     row = find_row(G.gs_off, 0, n, j0);
     for (int32_t j = j0; j < j1; ++j) {
       while (G.gs_off[row + 1] <= j) ++row;
@@ -1946,6 +1969,22 @@ __global__ void k_unit_cost4(DevGraph G, int32_t cmax, int32_t* cost, const int3
   }
 }
 
+// The same for the k = 5 core-reuse kernel: every G* entry (b, a) is a unit
+// whose partners are about half of b's row, taken in sub-chunks, so its cost
+// grows with d*(b); the fixed part covers the unit's labels and barriers.
+__global__ void k_unit_cost5(DevGraph G, int32_t cmax, int32_t* cost, const int32_t* st) {
+  if (st[kStatus] != 0) return;
+  const int32_t total = G.gs_off[G.n];
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < G.gs_cap; j += (int64_t)gridDim.x * blockDim.x) {
+    int32_t c = 0;
+    if (j < total) {
+      const int32_t r = G.gs_row[j];
+      c = min(cmax, 8 + (G.gs_off[r + 1] - G.gs_off[r]));
+    }
+    cost[j] = c;
+  }
+}
+
 // Hub slots for the core-reuse scheme: the vertices of largest degree get one
 // of kMaxHubs rows of the per-core W table; the threshold is the smallest
 // power of two whose degree bucket and all above hold at most kMaxHubs
@@ -2106,7 +2145,7 @@ size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int nu
   if ((k == 4 || k == 5) && tuning_for(k).heavy == 1)
     b += al(sizeof(int32_t) * (N + 1)) + al(64 * sizeof(int32_t)) +
          al(sizeof(uint32_t) * 16 * (size_t)(maxn > 0 ? maxn : N) * grid_size(k, num_cus));
-  if (k == 4 && tuning_for(k).heavy == 1)  // cost prefix of the G* entries and its scan scratch
+  if ((k == 4 || k == 5) && tuning_for(k).heavy == 1)  // cost prefix of the G* entries and its scan scratch
     b += al(sizeof(int32_t) * (2 * M + 1)) + al(sizeof(int32_t) * (size_t)scan_scratch(2 * M + 1));
   if ((k == 4 || k == 5) && tuning_for(k).heavy == 1) {
     const int64_t mn = maxn > 0 ? maxn : N;
@@ -2194,11 +2233,14 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
         }
       }
       const int32_t* cpre = nullptr;
-      if (reuse && k == 4) {
+      if (reuse) {
         int32_t* cost = p.arena.take<int32_t>((size_t)g.gs_cap);
         int32_t* scr = p.arena.take<int32_t>((size_t)scan_scratch(g.gs_cap));
         const int32_t cmax = (int32_t)std::max<int64_t>(2, std::min<int64_t>(1 << 16, (int64_t(1) << 30) / g.gs_cap));
-        hipLaunchKernelGGL(k_unit_cost4, dim3(blocks_for(g.gs_cap, 256)), dim3(256), 0, s, g, cmax, cost, p.status);
+        if (k == 4)
+          hipLaunchKernelGGL(k_unit_cost4, dim3(blocks_for(g.gs_cap, 256)), dim3(256), 0, s, g, cmax, cost, p.status);
+        else
+          hipLaunchKernelGGL(k_unit_cost5, dim3(blocks_for(g.gs_cap, 256)), dim3(256), 0, s, g, cmax, cost, p.status);
         scan_excl(cost, g.gs_cap, scr, s);
         cpre = cost;
       }
