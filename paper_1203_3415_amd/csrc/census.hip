@@ -649,7 +649,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   constexpr int C = K == 4 ? 199 : 9364, NL = K == 4 ? 16 : 64, LB = K == 4 ? 4 : 8;
   constexpr int S1 = K - 2, S2 = K - 1;  // member slots
   // LDS rows of W: fewer where the k = 5 counters and labels leave no room
-  constexpr int HUBS = (K == 5 && LCAP == 32768) ? 224 : (K == 4 && LCAP == 65536) ? 384 : kMaxHubs;
+  constexpr int HUBS = (K == 5 && LCAP == 32768) ? 220 : (K == 4 && LCAP == 65536) ? 384 : kMaxHubs;
   constexpr bool GL = LCAP == 0;
   __shared__ u64 hist[C];
   __shared__ uint16_t lut_lds[K == 4 ? 4096 : 1];
@@ -674,7 +674,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   __shared__ uint8_t tpid[T5];
   __shared__ uint32_t U5[K == 5 ? kU5 : 1];
   __shared__ int32_t cnU[16];
-  __shared__ int32_t p5_v[P5], p5_off[P5], p5_dc[P5], p5_ctl[5];
+  __shared__ int32_t p5_v[P5], p5_row[P5], p5_off[P5], p5_dc[P5], p5_ctl[5];
   __shared__ uint16_t tlist[K == 5 ? kT5Load : 1];  // slots of the table's keys
   __shared__ uint32_t p5_base[P5], p5_db[P5];
   // k = 4: the no-edge half of every edge move, per label pair (min, max),
@@ -1774,8 +1774,9 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
               if (threadIdx.x < 64) {
                 const int32_t lane = (int32_t)threadIdx.x, u = u0 + lane;
                 const bool in = lane < kNP5 && u < nlight;
-                int32_t c2 = -1, cost = 0;
+                int32_t c2 = -1, cost = 0, rs2 = 0;
                 uint32_t base = 0;
+                if (lane < 16) cnU[lane] = 0;  // read by the closed forms of the previous sub-chunk
                 if (in) {
                   const uint32_t ec = G.gs_idx[unit_list[BLOCK - 1 - u]];
                   c2 = (int32_t)(ec & kIdMask);
@@ -1784,7 +1785,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                   if (tac && (c > x || c > c2)) {
                     c2 = -1;  // triangle: taken at its smallest id
                   } else {
-                    cost = G.gs_off[c2 + 1] - G.gs_off[c2] + 1;
+                    rs2 = G.gs_off[c2];
+                    cost = G.gs_off[c2 + 1] - rs2 + 1;
                     base = ((tcx & 1u) ? 1u << cbit<K>(0, 1) : 0u) | ((tcx & 2u) ? 1u << cbit<K>(1, 0) : 0u) |
                            ((tbc & 1u) ? 1u << cbit<K>(0, 2) : 0u) | ((tbc & 2u) ? 1u << cbit<K>(2, 0) : 0u) |
                            ((tac & 1u) ? 1u << cbit<K>(1, 2) : 0u) | ((tac & 2u) ? 1u << cbit<K>(2, 1) : 0u);
@@ -1804,6 +1806,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                 if (act) {
                   const int32_t k = __popcll(am & ((1ull << lane) - 1ull));
                   p5_v[k] = c2;
+                  p5_row[k] = rs2;
                   p5_base[k] = base;
                   p5_off[k] = inc - cost;
                 }
@@ -1836,7 +1839,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                   if (h < kT5) tpid[h] = (uint8_t)(lo + 1);
                   lab.set_bits((uint32_t)c2, kInT5);
                 } else {
-                  const uint32_t e = G.gs_idx[G.gs_off[c2] + kk - 1];
+                  const uint32_t e = G.gs_idx[p5_row[lo] + kk - 1];
                   const uint32_t v = e & kIdMask;
                   if ((int32_t)v != c) {
                     const uint32_t h = t5_insert(v);
@@ -1884,7 +1887,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                     if (kk == 0) {
                       pair5(x, lo, c2, true, 0u);
                     } else {
-                      const uint32_t e = G.gs_idx[G.gs_off[c2] + kk - 1];
+                      const uint32_t e = G.gs_idx[p5_row[lo] + kk - 1];
                       if ((int32_t)(e & kIdMask) != c) pair5(x, lo, (int32_t)(e & kIdMask), false, e >> kTypeShift);
                     }
                   }
@@ -1921,8 +1924,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                   }
                 }
               }
-              for (int32_t p = (int32_t)(threadIdx.x >> 6); p < np; p += NW) close5(p, x);
-              bar<GL>();
+              // the table is not read any more: cleared alongside the closed forms
               for (int32_t k = threadIdx.x; k < p5_ctl[4]; k += BLOCK) {
                 const uint32_t h = tlist[k];
                 lab.clear_bits(tkey[h], kInT5);
@@ -1930,7 +1932,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                 ttyp[h] = 0ull;
                 tpid[h] = 0;
               }
-              if (threadIdx.x < 16) cnU[threadIdx.x] = 0;
+              for (int32_t p = (int32_t)(threadIdx.x >> 6); p < np; p += NW) close5(p, x);
               bar<GL>();
             }
           }
