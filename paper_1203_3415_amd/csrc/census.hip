@@ -83,11 +83,12 @@ constexpr int kLightDeg = 256;  // k = 4 anchors whose side has at most this deg
 constexpr int kWaveHashBits = 9;
 constexpr int kWaveHash = 1 << kWaveHashBits;  // slots of the wave-private hash of N(side): load <= 1/2
 constexpr uint32_t kEmptySlot = ~0u;
-constexpr int kLight5C = 128;       // k = 5 triples whose side c has at most this degree are light
+constexpr int kLight5C = 512;       // k = 5 triples whose lighter side c has at most this degree are light
 constexpr int kNP5 = 32;            // light partners c per sub-chunk of a k = 5 unit (2 type bits each in 64)
 constexpr int kT5Bits = 10;
 constexpr int kT5 = 1 << kT5Bits;   // slots of the merged table of the sub-chunk's N(c) ...
 constexpr int kT5Load = 768;        // ... holding at most this many keys (sum of d*(c) + 1)
+static_assert(kLight5C + 1 <= kT5Load, "a light partner must fit the table alone");
 constexpr uint32_t kInT5 = 64u;     // label bit 6: the vertex is a key of that table
 constexpr int kU5 = 16 * 48;        // per-unit move counters: (x label, y label, r), labels of 4 bits
 constexpr int kSoloDeg = 64;        // k = 4 anchors whose core has at most this degree run alone on one wave
@@ -1798,7 +1799,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                   const int32_t t = __shfl_up(inc, d);
                   if (lane >= d) inc += t;
                 }
-                // a prefix of the lanes: lane 0 always fits (cost <= kLight5C + 1)
+                // a prefix of the lanes: lane 0 always fits (cost <= kLight5C + 1 <= kT5Load)
                 const bool take = in && inc <= kT5Load;
                 const int32_t ntake = __popcll(__ballot(take));
                 const bool act = take && c2 >= 0;

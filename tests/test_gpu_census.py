@@ -354,6 +354,22 @@ def test_k5_light_subchunks(pm):
     g = _partner_fan()
     assert_parity(pm, g, 5, "partner fan")
     assert_parity(pm, gg.relabel(g, seed=6), 5, "partner fan relabelled")
+    # light partners of a few hundred neighbours (one or two per sub-chunk):
+    # too many connected 5-sets for the oracle, so against the per-anchor
+    # kernel, itself checked against the oracle above
+    g = _partner_fan(n_part=12, d_part=300, d_a=400, seed=7)
+    off, idx = pm.to_device(g.out_off, g.out_idx)
+    saved = pm.get_tuning(5)
+    try:
+        print(f"[case] wide partner fan n={g.n} m={g.m}", flush=True)
+        pm.set_tuning(5, heavy=1)
+        a = pm.census(off, idx, g.n, 5)
+        pm.set_tuning(5, heavy=2)
+        b = pm.census(off, idx, g.n, 5)
+    finally:
+        pm.set_tuning(5, **saved)
+    assert np.array_equal(a, b)
+    assert int(a.sum()) > 0
 
 
 @pytest.mark.gpu
