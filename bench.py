@@ -132,7 +132,7 @@ def kr5_kernel_bytes(st) -> float:
     N(x) u N(c2) its offsets and W row (44 B) and N+ row (4 d+(q)); the
     union is the sum over both rows minus the common neighbours, counted
     through the co-degrees t(c, q): sum over c != q of C(t, 2) g(q).
-    Light triples (lighter side of degree <= 128) read the heavier side's
+    Light triples (lighter side of degree <= 512) read the heavier side's
     part f(x) = 4 d_x + sum g(q) once per sub-chunk of at most 32 partners
     (and 768 table keys) instead of once per triple; the sub-chunks of a
     unit are counted as ceil(max(n_l / 32, sum(d + 1) / 768))."""
@@ -154,7 +154,7 @@ def kr5_kernel_bytes(st) -> float:
     key = deg * n + np.arange(n)  # rank (d*, id)
     order = np.lexsort((key[dst], src))
     cs, xs = src[order], dst[order]
-    light = (deg[xs] <= 128).astype(np.float64)
+    light = (deg[xs] <= 512).astype(np.float64)
     cl = np.cumsum(light) - light  # light entries before each position
     cd = np.cumsum(light * (deg[xs] + 1.0)) - light * (deg[xs] + 1.0)
     start = np.searchsorted(cs, cs, side="left")
