@@ -34,7 +34,7 @@ int32_t g_init_err = 0;
 Tuning g_tuning[6] = {
     {256, 4, 16, 1}, {256, 4, 16, 1}, {256, 4, 16, 1},
     {256, 4, 16, 1},    // k = 3: tile*16 vertices per tile (at most 1024)
-    {1024, 1, 8, 1},    // k = 4: core reuse (tile = cost tiles per workgroup)
+    {1024, 1, 3, 1},    // k = 4: core reuse (tile = cost tiles per workgroup)
     {1024, 1, 64, 1},   // k = 5: core reuse (tile = cost tiles per workgroup)
 };
 
@@ -474,7 +474,7 @@ int32_t motif_autotune(const motif_graph_t* graphs, int32_t count, int32_t k, ui
   } else if (k == 4) {  // both schemes: core reuse (1) and per-anchor scan (2)
     for (int block : {512, 1024})
       for (int gpc : {1, 2})
-        for (int tile : {4, 8, 16}) cands.push_back({block, gpc, tile, 1});
+        for (int tile : {3, 8, 16}) cands.push_back({block, gpc, tile, 1});
     for (int block : {256, 512})
       for (int gpc : {2, 4})
         for (int tile : {8, 32}) cands.push_back({block, gpc, tile, 2});

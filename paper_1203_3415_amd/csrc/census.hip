@@ -1510,6 +1510,51 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     core_setup(c);
   };
 
+  // One pull of the cost-cut work queue by wave 0: [sh_j0, sh_j1) are the
+  // entries whose cost prefix lies in the pulled interval (sh_j0 = -1 once
+  // the queue is empty).  Tiles of tc cost units, the last quarter of the
+  // cost (from split) in tiles of tc_end from a second counter.  Each cut is
+  // a 64-way search of cpre: about four dependent reads instead of ~20.
+  auto pull_tile = [&](int32_t tot_cost, int32_t tc, int32_t split, int32_t tc_end) {
+    if (threadIdx.x < 64) {
+      const int32_t lane = (int32_t)threadIdx.x;
+      int32_t c0 = 0, c1 = 0;
+      if (lane == 0) {
+        c0 = atomicAdd(&queue[0], tc);
+        c1 = min(split, c0 + tc);
+        if (c0 >= split) {
+          c0 = split + atomicAdd(&queue[1], tc_end);
+          c1 = min(tot_cost, c0 + tc_end);
+        }
+      }
+      c0 = __shfl(c0, 0);
+      c1 = __shfl(c1, 0);
+      auto first_at = [&](int64_t key) -> int32_t {  // first entry whose cost prefix is >= key
+        int32_t lo = 0, hi = total;
+        while (lo < hi) {
+          const int32_t step = (hi - lo + 63) >> 6;
+          const int32_t pr = lo + lane * step;
+          const int32_t cnt = __popcll(__ballot(pr < hi && (int64_t)cpre[pr] < key));
+          if (cnt == 0) {
+            hi = lo;
+          } else {
+            const int32_t nlo = lo + (cnt - 1) * step + 1;
+            hi = min(hi, lo + cnt * step);
+            lo = nlo;
+          }
+        }
+        return lo;
+      };
+      const bool done = c0 >= tot_cost;
+      const int32_t a0 = done ? -1 : first_at(c0);
+      const int32_t a1 = done ? -1 : first_at(c1);
+      if (lane == 0) {
+        sh_j0 = a0;
+        sh_j1 = a1;
+      }
+    }
+  };
+
   if constexpr (K == 4) {
     // Tiles of G* entries cut by estimated cost: cpre is the exclusive prefix
     // sum of a per-entry cost (k_unit_cost4), and a tile is the run of
@@ -1520,27 +1565,11 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     const int32_t tot_cost = cpre[total];
     const int64_t parts = (int64_t)gridDim.x * (tile > 0 ? tile : 1);
     const int32_t tc = (int32_t)max((int64_t)1, ((int64_t)tot_cost + parts - 1) / parts);
-    auto first_at = [&](int64_t key) {  // first entry whose cost prefix is >= key
-      int32_t lo = 0, hi = total;
-      while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if ((int64_t)cpre[mid] < key) lo = mid + 1; else hi = mid;
-      }
-      return lo;
-    };
     // The last quarter of the cost is cut four times finer (second counter),
     // so the tiles still running at the end are small.
     const int32_t split = tot_cost - tot_cost / 4, tc_end = max(1, tc / 4);
     for (;;) {
-      if (threadIdx.x == 0) {
-        int32_t c0 = atomicAdd(&queue[0], tc), c1 = min(split, c0 + tc);
-        if (c0 >= split) {
-          c0 = split + atomicAdd(&queue[1], tc_end);
-          c1 = min(tot_cost, c0 + tc_end);
-        }
-        sh_j0 = c0 >= tot_cost ? -1 : first_at(c0);
-        sh_j1 = c0 >= tot_cost ? -1 : first_at(c1);
-      }
+      pull_tile(tot_cost, tc, split, tc_end);
       bar<GL>();
       const int32_t j0 = sh_j0, j1 = sh_j1;
       bar<GL>();
@@ -1586,7 +1615,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
         jc = jce;
       }
       // units of the other cores, one core row at a time
-      row = find_row(G.gs_off, 0, n, j0);
+      row = G.gs_row[j0];
       for (int32_t js = j0; js < j1;) {
         while (G.gs_off[row + 1] <= js) ++row;
         const int32_t c = row;
@@ -1659,29 +1688,13 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   const int32_t tc = (int32_t)max((int64_t)1, ((int64_t)tot_cost + parts - 1) / parts);
   const int32_t split = tot_cost - tot_cost / 4, tc_end = max(1, tc / 4);
   for (;;) {
-    if (threadIdx.x == 0) {
-      int32_t c0 = atomicAdd(&queue[0], tc), c1 = min(split, c0 + tc);
-      if (c0 >= split) {
-        c0 = split + atomicAdd(&queue[1], tc_end);
-        c1 = min(tot_cost, c0 + tc_end);
-      }
-      auto first_at = [&](int64_t key) {  // first entry whose cost prefix is >= key
-        int32_t lo = 0, hi = total;
-        while (lo < hi) {
-          const int32_t mid = (lo + hi) >> 1;
-          if ((int64_t)cpre[mid] < key) lo = mid + 1; else hi = mid;
-        }
-        return lo;
-      };
-      sh_j0 = c0 >= tot_cost ? -1 : first_at(c0);
-      sh_j1 = c0 >= tot_cost ? -1 : first_at(c1);
-    }
+    pull_tile(tot_cost, tc, split, tc_end);
     bar<GL>();
     const int32_t j0 = sh_j0, j1 = sh_j1;
     bar<GL>();
     if (j0 < 0) break;
     if (j0 >= j1) continue;
-    row = find_row(G.gs_off, 0, n, j0);
+    row = G.gs_row[j0];
     for (int32_t j = j0; j < j1; ++j) {
       while (G.gs_off[row + 1] <= j) ++row;
       const int32_t c = row;
