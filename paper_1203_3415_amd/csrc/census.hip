@@ -30,8 +30,10 @@
 //
 // k4_kernel and k5_kernel follow this per anchor.  The default kernels for
 // k = 4, 5 (kr_kernel) compute the same sums with the neighbourhood of the
-// highest-ranked anchor vertex scanned once for all of its anchors, and run
-// small anchors on single waves with their labels in LDS hashes.
+// highest-ranked anchor vertex scanned once for all of its anchors; for
+// k = 4 small anchors run on single waves with their labels in LDS hashes,
+// for k = 5 the triples of one centre and one heavier side share that
+// side's sums and are corrected per lighter side.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
