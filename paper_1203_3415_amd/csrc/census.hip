@@ -685,6 +685,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   // the wave paths, one table for the workgroup path)
   __shared__ uint32_t wE[K == 4 ? NW * NL * NL : 1], bE[K == 4 ? NL * NL : 1];
   __shared__ int32_t unit_list[BLOCK], unit_ctr[3];
+  __shared__ int32_t lbk[K == 4 ? 32 : 1];  // k = 4 light units: counts and fills per log2 degree bucket
   __shared__ uint32_t lds_labels[LCAP > 0 ? LCAP / 4 : 1];
   if (st[kStatus] != 0) return;
   Labels<LB, GL> lab{LCAP > 0 ? lds_labels : glabels + (int64_t)blockIdx.x * label_words};
@@ -1628,16 +1629,33 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
         }
         const int32_t je = min(min(j1, rowb), js + BLOCK);
         if (threadIdx.x < 3) unit_ctr[threadIdx.x] = 0;
+        if (threadIdx.x < 32) lbk[threadIdx.x] = 0;
         bar<GL>();
         {
+          // heavy units to the front of the list; light units to the back,
+          // counted per log2 of the side's degree and then placed largest
+          // bucket first, so the waves take the long anchors first
           const int32_t j = js + (int32_t)threadIdx.x;
+          int32_t bk = -1;
           if (j < je) {
             const int32_t x = (int32_t)(G.gs_idx[j] & kIdMask);
             const int32_t dc = rowb - rowa, dx = G.gs_off[x + 1] - G.gs_off[x];
             if (dx < dc || (dx == dc && x < c)) {  // anchor edge {c, x} owned by its higher-rank end
-              if (dx > kLightDeg) unit_list[atomicAdd(&unit_ctr[0], 1)] = j;
-              else unit_list[BLOCK - 1 - atomicAdd(&unit_ctr[1], 1)] = j;
+              if (dx > kLightDeg) {
+                unit_list[atomicAdd(&unit_ctr[0], 1)] = j;
+              } else {
+                bk = 31 - __clz(max(dx, 1));  // 0 .. 8
+                atomicAdd(&unit_ctr[1], 1);
+                atomicAdd(&lbk[bk], 1);
+              }
             }
+          }
+          bar<GL>();
+          if (bk >= 0) {
+            int32_t pos = 0;
+            for (int32_t b2 = bk + 1; b2 < 16; ++b2) pos += lbk[b2];
+            pos += atomicAdd(&lbk[16 + bk], 1);
+            unit_list[BLOCK - 1 - pos] = j;
           }
         }
         bar<GL>();
