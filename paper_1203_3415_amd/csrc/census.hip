@@ -77,7 +77,7 @@ constexpr int kMaxHubs = 512;  // rows of the per-core W table in LDS
 constexpr int kMaxBig = 64;          // cores whose W / M tables are built once per call
 constexpr int kBigMinDeg = 256;      // ... among vertices of at least this degree
 constexpr int64_t kBigBytes = 512ll << 20;  // ... within this many bytes of tables
-constexpr int kBigRow = 12;          // words per W row of a big core (9 used, 16-byte aligned)
+constexpr int kBigRow = 12;          // words per W row (9 used, 16-byte aligned), big-core tables and WG slices
 constexpr int kUnroll = 4;
 constexpr int kBucketShift = 6;     // the row-scan layout records the row at every 64th entry ...
 constexpr int kBuckets = 1024;      // ... for layouts of up to 64 K entries (else plain binary search)         // N+ entries per lane and pass of the flattened scans
@@ -726,7 +726,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   int32_t cur_g = -1, row = 0, core = -1, par = 0;
   int32_t cbig = -1;  // slot of the current core among the precomputed big cores, or -1
   int64_t wbase = 0;  // first vertex of the core's graph
-  auto wrow = [&](int32_t q) { return WG + (int64_t)(q - wbase) * 16; };
+  auto wrow = [&](int32_t q) { return WG + (int64_t)(q - wbase) * kBigRow; };
   auto hub = [&](int32_t q) {
     const int32_t h = hub_id[q];
     return h < HUBS ? h : -1;
@@ -2180,7 +2180,7 @@ size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int nu
   size_t b = build_bytes(N, M, G, batch);
   if ((k == 4 || k == 5) && tuning_for(k).heavy == 1)
     b += al(sizeof(int32_t) * (N + 1)) + al(64 * sizeof(int32_t)) +
-         al(sizeof(uint32_t) * 16 * (size_t)(maxn > 0 ? maxn : N) * grid_size(k, num_cus));
+         al(sizeof(uint32_t) * kBigRow * (size_t)(maxn > 0 ? maxn : N) * grid_size(k, num_cus));
   if ((k == 4 || k == 5) && tuning_for(k).heavy == 1)  // cost prefix of the G* entries and its scan scratch
     b += al(sizeof(int32_t) * (2 * M + 1)) + al(sizeof(int32_t) * (size_t)scan_scratch(2 * M + 1));
   if ((k == 4 || k == 5) && tuning_for(k).heavy == 1) {
@@ -2252,7 +2252,7 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
         enqueue_zero(mbig, sizeof(uint32_t) * 32 * kMaxBig, s);
       }
       if (reuse) {
-        ws = 16 * (int64_t)(g.max_graph_n > 0 ? g.max_graph_n : g.n);
+        ws = kBigRow * (int64_t)(g.max_graph_n > 0 ? g.max_graph_n : g.n);
         wg = p.arena.take<uint32_t>((size_t)ws * grid);
         enqueue_zero(wg, sizeof(uint32_t) * (size_t)ws * grid, s);
         hub_id = p.arena.take<int32_t>(g.n + 1);
