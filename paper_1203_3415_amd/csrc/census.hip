@@ -652,7 +652,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   constexpr int C = K == 4 ? 199 : 9364, NL = K == 4 ? 16 : 64, LB = K == 4 ? 4 : 8;
   constexpr int S1 = K - 2, S2 = K - 1;  // member slots
   // LDS rows of W: fewer where the k = 5 counters and labels leave no room
-  constexpr int HUBS = (K == 5 && LCAP == 32768) ? 220 : (K == 4 && LCAP == 65536) ? 384 : kMaxHubs;
+  constexpr int HUBS = (K == 5 && LCAP == 32768) ? 200 : (K == 4 && LCAP == 65536) ? 384 : kMaxHubs;
   constexpr bool GL = LCAP == 0;
   __shared__ u64 hist[C];
   __shared__ uint16_t lut_lds[K == 4 ? 4096 : 1];
@@ -676,10 +676,12 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   __shared__ u64 ttyp[T5];
   __shared__ uint8_t tpid[T5];
   __shared__ uint32_t U5[K == 5 ? kU5 : 1];
-  __shared__ int32_t cnU[16];
-  __shared__ int32_t p5_v[P5], p5_row[P5], p5_off[P5], p5_dc[P5], p5_ctl[5];
+  // two buffers: the partner set of the next sub-chunk is chosen while the
+  // current one finishes; sb is the buffer of the current sub-chunk
+  __shared__ int32_t cnUb[2][16];
+  __shared__ int32_t p5_vb[2][P5], p5_rowb[2][P5], p5_offb[2][P5], p5_ctlb[2][5], p5_dc[P5];
   __shared__ uint16_t tlist[K == 5 ? kT5Load : 1];  // slots of the table's keys
-  __shared__ uint32_t p5_base[P5], p5_db[P5];
+  __shared__ uint32_t p5_baseb[2][P5], p5_db[P5];
   // k = 4: the no-edge half of every edge move, per label pair (min, max),
   // summed for the current anchor and added in its closed form (per wave for
   // the wave paths, one table for the workgroup path)
@@ -708,7 +710,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       tpid[i] = 0;
     }
     for (int i = threadIdx.x; i < kU5; i += BLOCK) U5[i] = 0u;
-    if (threadIdx.x < 16) cnU[threadIdx.x] = 0;
+    if (threadIdx.x < 32) cnUb[threadIdx.x >> 4][threadIdx.x & 15] = 0;
   }
   if (K == 4) {
     for (int i = threadIdx.x; i < NW * NL * NL; i += BLOCK) wE[i] = 0u;
@@ -724,6 +726,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   // within 3 |E*| in magnitude: exact while |E*| < 2^29
   const bool fact5 = total < (1 << 30);
   int32_t cur_g = -1, row = 0, core = -1, par = 0;
+  int32_t sb = 0;  // k = 5: buffer of the current light sub-chunk
   int32_t cbig = -1;  // slot of the current core among the precomputed big cores, or -1
   int64_t wbase = 0;  // first vertex of the core's graph
   auto wrow = [&](int32_t q) { return WG + (int64_t)(q - wbase) * kBigRow; };
@@ -1260,7 +1263,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     uint32_t h = t5_slot(v);
     for (int i = 0; i < kT5; ++i) {
       const uint32_t old = atomicCAS(&tkey[h], kEmptySlot, v);
-      if (old == kEmptySlot) tlist[atomicAdd(&p5_ctl[4], 1)] = (uint16_t)h;
+      if (old == kEmptySlot) tlist[atomicAdd(&p5_ctlb[sb][4], 1)] = (uint16_t)h;
       if (old == kEmptySlot || old == v) return h;
       h = (h + 1) & (kT5 - 1);
     }
@@ -1335,7 +1338,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     }
     const bool mq = i > 0;
     const uint32_t Lq = lab.get((uint32_t)q) & (mq ? 15u : 3u), cq = Lq & 3u;
-    if (mq) atomicAdd(&cnU[Lq], 1);
+    if (mq) atomicAdd(&cnUb[sb][Lq], 1);
     const Row9 wq = load_w(q);
 #pragma unroll
     for (int tr = 0; tr < 9; ++tr) {
@@ -1363,7 +1366,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       if (ina) atomicAdd(&cn[LU], -1);
       atomicAdd(&cn[LT], 1);
     }
-    const uint32_t bp = p5_base[p];
+    const uint32_t bp = p5_baseb[sb][p];
     const Row9 wv = load_w(v);
     // self: side of its own triple; when in N(a), its member terms in U
     // leave.  Else a member with label LT instead of LU (or of nothing).
@@ -1419,13 +1422,13 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       if (pq >= 0) {
         bool syT;
         const uint32_t LyT = ylab(y, a, ly, ty, py, pq, syT);
-        if (syT || LyT) emove(p5_base[pq], cq, false, LyT, syT, r, 1ull);
+        if (syT || LyT) emove(p5_baseb[sb][pq], cq, false, LyT, syT, r, 1ull);
       }
       for (u64 m = pairs2(tq); m; m &= m - 1ull) {
         const int32_t p = __builtin_ctzll(m) >> 1;
         bool syT;
         const uint32_t LyT = ylab(y, a, ly, ty, py, p, syT);
-        if (syT || LyT) emove(p5_base[p], cq | (((uint32_t)(tq >> (2 * p)) & 3u) << 4), true, LyT, syT, r, 1ull);
+        if (syT || LyT) emove(p5_baseb[sb][p], cq | (((uint32_t)(tq >> (2 * p)) & 3u) << 4), true, LyT, syT, r, 1ull);
       }
       return;
     }
@@ -1435,17 +1438,17 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     if (inU) umove(Lq, mq, LyU, syU, r);
     if (!((lq | ly) & kInT5)) return;
     if (pq >= 0) {  // partner q: its member edge leaves, its side edge comes in
-      if (inU) emove(p5_base[pq], Lq, mq, LyU, syU, r, kMinusOne);
+      if (inU) emove(p5_baseb[sb][pq], Lq, mq, LyU, syU, r, kMinusOne);
       bool syT;
       const uint32_t LyT = ylab(y, a, ly, ty, py, pq, syT);
-      if (syT || LyT) emove(p5_base[pq], Lq & 3u, false, LyT, syT, r, 1ull);
+      if (syT || LyT) emove(p5_baseb[sb][pq], Lq & 3u, false, LyT, syT, r, 1ull);
     }
     u64 cm = pairs2((mq ? tq : 0ull) | ty);
     if (py >= 0) cm |= 1ull << (2 * py);
     if (pq >= 0) cm &= ~(1ull << (2 * pq));
     for (u64 m = cm; m; m &= m - 1ull) {
       const int32_t p = __builtin_ctzll(m) >> 1;
-      const uint32_t bp = p5_base[p];
+      const uint32_t bp = p5_baseb[sb][p];
       const uint32_t LT = mq ? (Lq | (((uint32_t)(tq >> (2 * p)) & 3u) << 4)) : Lq;
       bool syT;
       const uint32_t LyT = ylab(y, a, ly, ty, py, p, syT);
@@ -1457,10 +1460,10 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   // sizes plus its own differences; then the non-empty sets of the 63
   auto close5 = [&](int32_t p, int32_t a) {
     const int32_t lane = (int32_t)(threadIdx.x & 63u);
-    const int32_t c2 = p5_v[p];
-    const uint32_t base = p5_base[p];
+    const int32_t c2 = p5_vb[sb][p];
+    const uint32_t base = p5_baseb[sb][p];
     int32_t* cn = wcnt + p * NL;
-    if (lane < 16) cn[lane] += cnU[lane];
+    if (lane < 16) cn[lane] += cnUb[sb][lane];
     wave_sync();
     // sizes of the core-only sets: N(core) minus the sides minus R'
     if (lane >= 1 && lane <= 3) {
@@ -1803,14 +1806,17 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
           }
           if (nlight > 0) {
             // light partners, up to kNP5 at a time with at most kT5Load keys
-            // in the merged table; triangles not taken here are dropped
-            for (int32_t u0 = 0; u0 < nlight;) {
-              if (threadIdx.x < 64) {
-                const int32_t lane = (int32_t)threadIdx.x, u = u0 + lane;
+            // in the merged table; triangles not taken here are dropped.
+            // The last wave chooses the next sub-chunk's partners (into the
+            // other buffer) while the current sub-chunk finishes.
+            constexpr int PW = NW - 1;
+            auto pick5 = [&](int32_t u0, int32_t b) {
+              if ((int32_t)(threadIdx.x >> 6) == PW) {
+                const int32_t lane = (int32_t)(threadIdx.x & 63u), u = u0 + lane;
                 const bool in = lane < kNP5 && u < nlight;
                 int32_t c2 = -1, cost = 0, rs2 = 0;
                 uint32_t base = 0;
-                if (lane < 16) cnU[lane] = 0;  // read by the closed forms of the previous sub-chunk
+                if (lane < 16) cnUb[b][lane] = 0;
                 if (in) {
                   const uint32_t ec = G.gs_idx[unit_list[BLOCK - 1 - u]];
                   c2 = (int32_t)(ec & kIdMask);
@@ -1839,135 +1845,139 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                 const unsigned long long am = __ballot(act);
                 if (act) {
                   const int32_t k = __popcll(am & ((1ull << lane) - 1ull));
-                  p5_v[k] = c2;
-                  p5_row[k] = rs2;
-                  p5_base[k] = base;
-                  p5_off[k] = inc - cost;
+                  p5_vb[b][k] = c2;
+                  p5_rowb[b][k] = rs2;
+                  p5_baseb[b][k] = base;
+                  p5_offb[b][k] = inc - cost;
                 }
                 const int32_t tot = __shfl(inc, ntake - 1);
                 if (lane == 0) {
-                  p5_ctl[0] = __popcll(am);
-                  p5_ctl[1] = u0 + ntake;
-                  p5_ctl[2] = tot;
-                  p5_ctl[3] = 0;
-                  p5_ctl[4] = 0;
+                  p5_ctlb[b][0] = __popcll(am);
+                  p5_ctlb[b][1] = u0 + ntake;
+                  p5_ctlb[b][2] = tot;
+                  p5_ctlb[b][3] = 0;
+                  p5_ctlb[b][4] = 0;
                 }
               }
-              bar<GL>();
-              const int32_t np = p5_ctl[0], tot = p5_ctl[2];
-              u0 = p5_ctl[1];
-              if (np == 0) {
+            };
+            sb = 0;
+            pick5(0, 0);
+            bar<GL>();
+            for (;;) {
+              const int32_t np = p5_ctlb[sb][0], tot = p5_ctlb[sb][2], u1 = p5_ctlb[sb][1];
+              if (np > 0) {
+                // merged table: partner k's row at [p5_offb[sb][k] + 1, ...), k itself at p5_offb[sb][k]
+                for (int32_t t = threadIdx.x; t < tot; t += BLOCK) {
+                  int32_t lo = 0, hi = np - 1;
+                  while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (p5_offb[sb][mid] <= t) lo = mid; else hi = mid - 1;
+                  }
+                  const int32_t c2 = p5_vb[sb][lo], kk = t - p5_offb[sb][lo];
+                  if (kk == 0) {
+                    const uint32_t h = t5_insert((uint32_t)c2);
+                    if (h < kT5) tpid[h] = (uint8_t)(lo + 1);
+                    lab.set_bits((uint32_t)c2, kInT5);
+                  } else {
+                    const uint32_t e = G.gs_idx[p5_rowb[sb][lo] + kk - 1];
+                    const uint32_t v = e & kIdMask;
+                    if ((int32_t)v != c) {
+                      const uint32_t h = t5_insert(v);
+                      if (h < kT5) atomicOr(&ttyp[h], (u64)(e >> kTypeShift) << (2 * lo));
+                      lab.set_bits(v, kInT5);
+                    }
+                  }
+                }
+                // distinct base codes of the sub-chunk with their multiplicities
+                if ((int32_t)threadIdx.x < np) {
+                  const uint32_t bs = p5_baseb[sb][threadIdx.x];
+                  bool first = true;
+                  int32_t nb = 0;
+                  for (int32_t k = 0; k < np; ++k) {
+                    const bool same = p5_baseb[sb][k] == bs;
+                    nb += same;
+                    first = first && !(same && k < (int32_t)threadIdx.x);
+                  }
+                  if (first) {
+                    const int32_t d = atomicAdd(&p5_ctlb[sb][3], 1);
+                    p5_db[d] = bs;
+                    p5_dc[d] = nb;
+                  }
+                }
+                // edges inside N(core): the same for every triple of the unit
+                if (threadIdx.x < 27) {
+                  const uint32_t w = Mc[threadIdx.x];
+                  if (w) U5[u5i(threadIdx.x / 9 + 1, (threadIdx.x / 3) % 3 + 1, threadIdx.x % 3 + 1)] += w;
+                }
                 bar<GL>();
-                continue;
-              }
-              // merged table: partner k's row at [p5_off[k] + 1, ...), k itself at p5_off[k]
-              for (int32_t t = threadIdx.x; t < tot; t += BLOCK) {
-                int32_t lo = 0, hi = np - 1;
-                while (lo < hi) {
-                  const int32_t mid = (lo + hi + 1) >> 1;
-                  if (p5_off[mid] <= t) lo = mid; else hi = mid - 1;
-                }
-                const int32_t c2 = p5_v[lo], kk = t - p5_off[lo];
-                if (kk == 0) {
-                  const uint32_t h = t5_insert((uint32_t)c2);
-                  if (h < kT5) tpid[h] = (uint8_t)(lo + 1);
-                  lab.set_bits((uint32_t)c2, kInT5);
-                } else {
-                  const uint32_t e = G.gs_idx[p5_row[lo] + kk - 1];
-                  const uint32_t v = e & kIdMask;
-                  if ((int32_t)v != c) {
-                    const uint32_t h = t5_insert(v);
-                    if (h < kT5) atomicOr(&ttyp[h], (u64)(e >> kTypeShift) << (2 * lo));
-                    lab.set_bits(v, kInT5);
-                  }
-                }
-              }
-              // distinct base codes of the sub-chunk with their multiplicities
-              if ((int32_t)threadIdx.x < np) {
-                const uint32_t bs = p5_base[threadIdx.x];
-                bool first = true;
-                int32_t nb = 0;
-                for (int32_t k = 0; k < np; ++k) {
-                  const bool same = p5_base[k] == bs;
-                  nb += same;
-                  first = first && !(same && k < (int32_t)threadIdx.x);
-                }
-                if (first) {
-                  const int32_t d = atomicAdd(&p5_ctl[3], 1);
-                  p5_db[d] = bs;
-                  p5_dc[d] = nb;
-                }
-              }
-              // edges inside N(core): the same for every triple of the unit
-              if (threadIdx.x < 27) {
-                const uint32_t w = Mc[threadIdx.x];
-                if (w) U5[u5i(threadIdx.x / 9 + 1, (threadIdx.x / 3) % 3 + 1, threadIdx.x % 3 + 1)] += w;
-              }
-              bar<GL>();
-              {
-                const int32_t na = 1 + (xb - xa);
-                // the per-(vertex, partner) pairs of the table share the
-                // latency of the first layout pass: they go to the last
-                // threads, whose waves have no item when the items and the
-                // pairs fit in one pass together
-                auto pairs = [&] {
-                  for (int32_t t = BLOCK - 1 - (int32_t)threadIdx.x; t < tot; t += BLOCK) {
-                    int32_t lo = 0, hi = np - 1;
-                    while (lo < hi) {
-                      const int32_t mid = (lo + hi + 1) >> 1;
-                      if (p5_off[mid] <= t) lo = mid; else hi = mid - 1;
+                {
+                  const int32_t na = 1 + (xb - xa);
+                  // the per-(vertex, partner) pairs of the table share the
+                  // latency of the first layout pass: they go to the last
+                  // threads, whose waves have no item when the items and the
+                  // pairs fit in one pass together
+                  auto pairs = [&] {
+                    for (int32_t t = BLOCK - 1 - (int32_t)threadIdx.x; t < tot; t += BLOCK) {
+                      int32_t lo = 0, hi = np - 1;
+                      while (lo < hi) {
+                        const int32_t mid = (lo + hi + 1) >> 1;
+                        if (p5_offb[sb][mid] <= t) lo = mid; else hi = mid - 1;
+                      }
+                      const int32_t c2 = p5_vb[sb][lo], kk = t - p5_offb[sb][lo];
+                      if (kk == 0) {
+                        pair5(x, lo, c2, true, 0u);
+                      } else {
+                        const uint32_t e = G.gs_idx[p5_rowb[sb][lo] + kk - 1];
+                        if ((int32_t)(e & kIdMask) != c) pair5(x, lo, (int32_t)(e & kIdMask), false, e >> kTypeShift);
+                      }
                     }
-                    const int32_t c2 = p5_v[lo], kk = t - p5_off[lo];
-                    if (kk == 0) {
-                      pair5(x, lo, c2, true, 0u);
-                    } else {
-                      const uint32_t e = G.gs_idx[p5_row[lo] + kk - 1];
-                      if ((int32_t)(e & kIdMask) != c) pair5(x, lo, (int32_t)(e & kIdMask), false, e >> kTypeShift);
-                    }
-                  }
-                };
-                flat_rows_pre(
-                    na + p5_ctl[4], pairs,
-                    [&](int32_t i) { return i < na ? u5_pick(c, x, xa, i) : c5_pick(x, i - na); },
-                    [&](int32_t q, uint32_t f) { s5_visit(c, x, q, f); });
-              }
-              {
-                const int32_t nd = p5_ctl[3];
-                for (int32_t t = threadIdx.x; t < kU5; t += BLOCK) {
-                  const uint32_t w = U5[t];
-                  if (!w) continue;
-                  U5[t] = 0u;
-                  const uint32_t X = (uint32_t)t / 48u, Y = ((uint32_t)t / 3u) % 16u, r = (uint32_t)t % 3u + 1u;
-                  const u64 w64 = (u64)(int64_t)(int32_t)w;
-                  const uint32_t sx = slot_code<K, S1>(X) | slot_code<K, S2>(Y), rc = rel_code<K>(r);
-                  for (int32_t d0 = 0; d0 < nd; d0 += 4) {  // table reads of 4 bases, then the counters
-                    uint32_t kf[4], kn[4];
+                  };
+                  flat_rows_pre(
+                      na + p5_ctlb[sb][4], pairs,
+                      [&](int32_t i) { return i < na ? u5_pick(c, x, xa, i) : c5_pick(x, i - na); },
+                      [&](int32_t q, uint32_t f) { s5_visit(c, x, q, f); });
+                }
+                {
+                  const int32_t nd = p5_ctlb[sb][3];
+                  for (int32_t t = threadIdx.x; t < kU5; t += BLOCK) {
+                    const uint32_t w = U5[t];
+                    if (!w) continue;
+                    U5[t] = 0u;
+                    const uint32_t X = (uint32_t)t / 48u, Y = ((uint32_t)t / 3u) % 16u, r = (uint32_t)t % 3u + 1u;
+                    const u64 w64 = (u64)(int64_t)(int32_t)w;
+                    const uint32_t sx = slot_code<K, S1>(X) | slot_code<K, S2>(Y), rc = rel_code<K>(r);
+                    for (int32_t d0 = 0; d0 < nd; d0 += 4) {  // table reads of 4 bases, then the counters
+                      uint32_t kf[4], kn[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                      const uint32_t c0 = p5_db[min(d0 + u, nd - 1)] | sx;
-                      kf[u] = lut[c0 | rc];
-                      kn[u] = lut[c0];
-                    }
+                      for (int u = 0; u < 4; ++u) {
+                        const uint32_t c0 = p5_db[min(d0 + u, nd - 1)] | sx;
+                        kf[u] = lut[c0 | rc];
+                        kn[u] = lut[c0];
+                      }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                      if (d0 + u >= nd) break;
-                      const u64 wd = w64 * (u64)p5_dc[d0 + u];
-                      atomicAdd(&hist[kf[u]], wd);
-                      atomicAdd(&hist[kn[u]], (u64)0 - wd);
+                      for (int u = 0; u < 4; ++u) {
+                        if (d0 + u >= nd) break;
+                        const u64 wd = w64 * (u64)p5_dc[d0 + u];
+                        atomicAdd(&hist[kf[u]], wd);
+                        atomicAdd(&hist[kn[u]], (u64)0 - wd);
+                      }
                     }
                   }
                 }
+                // the table is not read any more: cleared alongside the closed forms
+                for (int32_t k = threadIdx.x; k < p5_ctlb[sb][4]; k += BLOCK) {
+                  const uint32_t h = tlist[k];
+                  lab.clear_bits(tkey[h], kInT5);
+                  tkey[h] = kEmptySlot;
+                  ttyp[h] = 0ull;
+                  tpid[h] = 0;
+                }
               }
-              // the table is not read any more: cleared alongside the closed forms
-              for (int32_t k = threadIdx.x; k < p5_ctl[4]; k += BLOCK) {
-                const uint32_t h = tlist[k];
-                lab.clear_bits(tkey[h], kInT5);
-                tkey[h] = kEmptySlot;
-                ttyp[h] = 0ull;
-                tpid[h] = 0;
-              }
+              if (u1 < nlight) pick5(u1, sb ^ 1);
               for (int32_t p = (int32_t)(threadIdx.x >> 6); p < np; p += NW) close5(p, x);
               bar<GL>();
+              if (u1 >= nlight) break;
+              sb ^= 1;
             }
           }
           // skipped triples read x's labels without a barrier (see k5_kernel)
