@@ -81,7 +81,7 @@ constexpr int kBigRow = 12;          // words per W row (9 used, 16-byte aligned
 constexpr int kUnroll = 4;
 constexpr int kBucketShift = 6;     // the row-scan layout records the row at every 64th entry ...
 constexpr int kBuckets = 1024;      // ... for layouts of up to 64 K entries (else plain binary search)         // N+ entries per lane and pass of the flattened scans
-constexpr int kLightDeg = 256;  // k = 4 anchors whose side has at most this degree run on one wave
+constexpr int kLightDeg = 192;  // k = 4 anchors whose side has at most this degree run on one wave
 constexpr int kWaveHashBits = 9;
 constexpr int kWaveHash = 1 << kWaveHashBits;  // slots of the wave-private hash of N(side): load <= 1/2
 constexpr uint32_t kEmptySlot = ~0u;
