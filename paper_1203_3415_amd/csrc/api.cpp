@@ -99,10 +99,10 @@ int32_t get_pipeline(int dev, hipStream_t s, size_t bytes, Pipeline** out) {
       return MOTIF_ENOMEM;
   }
   if (p->arena.cap < bytes) {
-    if (p->arena.base) {
-      hipStreamSynchronize(s);
-      if (p->side) hipStreamSynchronize(p->side);
-      hipFree(p->arena.base);
+    if (p->arena.base) {  // a failure here shows up as a failed allocation below
+      (void)hipStreamSynchronize(s);
+      if (p->side) (void)hipStreamSynchronize(p->side);
+      (void)hipFree(p->arena.base);
       p->arena.base = nullptr;
       p->arena.cap = 0;
     }
@@ -149,7 +149,7 @@ ProfState g_prof;
 
 const DevTables& dev_tables() {
   int dev = 0;
-  hipGetDevice(&dev);
+  (void)hipGetDevice(&dev);  // device 0 if it fails; tables were set up by ensure_init
   return g_dev[dev].tables;
 }
 
@@ -158,8 +158,11 @@ Tuning& tuning_for(int k) { return g_tuning[k]; }
 void profile_mark(int k, int what, bool begin, hipStream_t s) {
   if (!g_prof.on || k < 3 || k > 5) return;
   hipEvent_t& e = g_prof.ev[k][what * 2 + (begin ? 0 : 1)];
-  if (!e) hipEventCreate(&e);
-  hipEventRecord(e, s);
+  if (!e && hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+    return;  // no timing for this mark; the census is unaffected
+  }
+  (void)hipEventRecord(e, s);
   if (what == 1 && !begin) g_prof.have[k] = true;
 }
 
@@ -235,17 +238,17 @@ int32_t motif_init(void) {
 
 int32_t motif_shutdown(void) {
   std::lock_guard<std::mutex> lk(g_mu);
-  for (auto& kv : g_dev) {
-    hipSetDevice(kv.first);
-    hipDeviceSynchronize();
-    for (void* ptr : kv.second.owned) hipFree(ptr);
+  for (auto& kv : g_dev) {  // tear-down: errors change nothing a caller could act on
+    (void)hipSetDevice(kv.first);
+    (void)hipDeviceSynchronize();
+    for (void* ptr : kv.second.owned) (void)hipFree(ptr);
     for (auto& pp : kv.second.pipes) {
-      if (pp.second->side) hipStreamDestroy(pp.second->side);
-      if (pp.second->ev_fork) hipEventDestroy(pp.second->ev_fork);
-      if (pp.second->ev_join) hipEventDestroy(pp.second->ev_join);
-      if (pp.second->arena.base) hipFree(pp.second->arena.base);
-      if (pp.second->status) hipFree(pp.second->status);
-      if (pp.second->host_status) hipHostFree(pp.second->host_status);
+      if (pp.second->side) (void)hipStreamDestroy(pp.second->side);
+      if (pp.second->ev_fork) (void)hipEventDestroy(pp.second->ev_fork);
+      if (pp.second->ev_join) (void)hipEventDestroy(pp.second->ev_join);
+      if (pp.second->arena.base) (void)hipFree(pp.second->arena.base);
+      if (pp.second->status) (void)hipFree(pp.second->status);
+      if (pp.second->host_status) (void)hipHostFree(pp.second->host_status);
       delete pp.second;
     }
   }
@@ -402,6 +405,7 @@ int32_t motif_census_batch(const motif_graph_t* graphs, int32_t count, int32_t k
   enqueue_zero(p->status, sizeof(int32_t) * kStatusWords, s);
   profile_mark(k, 0, true, s);
   BuildInput in = enqueue_pack(*p, graphs, count, voff.data(), aoff.data(), s);
+  if (in.copy_error) return MOTIF_EDEVICE;
   DevGraph g = enqueue_build(*p, in, s);
   profile_mark(k, 0, false, s);
   rc = read_status(*p, s);
@@ -502,8 +506,12 @@ int32_t motif_autotune(const motif_graph_t* graphs, int32_t count, int32_t k, ui
     if (!slow) rc = motif_census_batch(graphs, count, k, hists, stream);
     auto t1 = std::chrono::steady_clock::now();
     if (rc) { tuning_for(k) = saved; return rc; }
-    hipMemcpyAsync(i == 0 ? ref.data() : cur.data(), hists, sizeof(uint64_t) * ref.size(), hipMemcpyDeviceToHost, s);
-    hipStreamSynchronize(s);
+    if (hipMemcpyAsync(i == 0 ? ref.data() : cur.data(), hists, sizeof(uint64_t) * ref.size(), hipMemcpyDeviceToHost,
+                       s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      tuning_for(k) = saved;
+      return MOTIF_EDEVICE;
+    }
     if (i > 0 && cur != ref) { tuning_for(k) = saved; return MOTIF_EINTERNAL; }
     const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     if (!slow && ms < best_ms) {
@@ -541,7 +549,8 @@ namespace {
 
 // The whole batched census (status reset, pack, build, census, division) as
 // one stream-ordered sequence with no host interaction, so it can be captured.
-void enqueue_plan(motif_batch_plan* b) {
+// Returns false if a host-to-device copy could not be enqueued.
+bool enqueue_plan(motif_batch_plan* b) {
   const int C = motif_num_classes(b->k);
   b->p.arena.reset();
   enqueue_zero(b->p.status, sizeof(int32_t) * kStatusWords, b->stream);
@@ -549,21 +558,22 @@ void enqueue_plan(motif_batch_plan* b) {
   DevGraph g = enqueue_build(b->p, in, b->stream);
   uint64_t* acc = b->p.arena.take<uint64_t>((size_t)b->count * C);
   enqueue_census(b->p, g, b->k, acc, b->hists, b->stream);
+  return !in.copy_error;
 }
 
 void plan_free(motif_batch_plan* b) {
-  if (!b) return;
-  if (b->stream) hipStreamSynchronize(b->stream);
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
-  if (b->p.arena.base) hipFree(b->p.arena.base);
-  if (b->p.status) hipFree(b->p.status);
-  if (b->p.host_status) hipHostFree(b->p.host_status);
-  if (b->graphs) hipHostFree(b->graphs);
-  if (b->voff) hipHostFree(b->voff);
-  if (b->aoff) hipHostFree(b->aoff);
-  if (b->ready) hipEventDestroy(b->ready);
-  if (b->stream) hipStreamDestroy(b->stream);
+  if (!b) return;  // tear-down: errors change nothing a caller could act on
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->p.arena.base) (void)hipFree(b->p.arena.base);
+  if (b->p.status) (void)hipFree(b->p.status);
+  if (b->p.host_status) (void)hipHostFree(b->p.host_status);
+  if (b->graphs) (void)hipHostFree(b->graphs);
+  if (b->voff) (void)hipHostFree(b->voff);
+  if (b->aoff) (void)hipHostFree(b->aoff);
+  if (b->ready) (void)hipEventDestroy(b->ready);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
 
@@ -636,8 +646,10 @@ motif_batch_plan_t* motif_batch_plan_create(const motif_graph_t* graphs, int32_t
     plan_free(b);
     return nullptr;
   }
-  enqueue_plan(b);
-  if ((*err = read_status(b->p, b->stream))) {
+  const bool copied = enqueue_plan(b);
+  *err = read_status(b->p, b->stream);
+  if (!*err && !copied) *err = MOTIF_EDEVICE;
+  if (*err) {
     plan_free(b);
     return nullptr;
   }
@@ -646,8 +658,9 @@ motif_batch_plan_t* motif_batch_plan_create(const motif_graph_t* graphs, int32_t
   g_prof.on = false;
   hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    enqueue_plan(b);
+    const bool ok = enqueue_plan(b);
     e = hipStreamEndCapture(b->stream, &b->graph);
+    if (!ok && e == hipSuccess) e = hipErrorUnknown;
   }
   g_prof.on = prof;
   if (e != hipSuccess || hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {

@@ -611,9 +611,10 @@ BuildInput enqueue_pack(Pipeline& p, const motif_graph_t* graphs, int32_t count,
   int64_t* daoff = A.take<int64_t>(count + 1);
   motif_graph_t* dg = A.take<motif_graph_t>(count);
   int32_t* has_in = A.take<int32_t>(count);
-  hipMemcpyAsync(dvoff, voff, sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s);
-  hipMemcpyAsync(daoff, aoff, sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s);
-  hipMemcpyAsync(dg, graphs, sizeof(motif_graph_t) * count, hipMemcpyHostToDevice, s);
+  const bool copy_error =
+      hipMemcpyAsync(dvoff, voff, sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(daoff, aoff, sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(dg, graphs, sizeof(motif_graph_t) * count, hipMemcpyHostToDevice, s) != hipSuccess;
   hipLaunchKernelGGL(k_pack_rows, dim3(grid_for(N + 1)), dim3(kB), 0, s, dg, count, dvoff, daoff, N, M, uoff,
                      uin_off, gid, has_in, p.status);
   bool any_in = false;
@@ -635,6 +636,7 @@ BuildInput enqueue_pack(Pipeline& p, const motif_graph_t* graphs, int32_t count,
   int64_t mx = 0;
   for (int32_t g = 0; g < count; ++g) mx = std::max<int64_t>(mx, voff[g + 1] - voff[g]);
   in.max_graph_n = (int32_t)mx;
+  in.copy_error = copy_error;
   return in;
 }
 

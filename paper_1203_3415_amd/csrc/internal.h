@@ -115,6 +115,7 @@ struct BuildInput {
   const int32_t* has_in = nullptr;  // batch only: graph supplied an in-CSR
   const int64_t* voff = nullptr;    // batch only: first vertex of each graph (device)
   int32_t max_graph_n = 0;          // largest vertex count of one graph
+  bool copy_error = false;          // a host-to-device copy could not be enqueued
 };
 
 // Enqueue validation + G* + N+ build.  Returns the built view (device pointers

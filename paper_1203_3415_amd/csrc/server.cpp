@@ -105,13 +105,14 @@ struct motif_server {
 };
 
 void motif_server::worker_main(int /*wid*/) {
-  hipSetDevice(device);
-  hipStream_t s;
+  hipStream_t s = nullptr;
   Pipeline p;
   p.num_cus = cus;
-  if (hipStreamCreate(&s) != hipSuccess) return;
-  hipMalloc(&p.status, kStatusWords * sizeof(int32_t));
-  hipHostMalloc(&p.host_status, kStatusWords * sizeof(int32_t), hipHostMallocDefault);
+  // a worker whose stream or status words cannot be set up still takes
+  // requests and ends them with MOTIF_EDEVICE, so no waiter is left behind
+  const bool ready = hipSetDevice(device) == hipSuccess && hipStreamCreate(&s) == hipSuccess &&
+                     hipMalloc(&p.status, kStatusWords * sizeof(int32_t)) == hipSuccess &&
+                     hipHostMalloc(&p.host_status, kStatusWords * sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     Request* r = nullptr;
@@ -140,11 +141,17 @@ void motif_server::worker_main(int /*wid*/) {
     p.arena.base = (char*)d_hist + al(sizeof(uint64_t) * C);
     p.arena.cap = r->footprint - (size_t)(p.arena.base - base);
     int32_t rc = 0;
-    if (r->n == 0) {
+    if (!ready) {
+      rc = MOTIF_EDEVICE;
+    } else if (r->n == 0) {
       std::fill(r->hist_out, r->hist_out + C, 0ull);
+    } else if (hipMemcpyAsync(d_off, r->off.data(), sizeof(int32_t) * (size_t)(r->n + 1), hipMemcpyHostToDevice, s) !=
+                   hipSuccess ||
+               (r->m && hipMemcpyAsync(d_idx, r->idx.data(), sizeof(int32_t) * (size_t)r->m, hipMemcpyHostToDevice,
+                                       s) != hipSuccess)) {
+      (void)hipStreamSynchronize(s);  // a copy already enqueued ends before its buffers are released
+      rc = MOTIF_EDEVICE;
     } else {
-      hipMemcpyAsync(d_off, r->off.data(), sizeof(int32_t) * (size_t)(r->n + 1), hipMemcpyHostToDevice, s);
-      if (r->m) hipMemcpyAsync(d_idx, r->idx.data(), sizeof(int32_t) * (size_t)r->m, hipMemcpyHostToDevice, s);
       BuildInput in{};
       in.out_off = d_off;
       in.out_idx = d_idx;
@@ -171,10 +178,13 @@ void motif_server::worker_main(int /*wid*/) {
     cv_work.notify_all();
   }
   lk.unlock();
-  hipStreamSynchronize(s);
-  hipStreamDestroy(s);
-  hipFree(p.status);
-  hipHostFree(p.host_status);
+  // tear-down: errors here change nothing that a caller could act on
+  if (s) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  if (p.status) (void)hipFree(p.status);
+  if (p.host_status) (void)hipHostFree(p.host_status);
 }
 
 extern "C" {
@@ -292,8 +302,8 @@ int32_t motif_server_destroy(motif_server_t* s) {
     s->cv_done.notify_all();
   }
   for (auto& t : s->workers) t.join();
-  hipSetDevice(s->device);
-  hipFree(s->pool);
+  (void)hipSetDevice(s->device);  // tear-down: errors change nothing a caller could act on
+  (void)hipFree(s->pool);
   delete s->ranges;
   for (auto& kv : s->requests) delete kv.second;
   delete s;
