@@ -27,15 +27,20 @@
  *  - Return 0 on success, a negative MOTIF_E* code on error.  On error no
  *    output buffer is written.
  *  - Graphs are int32 out-CSR: the arcs of vertex u are u -> out_idx[j] for
- *    out_off[u] <= j < out_off[u+1].  n < 2^30, m < 2^30.
+ *    out_off[u] <= j < out_off[u+1].  n < 2^30 and m < 2^30 (a larger n or m
+ *    returns MOTIF_EINVAL_SHAPE): a vertex id shares one 32-bit word with its
+ *    two type bits in the typed undirected rows, and the 2m half-edges of
+ *    those rows are addressed by int32 offsets.
  *  - Device pointers are hipMalloc'ed (or torch CUDA) memory owned by the
  *    caller; the library never frees them.  The library owns its internal
  *    workspaces and class tables (device memory), released by
  *    motif_shutdown().
  *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
- *    on it; input validation ends with one host wait on that stream so that
- *    an invalid graph is reported by the return code.  The histogram is
- *    complete when the stream is synchronised.
+ *    on it.  motif_census(), motif_census_multi() and the batch calls then
+ *    wait for that stream once, at the end, so that an invalid graph or a
+ *    failed self-check is reported by the return code; the histogram is
+ *    complete when they return.  motif_census_async() does not wait: it
+ *    reports the outcome through a device status word instead.
  *  - Thread safety: calls on different streams may run concurrently (each
  *    stream gets its own workspace); calls on the same stream are ordered.
  */
@@ -129,6 +134,21 @@ int32_t motif_census(const int32_t* out_off, const int32_t* out_idx, const int32
                      const int32_t* in_idx, int32_t n, int64_t m, int32_t k, uint64_t* hist,
                      void* stream);
 
+/* Asynchronous form of motif_census() (same arguments and result), for callers
+ * that synchronise the stream themselves.  Returns 0 once everything is
+ * enqueued on `stream`, or an error found on the host before any work was
+ * enqueued (MOTIF_EINVAL_K, MOTIF_EINVAL_SHAPE, MOTIF_EINVAL_ARG,
+ * MOTIF_ENOMEM, MOTIF_EDEVICE).
+ *  status : device, one int32 owned by the caller; written on `stream` after
+ *           the census with 0 or the validation / self-check error code.
+ *  hist   : written (on `stream`) only when the status is 0.
+ * The stream's workspace is reused by the next call on the same stream, which
+ * runs after this one in stream order; the caller keeps the input buffers
+ * alive until it has synchronised. */
+int32_t motif_census_async(const int32_t* out_off, const int32_t* out_idx, const int32_t* in_off,
+                           const int32_t* in_idx, int32_t n, int64_t m, int32_t k, uint64_t* hist,
+                           int32_t* status, void* stream);
+
 /* Census of one graph for several sizes: ks[0..nk) are distinct values of
  * {3, 4, 5} and hists[i] (device, motif_num_classes(ks[i]) uint64) receives
  * exactly what motif_census(..., ks[i], hists[i], ...) would write.  The
@@ -191,21 +211,43 @@ typedef struct motif_tuning {
   int32_t heavy;        /* census scheme for k = 4, 5: 1 = core reuse (neighbourhood
                            of the highest-ranked anchor vertex scanned once per
                            work unit), 2 = per-anchor scan; 0 = keep              */
+  /* Work placement of the core-reuse schemes (degrees in the undirected
+   * graph G*); they move work between waves and workgroups, never change
+   * the result. */
+  int32_t solo_deg;     /* k = 4: a core (higher-ranked anchor end) of at most this
+                           degree runs whole anchors on one wave (1..64)        */
+  int32_t light_deg;    /* k = 4: an anchor whose other end has at most this
+                           degree runs on one wave, else on the workgroup
+                           (1..256)                                             */
+  int32_t light5;       /* k = 5: a triple whose lighter side has at most this
+                           degree takes the factored wave path (1..767)         */
 } motif_tuning_t;
 
-/* Read / override the parameters used for k (0 in a field = keep default). */
+/* Read / override the default parameters for k (0 in a field = keep).
+ * Setting them also drops the autotuner's cached entries for k. */
 int32_t motif_get_tuning(int32_t k, motif_tuning_t* out);
 int32_t motif_set_tuning(int32_t k, const motif_tuning_t* in);
 
 /* Autotuner: times the fused batch census of `graphs` (device pointers, as for
- * motif_census_batch) under a small grid of candidate tunings -- block,
- * grid, tile and, for k = 4 and 5, the census scheme -- keeps the fastest
- * for k (it is then used by every later call) and writes it to *best.
- * `hists` is scratch output (count * C uint64, device).  Every candidate's
- * histograms are checked equal to the first candidate's; a mismatch returns
+ * motif_census_batch; count = 1 tunes the single-graph path) under candidate
+ * tunings -- a coordinate descent, two passes, over block, grid, tile, the
+ * census scheme and the work-placement limits -- each candidate timed as the
+ * median of 3 runs after a warm-up.  The fastest is cached for (this device,
+ * k, batch or single graph, floor(log2(total arcs))) and used by every later
+ * call that falls in that bucket; it is also written to *best.  `hists` is
+ * scratch output (count * C uint64, device).  Every candidate's histograms
+ * are checked equal to the first candidate's; a mismatch returns
  * MOTIF_EINTERNAL. */
 int32_t motif_autotune(const motif_graph_t* graphs, int32_t count, int32_t k, uint64_t* hists,
                        void* stream, motif_tuning_t* best);
+
+/* Save the autotuner cache as text (one line per entry, keyed by the
+ * device's architecture name and compute-unit count) / load such a file into
+ * the cache of the current device: entries of another device kind or with
+ * out-of-range values are skipped.  load returns the number of entries taken
+ * (>= 0) or an error code; save returns 0 or MOTIF_EINVAL_ARG (file error). */
+int32_t motif_tune_cache_save(const char* path);
+int32_t motif_tune_cache_load(const char* path);
 
 /* ---- measurement ------------------------------------------------------------ */
 

@@ -11,6 +11,7 @@ from .binding import (  # noqa: F401
     lib,
     lib_path,
     census,
+    census_async,
     census_batch,
     census_multi,
     census_batch_loop,
@@ -22,6 +23,8 @@ from .binding import (  # noqa: F401
     get_tuning,
     set_tuning,
     autotune,
+    tune_cache_save,
+    tune_cache_load,
     profile_enable,
     profile_read,
     to_device,

@@ -38,9 +38,14 @@ class _Graph(ctypes.Structure):
     ]
 
 
+_TUNING_FIELDS = ("block", "grid_per_cu", "tile", "heavy", "solo_deg", "light_deg", "light5")
+
+
 class _Tuning(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("heavy", ctypes.c_int32)]
+    _fields_ = [(f, ctypes.c_int32) for f in _TUNING_FIELDS]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f in _TUNING_FIELDS}
 
 
 _LOCK = threading.Lock()
@@ -75,12 +80,15 @@ def lib():
             "motif_class_of_code": ([I32, U32], I32),
             "motif_strerror": ([I32], ctypes.c_char_p),
             "motif_census": ([P, P, P, P, I32, I64, I32, P, P], I32),
+            "motif_census_async": ([P, P, P, P, I32, I64, I32, P, P, P], I32),
             "motif_census_batch": ([P, I32, I32, P, P], I32),
             "motif_census_multi": ([P, I32, P, P, P], I32),
             "motif_census_batch_loop": ([P, I32, I32, P, P], I32),
             "motif_get_tuning": ([I32, ctypes.POINTER(_Tuning)], I32),
             "motif_set_tuning": ([I32, ctypes.POINTER(_Tuning)], I32),
             "motif_autotune": ([P, I32, I32, P, P, ctypes.POINTER(_Tuning)], I32),
+            "motif_tune_cache_save": ([ctypes.c_char_p], I32),
+            "motif_tune_cache_load": ([ctypes.c_char_p], I32),
             "motif_batch_plan_create": ([P, I32, I32, P, P, ctypes.POINTER(I32)], P),
             "motif_batch_plan_run": ([P], I32),
             "motif_batch_plan_destroy": ([P], I32),
@@ -180,6 +188,25 @@ def census(out_off, out_idx, n: int, k: int, in_off=None, in_idx=None, stream=No
     if out is not None:
         return out
     return hist.cpu().numpy().view(np.uint64)
+
+
+def census_async(out_off, out_idx, n: int, k: int, hist, status, in_off=None, in_idx=None, stream=None):
+    """Enqueue a census without waiting: `hist` (int64 CUDA tensor of C
+    entries) is written, and `status` (int32 CUDA tensor of 1 entry) receives
+    0 or the error code, on the stream.  Raises only for errors found before
+    anything is enqueued."""
+    torch = _torch()
+    for t, nm in ((out_off, "out_off"), (out_idx, "out_idx"), (in_off, "in_off"), (in_idx, "in_idx"),
+                  (status, "status")):
+        _check_dev(t, nm)
+    C = NUM_CLASSES.get(k)
+    if C is None:
+        raise MotifError(-1, "census_async")
+    if not (torch.is_tensor(hist) and hist.is_cuda and hist.dtype == torch.int64 and hist.numel() == C):
+        raise TypeError("hist must be an int64 CUDA tensor of C entries")
+    rc = lib().motif_census_async(_ptr(out_off), _ptr(out_idx), _ptr(in_off), _ptr(in_idx), int(n),
+                                  int(out_idx.numel()), int(k), _ptr(hist), _ptr(status), _stream_handle(stream))
+    _check(rc, "motif_census_async")
 
 
 def census_multi(out_off, out_idx, n: int, ks, in_off=None, in_idx=None, stream=None, outs=None):
@@ -289,12 +316,24 @@ class BatchPlan:
 def get_tuning(k: int) -> dict:
     t = _Tuning()
     _check(lib().motif_get_tuning(k, ctypes.byref(t)), "motif_get_tuning")
-    return {"block": t.block, "grid_per_cu": t.grid_per_cu, "tile": t.tile, "heavy": t.heavy}
+    return t.as_dict()
 
 
-def set_tuning(k: int, block=0, grid_per_cu=0, tile=0, heavy=0):
-    t = _Tuning(block, grid_per_cu, tile, heavy)
+def set_tuning(k: int, block=0, grid_per_cu=0, tile=0, heavy=0, solo_deg=0, light_deg=0, light5=0):
+    t = _Tuning(block, grid_per_cu, tile, heavy, solo_deg, light_deg, light5)
     _check(lib().motif_set_tuning(k, ctypes.byref(t)), "motif_set_tuning")
+
+
+def tune_cache_save(path: str) -> None:
+    _check(lib().motif_tune_cache_save(os.fsencode(path)), "motif_tune_cache_save")
+
+
+def tune_cache_load(path: str) -> int:
+    """Entries taken from the file into the current device's tuning cache."""
+    r = lib().motif_tune_cache_load(os.fsencode(path))
+    if r < 0:
+        raise MotifError(r, "motif_tune_cache_load")
+    return int(r)
 
 
 def autotune(graphs, k: int, stream=None) -> dict:
@@ -305,7 +344,7 @@ def autotune(graphs, k: int, stream=None) -> dict:
     t = _Tuning()
     _check(lib().motif_autotune(ctypes.cast(arr, ctypes.c_void_p), len(graphs), int(k), _ptr(hist),
                                 _stream_handle(stream), ctypes.byref(t)), "motif_autotune")
-    return {"block": t.block, "grid_per_cu": t.grid_per_cu, "tile": t.tile, "heavy": t.heavy}
+    return t.as_dict()
 
 
 def profile_enable(on: bool = True):

@@ -9,6 +9,8 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "classes.h"
@@ -20,23 +22,30 @@ namespace {
 
 std::mutex g_mu;
 
+// Autotuner cache key: (k, batch of several graphs?, floor(log2 of the
+// total arc count)).
+using TuneKey = std::tuple<int32_t, int32_t, int32_t>;
+
 struct DeviceState {
   bool ready = false;
   int num_cus = 0;
+  std::string arch;  // gcnArchName up to the first ':'
   DevTables tables;
   std::vector<void*> owned;  // table buffers
   std::map<hipStream_t, Pipeline*> pipes;
+  std::map<TuneKey, Tuning> tuned;  // filled by motif_autotune / motif_tune_cache_load
 };
 
 std::map<int, DeviceState> g_dev;
 int32_t g_init_err = 0;
 
-Tuning g_tuning[6] = {
+// Guarded by g_mu; every call works on a copy (tuning_snapshot).
+TuningSet g_tuning = {{
     {256, 4, 16, 1}, {256, 4, 16, 1}, {256, 4, 16, 1},
     {256, 4, 16, 1},    // k = 3: tile*16 vertices per tile (at most 1024)
     {1024, 1, 3, 1},    // k = 4: core reuse (tile = cost tiles per workgroup)
     {1024, 1, 64, 1},   // k = 5: core reuse (tile = cost tiles per workgroup)
-};
+}};
 
 int32_t current_device(int* dev) {
   if (hipGetDevice(dev) != hipSuccess) return MOTIF_EDEVICE;
@@ -51,6 +60,8 @@ int32_t init_device_locked(int dev) {
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MOTIF_EDEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MOTIF_EDEVICE;
   d.num_cus = prop.multiProcessorCount;
+  d.arch = prop.gcnArchName;
+  d.arch = d.arch.substr(0, d.arch.find(':'));
   for (int k = 3; k <= 5; ++k) {
     const ClassTable* t = class_table(k);
     void *lut = nullptr, *mult = nullptr;
@@ -153,7 +164,103 @@ const DevTables& dev_tables() {
   return g_dev[dev].tables;
 }
 
-Tuning& tuning_for(int k) { return g_tuning[k]; }
+TuningSet tuning_snapshot() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_tuning;
+}
+
+namespace {
+int32_t size_bucket(int64_t arcs) { return arcs > 1 ? 63 - __builtin_clzll((unsigned long long)arcs) : 0; }
+}  // namespace
+
+TuningSet tuning_for_call(int dev, int32_t nk, const int32_t* ks, bool batch, int64_t arcs) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  TuningSet t = g_tuning;
+  const DeviceState& d = g_dev[dev];
+  for (int32_t i = 0; i < nk; ++i) {
+    auto it = d.tuned.find(TuneKey{ks[i], batch ? 1 : 0, size_bucket(arcs)});
+    if (it != d.tuned.end()) t.k[ks[i]] = it->second;
+  }
+  return t;
+}
+
+namespace {
+
+constexpr int kTuneReps = 3;  // timed runs per autotuner candidate (the median is kept)
+
+motif_tuning_t to_public(const Tuning& t) {
+  motif_tuning_t o{};
+  o.block = t.block;
+  o.grid_per_cu = t.grid_per_cu;
+  o.tile = t.tile;
+  o.heavy = t.heavy == 1 ? 1 : 2;
+  o.solo_deg = t.solo_deg;
+  o.light_deg = t.light_deg;
+  o.light5 = t.light5;
+  return o;
+}
+
+// Checks every non-zero field of `in` for k and writes it into *t.
+int32_t apply_public(int32_t k, const motif_tuning_t& in, Tuning* t) {
+  Tuning r = *t;
+  if (in.block) {
+    const bool ok = k == 3 ? in.block == 256 : k == 4 ? (in.block == 256 || in.block == 512 || in.block == 1024)
+                                                     : (in.block == 512 || in.block == 1024);
+    if (!ok) return MOTIF_EINVAL_ARG;
+    r.block = in.block;
+  }
+  if (in.grid_per_cu) {
+    if (in.grid_per_cu < 1 || in.grid_per_cu > 16) return MOTIF_EINVAL_ARG;
+    r.grid_per_cu = in.grid_per_cu;
+  }
+  if (in.tile) {
+    if (in.tile < 1 || in.tile > 4096) return MOTIF_EINVAL_ARG;
+    r.tile = in.tile;
+  }
+  if (in.heavy) {
+    // 1 = core-reuse scheme, 2 = per-anchor scan (k = 4, 5)
+    if (in.heavy < 1 || in.heavy > 2) return MOTIF_EINVAL_ARG;
+    r.heavy = in.heavy == 2 ? 0 : 1;
+  }
+  if (in.solo_deg) {
+    if (in.solo_deg < 1 || in.solo_deg > 64) return MOTIF_EINVAL_ARG;
+    r.solo_deg = in.solo_deg;
+  }
+  if (in.light_deg) {
+    if (in.light_deg < 1 || in.light_deg > 256) return MOTIF_EINVAL_ARG;
+    r.light_deg = in.light_deg;
+  }
+  if (in.light5) {
+    if (in.light5 < 1 || in.light5 > 767) return MOTIF_EINVAL_ARG;
+    r.light5 = in.light5;
+  }
+  *t = r;
+  return 0;
+}
+
+// One tunable of k and the values the autotuner tries for it.
+struct TuneAxis {
+  int Tuning::*mem;
+  std::vector<int> values;
+  bool reuse_only;  // only meaningful for the core-reuse scheme
+  int& field(Tuning& t) const { return t.*mem; }
+};
+
+std::vector<TuneAxis> tune_axes(int k) {
+  if (k == 3) return {{&Tuning::tile, {4, 8, 16, 32, 64}, false}, {&Tuning::grid_per_cu, {2, 4, 8}, false}};
+  if (k == 4)
+    return {{&Tuning::heavy, {1, 0}, false},
+            {&Tuning::block, {512, 1024}, false},
+            {&Tuning::grid_per_cu, {1, 2}, false},
+            {&Tuning::tile, {2, 3, 4, 8, 16}, false},
+            {&Tuning::solo_deg, {16, 32, 48, 64}, true},
+            {&Tuning::light_deg, {96, 128, 160, 192, 224, 256}, true}};
+  return {{&Tuning::block, {512, 1024}, false},
+          {&Tuning::tile, {16, 32, 64, 128, 256}, false},
+          {&Tuning::light5, {128, 256, 384, 512, 640, 767}, true}};
+}
+
+}  // namespace
 
 void profile_mark(int k, int what, bool begin, hipStream_t s) {
   if (!g_prof.on || k < 3 || k > 5) return;
@@ -166,19 +273,35 @@ void profile_mark(int k, int what, bool begin, hipStream_t s) {
   if (what == 1 && !begin) g_prof.have[k] = true;
 }
 
+// A workspace sizing error stopped an enqueue half way: the kernels already
+// enqueued only touch regions taken before it; wait for them (on both
+// streams) so that the workspace can be reused, and report the error.
+int32_t drain_after_error(Pipeline& p, hipStream_t s) {
+  (void)hipStreamSynchronize(s);  // best effort: the error below is what the caller acts on
+  if (p.side) (void)hipStreamSynchronize(p.side);
+  return MOTIF_EINTERNAL;
+}
+
+int32_t run_census_multi_enqueue(Pipeline& p, const BuildInput& in, int32_t nk, const int32_t* ks,
+                                 uint64_t* const* hists, hipStream_t s);
+
 // One census on a sized pipeline: build + status wait + census + status wait.
 // The census is enqueued right behind the build, with no host wait in
 // between: every census kernel returns at once when the build has set the
 // status word, and the exact division writes nothing then.
 int32_t run_census_on(Pipeline& p, const BuildInput& in, int32_t k, uint64_t* hist, hipStream_t s) {
   const int C = motif_num_classes(k);
-  p.arena.reset();
-  enqueue_zero(p.status, sizeof(int32_t) * kStatusWords, s);
-  profile_mark(k, 0, true, s);
-  DevGraph g = enqueue_build(p, in, s);
-  profile_mark(k, 0, false, s);
-  uint64_t* acc = p.arena.take<uint64_t>((size_t)in.ngraphs * C);
-  enqueue_census(p, g, k, acc, hist, s);
+  try {
+    p.arena.reset();
+    enqueue_zero(p.status, sizeof(int32_t) * kStatusWords, s);
+    profile_mark(k, 0, true, s);
+    DevGraph g = enqueue_build(p, in, s);
+    profile_mark(k, 0, false, s);
+    uint64_t* acc = p.arena.take<uint64_t>((size_t)in.ngraphs * C);
+    enqueue_census(p, g, k, acc, hist, s);
+  } catch (const WorkspaceError&) {
+    return drain_after_error(p, s);
+  }
   return read_status(p, s);
 }
 
@@ -188,6 +311,15 @@ int32_t run_census_on(Pipeline& p, const BuildInput& in, int32_t k, uint64_t* hi
 // largest census leaves idle at its end.  Each census has its own workspace.
 int32_t run_census_multi_on(Pipeline& p, const BuildInput& in, int32_t nk, const int32_t* ks, uint64_t* const* hists,
                             hipStream_t s) {
+  try {
+    return run_census_multi_enqueue(p, in, nk, ks, hists, s);
+  } catch (const WorkspaceError&) {
+    return drain_after_error(p, s);
+  }
+}
+
+int32_t run_census_multi_enqueue(Pipeline& p, const BuildInput& in, int32_t nk, const int32_t* ks,
+                                 uint64_t* const* hists, hipStream_t s) {
   p.arena.reset();
   enqueue_zero(p.status, sizeof(int32_t) * kStatusWords, s);
   for (int32_t i = 0; i < nk; ++i) profile_mark(ks[i], 0, true, s);  // the shared build, seen by every k
@@ -219,10 +351,62 @@ int32_t run_census(const BuildInput& in, int32_t k, uint64_t* hist, hipStream_t 
   int dev;
   int32_t rc = ensure_init(&dev);
   if (rc) return rc;
+  const TuningSet tune = tuning_for_call(dev, 1, &k, false, in.m);
   Pipeline* p = nullptr;
-  rc = get_pipeline(dev, s, pipeline_bytes(in.n, in.m, in.ngraphs, false, k, device_cus(dev), in.n), &p);
+  rc = get_pipeline(dev, s, pipeline_bytes(in.n, in.m, in.ngraphs, false, k, device_cus(dev), in.n, tune.k[k]), &p);
   if (rc) return rc;
+  p->tune = tune;
   return run_census_on(*p, in, k, hist, s);
+}
+
+// Fused census of a batch under an explicit tuning (motif_census_batch and
+// the autotuner's candidates).
+int32_t census_batch_with(const motif_graph_t* graphs, int32_t count, int32_t k, uint64_t* hists, hipStream_t s,
+                          const TuningSet& tune) {
+  std::vector<int64_t> voff(count + 1, 0), aoff(count + 1, 0);
+  for (int32_t g = 0; g < count; ++g) {
+    const motif_graph_t& G = graphs[g];
+    if (!check_shape(G.n, G.m)) return MOTIF_EINVAL_SHAPE;
+    if (G.n == 0 && G.m != 0) return MOTIF_EINVAL_SHAPE;
+    if ((G.n > 0 && !G.out_off) || (G.m > 0 && !G.out_idx)) return MOTIF_EINVAL_ARG;
+    if (G.in_off && G.m > 0 && !G.in_idx) return MOTIF_EINVAL_ARG;
+    voff[g + 1] = voff[g] + G.n;
+    aoff[g + 1] = aoff[g] + G.m;
+  }
+  if (voff[count] >= kMaxN || aoff[count] >= kMaxN) return MOTIF_EINVAL_SHAPE;
+  int dev;
+  int32_t rc = ensure_init(&dev);
+  if (rc) return rc;
+  const int C = motif_num_classes(k);
+  if (voff[count] == 0) {
+    enqueue_zero(hists, sizeof(uint64_t) * C * (size_t)count, s);
+    return hipStreamSynchronize(s) == hipSuccess ? 0 : MOTIF_EDEVICE;
+  }
+  // Graphs with n = 0 contribute no vertices; the pack kernel never sees them.
+  Pipeline* p = nullptr;
+  int64_t maxn = 0;
+  for (int32_t g = 0; g < count; ++g) maxn = std::max<int64_t>(maxn, graphs[g].n);
+  rc = get_pipeline(dev, s,
+                    pipeline_bytes(voff[count], aoff[count], count, true, k, device_cus(dev), maxn, tune.k[k]), &p);
+  if (rc) return rc;
+  p->tune = tune;
+  try {
+    p->arena.reset();
+    enqueue_zero(p->status, sizeof(int32_t) * kStatusWords, s);
+    profile_mark(k, 0, true, s);
+    BuildInput in = enqueue_pack(*p, graphs, count, voff.data(), aoff.data(), s);
+    if (in.copy_error) {
+      (void)hipStreamSynchronize(s);  // copies already enqueued end before the workspace is reused
+      return MOTIF_EDEVICE;
+    }
+    DevGraph g = enqueue_build(*p, in, s);
+    profile_mark(k, 0, false, s);
+    uint64_t* acc = p->arena.take<uint64_t>((size_t)count * C);
+    enqueue_census(*p, g, k, acc, hists, s);
+  } catch (const WorkspaceError&) {
+    return drain_after_error(*p, s);
+  }
+  return read_status(*p, s);
 }
 
 }  // namespace motif
@@ -333,6 +517,48 @@ int32_t motif_census(const int32_t* out_off, const int32_t* out_idx, const int32
   return run_census(in, k, hist, s);
 }
 
+int32_t motif_census_async(const int32_t* out_off, const int32_t* out_idx, const int32_t* in_off,
+                           const int32_t* in_idx, int32_t n, int64_t m, int32_t k, uint64_t* hist, int32_t* status,
+                           void* stream) {
+  if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
+  if (!check_shape(n, m) || (n == 0 && m != 0)) return MOTIF_EINVAL_SHAPE;
+  if (!hist || !status || !out_off || (m > 0 && !out_idx)) return MOTIF_EINVAL_ARG;
+  if (in_off && m > 0 && !in_idx) return MOTIF_EINVAL_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  int dev;
+  int32_t rc = ensure_init(&dev);
+  if (rc) return rc;
+  const TuningSet tune = tuning_for_call(dev, 1, &k, false, m);
+  Pipeline* p = nullptr;
+  rc = get_pipeline(dev, s, pipeline_bytes(n, m, 1, false, k, device_cus(dev), n, tune.k[k]), &p);
+  if (rc) return rc;
+  p->tune = tune;
+  BuildInput in{};
+  in.out_off = out_off;
+  in.out_idx = out_idx;
+  in.in_off = in_off;
+  in.in_idx = in_off ? in_idx : nullptr;
+  in.n = n;
+  in.m = m;
+  try {
+    p->arena.reset();
+    enqueue_zero(p->status, sizeof(int32_t) * kStatusWords, s);
+    if (n == 0) {
+      enqueue_zero(hist, sizeof(uint64_t) * motif_num_classes(k), s);
+    } else {
+      profile_mark(k, 0, true, s);
+      DevGraph g = enqueue_build(*p, in, s);
+      profile_mark(k, 0, false, s);
+      uint64_t* acc = p->arena.take<uint64_t>((size_t)motif_num_classes(k));
+      enqueue_census(*p, g, k, acc, hist, s);
+    }
+    enqueue_status_out(status, p->status, s);
+  } catch (const WorkspaceError&) {
+    return drain_after_error(*p, s);
+  }
+  return 0;
+}
+
 int32_t motif_census_multi(const motif_graph_t* g, int32_t nk, const int32_t* ks, uint64_t* const* hists,
                            void* stream) {
   if (!g || !ks || !hists || nk < 1 || nk > 3) return MOTIF_EINVAL_ARG;
@@ -362,12 +588,15 @@ int32_t motif_census_multi(const motif_graph_t* g, int32_t nk, const int32_t* ks
   in.n = g->n;
   in.m = g->m;
   // one build plus the workspace of every size (the censuses may run at once)
+  const TuningSet tune = tuning_for_call(dev, nk, ks, false, in.m);
   const size_t build = build_bytes(in.n, in.m, 1, false);
   size_t bytes = build;
-  for (int32_t i = 0; i < nk; ++i) bytes += pipeline_bytes(in.n, in.m, 1, false, ks[i], device_cus(dev), in.n) - build;
+  for (int32_t i = 0; i < nk; ++i)
+    bytes += pipeline_bytes(in.n, in.m, 1, false, ks[i], device_cus(dev), in.n, tune.k[ks[i]]) - build;
   Pipeline* p = nullptr;
   rc = get_pipeline(dev, s, bytes, &p);
   if (rc) return rc;
+  p->tune = tune;
   return run_census_multi_on(*p, in, nk, ks, hists, s);
 }
 
@@ -375,44 +604,12 @@ int32_t motif_census_batch(const motif_graph_t* graphs, int32_t count, int32_t k
   if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
   if (count < 0 || (count > 0 && (!graphs || !hists))) return MOTIF_EINVAL_ARG;
   if (count == 0) return 0;
-  std::vector<int64_t> voff(count + 1, 0), aoff(count + 1, 0);
-  for (int32_t g = 0; g < count; ++g) {
-    const motif_graph_t& G = graphs[g];
-    if (!check_shape(G.n, G.m)) return MOTIF_EINVAL_SHAPE;
-    if (G.n == 0 && G.m != 0) return MOTIF_EINVAL_SHAPE;
-    if ((G.n > 0 && !G.out_off) || (G.m > 0 && !G.out_idx)) return MOTIF_EINVAL_ARG;
-    if (G.in_off && G.m > 0 && !G.in_idx) return MOTIF_EINVAL_ARG;
-    voff[g + 1] = voff[g] + G.n;
-    aoff[g + 1] = aoff[g] + G.m;
-  }
-  if (voff[count] >= kMaxN || aoff[count] >= kMaxN) return MOTIF_EINVAL_SHAPE;
   int dev;
   int32_t rc = ensure_init(&dev);
   if (rc) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  const int C = motif_num_classes(k);
-  if (voff[count] == 0) {
-    enqueue_zero(hists, sizeof(uint64_t) * C * (size_t)count, s);
-    return hipStreamSynchronize(s) == hipSuccess ? 0 : MOTIF_EDEVICE;
-  }
-  // Graphs with n = 0 contribute no vertices; the pack kernel never sees them.
-  Pipeline* p = nullptr;
-  int64_t maxn = 0;
-  for (int32_t g = 0; g < count; ++g) maxn = std::max<int64_t>(maxn, graphs[g].n);
-  rc = get_pipeline(dev, s, pipeline_bytes(voff[count], aoff[count], count, true, k, device_cus(dev), maxn), &p);
-  if (rc) return rc;
-  p->arena.reset();
-  enqueue_zero(p->status, sizeof(int32_t) * kStatusWords, s);
-  profile_mark(k, 0, true, s);
-  BuildInput in = enqueue_pack(*p, graphs, count, voff.data(), aoff.data(), s);
-  if (in.copy_error) return MOTIF_EDEVICE;
-  DevGraph g = enqueue_build(*p, in, s);
-  profile_mark(k, 0, false, s);
-  rc = read_status(*p, s);
-  if (rc) return rc;
-  uint64_t* acc = p->arena.take<uint64_t>((size_t)count * C);
-  enqueue_census(*p, g, k, acc, hists, s);
-  return read_status(*p, s);
+  int64_t arcs = 0;
+  for (int32_t g = 0; g < count; ++g) arcs += std::max<int64_t>(0, graphs[g].m);
+  return census_batch_with(graphs, count, k, hists, (hipStream_t)stream, tuning_for_call(dev, 1, &k, count > 1, arcs));
 }
 
 int32_t motif_census_batch_loop(const motif_graph_t* graphs, int32_t count, int32_t k, uint64_t* hists,
@@ -431,37 +628,21 @@ int32_t motif_census_batch_loop(const motif_graph_t* graphs, int32_t count, int3
 int32_t motif_get_tuning(int32_t k, motif_tuning_t* out) {
   if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
   if (!out) return MOTIF_EINVAL_ARG;
-  const Tuning& t = tuning_for(k);
-  out->block = t.block;
-  out->grid_per_cu = t.grid_per_cu;
-  out->tile = t.tile;
-  out->heavy = t.heavy == 1 ? 1 : 2;
+  *out = to_public(tuning_snapshot().k[k]);
   return 0;
 }
 
 int32_t motif_set_tuning(int32_t k, const motif_tuning_t* in) {
   if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
   if (!in) return MOTIF_EINVAL_ARG;
-  Tuning& t = tuning_for(k);
-  if (in->block) {
-    const bool ok = k == 3 ? in->block == 256 : k == 4 ? (in->block == 256 || in->block == 512 || in->block == 1024)
-                                                      : (in->block == 512 || in->block == 1024);
-    if (!ok) return MOTIF_EINVAL_ARG;
-    t.block = in->block;
-  }
-  if (in->grid_per_cu) {
-    if (in->grid_per_cu < 1 || in->grid_per_cu > 16) return MOTIF_EINVAL_ARG;
-    t.grid_per_cu = in->grid_per_cu;
-  }
-  if (in->tile) {
-    if (in->tile < 1 || in->tile > 4096) return MOTIF_EINVAL_ARG;
-    t.tile = in->tile;
-  }
-  if (in->heavy) {
-    // 1 = core-reuse scheme, 2 = per-anchor scan (k = 4, 5)
-    if (in->heavy < 1 || in->heavy > 2) return MOTIF_EINVAL_ARG;
-    t.heavy = in->heavy == 2 ? 0 : 1;
-  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  Tuning t = g_tuning.k[k];
+  if (int32_t rc = apply_public(k, *in, &t)) return rc;
+  g_tuning.k[k] = t;
+  // an explicit choice replaces what the autotuner cached for k
+  for (auto& d : g_dev)
+    for (auto it = d.second.tuned.begin(); it != d.second.tuned.end();)
+      it = std::get<0>(it->first) == k ? d.second.tuned.erase(it) : std::next(it);
   return 0;
 }
 
@@ -469,63 +650,121 @@ int32_t motif_autotune(const motif_graph_t* graphs, int32_t count, int32_t k, ui
                        motif_tuning_t* best) {
   if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
   if (count <= 0 || !graphs || !hists) return MOTIF_EINVAL_ARG;
+  int dev;
+  if (int32_t rc = ensure_init(&dev)) return rc;
   const int C = motif_num_classes(k);
   hipStream_t s = (hipStream_t)stream;
-  std::vector<motif_tuning_t> cands;
-  if (k == 3) {
-    for (int tile : {4, 16, 64})
-      for (int gpc : {2, 4, 8}) cands.push_back({256, gpc, tile, 0});
-  } else if (k == 4) {  // both schemes: core reuse (1) and per-anchor scan (2)
-    for (int block : {512, 1024})
-      for (int gpc : {1, 2})
-        for (int tile : {3, 8, 16}) cands.push_back({block, gpc, tile, 1});
-    for (int block : {256, 512})
-      for (int gpc : {2, 4})
-        for (int tile : {8, 32}) cands.push_back({block, gpc, tile, 2});
-  } else {
-    for (int block : {512, 1024})
-      for (int tile : {16, 64, 256}) cands.push_back({block, 1, tile, 1});
-    for (int tile : {1, 4}) cands.push_back({1024, 1, tile, 2});
+  int64_t arcs = 0;
+  for (int32_t g = 0; g < count; ++g) arcs += std::max<int64_t>(0, graphs[g].m);
+  const bool batch = count > 1;
+  const TuneKey key{k, batch ? 1 : 0, size_bucket(arcs)};
+  TuningSet base = tuning_snapshot();
+  {
+    std::lock_guard<std::mutex> lk(g_mu);  // start from the cached entry of this bucket, if any
+    auto it = g_dev[dev].tuned.find(key);
+    if (it != g_dev[dev].tuned.end()) base.k[k] = it->second;
   }
-  const Tuning saved = tuning_for(k);
   std::vector<uint64_t> ref((size_t)count * C), cur((size_t)count * C);
-  double best_ms = 1e300;
-  motif_tuning_t best_t{saved.block, saved.grid_per_cu, saved.tile, saved.heavy == 1 ? 1 : 2};
-  for (size_t i = 0; i < cands.size(); ++i) {
-    Tuning& t = tuning_for(k);
-    t.block = cands[i].block;
-    t.grid_per_cu = cands[i].grid_per_cu;
-    t.tile = cands[i].tile;
-    if (k > 3) t.heavy = cands[i].heavy == 1 ? 1 : 0;
-    auto tw = std::chrono::steady_clock::now();
-    int32_t rc = motif_census_batch(graphs, count, k, hists, stream);  // warm-up
-    if (rc) { tuning_for(k) = saved; return rc; }
-    auto t0 = std::chrono::steady_clock::now();
-    // a candidate whose warm-up is 4x slower than the best so far is not timed
-    const bool slow = std::chrono::duration<double, std::milli>(t0 - tw).count() > 4.0 * best_ms;
-    if (!slow) rc = motif_census_batch(graphs, count, k, hists, stream);
-    auto t1 = std::chrono::steady_clock::now();
-    if (rc) { tuning_for(k) = saved; return rc; }
-    if (hipMemcpyAsync(i == 0 ? ref.data() : cur.data(), hists, sizeof(uint64_t) * ref.size(), hipMemcpyDeviceToHost,
-                       s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-      tuning_for(k) = saved;
-      return MOTIF_EDEVICE;
+  bool have_ref = false;
+  // One candidate: warm-up, then the median wall time of kTuneReps runs; its
+  // histograms must equal those of the first candidate.
+  auto measure = [&](const Tuning& t, double* ms_out) -> int32_t {
+    TuningSet ts = base;
+    ts.k[k] = t;
+    int32_t rc = census_batch_with(graphs, count, k, hists, s, ts);
+    if (rc) return rc;
+    std::vector<double> ms;
+    for (int r = 0; r < kTuneReps; ++r) {
+      auto t0 = std::chrono::steady_clock::now();
+      rc = census_batch_with(graphs, count, k, hists, s, ts);
+      auto t1 = std::chrono::steady_clock::now();
+      if (rc) return rc;
+      ms.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
     }
-    if (i > 0 && cur != ref) { tuning_for(k) = saved; return MOTIF_EINTERNAL; }
-    const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    if (!slow && ms < best_ms) {
-      best_ms = ms;
-      best_t = cands[i];
+    std::sort(ms.begin(), ms.end());
+    *ms_out = ms[ms.size() / 2];
+    std::vector<uint64_t>& dst = have_ref ? cur : ref;
+    if (hipMemcpyAsync(dst.data(), hists, sizeof(uint64_t) * ref.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return MOTIF_EDEVICE;
+    if (have_ref && cur != ref) return MOTIF_EINTERNAL;
+    have_ref = true;
+    return 0;
+  };
+  // Coordinate descent over the tunables of k, two passes: each field in
+  // turn takes the best of its candidate values with the others held.
+  Tuning bt = base.k[k];
+  double best_ms = 0;
+  if (int32_t rc = measure(bt, &best_ms)) return rc;
+  const std::vector<TuneAxis> axes = tune_axes(k);
+  for (int pass = 0; pass < 2; ++pass) {
+    for (const TuneAxis& ax : axes) {
+      if (ax.reuse_only && bt.heavy != 1) continue;
+      for (int v : ax.values) {
+        Tuning t = bt;
+        if (ax.field(t) == v) continue;
+        ax.field(t) = v;
+        double ms = 0;
+        if (int32_t rc = measure(t, &ms)) return rc;
+        if (ms < best_ms) {
+          best_ms = ms;
+          bt = t;
+        }
+      }
     }
   }
-  Tuning& t = tuning_for(k);
-  t.block = best_t.block;
-  t.grid_per_cu = best_t.grid_per_cu;
-  t.tile = best_t.tile;
-  if (k > 3) t.heavy = best_t.heavy == 1 ? 1 : 0;
-  if (best) *best = best_t;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_dev[dev].tuned[key] = bt;
+  }
+  if (best) *best = to_public(bt);
   return 0;
+}
+
+int32_t motif_tune_cache_save(const char* path) {
+  if (!path) return MOTIF_EINVAL_ARG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return MOTIF_EINVAL_ARG;
+  std::fprintf(f, "# arch cus k batch bucket block grid_per_cu tile heavy solo_deg light_deg light5\n");
+  for (auto& d : g_dev)
+    for (auto& e : d.second.tuned) {
+      const Tuning& t = e.second;
+      std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d\n", d.second.arch.c_str(), d.second.num_cus,
+                   std::get<0>(e.first), std::get<1>(e.first), std::get<2>(e.first), t.block, t.grid_per_cu, t.tile,
+                   t.heavy, t.solo_deg, t.light_deg, t.light5);
+    }
+  return std::fclose(f) == 0 ? 0 : MOTIF_EINVAL_ARG;
+}
+
+int32_t motif_tune_cache_load(const char* path) {
+  if (!path) return MOTIF_EINVAL_ARG;
+  int dev;
+  if (int32_t rc = ensure_init(&dev)) return rc;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return MOTIF_EINVAL_ARG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceState& d = g_dev[dev];
+  int32_t loaded = 0;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#') continue;
+    char arch[64];
+    int cus, k, batch, bucket;
+    Tuning t;
+    if (std::sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %d %d", arch, &cus, &k, &batch, &bucket, &t.block,
+                    &t.grid_per_cu, &t.tile, &t.heavy, &t.solo_deg, &t.light_deg, &t.light5) != 12)
+      continue;
+    // entries of another kind of device, and values outside the accepted
+    // ranges, are skipped
+    if (d.arch != arch || d.num_cus != cus || motif_num_classes(k) < 0) continue;
+    Tuning chk = g_tuning.k[k];
+    if (apply_public(k, to_public(t), &chk)) continue;
+    d.tuned[TuneKey{k, batch ? 1 : 0, bucket}] = chk;
+    ++loaded;
+  }
+  std::fclose(f);
+  return loaded;
 }
 
 }  // extern "C"
@@ -549,16 +788,21 @@ namespace {
 
 // The whole batched census (status reset, pack, build, census, division) as
 // one stream-ordered sequence with no host interaction, so it can be captured.
-// Returns false if a host-to-device copy could not be enqueued.
+// Returns false if a host-to-device copy could not be enqueued or the
+// workspace was sized too small.
 bool enqueue_plan(motif_batch_plan* b) {
   const int C = motif_num_classes(b->k);
-  b->p.arena.reset();
-  enqueue_zero(b->p.status, sizeof(int32_t) * kStatusWords, b->stream);
-  BuildInput in = enqueue_pack(b->p, b->graphs, b->count, b->voff, b->aoff, b->stream);
-  DevGraph g = enqueue_build(b->p, in, b->stream);
-  uint64_t* acc = b->p.arena.take<uint64_t>((size_t)b->count * C);
-  enqueue_census(b->p, g, b->k, acc, b->hists, b->stream);
-  return !in.copy_error;
+  try {
+    b->p.arena.reset();
+    enqueue_zero(b->p.status, sizeof(int32_t) * kStatusWords, b->stream);
+    BuildInput in = enqueue_pack(b->p, b->graphs, b->count, b->voff, b->aoff, b->stream);
+    DevGraph g = enqueue_build(b->p, in, b->stream);
+    uint64_t* acc = b->p.arena.take<uint64_t>((size_t)b->count * C);
+    enqueue_census(b->p, g, b->k, acc, b->hists, b->stream);
+    return !in.copy_error;
+  } catch (const WorkspaceError&) {
+    return false;
+  }
 }
 
 void plan_free(motif_batch_plan* b) {
@@ -624,7 +868,8 @@ motif_batch_plan_t* motif_batch_plan_create(const motif_graph_t* graphs, int32_t
   b->p.num_cus = device_cus(dev);
   int64_t maxn = 0;
   for (int32_t g = 0; g < count; ++g) maxn = std::max<int64_t>(maxn, graphs[g].n);
-  const size_t bytes = pipeline_bytes(N, M, count, true, k, b->p.num_cus, maxn);
+  b->p.tune = tuning_for_call(dev, 1, &k, count > 1, M);
+  const size_t bytes = pipeline_bytes(N, M, count, true, k, b->p.num_cus, maxn, b->p.tune.k[k]);
   if (hipMalloc(&b->p.arena.base, bytes) != hipSuccess || hipMalloc(&b->p.status, kStatusWords * 4) != hipSuccess ||
       hipHostMalloc(&b->p.host_status, kStatusWords * 4, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(&b->graphs, sizeof(motif_graph_t) * count, hipHostMallocDefault) != hipSuccess ||

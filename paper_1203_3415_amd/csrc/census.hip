@@ -81,21 +81,27 @@ constexpr int kBigRow = 12;          // words per W row (9 used, 16-byte aligned
 constexpr int kUnroll = 4;
 constexpr int kBucketShift = 6;     // the row-scan layout records the row at every 64th entry ...
 constexpr int kBuckets = 1024;      // ... for layouts of up to 64 K entries (else plain binary search)         // N+ entries per lane and pass of the flattened scans
-constexpr int kLightDeg = 192;  // k = 4 anchors whose side has at most this degree run on one wave
+constexpr int kLightDegMax = 256;  // cap of the k = 4 light-side limit (wave hash load <= 1/2)
 constexpr int kWaveHashBits = 9;
 constexpr int kWaveHash = 1 << kWaveHashBits;  // slots of the wave-private hash of N(side): load <= 1/2
 constexpr uint32_t kEmptySlot = ~0u;
-constexpr int kLight5C = 512;       // k = 5 triples whose lighter side c has at most this degree are light
+constexpr int kLight5Max = 767;     // cap of the k = 5 light-partner limit (a partner must fit the table alone)
 constexpr int kNP5 = 32;            // light partners c per sub-chunk of a k = 5 unit (2 type bits each in 64)
 constexpr int kT5Bits = 10;
 constexpr int kT5 = 1 << kT5Bits;   // slots of the merged table of the sub-chunk's N(c) ...
 constexpr int kT5Load = 768;        // ... holding at most this many keys (sum of d*(c) + 1)
-static_assert(kLight5C + 1 <= kT5Load, "a light partner must fit the table alone");
+static_assert(kLight5Max + 1 <= kT5Load, "a light partner must fit the table alone");
 constexpr uint32_t kInT5 = 64u;     // label bit 6: the vertex is a key of that table
 constexpr int kU5 = 16 * 48;        // per-unit move counters: (x label, y label, r), labels of 4 bits
-constexpr int kSoloDeg = 64;        // k = 4 anchors whose core has at most this degree run alone on one wave
+constexpr int kSoloDegMax = 64;     // cap of the k = 4 solo-core limit (one lane per core neighbour)
 constexpr int kSoloHashBits = 8;
 constexpr int kSoloHash = 1 << kSoloHashBits;  // keys of the solo hash of N(c) u N(s): load < 1/2
+
+// Work-placement limits of the core-reuse kernels, from the tuning (each
+// clamped to its cap above).
+struct Limits {
+  int32_t solo, light, light5;
+};
 
 __device__ __forceinline__ uint32_t hash_slot(int32_t y) {
   return ((uint32_t)y * 2654435761u) >> (32 - kWaveHashBits);  // Fibonacci hashing
@@ -401,7 +407,8 @@ __global__ __launch_bounds__(BLOCK) void k4_kernel(DevGraph G, const uint16_t* _
   const int32_t total = G.gs_off[n];
   int32_t cur_g = -1, u = 0;
   for (;;) {
-    if (threadIdx.x == 0) sh_j0 = atomicAdd(queue, tile);
+    if (threadIdx.x == 0)  // 64-bit cursor: pulls past the end never wrap
+      sh_j0 = (int32_t)min((u64)total, (u64)atomicAdd(reinterpret_cast<u64*>(queue), (u64)tile));
     bar<LCAP == 0>();
     const int32_t j0 = sh_j0;
     bar<LCAP == 0>();
@@ -508,7 +515,8 @@ __global__ __launch_bounds__(BLOCK) void k5_kernel(DevGraph G, const uint16_t* _
   const int32_t total = G.gs_off[n];
   int32_t cur_g = -1, b = 0, cur_b = -1;
   for (;;) {
-    if (threadIdx.x == 0) sh_j0 = atomicAdd(queue, tile);
+    if (threadIdx.x == 0)  // 64-bit cursor: pulls past the end never wrap
+      sh_j0 = (int32_t)min((u64)total, (u64)atomicAdd(reinterpret_cast<u64*>(queue), (u64)tile));
     bar<LCAP == 0>();
     const int32_t j0 = sh_j0;
     bar<LCAP == 0>();
@@ -648,7 +656,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                                                    const int32_t* __restrict__ cpre,
                                                    const int32_t* __restrict__ big_id,
                                                    const uint32_t* __restrict__ wbig, int64_t wbig_stride,
-                                                   const uint32_t* __restrict__ mbig) {
+                                                   const uint32_t* __restrict__ mbig, Limits lim) {
   constexpr int C = K == 4 ? 199 : 9364, NL = K == 4 ? 16 : 64, LB = K == 4 ? 4 : 8;
   constexpr int S1 = K - 2, S2 = K - 1;  // member slots
   // LDS rows of W: fewer where the k = 5 counters and labels leave no room
@@ -1002,7 +1010,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     if (threadIdx.x < NL) cnt[threadIdx.x] = 0;
   };
 
-  // Light k = 4 anchor {c, s} (d*(s) <= kLightDeg) on one wave.  The types
+  // Light k = 4 anchor {c, s} (d*(s) <= lim.light) on one wave.  The types
   // of N(s) towards s sit in a wave-private hash table instead of the dense
   // labels (which then hold only the core's types), so the waves of the
   // workgroup take different anchors of the same core at the same time with
@@ -1140,7 +1148,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     for (int32_t i = lane; i < WH; i += 64) H[i] = kEmptySlot;
     wave_sync();
   };
-  // Solo k = 4 anchor {c, s} with d*(c) <= kSoloDeg on one wave: the plain
+  // Solo k = 4 anchor {c, s} with d*(c) <= lim.solo on one wave: the plain
   // per-anchor method (as in k4_kernel) with the labels of N(c) u N(s) in a
   // wave-private hash (keys, then complemented label bits, in the wave's
   // table), so small cores need no workgroup set-up at all.  Members are the
@@ -1164,7 +1172,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
         h = (h + 1) & (kSoloHash - 1);
       }
     };
-    const int32_t ca = G.gs_off[c], dc = G.gs_off[c + 1] - ca;  // dc <= kSoloDeg <= 64
+    const int32_t ca = G.gs_off[c], dc = G.gs_off[c + 1] - ca;  // dc <= lim.solo <= 64
     if (lane < dc) {
       const uint32_t e = G.gs_idx[ca + lane];
       if ((int32_t)(e & kIdMask) != s) insert(e & kIdMask, e >> kTypeShift);
@@ -1521,16 +1529,19 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   // the queue is empty).  Tiles of tc cost units, the last quarter of the
   // cost (from split) in tiles of tc_end from a second counter.  Each cut is
   // a 64-way search of cpre: about four dependent reads instead of ~20.
+  // The two counters are 64-bit: every pull adds to the first, also after it
+  // has passed split, so it may run past the 31-bit range of the costs.
   auto pull_tile = [&](int32_t tot_cost, int32_t tc, int32_t split, int32_t tc_end) {
     if (threadIdx.x < 64) {
       const int32_t lane = (int32_t)threadIdx.x;
-      int32_t c0 = 0, c1 = 0;
+      u64* q64 = reinterpret_cast<u64*>(queue);
+      int64_t c0 = 0, c1 = 0;
       if (lane == 0) {
-        c0 = atomicAdd(&queue[0], tc);
-        c1 = min(split, c0 + tc);
+        c0 = (int64_t)atomicAdd(&q64[0], (u64)tc);
+        c1 = min((int64_t)split, c0 + tc);
         if (c0 >= split) {
-          c0 = split + atomicAdd(&queue[1], tc_end);
-          c1 = min(tot_cost, c0 + tc_end);
+          c0 = split + (int64_t)atomicAdd(&q64[1], (u64)tc_end);
+          c1 = min((int64_t)tot_cost, c0 + tc_end);
         }
       }
       c0 = __shfl(c0, 0);
@@ -1598,7 +1609,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
           if (j < jce) {
             const int32_t c = G.gs_row[j];
             const int32_t dc = G.gs_off[c + 1] - G.gs_off[c];
-            if (dc <= kSoloDeg) {
+            if (dc <= lim.solo) {
               const int32_t x = (int32_t)(G.gs_idx[j] & kIdMask), dx = G.gs_off[x + 1] - G.gs_off[x];
               if (dx < dc || (dx == dc && x < c)) unit_list[atomicAdd(&unit_ctr[0], 1)] = j;
             }
@@ -1626,7 +1637,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
         while (G.gs_off[row + 1] <= js) ++row;
         const int32_t c = row;
         const int32_t rowa = G.gs_off[c], rowb = G.gs_off[c + 1];
-        if (rowb - rowa <= kSoloDeg) {  // taken above
+        if (rowb - rowa <= lim.solo) {  // taken above
           js = min(j1, rowb);
           continue;
         }
@@ -1644,7 +1655,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
             const int32_t x = (int32_t)(G.gs_idx[j] & kIdMask);
             const int32_t dc = rowb - rowa, dx = G.gs_off[x + 1] - G.gs_off[x];
             if (dx < dc || (dx == dc && x < c)) {  // anchor edge {c, x} owned by its higher-rank end
-              if (dx > kLightDeg) {
+              if (dx > lim.light) {
                 unit_list[atomicAdd(&unit_ctr[0], 1)] = j;
               } else {
                 bk = 31 - __clz(max(dx, 1));  // 0 .. 8
@@ -1773,7 +1784,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
               const int32_t c2 = (int32_t)(G.gs_idx[jc] & kIdMask);
               const int32_t d2 = G.gs_off[c2 + 1] - G.gs_off[c2];
               if (d2 < dx || (d2 == dx && c2 < x)) {
-                if (fact5 && d2 <= kLight5C)
+                if (fact5 && d2 <= lim.light5)
                   unit_list[BLOCK - 1 - atomicAdd(&unit_ctr[1], 1)] = jc;
                 else
                   unit_list[atomicAdd(&unit_ctr[0], 1)] = jc;
@@ -1838,7 +1849,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                   const int32_t t = __shfl_up(inc, d);
                   if (lane >= d) inc += t;
                 }
-                // a prefix of the lanes: lane 0 always fits (cost <= kLight5C + 1 <= kT5Load)
+                // a prefix of the lanes: lane 0 always fits (cost <= lim.light5 + 1 <= kT5Load)
                 const bool take = in && inc <= kT5Load;
                 const int32_t ntake = __popcll(__ballot(take));
                 const bool act = take && c2 >= 0;
@@ -1999,8 +2010,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
 // work queue into tiles of similar cost: 1 for an entry that is not a unit,
 // else a fixed part (larger for a heavy unit, which takes the whole
 // workgroup) plus a quarter of the side's degree.  Clamped to cmax so that
-// the prefix sum stays below 2^30; any positive costs give a correct tiling.
-__global__ void k_unit_cost4(DevGraph G, int32_t cmax, int32_t* cost, const int32_t* st) {
+// the prefix sum stays below 2^31; any positive costs give a correct tiling.
+__global__ void k_unit_cost4(DevGraph G, int32_t cmax, int32_t light_deg, int32_t* cost, const int32_t* st) {
   if (st[kStatus] != 0) return;
   const int32_t total = G.gs_off[G.n];
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < G.gs_cap; j += (int64_t)gridDim.x * blockDim.x) {
@@ -2009,7 +2020,7 @@ __global__ void k_unit_cost4(DevGraph G, int32_t cmax, int32_t* cost, const int3
       const int32_t r = G.gs_row[j], x = (int32_t)(G.gs_idx[j] & kIdMask);
       const int32_t dr = G.gs_off[r + 1] - G.gs_off[r], dx = G.gs_off[x + 1] - G.gs_off[x];
       c = 1;
-      if (dx < dr || (dx == dr && x < r)) c = min(cmax, (dx > kLightDeg ? 40 : 4) + (dx >> 2));
+      if (dx < dr || (dx == dr && x < r)) c = min(cmax, (dx > light_deg ? 40 : 4) + (dx >> 2));
     }
     cost[j] = c;
   }
@@ -2178,22 +2189,27 @@ int big_slots(int64_t maxn) {
 }
 int64_t big_label_words(int64_t maxn) { return ((maxn > 0 ? maxn : 1) + 15) / 16; }
 
-int grid_size(int k, int num_cus) {
-  const Tuning& t = tuning_for(k);
-  return num_cus * t.grid_per_cu;
+int grid_size(const Tuning& t, int num_cus) { return num_cus * t.grid_per_cu; }
+
+// Largest per-entry cost that keeps the exclusive cost prefix of gs_cap
+// entries (costs >= 1) within int32: tot <= cmax * gs_cap <= 2^31 - 1.
+int32_t cost_cap(int64_t gs_cap) {
+  return (int32_t)std::max<int64_t>(1, std::min<int64_t>(1 << 16, ((int64_t(1) << 31) - 1) / gs_cap));
 }
 
 }  // namespace
 
-size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int num_cus, int64_t maxn) {
+size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int num_cus, int64_t maxn,
+                      const Tuning& t) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   size_t b = build_bytes(N, M, G, batch);
-  if ((k == 4 || k == 5) && tuning_for(k).heavy == 1)
+  const bool reuse = (k == 4 || k == 5) && t.heavy == 1;
+  if (reuse)
     b += al(sizeof(int32_t) * (N + 1)) + al(64 * sizeof(int32_t)) +
-         al(sizeof(uint32_t) * kBigRow * (size_t)(maxn > 0 ? maxn : N) * grid_size(k, num_cus));
-  if ((k == 4 || k == 5) && tuning_for(k).heavy == 1)  // cost prefix of the G* entries and its scan scratch
+         al(sizeof(uint32_t) * kBigRow * (size_t)(maxn > 0 ? maxn : N) * grid_size(t, num_cus));
+  if (reuse)  // cost prefix of the G* entries and its scan scratch
     b += al(sizeof(int32_t) * (2 * M + 1)) + al(sizeof(int32_t) * (size_t)scan_scratch(2 * M + 1));
-  if ((k == 4 || k == 5) && tuning_for(k).heavy == 1) {
+  if (reuse) {
     const int64_t mn = maxn > 0 ? maxn : N;
     const int nb = big_slots(mn);
     if (nb > 0)  // big-core ids, list, labels, W rows, M counts
@@ -2204,7 +2220,7 @@ size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int nu
   b += 2 * al(sizeof(uint64_t) * (size_t)G * num_classes(k));  // accumulators (+ output staging)
   b += al(64 * sizeof(int32_t));                               // queue counters
   const int cap = k == 4 ? label_cap_k4((int32_t)N) : k == 5 ? label_cap_k5((int32_t)N) : 1;
-  if (cap == 0) b += al(sizeof(uint32_t) * (size_t)label_words(k, (int32_t)N) * grid_size(k, num_cus));
+  if (cap == 0) b += al(sizeof(uint32_t) * (size_t)label_words(k, (int32_t)N) * grid_size(t, num_cus));
   return b + 4096;
 }
 
@@ -2213,7 +2229,7 @@ size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int nu
                      glabels, lw, t.tile)
 #define LAUNCH_KR(K, BLOCK, CAP)                                                                        \
   hipLaunchKernelGGL((kr_kernel<K, BLOCK, CAP>), dim3(grid), dim3(BLOCK), 0, s, g, T.lut[K], acc, p.status, queue, \
-                     glabels, lw, hub_id, wg, ws, t.tile, cpre, big_id, wbig, wbig_stride, mbig)
+                     glabels, lw, hub_id, wg, ws, t.tile, cpre, big_id, wbig, wbig_stride, mbig, lim)
 #define LAUNCH_K5(BLOCK, CAP)                                                                                   \
   hipLaunchKernelGGL((k5_kernel<BLOCK, CAP>), dim3(grid), dim3(BLOCK), 0, s, g, T.lut[5], acc, p.status, queue, \
                      glabels, lw, t.tile)
@@ -2225,8 +2241,10 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
   enqueue_zero(acc, sizeof(uint64_t) * total, s);
   int32_t* queue = p.arena.take<int32_t>(64);
   enqueue_zero(queue, 64 * sizeof(int32_t), s);
-  const Tuning& t = tuning_for(k);
-  const int grid = grid_size(k, p.num_cus);
+  const Tuning& t = p.tune.k[k];
+  const int grid = grid_size(t, p.num_cus);
+  const Limits lim{std::min(t.solo_deg, kSoloDegMax), std::min(t.light_deg, kLightDegMax),
+                   std::min(t.light5, kLight5Max)};
   bool marked = false;  // the profiling events bracket the main census kernel only
   if (g.n > 0) {
     if (k == 3) {
@@ -2282,9 +2300,10 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
       if (reuse) {
         int32_t* cost = p.arena.take<int32_t>((size_t)g.gs_cap);
         int32_t* scr = p.arena.take<int32_t>((size_t)scan_scratch(g.gs_cap));
-        const int32_t cmax = (int32_t)std::max<int64_t>(2, std::min<int64_t>(1 << 16, (int64_t(1) << 30) / g.gs_cap));
+        const int32_t cmax = cost_cap(g.gs_cap);
         if (k == 4)
-          hipLaunchKernelGGL(k_unit_cost4, dim3(blocks_for(g.gs_cap, 256)), dim3(256), 0, s, g, cmax, cost, p.status);
+          hipLaunchKernelGGL(k_unit_cost4, dim3(blocks_for(g.gs_cap, 256)), dim3(256), 0, s, g, cmax, lim.light, cost,
+                             p.status);
         else
           hipLaunchKernelGGL(k_unit_cost5, dim3(blocks_for(g.gs_cap, 256)), dim3(256), 0, s, g, cmax, cost, p.status);
         scan_excl(cost, g.gs_cap, scr, s);

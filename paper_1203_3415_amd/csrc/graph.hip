@@ -577,6 +577,16 @@ void enqueue_zero(void* ptr, size_t bytes, hipStream_t s) {
   hipLaunchKernelGGL(k_zero, dim3(grid_for((int64_t)words)), dim3(kB), 0, s, (uint32_t*)ptr, words);
 }
 
+namespace {
+__global__ void k_status_out(int32_t* dst, const int32_t* st) {
+  if (threadIdx.x == 0) dst[0] = st[kStatus];
+}
+}  // namespace
+
+void enqueue_status_out(int32_t* dst, const int32_t* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, s, dst, st);
+}
+
 size_t build_bytes(int64_t N, int64_t M, int32_t G, bool batch) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   size_t b = 0;

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <stdexcept>
 
 #include "../../include/motif.h"
 
@@ -51,6 +52,12 @@ struct DevTables {
 };
 const DevTables& dev_tables();
 
+// Thrown by Arena::take when a workspace was sized too small; the entry
+// points turn it into MOTIF_EINTERNAL after draining what was enqueued.
+struct WorkspaceError : std::runtime_error {
+  WorkspaceError() : std::runtime_error("motif: workspace sizing error") {}
+};
+
 // Grow-only device arena with a bump allocator.
 struct Arena {
   char* base = nullptr;
@@ -62,19 +69,41 @@ struct Arena {
   size_t mark() const { return used; }
   void rewind(size_t m) { used = m; }
   // Every region is carved before the kernels that use it are launched, so an
-  // undersized arena stops the process before any kernel could write past it.
+  // undersized arena is caught before any kernel could write past it: the
+  // call throws WorkspaceError, and kernels already enqueued only touch
+  // regions taken before it.
   template <class T>
   T* take(size_t count) {
     size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
-    if (used + bytes > cap) {
-      std::fprintf(stderr, "motif: workspace sizing error (%zu + %zu > %zu)\n", used, bytes, cap);
-      std::abort();
-    }
+    if (used + bytes > cap) throw WorkspaceError();
     T* p = reinterpret_cast<T*>(base + used);
     used += bytes;
     return p;
   }
 };
+
+// Launch parameters used by the census kernels.
+struct Tuning {
+  int block = 256;
+  int grid_per_cu = 4;
+  int tile = 16;
+  int heavy = 1;  // census scheme for k = 4, 5: 1 = core reuse, 0 = per-anchor scan
+  // Work-placement limits of the core-reuse kernels (degrees in G*):
+  int solo_deg = 64;    // k = 4: cores of at most this degree run whole anchors on one wave (<= 64)
+  int light_deg = 192;  // k = 4: sides of at most this degree run on one wave (<= 256)
+  int light5 = 512;     // k = 5: lighter sides of at most this degree take the factored path (<= 767)
+};
+// The tuning of every k, copied once per call so that a concurrent
+// motif_set_tuning() or autotune never changes a call between the sizing of
+// its workspace and its launches.
+struct TuningSet {
+  Tuning k[6];
+};
+TuningSet tuning_snapshot();
+// The tuning a call uses on device `dev`: the defaults, with the autotuner's
+// cached entry for (k, batch, floor(log2 arcs)) in place of k's when there is
+// one, for each of ks[0..nk).
+TuningSet tuning_for_call(int dev, int32_t nk, const int32_t* ks, bool batch, int64_t arcs);
 
 // Buffers of one census pipeline (one stream).
 struct Pipeline {
@@ -86,20 +115,13 @@ struct Pipeline {
   // the shared build and joined before the status is read (default priority)
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  TuningSet tune;  // the tuning this call was sized with (set before any enqueue)
 };
-
-// Launch parameters used by the census kernels.
-struct Tuning {
-  int block = 256;
-  int grid_per_cu = 4;
-  int tile = 16;
-  int heavy = 1;  // census scheme for k = 4, 5: 1 = core reuse, 0 = per-anchor scan
-};
-Tuning& tuning_for(int k);
 
 // Bytes the arena needs for a union graph of N vertices, M arcs, G graphs
-// (G > 1 includes the packing buffers of a batch).
-size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int num_cus, int64_t maxn);
+// (G > 1 includes the packing buffers of a batch) under tuning t.
+size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int num_cus, int64_t maxn,
+                      const Tuning& t);
 size_t build_bytes(int64_t N, int64_t M, int32_t G, bool batch);
 
 // Inputs of the build: either one graph or a packed batch.
@@ -135,6 +157,8 @@ BuildInput enqueue_pack(Pipeline& p, const motif_graph_t* graphs, int32_t count,
 
 // Zero fill helper (a kernel, so it is safe inside captured graphs).
 void enqueue_zero(void* ptr, size_t bytes, hipStream_t s);
+// dst[0] = st[kStatus], stream-ordered (a kernel).
+void enqueue_status_out(int32_t* dst, const int32_t* st, hipStream_t s);
 
 // In-place exclusive scan of int32 data[0..len) on the device; `scratch`
 // holds scan_scratch(len) ints.

@@ -37,6 +37,8 @@ struct Request {
   std::vector<int32_t> off, idx;
   uint64_t* hist_out = nullptr;
   size_t footprint = 0;
+  TuningSet tune;       // taken at submit: sizes the footprint and drives the run
+  bool waited = false;  // a thread is in motif_server_wait on this request
   enum State { kPending, kRunning, kDone, kCanceled } state = kPending;
   int32_t status = 0;
 };
@@ -77,10 +79,10 @@ class RangeAlloc {
   std::map<size_t, size_t> free_;
 };
 
-size_t request_bytes(int32_t n, int64_t m, int32_t k, int cus) {
+size_t request_bytes(int32_t n, int64_t m, int32_t k, int cus, const Tuning& t) {
   const int C = motif_num_classes(k);
   return al(sizeof(int32_t) * (size_t)(n + 1)) + al(sizeof(int32_t) * (size_t)(m + 1)) + al(sizeof(uint64_t) * C) +
-         al(pipeline_bytes(n, m, 1, false, k, cus, n));
+         al(pipeline_bytes(n, m, 1, false, k, cus, n, t));
 }
 
 }  // namespace
@@ -157,6 +159,7 @@ void motif_server::worker_main(int /*wid*/) {
       in.out_idx = d_idx;
       in.n = r->n;
       in.m = r->m;
+      p.tune = r->tune;  // the tuning the footprint was sized with
       rc = run_census_on(p, in, r->k, d_hist, s);
       if (rc == 0) {
         if (hipMemcpyAsync(r->hist_out, d_hist, sizeof(uint64_t) * C, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -194,7 +197,7 @@ int64_t motif_request_footprint(int32_t n, int64_t m, int32_t k) {
   if (n < 0 || m < 0 || n >= kMaxN || m >= kMaxN) return MOTIF_EINVAL_SHAPE;
   int dev = 0;
   if (ensure_init(&dev)) return MOTIF_EDEVICE;
-  return (int64_t)request_bytes(n, m, k, device_cus(dev));
+  return (int64_t)request_bytes(n, m, k, device_cus(dev), tuning_for_call(dev, 1, &k, false, m).k[k]);
 }
 
 motif_server_t* motif_server_create(size_t hbm_budget_bytes, int32_t max_inflight) {
@@ -227,7 +230,8 @@ int32_t motif_server_submit(motif_server_t* s, const motif_graph_t* g, int32_t k
   r->n = g->n;
   r->m = g->m;
   r->hist_out = hist_out_host;
-  r->footprint = request_bytes(g->n, g->m, k, s->cus);
+  r->tune = tuning_for_call(s->device, 1, &k, false, g->m);
+  r->footprint = request_bytes(g->n, g->m, k, s->cus, r->tune.k[k]);
   if (r->footprint > s->budget) {
     delete r;
     return MOTIF_ETOOBIG;
@@ -253,10 +257,15 @@ int32_t motif_server_wait(motif_server_t* s, uint64_t ticket, int64_t timeout_us
   auto it = s->requests.find(ticket);
   if (it == s->requests.end()) return MOTIF_EINVAL_ARG;
   Request* r = it->second;
+  // one waiter per ticket: the waiter that sees the request end frees it, so
+  // a second concurrent waiter would read freed memory
+  if (r->waited) return MOTIF_EINVAL_ARG;
+  r->waited = true;
   auto done = [r] { return r->state == Request::kDone || r->state == Request::kCanceled; };
   if (timeout_us < 0) {
     s->cv_done.wait(lk, done);
   } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done)) {
+    r->waited = false;
     return MOTIF_ETIMEOUT;
   }
   const int32_t rc = r->state == Request::kCanceled ? MOTIF_ECANCELED : r->status;

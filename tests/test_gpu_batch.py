@@ -74,15 +74,49 @@ def test_plan_rejects_invalid_batch(pm):
     assert e.value.name == "ESELFLOOP"
 
 
-def test_autotune_keeps_results(pm):
+def test_autotune_keeps_results(pm, tmp_path):
     graphs = _ensemble(10, 77)
     dev = [(*pm.to_device(g.out_off, g.out_idx), g.n) for g in graphs]
     saved = pm.get_tuning(4)
     try:
+        print("[case] autotune k=4 on 10 graphs", flush=True)
         best = pm.autotune(dev, 4)
         assert best["block"] in (256, 512, 1024)
+        assert 1 <= best["solo_deg"] <= 64 and 1 <= best["light_deg"] <= 256
         hb = pm.census_batch(dev, 4)
         for i, g in enumerate(graphs):
             assert np.array_equal(hb[i], oracle.census(g, 4))
+        # the cache survives a save / clear / load round trip
+        path = str(tmp_path / "tune.txt")
+        pm.tune_cache_save(path)
+        text = open(path).read()
+        assert "gfx950" in text
+        pm.set_tuning(4, **saved)          # drops the cached entries of k = 4
+        assert pm.tune_cache_load(path) >= 1
+        hb2 = pm.census_batch(dev, 4)
+        assert np.array_equal(hb2, hb)
     finally:
         pm.set_tuning(4, **saved)
+
+
+def test_placement_limits_keep_results(pm):
+    # The work-placement limits only move work between waves and workgroups.
+    g = gg.chung_lu(3000, 24000, 2.1, 2.1, 0.2, seed=31)
+    off, idx = pm.to_device(g.out_off, g.out_idx)
+    want4 = oracle.census(g, 4)
+    saved4, saved5 = pm.get_tuning(4), pm.get_tuning(5)
+    try:
+        for solo, light in ((1, 1), (16, 96), (64, 256), (40, 200)):
+            print(f"[case] k=4 solo={solo} light={light}", flush=True)
+            pm.set_tuning(4, solo_deg=solo, light_deg=light)
+            assert np.array_equal(pm.census(off, idx, g.n, 4), want4)
+        h = gg.chung_lu(700, 3500, 2.2, 2.5, 0.1, seed=32)
+        ho, hi = pm.to_device(h.out_off, h.out_idx)
+        want5 = oracle.census(h, 5)
+        for light5 in (1, 64, 767):
+            print(f"[case] k=5 light5={light5}", flush=True)
+            pm.set_tuning(5, light5=light5)
+            assert np.array_equal(pm.census(ho, hi, h.n, 5), want5)
+    finally:
+        pm.set_tuning(4, **saved4)
+        pm.set_tuning(5, **saved5)

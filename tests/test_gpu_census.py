@@ -190,6 +190,36 @@ def test_errors(pm):
     assert bool((out == 7).all())
 
 
+def test_async_census(pm):
+    # Enqueue-only form: the stream carries the histogram and a status word.
+    import torch
+    g = gg.chung_lu(900, 4500, 2.2, 2.3, 0.15, seed=43)
+    off, idx = _dev(pm, g.out_off, g.out_idx)
+    s = torch.cuda.Stream()
+    for k in (3, 4, 5):
+        print(f"[case] async k={k}", flush=True)
+        hist = torch.full((pm.NUM_CLASSES[k],), 7, dtype=torch.int64, device="cuda")
+        status = torch.full((1,), 99, dtype=torch.int32, device="cuda")
+        pm.census_async(off, idx, g.n, k, hist, status, stream=s)
+        s.synchronize()
+        assert int(status.item()) == 0
+        assert np.array_equal(hist.cpu().numpy().view(np.uint64), oracle.census(g, k))
+    # an invalid graph: the status word carries the code, the histogram is untouched
+    bo, bi = _dev(pm, np.asarray([0, 1, 2, 2], np.int32), np.asarray([1, 1], np.int32))
+    hist = torch.full((13,), 7, dtype=torch.int64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pm.census_async(bo, bi, 3, 3, hist, status, stream=s)
+    s.synchronize()
+    assert int(status.item()) == -4   # MOTIF_ESELFLOOP
+    assert bool((hist == 7).all())
+    # and the next call on the same stream is unaffected
+    hist4 = torch.zeros(199, dtype=torch.int64, device="cuda")
+    pm.census_async(off, idx, g.n, 4, hist4, status, stream=s)
+    s.synchronize()
+    assert int(status.item()) == 0
+    assert np.array_equal(hist4.cpu().numpy().view(np.uint64), oracle.census(g, 4))
+
+
 @pytest.mark.parametrize("k", [3, 4, 5])
 def test_invariances(pm, k):
     g = gg.chung_lu(400, 1600, 2.2, 2.4, 0.2, seed=41)

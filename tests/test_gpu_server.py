@@ -84,3 +84,21 @@ def test_server_cancel(pm):
         else:
             srv.wait(t1)
     assert h0.sum() > 0
+
+
+def test_server_second_waiter_is_refused(pm):
+    # One waiter per ticket: a second concurrent wait gets EINVAL_ARG instead
+    # of racing the first waiter, which frees the request.
+    import ctypes
+    big = gg.chung_lu(20000, 100000, 2.2, 2.2, 0.1, seed=8)
+    print("[case] second waiter", flush=True)
+    with pm.Server(1 << 31, max_inflight=1) as srv:
+        t0 = srv.submit(big.out_off, big.out_idx, big.n, 4)
+        got = {}
+        th = threading.Thread(target=lambda: got.setdefault("h", srv.wait(t0)))
+        th.start()
+        time.sleep(0.2)
+        rc = pm.lib().motif_server_wait(srv._h, ctypes.c_uint64(t0), 0)
+        th.join()
+    assert rc == -13
+    assert got["h"].sum() > 0

@@ -62,3 +62,35 @@ def test_host_argument_errors(lib):
     assert lib.num_classes(2) == -1
     with pytest.raises(lib.MotifError):
         lib.class_multiplicity(4, 199)
+
+
+def test_shape_limit_is_checked_on_the_host(lib):
+    # n and m below 2^30: the typed G* rows keep a vertex id and its two type
+    # bits in one 32-bit word, and the 2m half-edges use int32 offsets.  The
+    # check runs before any device call, so it holds without a GPU.
+    import ctypes
+    L = lib.lib()
+    hist = ctypes.c_void_p(8)
+    for n, m in ((1 << 30, 0), (10, 1 << 30), (-1, 0), (0, -1)):
+        assert L.motif_census(None, None, None, None, n, m, 4, hist, None) == -2
+        assert L.motif_census_async(None, None, None, None, n, m, 4, hist, hist, None) == -2
+    assert L.motif_census(None, None, None, None, 10, 0, 6, hist, None) == -1
+    # the largest accepted shape gets past the shape check (to the pointer check)
+    assert L.motif_census(None, None, None, None, (1 << 30) - 1, (1 << 30) - 1, 3, hist, None) == -13
+
+
+def test_tuning_fields_are_validated(lib):
+    saved = lib.get_tuning(4)
+    try:
+        for bad in (dict(solo_deg=65), dict(light_deg=257), dict(light5=768), dict(block=300), dict(tile=5000)):
+            k = 5 if "light5" in bad else 4
+            with pytest.raises(lib.MotifError) as e:
+                lib.set_tuning(k, **bad)
+            assert e.value.name == "EINVAL_ARG"
+        lib.set_tuning(4, solo_deg=32, light_deg=128)
+        t = lib.get_tuning(4)
+        assert (t["solo_deg"], t["light_deg"]) == (32, 128)
+        assert t["block"] == saved["block"]   # 0 fields keep their value
+    finally:
+        lib.set_tuning(4, **saved)
+    assert lib.get_tuning(4) == saved
