@@ -22,10 +22,12 @@ from .core import (
     relabel,
     reverse,
     random_small,
+    planted_hubs,
+    pad_relabel,
 )
 
 __all__ = [
     "Digraph", "from_arcs", "gnm_reciprocal", "chung_lu", "arc_switch", "arc_switch_many",
     "directed_cycle", "directed_path", "complete_digraph", "transitive_tournament",
-    "star", "disjoint_union", "relabel", "reverse", "random_small",
+    "star", "disjoint_union", "relabel", "reverse", "random_small", "planted_hubs", "pad_relabel",
 ]

@@ -222,6 +222,47 @@ def arc_switch_many(g: Digraph, attempts: int, seeds) -> list:
     return [from_arcs(g.n, np.stack([src, out[i]], axis=1)) for i in range(len(seeds))]
 
 
+def planted_hubs(n: int, m_bg: int, n_hubs: int, hub_deg: int, hub_links: int, r: float, seed: int) -> Digraph:
+    """Chung-Lu background (gamma 2.1 in and out, reciprocity r, m_bg arcs)
+    plus n_hubs planted hubs: each hub is joined to hub_deg vertices drawn
+    uniformly (so hubs share some neighbours) and to hub_links other hubs, by
+    an arc out of the hub, into it or both ways (both with probability r, the
+    other two equally likely).  Gives many vertices of large degree with
+    mixed arc types at a modest number of connected small subgraphs."""
+    rng = np.random.default_rng(seed)
+    g = chung_lu(n, m_bg, 2.1, 2.1, r, seed)
+    keys = [g.arcs()[:, 0] * n + g.arcs()[:, 1]]
+    hubs = rng.choice(n, size=n_hubs, replace=False)
+
+    def join(h, others):
+        kind = rng.random(others.size)
+        out = kind < (1 - r) / 2
+        inn = (kind >= (1 - r) / 2) & (kind < 1 - r)
+        both = kind >= 1 - r
+        ks = [h * n + others[out | both], others[inn | both] * n + h]
+        return np.concatenate(ks)
+
+    for h in hubs:
+        nb = rng.choice(n, size=hub_deg, replace=False)
+        nb = nb[nb != h].astype(np.int64)
+        keys.append(join(np.int64(h), nb))
+        hl = rng.choice(hubs, size=min(hub_links, n_hubs - 1) + 1, replace=False)
+        hl = hl[hl != h][:hub_links].astype(np.int64)
+        keys.append(join(np.int64(h), hl))
+    return _keys_to_graph(n, np.concatenate(keys))
+
+
+def pad_relabel(g: Digraph, n_total: int, seed: int) -> Digraph:
+    """g plus n_total - g.n isolated vertices, all relabelled by a seeded
+    permutation.  Isolated vertices belong to no connected k-set, so the
+    census is unchanged; only the vertex-id range grows."""
+    if n_total < g.n:
+        raise ValueError("n_total below g.n")
+    perm = np.random.default_rng(seed).permutation(n_total)
+    a = g.arcs()
+    return from_arcs(n_total, perm[a])
+
+
 def directed_cycle(n: int) -> Digraph:
     return from_arcs(n, [(i, (i + 1) % n) for i in range(n)] if n >= 2 else [])
 

@@ -16,6 +16,12 @@ Parity: every function here is pinned in ``tests/test_oracle.py`` against the
 paper's class counts, its star worked example, its multiplicities and closed
 forms, and against the independent pure-Python all-subsets checker in
 ``oracle/brute.py``.
+
+``method_census`` and ``undirected4`` (``method_ref.c``) are a second CPU
+route: the paper's own combinatorial method (Algorithms "Count 3/4/5 Sized
+Patterns", and Algorithm "und4" with Table "ept" on the undirected version),
+written out step by step.  They are pinned against the ESU census above in
+``tests/test_method_ref.py`` and serve for the workloads too large for ESU.
 """
 from __future__ import annotations
 
@@ -27,7 +33,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "method_ref.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 N_CLASSES = {3: 13, 4: 199, 5: 9364}
@@ -35,9 +41,9 @@ N_CLASSES = {3: 13, 4: 199, 5: 9364}
 
 def build(force: bool = False) -> str:
     """Compile the C oracle with gcc (OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(s) for s in _SRCS):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, *_SRCS])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -58,6 +64,10 @@ def _lib():
     lib.oracle_census_timed.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, P, ctypes.c_int32, P, ctypes.c_int32,
                                         P, ctypes.c_int32, ctypes.c_double]
     lib.oracle_census_timed.restype = ctypes.c_int
+    lib.mref_census.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, P, P, ctypes.c_int32, P, ctypes.c_int32]
+    lib.mref_census.restype = ctypes.c_int
+    lib.mref_undirected4.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int32]
+    lib.mref_undirected4.restype = ctypes.c_int
     return lib
 
 
@@ -135,6 +145,55 @@ def census_timed(g, k: int, roots, seconds: float, threads: int = 0) -> np.ndarr
     if rc != 0:
         raise RuntimeError(f"oracle_census_timed failed: {rc}")
     return hist
+
+
+@functools.lru_cache(maxsize=4)
+def multiplicities(k: int) -> np.ndarray:
+    """int32 [C]: the oracle's multiplicity of every class (anchors that see
+    one occurrence)."""
+    _, canon, _, _ = class_table(k)
+    lib = _lib()
+    m = np.array([lib.oracle_multiplicity(k, int(c)) for c in canon], dtype=np.int32)
+    m.setflags(write=False)
+    return m
+
+
+def _csr(g):
+    off = np.ascontiguousarray(g.out_off, dtype=np.int32)
+    idx = np.ascontiguousarray(g.out_idx, dtype=np.int32)
+    if idx.size == 0:
+        idx = np.zeros(1, np.int32)
+    return off, idx
+
+
+def method_census(g, k: int, threads: int = 0) -> np.ndarray:
+    """uint64 histogram by the paper's combinatorial method (method_ref.c):
+    per-anchor set sizes, m-variables and closed forms, then the exact
+    division by the class multiplicities."""
+    cls, canon, _, _ = class_table(k)
+    mult = multiplicities(k)
+    hist = np.zeros(len(canon), dtype=np.uint64)
+    off, idx = _csr(g)
+    rc = _lib().mref_census(int(g.n), _ptr(off), _ptr(idx), k, _ptr(cls), _ptr(mult), len(canon), _ptr(hist),
+                            threads)
+    if rc != 0:
+        raise RuntimeError(f"mref_census failed: {rc}")
+    return hist
+
+
+UNDIRECTED4 = ("P4", "tailed_triangle", "claw", "C4", "diamond", "K4")
+
+
+def undirected4(g, threads: int = 0) -> np.ndarray:
+    """uint64 [6]: induced connected 4-vertex subgraphs of the undirected
+    version G*, by skeleton (P4, tailed triangle, claw, C4, K4 minus an edge,
+    K4), by Algorithm "und4" and Table "ept"."""
+    out = np.zeros(6, dtype=np.uint64)
+    off, idx = _csr(g)
+    rc = _lib().mref_undirected4(int(g.n), _ptr(off), _ptr(idx), _ptr(out), threads)
+    if rc != 0:
+        raise RuntimeError(f"mref_undirected4 failed: {rc}")
+    return out
 
 
 def code_of(k: int, arcs) -> int:
