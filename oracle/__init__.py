@@ -66,6 +66,9 @@ def _lib():
     lib.oracle_census_timed.restype = ctypes.c_int
     lib.mref_census.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, P, P, ctypes.c_int32, P, ctypes.c_int32]
     lib.mref_census.restype = ctypes.c_int
+    lib.mref_census_sample.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, P, ctypes.c_int32, P, ctypes.c_int32,
+                                       ctypes.c_int64]
+    lib.mref_census_sample.restype = ctypes.c_int
     lib.mref_undirected4.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int32]
     lib.mref_undirected4.restype = ctypes.c_int
     return lib
@@ -179,6 +182,18 @@ def method_census(g, k: int, threads: int = 0) -> np.ndarray:
     if rc != 0:
         raise RuntimeError(f"mref_census failed: {rc}")
     return hist
+
+
+def method_census_sample(g, k: int, stride: int, threads: int = 0) -> None:
+    """Timing only: the method's per-anchor work on a pseudo-random 1/stride
+    of the anchor units (no division, result discarded)."""
+    cls, canon, _, _ = class_table(k)
+    hist = np.zeros(len(canon), dtype=np.uint64)
+    off, idx = _csr(g)
+    rc = _lib().mref_census_sample(int(g.n), _ptr(off), _ptr(idx), k, _ptr(cls), len(canon), _ptr(hist), threads,
+                                   int(stride))
+    if rc != 0:
+        raise RuntimeError(f"mref_census_sample failed: {rc}")
 
 
 UNDIRECTED4 = ("P4", "tailed_triangle", "claw", "C4", "diamond", "K4")

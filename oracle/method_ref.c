@@ -359,8 +359,35 @@ static void census_unit(const gstar* g, const uint16_t* cls, const int32_t* row_
  * that see one occurrence of class c (the oracle's multiplicity).  hist[C] is
  * overwritten.  threads <= 0: the OpenMP default.
  */
+/* Pseudo-random choice of sampled units (Fibonacci hashing of the index), so
+ * that a sample is not biased towards the vertices of low id. */
+static uint64_t sample_hash(int64_t u) { return ((uint64_t)u * 0x9E3779B97F4A7C15ull) >> 24; }
+
+static int census_strided(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32_t k,
+                          const uint16_t* cls_of_code, const int32_t* mult, int32_t n_classes, uint64_t* hist,
+                          int32_t threads, int64_t stride);
+
 int mref_census(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32_t k, const uint16_t* cls_of_code,
                 const int32_t* mult, int32_t n_classes, uint64_t* hist, int32_t threads) {
+    return census_strided(n, out_off, out_idx, k, cls_of_code, mult, n_classes, hist, threads, 1);
+}
+
+/*
+ * Timing sample only: the same per-anchor work on a pseudo-random 1/stride
+ * of the anchor units (vertices for k = 3, G* entries for k = 4, 5), summed
+ * without the final division (a partial sum is not divisible).  stride * (its
+ * time) estimates the full census time.
+ */
+int mref_census_sample(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32_t k,
+                       const uint16_t* cls_of_code, int32_t n_classes, uint64_t* hist, int32_t threads,
+                       int64_t stride) {
+    if (stride < 2) return MR_EINVAL;
+    return census_strided(n, out_off, out_idx, k, cls_of_code, NULL, n_classes, hist, threads, stride);
+}
+
+static int census_strided(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32_t k,
+                          const uint16_t* cls_of_code, const int32_t* mult, int32_t n_classes, uint64_t* hist,
+                          int32_t threads, int64_t stride) {
     if (k < 3 || k > 5 || n < 0) return MR_EINVAL;
     memset(hist, 0, sizeof(uint64_t) * (size_t)n_classes);
     if (n == 0) return 0;
@@ -402,14 +429,15 @@ int mref_census(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32
         if (!ok) fail = 1;
 #pragma omp for schedule(dynamic, 16)
         for (int64_t u = 0; u < units; ++u)
-            if (ok) census_unit(&g, cls_of_code, row_of, u, &w);
+            if (ok && (stride == 1 || sample_hash(u) % (uint64_t)stride == 0))
+                census_unit(&g, cls_of_code, row_of, u, &w);
         free(w.lab); free(w.mem); free(w.mdir); free(w.mbi);
     }
     if (!fail) {
         for (int t = 0; t < nthreads; ++t)
             for (int c = 0; c < n_classes; ++c) hist[c] += th[(size_t)t * n_classes + c];
         /* Fact "correction" and its k = 3, 5 forms: exact division */
-        for (int c = 0; c < n_classes; ++c) {
+        for (int c = 0; mult && c < n_classes; ++c) {
             if (mult[c] <= 0 || hist[c] % (uint64_t)mult[c]) { rc = MR_EDIV; break; }
             hist[c] /= (uint64_t)mult[c];
         }
@@ -441,20 +469,26 @@ int mref_undirected4(int32_t n, const int32_t* out_off, const int32_t* out_idx, 
 #ifdef _OPENMP
     nthreads = threads > 0 ? threads : omp_get_max_threads();
 #endif
+    const int64_t entries = g.off[n];
+    int32_t* row_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)(entries + 1));
+    if (!row_of) { gstar_free(&g); return MR_ENOMEM; }
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t p = g.off[v]; p < g.off[v + 1]; ++p) row_of[p] = v;
     uint64_t tot[6] = {0, 0, 0, 0, 0, 0};
     int fail = 0;
 #pragma omp parallel num_threads(nthreads) reduction(| : fail)
     {
         /* lab bit 0: in N(u), bit 1: in N(v), FLAG: u or v.  X = 1, Y = 2, Z = 3 */
         uint8_t* lab = (uint8_t*)calloc((size_t)n, 1);
-        int32_t* mem = (int32_t*)malloc(sizeof(int32_t) * (size_t)(g.off[n] + 1));
+        int32_t* mem = (int32_t*)malloc(sizeof(int32_t) * (size_t)(entries + 1));
         uint64_t loc[6] = {0, 0, 0, 0, 0, 0};
         if (!lab || !mem) fail = 1;
-#pragma omp for schedule(dynamic, 64)
-        for (int32_t u = 0; u < n; ++u) {
+        /* one unit per G* entry (u, v): the edge {u, v} when u < v */
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t q = 0; q < entries; ++q) {
             if (!lab || !mem) continue;
-            for (int64_t q = g.off[u]; q < g.off[u + 1]; ++q) {
-                const int32_t v = g.nb[q];
+            {
+                const int32_t u = row_of[q], v = g.nb[q];
                 if (v < u) continue; /* each edge of G* once */
                 int64_t nm = 0;
                 for (int64_t p = g.off[u]; p < g.off[u + 1]; ++p) lab[g.nb[p]] |= 1u;
@@ -502,6 +536,7 @@ int mref_undirected4(int32_t n, const int32_t* out_off, const int32_t* out_idx, 
         for (int i = 0; i < 6; ++i) tot[i] += loc[i];
         free(lab); free(mem);
     }
+    free(row_of);
     gstar_free(&g);
     if (fail) return MR_ENOMEM;
     /* Fact "correction": P4 once, tailed triangle and S3 three times, C4 four,

@@ -11,13 +11,13 @@ here too: with a deadline it never reaches it equals census_roots.
 import json
 import math
 import os
-from collections import Counter
 
 import numpy as np
 import pytest
 
 import graphgen as gg
 import oracle
+from skeleton import project
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(HERE, "golden")
@@ -96,27 +96,6 @@ def test_matches_stored_esu_goldens(fname):
 
 
 # -- the undirected skeleton (Algorithm "und4", Table "ept") -------------------
-
-def _skeleton_of(k4_code):
-    """Index into oracle.UNDIRECTED4 of the undirected skeleton of a 4-vertex
-    code (connected)."""
-    und = set()
-    for i in range(4):
-        for j in range(4):
-            if i != j and k4_code >> (i * 3 + (j if j < i else j - 1)) & 1:
-                und.add((min(i, j), max(i, j)))
-    deg = sorted(Counter(x for e in und for x in e).values())
-    return {(3, (1, 1, 2, 2)): 0, (4, (1, 2, 2, 3)): 1, (3, (1, 1, 1, 3)): 2, (4, (2, 2, 2, 2)): 3,
-            (5, (2, 2, 3, 3)): 4, (6, (3, 3, 3, 3)): 5}[(len(und), tuple(deg))]
-
-
-def project(hist199):
-    _, canon, _, _ = oracle.class_table(4)
-    out = np.zeros(6, np.uint64)
-    for c, code in enumerate(canon):
-        out[_skeleton_of(int(code))] += hist199[c]
-    return out
-
 
 def test_undirected4_matches_esu_projection():
     rng = np.random.default_rng(31)
