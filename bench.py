@@ -184,11 +184,12 @@ def bench_census(args):
     g, ks = make_graph(args.workload)
     dev = torch.device("cuda:0")
     off, idx = pm.to_device(g.out_off, g.out_idx, dev)
+    ioff, iidx = pm.to_device(*g.in_csr(), dev)
     outs = {k: torch.empty(pm.NUM_CLASSES[k], dtype=torch.int64, device=dev) for k in ks}
     torch.cuda.synchronize()
 
-    def step():  # one shared G* build for all sizes of the workload
-        pm.census_multi(off, idx, g.n, ks, outs=[outs[k] for k in ks])
+    def step():  # out- and in-CSR validated, one shared G* build for all sizes of the workload
+        pm.census_multi(off, idx, g.n, ks, in_off=ioff, in_idx=iidx, outs=[outs[k] for k in ks])
 
     for _ in range(args.warmup):
         step()
@@ -346,193 +347,323 @@ def describe(name):
     }.get(name, name)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _mean_sd(xs):
+    xs = np.asarray(xs, dtype=np.float64)
+    return float(xs.mean()), float(xs.std(ddof=1)) if xs.size > 1 else 0.0
+
+
+def method_ref_timing(g, ks, threads, budget_s):
+    """The CPU method reference (the paper's algorithm written out in C, the
+    analogue of its Java acc-Motif) timed on the host: the full census on all
+    cores when a 1/64 sample predicts it fits the budget, else projected from
+    that sample; single thread projected from a 1/64 sample.  Projection =
+    build + 64 * (sample - build), the build timed on its own."""
+    import oracle
+    out, proj_all, proj_one = {}, 0.0, 0.0
+    for k in ks:
+        oracle.class_table(k)
+        oracle.multiplicities(k)
+
+        def timed(fn):
+            t = time.perf_counter()
+            fn()
+            return time.perf_counter() - t
+        build1 = timed(lambda: oracle.method_census_sample(g, k, 1 << 40, threads=1))
+        s1 = timed(lambda: oracle.method_census_sample(g, k, 64, threads=1))
+        buildn = timed(lambda: oracle.method_census_sample(g, k, 1 << 40, threads=threads))
+        sn = timed(lambda: oracle.method_census_sample(g, k, 64, threads=threads))
+        one = build1 + 64 * max(0.0, s1 - build1)
+        alln = buildn + 64 * max(0.0, sn - buildn)
+        how = "projected from a 1/64 sample"
+        if alln < budget_s:
+            alln = timed(lambda: oracle.method_census(g, k, threads=threads))
+            how = "full census"
+        proj_all += alln
+        proj_one += one
+        out[f"k{k}"] = {"seconds_all_cores": round(alln, 2), "all_cores": how,
+                        "seconds_single_thread": round(one, 2), "single_thread": "projected from a 1/64 sample"}
+    return {"value_all_cores": round(g.m / proj_all, 1), "value_single_thread": round(g.m / proj_one, 1),
+            "unit": "arcs/s", "detail": out}
+
+
 def cpu_baseline(g, ks, total_sets, seconds):
     """The oracle (ESU + k! canonical labelling) timed on the host cores on a
-    bounded sample: roots in a seeded random order for `seconds` per k; the
-    rate in connected sets per second projects the full census time."""
+    bounded sample: ESU from roots in a seeded random order for a fixed time,
+    5 rounds on all cores and 1 round on one thread per k; the rate in
+    connected sets per second projects the full census time.  Beside it, the
+    CPU method reference (the paper's own algorithm)."""
     import oracle
     threads = _threads()
     roots = np.random.default_rng(12345).permutation(g.n).astype(np.int32)
-    proj = 0.0
+    per_round = seconds / 6.0
+    proj, proj_sd2, proj_one = 0.0, 0.0, 0.0
     sample = {}
     for k in ks:
         oracle.class_table(k)  # table build excluded from timing
+        rates = []
+        for _ in range(5):
+            t = time.perf_counter()
+            h = oracle.census_timed(g, k, roots, per_round, threads=threads)
+            dt = time.perf_counter() - t
+            rates.append(int(h.sum()) / dt)
         t = time.perf_counter()
-        h = oracle.census_timed(g, k, roots, seconds, threads=threads)
-        dt = time.perf_counter() - t
-        done = int(h.sum())
-        rate = done / dt if dt > 0 else 0.0
-        proj += total_sets[k] / rate if rate > 0 else float("inf")
-        sample[f"k{k}"] = {"seconds": round(dt, 2), "sets": done, "sets_per_s": round(rate, 1)}
-    value = g.m / proj if proj > 0 else 0.0
+        h1 = oracle.census_timed(g, k, roots, per_round, threads=1)
+        rate1 = int(h1.sum()) / (time.perf_counter() - t)
+        mean, sd = _mean_sd(rates)
+        tk = total_sets[k] / mean
+        proj += tk
+        proj_sd2 += (tk * sd / mean) ** 2
+        proj_one += total_sets[k] / rate1
+        sample[f"k{k}"] = {"sets_per_s": round(mean, 1), "sets_per_s_sd": round(sd, 1),
+                           "sets_per_s_single_thread": round(rate1, 1), "projected_seconds": round(tk, 1)}
+    value = g.m / proj
+    value_sd = value * (proj_sd2 ** 0.5) / proj
     return {"value": round(value, 3), "unit": "arcs/s", "cores": threads, "kind": "oracle",
-            "sample": (f"ESU from roots in seeded random order, {seconds:.0f} s per k on {threads} threads; "
-                       f"full-census time projected from connected sets/s"),
-            "projected_seconds": round(proj, 1), "detail": sample}
+            "sample": (f"ESU from roots in seeded random order: 5 rounds of {per_round:.1f} s on {threads} threads "
+                       f"and 1 round on 1 thread per k; full-census time projected from connected sets/s"),
+            "value_sd": round(value_sd, 3), "rounds": 5, "cpu_model": cpu_model(),
+            "single_thread": {"value": round(g.m / proj_one, 3), "unit": "arcs/s"},
+            "projected_seconds": round(proj, 1), "detail": sample,
+            "method_ref": method_ref_timing(g, ks, threads, budget_s=seconds)}
 
 
 # ------------------------------------------------------- batch & serving ---
 
-def nullmodel_graphs(mode: str, count: int, switches_per_arc: int):
+def nullmodel_bases(mode: str, count: int):
     """mode 'same': one Chung-Lu base (n=2000, m=8000, exponent 2.3,
-    reciprocity 0.05, seed 3) plus `count` randomisations of it; mode
-    'uneven': `count`+1 graphs with n uniform in [500, 5000], m = 4n, each a
-    randomisation of its own Chung-Lu base.  Randomisation = switches_per_arc
-    * m attempted arc switches (seeds 1000+i)."""
+    reciprocity 0.05, seed 3), randomised `count` times; mode 'uneven':
+    `count`+1 graphs with n uniform in [500, 5000], m = 4n, each its own
+    Chung-Lu base (exponent 2.3, reciprocity 0.05), graphs 1..count each
+    randomised once.  Randomisation = switches_per_arc * m attempted arc
+    switches on the device (motif_null_randomize)."""
     import graphgen as gg
     if mode == "same":
-        base = gg.chung_lu(2000, 8000, 2.3, 2.3, 0.05, seed=3)
-        return [base] + gg.arc_switch_many(base, switches_per_arc * base.m, np.arange(1000, 1000 + count))
+        return [gg.chung_lu(2000, 8000, 2.3, 2.3, 0.05, seed=3)]
     rng = np.random.default_rng(33)
     out = []
     for i in range(count + 1):
         n = int(rng.integers(500, 5001))
-        b = gg.chung_lu(n, 4 * n, 2.3, 2.3, 0.05, seed=20000 + i)
-        out.append(b if i == 0 else gg.arc_switch_many(b, switches_per_arc * b.m, [1000 + i])[0])
+        out.append(gg.chung_lu(n, 4 * n, 2.3, 2.3, 0.05, seed=20000 + i))
     return out
 
 
 def bench_nullmodel(args):
     import torch
+    import graphgen as gg
     import paper_1203_3415_amd as pm
 
     dev = torch.device("cuda:0")
+    count, spa = args.null_graphs, args.switch_per_arc
     report = {}
-    for mode in ("same", "uneven"):
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
         t = time.perf_counter()
-        graphs = nullmodel_graphs(mode, args.null_graphs, args.switch_per_arc)
-        gen_s = time.perf_counter() - t
-        d = [(*pm.to_device(x.out_off, x.out_idx, dev), x.n) for x in graphs]
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    for mode in ("same", "uneven"):
+        bases = nullmodel_bases(mode, count)
+        dbase = [(*pm.to_device(x.out_off, x.out_idx, dev), x.n) for x in bases]
+        if mode == "same":
+            off, idx, n = dbase[0]
+            d = [dbase[0]] + [(off, idx.clone(), n) for _ in range(count)]
+        else:
+            d = [dbase[0]] + [(o, i.clone(), nn) for (o, i, nn) in dbase[1:]]
+        arcs = int(sum(int(t[1].numel()) for t in d))
+        # generation alone: the randomisation of graphs 1..count on the device
+        fresh = [t[1].clone() for t in d[1:]]
+
+        def regenerate(seed=1000):
+            for t, f in zip(d[1:], fresh):
+                t[1].copy_(f)
+            pm.null_randomize(d[1:], spa, seed)
+        regenerate()
+        gen_s = timed(lambda: regenerate(), max(1, args.steps // 2))
+        # host generator (graphgen's C switcher), for reference: 8 graphs, scaled
+        t = time.perf_counter()
+        gg.arc_switch_many(bases[0], spa * bases[0].m, np.arange(1000, 1008))
+        host_gen_s = (time.perf_counter() - t) / 8 * count
+        print(f"[nullmodel] {mode}: {len(d)} graphs, device generation {gen_s * 1e3:.1f} ms "
+              f"(host switcher ~{host_gen_s:.1f} s)", file=sys.stderr, flush=True)
+        regenerate()
         out = torch.empty((len(d), 199), dtype=torch.int64, device=dev)
-        print(f"[nullmodel] {mode}: {len(d)} graphs generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
         tuned = pm.autotune(d, 4) if args.autotune else pm.get_tuning(4)
         for _ in range(args.warmup):
             pm.census_batch(d, 4, out=out)
-        timings = {}
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(args.steps):
-            pm.census_batch(d, 4, out=out)
-        torch.cuda.synchronize()
-        timings["fused"] = (time.perf_counter() - t) / args.steps
-        print(f"[nullmodel] {mode}: fused {timings['fused'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        timings = {"fused": timed(lambda: pm.census_batch(d, 4, out=out), args.steps)}
         hb = out.cpu().numpy().view(np.uint64).copy()
         plan = pm.BatchPlan(d, 4)
         plan.run()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(args.steps):
-            plan.run()
-        torch.cuda.synchronize()
-        timings["graph_replay"] = (time.perf_counter() - t) / args.steps
-        print(f"[nullmodel] {mode}: graph replay {timings['graph_replay'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        timings["graph_replay"] = timed(plan.run, args.steps)
         hp = plan.hists().copy()
         plan.close()
         pm.census_batch_loop(d, 4, out=out)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(args.steps):
-            pm.census_batch_loop(d, 4, out=out)
-        torch.cuda.synchronize()
-        timings["loop"] = (time.perf_counter() - t) / args.steps
-        print(f"[nullmodel] {mode}: loop {timings['loop'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        timings["loop"] = timed(lambda: pm.census_batch_loop(d, 4, out=out), args.steps)
         hl = out.cpu().numpy().view(np.uint64).copy()
         z = pm.zscores(hb)
-        report[mode] = {
-            "graphs": len(d), "arcs_total": int(sum(x.m for x in graphs)), "generation_s": round(gen_s, 1),
-            "graphs_per_s": {kk: round(len(d) / v, 1) for kk, v in timings.items()},
-            "ms": {kk: round(v * 1e3, 2) for kk, v in timings.items()},
-            "identical_fused_replay_loop": bool(np.array_equal(hb, hl) and np.array_equal(hb, hp)),
-            "tuning": tuned,
-            "finite_z": int(np.isfinite(z).sum()),
-        }
-        del d, out
+        print(f"[nullmodel] {mode}: fused {timings['fused'] * 1e3:.1f} ms, replay "
+              f"{timings['graph_replay'] * 1e3:.1f} ms, loop {timings['loop'] * 1e3:.1f} ms", file=sys.stderr,
+              flush=True)
+        rec = {"graphs": len(d), "arcs_total": arcs,
+               "device_generation_ms": round(gen_s * 1e3, 2), "host_generation_s_est": round(host_gen_s, 1),
+               "census_graphs_per_s": {kk: round(len(d) / v, 1) for kk, v in timings.items()},
+               "census_ms": {kk: round(v * 1e3, 2) for kk, v in timings.items()},
+               "identical_fused_replay_loop": bool(np.array_equal(hb, hl) and np.array_equal(hb, hp)),
+               "tuning": tuned, "finite_z": int(np.isfinite(z).sum())}
+        if mode == "same":
+            # the whole job on the device: replicate, randomise, census, z-scores
+            off, idx, n = dbase[0]
+            hz = torch.empty((count + 1, 199), dtype=torch.int64, device=dev)
+            zz = torch.empty(199, dtype=torch.float64, device=dev)
+            pm.null_model(off, idx, n, count, 4, spa, 1000, out=hz, z_out=zz)
+            job = timed(lambda: pm.null_model(off, idx, n, count, 4, spa, 1000, out=hz, z_out=zz), args.steps)
+            hzn = hz.cpu().numpy().view(np.uint64)
+            zd = zz.cpu().numpy()
+            ok = np.isfinite(pm.zscores(hzn))
+            rec["job_ms"] = round(job * 1e3, 2)
+            rec["job_graphs_per_s"] = round(len(d) / job, 1)
+            rec["job_z_matches_host"] = bool(np.allclose(zd[ok], pm.zscores(hzn)[ok], rtol=1e-12, atol=0))
+            rec["job_hists_equal_in_place_ensemble"] = bool(np.array_equal(hzn, hb))
+            print(f"[nullmodel] same: whole job {job * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        report[mode] = rec
+        del d, out, dbase, fresh
         torch.cuda.empty_cache()
     main_mode = report["same"]
-    best = max(main_mode["graphs_per_s"]["fused"], main_mode["graphs_per_s"]["graph_replay"])
-    line = {"metric": "null-model graphs/sec", "value": best, "unit": "graphs/s",
+    value = main_mode["job_graphs_per_s"]
+    line = {"metric": "null-model graphs/sec", "value": value, "unit": "graphs/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": round(1e3 * main_mode["graphs"] / best, 3),
+            "ms_per_step": main_mode["job_ms"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-            "config": {"workload": "nullmodel_k4", "k": 4, "switch_attempts_per_arc": args.switch_per_arc,
+            "config": {"workload": "nullmodel_k4", "k": 4, "switch_attempts_per_arc": spa,
                        "same": "Chung-Lu n=2000 m=8000 exp 2.3 recip 0.05 + randomisations",
-                       "uneven": "n uniform in [500,5000], m=4n, each its own Chung-Lu base randomised"},
+                       "uneven": "n uniform in [500,5000], m=4n, each its own Chung-Lu base randomised",
+                       "value": "whole job on the device per graph: randomisation + fused census + z-scores"},
             "detail": report}
     print(json.dumps(line), flush=True)
 
 
+def _serving_graph(j: int, log_m_max: float):
+    import graphgen as gg
+    r = np.random.default_rng(10000 + j)
+    m = int(round(10 ** r.uniform(3, log_m_max)))
+    gamma = float(r.uniform(2.1, 2.6))
+    recip = float(r.uniform(0, 0.2))
+    k = int(r.integers(3, 6))
+    if k == 5 and m > 200_000:
+        k = int(r.integers(3, 5))
+    n = max(10, m // 5)
+    return gg.chung_lu(n, m, gamma, gamma, recip, seed=10000 + j), k
+
+
 def bench_serving(args):
-    """Open-loop Poisson arrivals (rate `--rate`/s for `--serve-seconds` s) of
-    census requests drawn from a pool of pregenerated graphs: m log-uniform in
+    """Open-loop Poisson arrivals (rate `--rate`/s) of census requests drawn
+    from a pool of `--pool` pregenerated graphs: m log-uniform in
     [1e3, 10^serve_log_m_max], n = m/5, Chung-Lu exponent uniform in
     [2.1, 2.6], reciprocity uniform in [0, 0.2], k uniform in {3,4,5} (k = 5
-    only for m <= 2e5).  Requests beyond `--max-outstanding` in flight are
-    shed (counted).  Latency = submit -> histogram on the host."""
-    import graphgen as gg
+    only for m <= 2e5).  `--serve-warmup` s of arrivals are served but not
+    measured, then `--serve-seconds` s are.  A request that arrives while
+    `--max-outstanding` are in flight is shed; a shed request counts as an SLO
+    miss (infinite latency) in the percentiles over offered requests.
+    Latency = arrival -> histogram on the host; every histogram is checked
+    against the same graph censused alone (before the run)."""
+    import multiprocessing as mp
+    import torch
     import paper_1203_3415_amd as pm
 
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as p:
+        pool = p.starmap(_serving_graph, [(j, args.serve_log_m_max) for j in range(args.pool)])
+    print(f"[serving] pool of {len(pool)} graphs generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    # each graph censused alone, through the plain entry point
+    alone = []
+    for g, k in pool:
+        off, idx = pm.to_device(g.out_off, g.out_idx)
+        alone.append(pm.census(off, idx, g.n, k))
+        del off, idx
+    torch.cuda.empty_cache()
+    print(f"[serving] alone results in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     rng = np.random.default_rng(5)
-    pool = []
-    for j in range(args.pool):
-        r = np.random.default_rng(10000 + j)
-        m = int(round(10 ** r.uniform(3, args.serve_log_m_max)))
-        gamma = float(r.uniform(2.1, 2.6))
-        recip = float(r.uniform(0, 0.2))
-        k = int(r.integers(3, 6))
-        if k == 5 and m > 200_000:
-            k = int(r.integers(3, 5))
-        n = max(10, m // 5)
-        pool.append((gg.chung_lu(n, m, gamma, gamma, recip, seed=10000 + j), k))
-    lam, dur = args.rate, args.serve_seconds
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=int(lam * dur * 2) + 10))
-    arrivals = arrivals[arrivals < dur]
+    lam, warm, dur = args.rate, args.serve_warmup, args.serve_seconds
+    total_t = warm + dur
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=int(lam * total_t * 2) + 10))
+    arrivals = arrivals[arrivals < total_t]
     picks = rng.integers(0, len(pool), size=arrivals.size)
-    lat, shed = [], 0
+    lat, shed, wrong = {}, set(), 0
     with pm.Server(args.hbm_budget, max_inflight=args.inflight) as srv:
-        # warm the device state (class tables, kernels) outside the measurement
-        g0, k0 = pool[0]
-        srv.wait(srv.submit(g0.out_off, g0.out_idx, g0.n, k0))
         start = time.perf_counter()
         pending = []
+        last_print = [start]
 
         def reap(block=False):
+            nonlocal wrong
             still = []
-            for tk2, ta in pending:
+            for tk2, ta, i in pending:
                 try:
-                    srv.wait(tk2, timeout_us=-1 if block else 0)
-                    lat.append(time.perf_counter() - ta)
+                    h = srv.wait(tk2, timeout_us=-1 if block else 0)
+                    lat[i] = time.perf_counter() - ta
+                    if not np.array_equal(h, alone[picks[i]]):
+                        wrong += 1
                 except TimeoutError:
-                    still.append((tk2, ta))
+                    still.append((tk2, ta, i))
             return still
 
-        for t_arr, p in zip(arrivals, picks):
+        for i, (t_arr, pidx) in enumerate(zip(arrivals, picks)):
             now = time.perf_counter() - start
             if t_arr > now:
                 time.sleep(t_arr - now)
             pending = reap()
+            if time.perf_counter() - last_print[0] > 5.0:
+                last_print[0] = time.perf_counter()
+                print(f"[serving] t={now:.0f} s: {len(lat)} done, {len(pending)} in flight, {len(shed)} shed",
+                      file=sys.stderr, flush=True)
             if len(pending) >= args.max_outstanding:
-                shed += 1
+                shed.add(i)
                 continue
-            g, k = pool[p]
+            g, k = pool[pidx]
             try:
                 tk = srv.submit(g.out_off, g.out_idx, g.n, k)
             except pm.MotifError:
-                shed += 1
+                shed.add(i)
                 continue
-            pending.append((tk, start + t_arr))
+            pending.append((tk, start + t_arr, i))
         pending = reap(block=True)
-        total = time.perf_counter() - start
+        end = time.perf_counter()
         stats = srv.stats()
-    lat = np.array(lat) * 1e3
-    line = {"metric": "census requests/sec", "value": round(len(lat) / total, 2), "unit": "req/s", "n_gpus": 1,
-            "steps": 1, "warmup": 1, "ms_per_step": round(total * 1e3, 1), "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-            "config": {"workload": "serving", "rate_per_s": lam, "seconds": dur, "pool": len(pool),
-                       "inflight": args.inflight, "max_outstanding": args.max_outstanding,
-                       "log10_m_range": [3, args.serve_log_m_max]},
-            "detail": {"p50_ms": round(float(np.percentile(lat, 50)), 2) if lat.size else None,
-                       "p99_ms": round(float(np.percentile(lat, 99)), 2) if lat.size else None,
-                       "completed": int(lat.size), "offered": int(arrivals.size), "shed": shed,
+    measured = [i for i in range(arrivals.size) if arrivals[i] >= warm]
+    m_done = [lat[i] for i in measured if i in lat]
+    m_shed = sum(1 for i in measured if i in shed)
+    # percentiles over offered requests: a shed request is an SLO miss (infinite latency)
+    offered = np.array([lat.get(i, np.inf) for i in measured]) * 1e3
+    done_t = [arrivals[i] + lat[i] for i in measured if i in lat]
+    span = (max(done_t) - warm) if done_t else dur
+    line = {"metric": "census requests/sec", "value": round(len(m_done) / max(span, dur), 2), "unit": "req/s",
+            "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round((end - start) * 1e3, 1),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": "serving", "rate_per_s": lam, "warmup_s": warm, "seconds": dur,
+                       "pool": len(pool), "inflight": args.inflight, "max_outstanding": args.max_outstanding,
+                       "hbm_budget_bytes": args.hbm_budget, "log10_m_range": [3, args.serve_log_m_max]},
+            "detail": {"p50_ms_offered": round(float(np.percentile(offered, 50)), 2) if offered.size else None,
+                       "p99_ms_offered": (round(float(np.percentile(offered, 99)), 2)
+                                          if offered.size and np.isfinite(np.percentile(offered, 99)) else "inf"),
+                       "p50_ms_completed": round(float(np.percentile(m_done, 50)) * 1e3, 2) if m_done else None,
+                       "p99_ms_completed": round(float(np.percentile(m_done, 99)) * 1e3, 2) if m_done else None,
+                       "offered": len(measured), "completed": len(m_done), "shed": m_shed,
+                       "responses_checked": len(lat), "responses_wrong": wrong,
                        "peak_bytes_admitted": stats["peak_bytes"]}}
     print(json.dumps(line), flush=True)
 
@@ -545,16 +676,17 @@ def main():
     ap.add_argument("--workload", default="chunglu_n1e5_k34",
                     choices=["chunglu_n1e5_k34", "gnm_n1000", "chunglu_n2e4_k5", "nullmodel_k4", "serving"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--null-graphs", type=int, default=1000)
     ap.add_argument("--switch-per-arc", type=int, default=100, help="arc-switch attempts per arc of each null graph")
     ap.add_argument("--autotune", action="store_true", help="null model: autotune on each ensemble first")
     ap.add_argument("--rate", type=float, default=200.0)
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-warmup", type=float, default=5.0)
     ap.add_argument("--max-outstanding", type=int, default=64)
     ap.add_argument("--serve-log-m-max", type=float, default=6.0)
-    ap.add_argument("--pool", type=int, default=64)
-    ap.add_argument("--inflight", type=int, default=8)
+    ap.add_argument("--pool", type=int, default=512)
+    ap.add_argument("--inflight", type=int, default=4)
     ap.add_argument("--hbm-budget", type=int, default=64 << 30)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB on the device (reference for HBM counters)")

@@ -198,6 +198,39 @@ motif_batch_plan_t* motif_batch_plan_create(const motif_graph_t* graphs, int32_t
 int32_t motif_batch_plan_run(motif_batch_plan_t* plan);
 int32_t motif_batch_plan_destroy(motif_batch_plan_t* plan);
 
+/* ---- null-model ensembles on the device ------------------------------------ */
+
+/* Degree-preserving randomisation of `count` graphs in place (the random
+ * graphs of the paper's significance step (iii), Section "Implementation";
+ * its ensembles in Section "Results and Discussion").  `graphs` is a host
+ * array of descriptors holding DEVICE pointers; each graph's out_idx is
+ * REWRITTEN (the const in motif_graph_t notwithstanding): switches_per_arc * m
+ * attempted arc switches, each taking two arcs a->b, c->d and rewiring them
+ * to a->d, c->b unless that makes a self-loop or a repeated arc.  Every arc
+ * keeps its slot in its source's row, so out_off and all out- and in-degrees
+ * are unchanged; rows are left unsorted; in_off/in_idx are ignored (the
+ * graph's transpose changes).  Random numbers: SplitMix64 on a counter, one
+ * stream per (seed, graph index), so the result depends only on the input,
+ * switches_per_arc and seed.  Errors: MOTIF_EINVAL_SHAPE (offsets not
+ * monotone from 0 to m), MOTIF_EINVAL_ARG.  Waits for the stream. */
+int32_t motif_null_randomize(const motif_graph_t* graphs, int32_t count, int32_t switches_per_arc,
+                             uint64_t seed, void* stream);
+
+/* The whole null-model job on the device: `count` randomisations of the real
+ * graph (device pointers; its in-CSR, if given, is validated for the real
+ * graph), each made as by motif_null_randomize(real copy, switches_per_arc,
+ * seed; graph i uses stream i of seed), then one fused census of the real
+ * graph and its copies (motif_census_batch), then the z-scores.
+ *  hists : device, (count + 1) * motif_num_classes(k) uint64; row 0 is the
+ *          real graph, row i the i-th randomisation.
+ *  z     : device, motif_num_classes(k) doubles: (h_real - mean) / sd over the
+ *          copies, sample sd (ddof = 1), from exact integer sums; NaN where the
+ *          sd is 0, count < 2, or a count of the class reaches 2^40.
+ * The library keeps a device buffer of count * m int32 per stream for the
+ * copies.  Errors as for motif_census() and motif_null_randomize(). */
+int32_t motif_null_model(const motif_graph_t* real, int32_t count, int32_t k, int32_t switches_per_arc,
+                         uint64_t seed, uint64_t* hists, double* z, void* stream);
+
 /* ---- tuning ---------------------------------------------------------------- */
 
 /* Tunable launch parameters of the census kernels. */

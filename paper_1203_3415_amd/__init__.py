@@ -16,6 +16,8 @@ from .binding import (  # noqa: F401
     census_multi,
     census_batch_loop,
     BatchPlan,
+    null_randomize,
+    null_model,
     num_classes,
     class_code,
     class_multiplicity,

@@ -89,6 +89,8 @@ def lib():
             "motif_autotune": ([P, I32, I32, P, P, ctypes.POINTER(_Tuning)], I32),
             "motif_tune_cache_save": ([ctypes.c_char_p], I32),
             "motif_tune_cache_load": ([ctypes.c_char_p], I32),
+            "motif_null_randomize": ([P, I32, I32, ctypes.c_uint64, P], I32),
+            "motif_null_model": ([P, I32, I32, I32, ctypes.c_uint64, P, P, P], I32),
             "motif_batch_plan_create": ([P, I32, I32, P, P, ctypes.POINTER(I32)], P),
             "motif_batch_plan_run": ([P], I32),
             "motif_batch_plan_destroy": ([P], I32),
@@ -271,6 +273,35 @@ def census_batch(graphs, k: int, stream=None, out=None, loop: bool = False):
 
 def census_batch_loop(graphs, k: int, stream=None, out=None):
     return census_batch(graphs, k, stream=stream, out=out, loop=True)
+
+
+def null_randomize(graphs, switches_per_arc: int, seed: int, stream=None) -> None:
+    """Randomise device graphs [(out_off, out_idx, n), ...] in place by
+    switches_per_arc * m degree-preserving arc switches each (out_idx is
+    rewritten; rows end up unsorted)."""
+    arr = _graph_array([g[:3] for g in graphs])
+    _check(lib().motif_null_randomize(ctypes.cast(arr, ctypes.c_void_p), len(graphs), int(switches_per_arc),
+                                      ctypes.c_uint64(seed), _stream_handle(stream)), "motif_null_randomize")
+
+
+def null_model(out_off, out_idx, n: int, count: int, k: int, switches_per_arc: int = 100, seed: int = 0,
+               in_off=None, in_idx=None, stream=None, out=None, z_out=None):
+    """Randomise, census and score on the device: returns (hists, z) as numpy
+    (uint64 [count + 1, C], row 0 the real graph; float64 [C]), or fills the
+    CUDA tensors `out` (int64 [count + 1, C]) and `z_out` (float64 [C])."""
+    torch = _torch()
+    C = NUM_CLASSES.get(k)
+    if C is None:
+        raise MotifError(-1, "null_model")
+    g = _graph_array([(out_off, out_idx, n) + ((in_off, in_idx) if in_off is not None else ())])
+    hist = out if out is not None else torch.empty((count + 1, C), dtype=torch.int64, device=out_off.device)
+    z = z_out if z_out is not None else torch.empty(C, dtype=torch.float64, device=out_off.device)
+    _check(lib().motif_null_model(ctypes.cast(g, ctypes.c_void_p), int(count), int(k), int(switches_per_arc),
+                                  ctypes.c_uint64(seed), _ptr(hist), _ptr(z), _stream_handle(stream)),
+           "motif_null_model")
+    if out is not None:
+        return out, z
+    return hist.cpu().numpy().view(np.uint64), z.cpu().numpy()
 
 
 class BatchPlan:

@@ -34,6 +34,8 @@ struct DeviceState {
   std::vector<void*> owned;  // table buffers
   std::map<hipStream_t, Pipeline*> pipes;
   std::map<TuneKey, Tuning> tuned;  // filled by motif_autotune / motif_tune_cache_load
+  // per-stream buffer of the randomised copies made by motif_null_model
+  std::map<hipStream_t, std::pair<int32_t*, size_t>> null_copies;
 };
 
 std::map<int, DeviceState> g_dev;
@@ -426,6 +428,7 @@ int32_t motif_shutdown(void) {
     (void)hipSetDevice(kv.first);
     (void)hipDeviceSynchronize();
     for (void* ptr : kv.second.owned) (void)hipFree(ptr);
+    for (auto& nc : kv.second.null_copies) (void)hipFree(nc.second.first);
     for (auto& pp : kv.second.pipes) {
       if (pp.second->side) (void)hipStreamDestroy(pp.second->side);
       if (pp.second->ev_fork) (void)hipEventDestroy(pp.second->ev_fork);
@@ -765,6 +768,128 @@ int32_t motif_tune_cache_load(const char* path) {
   }
   std::fclose(f);
   return loaded;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Validate the descriptors of graphs to randomise and fill the switch list.
+int32_t switch_list(const motif_graph_t* graphs, int32_t count, int32_t switches_per_arc, uint64_t seed,
+                    int64_t first_index, std::vector<SwitchGraph>* out, int64_t* max_n) {
+  if (switches_per_arc < 0) return MOTIF_EINVAL_ARG;
+  out->clear();
+  *max_n = 0;
+  for (int32_t g = 0; g < count; ++g) {
+    const motif_graph_t& G = graphs[g];
+    if (!check_shape(G.n, G.m) || (G.n == 0 && G.m != 0)) return MOTIF_EINVAL_SHAPE;
+    if ((G.n > 0 && !G.out_off) || (G.m > 0 && !G.out_idx)) return MOTIF_EINVAL_ARG;
+    SwitchGraph sg;
+    sg.off = G.out_off;
+    sg.idx = const_cast<int32_t*>(G.out_idx);  // rewritten in place, as the call documents
+    sg.n = G.n;
+    sg.m = (int32_t)G.m;
+    sg.key = switch_key(seed, first_index + g);
+    sg.rounds = ((int64_t)switches_per_arc * G.m + kSwitchProposals - 1) / kSwitchProposals;
+    out->push_back(sg);
+    *max_n = std::max<int64_t>(*max_n, G.n);
+  }
+  return 0;
+}
+
+// Check every graph's rows, then switch; one host wait at the end.
+int32_t run_switch(Pipeline& p, const std::vector<SwitchGraph>& sg, hipStream_t s) {
+  p.arena.reset();
+  try {
+    enqueue_zero(p.status, sizeof(int32_t) * kStatusWords, s);
+    for (const SwitchGraph& G : sg)
+      if (G.n > 0) enqueue_check_rows(G.off, G.n, G.m, p.status, s);
+    if (int32_t rc = enqueue_switch(p, sg.data(), (int32_t)sg.size(), s)) {
+      (void)hipStreamSynchronize(s);  // best effort: the error is what the caller acts on
+      return rc;
+    }
+  } catch (const WorkspaceError&) {
+    return drain_after_error(p, s);
+  }
+  return read_status(p, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t motif_null_randomize(const motif_graph_t* graphs, int32_t count, int32_t switches_per_arc, uint64_t seed,
+                             void* stream) {
+  if (count < 0 || (count > 0 && !graphs)) return MOTIF_EINVAL_ARG;
+  if (count == 0) return 0;
+  int dev;
+  if (int32_t rc = ensure_init(&dev)) return rc;
+  std::vector<SwitchGraph> sg;
+  int64_t max_n = 0;
+  if (int32_t rc = switch_list(graphs, count, switches_per_arc, seed, 0, &sg, &max_n)) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Pipeline* p = nullptr;
+  if (int32_t rc = get_pipeline(dev, s, switch_bytes(count, max_n, device_cus(dev)), &p)) return rc;
+  return run_switch(*p, sg, s);
+}
+
+int32_t motif_null_model(const motif_graph_t* real, int32_t count, int32_t k, int32_t switches_per_arc, uint64_t seed,
+                         uint64_t* hists, double* z, void* stream) {
+  if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
+  if (!real || !hists || !z || count < 1 || switches_per_arc < 0) return MOTIF_EINVAL_ARG;
+  if (!check_shape(real->n, real->m) || (real->n == 0 && real->m != 0)) return MOTIF_EINVAL_SHAPE;
+  if ((real->n > 0 && !real->out_off) || (real->m > 0 && !real->out_idx)) return MOTIF_EINVAL_ARG;
+  if (real->in_off && real->m > 0 && !real->in_idx) return MOTIF_EINVAL_ARG;
+  if ((int64_t)real->m * (count + 1) >= kMaxN || (int64_t)real->n * (count + 1) >= kMaxN) return MOTIF_EINVAL_SHAPE;
+  int dev;
+  if (int32_t rc = ensure_init(&dev)) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int C = motif_num_classes(k);
+  // the randomised copies: one target array each, sharing the real graph's offsets
+  int32_t* copies = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto& buf = g_dev[dev].null_copies[s];
+    const size_t need = sizeof(int32_t) * (size_t)std::max<int64_t>(1, real->m * count);
+    if (buf.second < need) {
+      if (buf.first) {
+        (void)hipStreamSynchronize(s);  // a failure here shows up as a failed allocation below
+        (void)hipFree(buf.first);
+        buf = {nullptr, 0};
+      }
+      if (hipMalloc(&buf.first, need) != hipSuccess) {
+        buf = {nullptr, 0};
+        return MOTIF_ENOMEM;
+      }
+      buf.second = need;
+    }
+    copies = buf.first;
+  }
+  std::vector<motif_graph_t> all(count + 1);
+  all[0] = *real;
+  for (int32_t g = 1; g <= count; ++g) {
+    all[g] = *real;
+    all[g].out_idx = copies + (size_t)(g - 1) * (size_t)real->m;
+    all[g].in_off = nullptr;  // the transpose of a randomised copy is built internally
+    all[g].in_idx = nullptr;
+  }
+  std::vector<SwitchGraph> sg;
+  int64_t max_n = 0;
+  if (int32_t rc = switch_list(all.data() + 1, count, switches_per_arc, seed, 0, &sg, &max_n)) return rc;
+  Pipeline* p = nullptr;
+  if (int32_t rc = get_pipeline(dev, s, switch_bytes(count, max_n, device_cus(dev)), &p)) return rc;
+  // 1. copy the real graph's targets into every slot, 2. randomise the slots
+  enqueue_zero(p->status, sizeof(int32_t) * kStatusWords, s);
+  if (real->n > 0) enqueue_check_rows(real->out_off, real->n, real->m, p->status, s);
+  if (real->m > 0) enqueue_replicate(real->out_idx, real->m, count, copies, p->status, s);
+  if (int32_t rc = run_switch(*p, sg, s)) return rc;
+  // 3. one fused census of the real graph and its copies
+  int32_t rc = census_batch_with(all.data(), count + 1, k, hists, s,
+                                 tuning_for_call(dev, 1, &k, true, real->m * (count + 1)));
+  if (rc) return rc;
+  // 4. z-scores of the real graph against the copies
+  enqueue_zscores(hists, C, count, z, p->status, s);
+  return hipStreamSynchronize(s) == hipSuccess ? 0 : MOTIF_EDEVICE;
 }
 
 }  // extern "C"

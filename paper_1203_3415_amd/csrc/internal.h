@@ -177,6 +177,35 @@ int32_t run_census_multi_on(Pipeline& p, const BuildInput& in, int32_t nk, const
                             hipStream_t s);
 int32_t read_status(Pipeline& p, hipStream_t s);
 
+// ---- null-model ensembles (nullmodel.hip) ----
+// One graph to randomise in place by arc switches: its out-CSR (targets
+// rewritten), the key of its random stream and the number of rounds of
+// kSwitchProposals proposals each.
+struct SwitchGraph {
+  const int32_t* off;
+  int32_t* idx;
+  int32_t n;
+  int32_t m;
+  uint64_t key;
+  int64_t rounds;
+};
+constexpr int kSwitchProposals = 1024;  // proposals (attempted switches) per round
+// Enqueue the randomisation of host_graphs[0..count) (descriptors copied to
+// the arena; waits for that copy).  Graphs are skipped if the status word is set.
+int32_t enqueue_switch(Pipeline& p, const SwitchGraph* host_graphs, int32_t count, hipStream_t s);
+size_t switch_bytes(int32_t count, int64_t max_n, int num_cus);
+// Key of graph `graph`'s random stream under `seed`.
+uint64_t switch_key(uint64_t seed, int64_t graph);
+// Sets MOTIF_EINVAL_SHAPE unless off[0..n] is monotone from 0 to m.
+void enqueue_check_rows(const int32_t* off, int32_t n, int64_t m, int32_t* st, hipStream_t s);
+// dst[g * m + i] = src[i] for g < copies.
+void enqueue_replicate(const int32_t* src, int64_t m, int32_t copies, int32_t* dst, const int32_t* st, hipStream_t s);
+// z-scores of row 0 of hists[(count + 1) * C] against rows 1..count.
+void enqueue_zscores(const uint64_t* hists, int32_t C, int32_t count, double* z, const int32_t* st, hipStream_t s);
+// The fused batch census under an explicit tuning (api.cpp).
+int32_t census_batch_with(const motif_graph_t* graphs, int32_t count, int32_t k, uint64_t* hists, hipStream_t s,
+                          const TuningSet& tune);
+
 // Optional event timing of the build and of the census kernel (motif_profile_*):
 // no-ops unless profiling is enabled.  `what` is 0 = build, 1 = census kernel.
 void profile_mark(int k, int what, bool begin, hipStream_t s);

@@ -1,0 +1,306 @@
+// Null-model ensembles on the device: degree-preserving arc-switch
+// randomisation, the fused "randomise + census + z-scores" job, and the
+// z-score kernel (the paper's step (iii), Section "Implementation", and its
+// random-graph ensembles, Section "Results and Discussion").
+//
+// Arc switch: pick two arcs a->b and c->d; rewire them to a->d and c->b
+// unless that makes a self-loop or an arc already present.  Out-degrees stay
+// because every arc keeps its source (its slot in the out-CSR row); only the
+// targets of two slots are exchanged, so in-degrees stay too.  Rows need not
+// stay sorted (the census sorts them).
+//
+// One workgroup randomises one graph at a time.  When the graph fits, its
+// offsets, targets and one lock word per row live in LDS for the whole run.
+// Each round, every thread draws one proposal (two arc slots, from a
+// counter-based generator, so the result is a function of the seed alone).
+// A proposal first reserves the two source rows: atomicMin of the thread's
+// index into each row's lock, so the lowest-numbered proposal on a row wins,
+// whatever the timing.  A proposal that holds both rows checks the two rows
+// (only it reads or writes them in this round) and swaps.  Which proposals
+// run depends only on the proposals, not on the graph, and each executed
+// switch is its own inverse, so every round is a symmetric move between
+// graphs of the same degrees: the chain keeps the uniform distribution over
+// them, as the one-switch-at-a-time chain does.  Every proposal counts as an
+// attempt, whether it loses its reservation, is rejected or is executed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+
+namespace motif {
+
+namespace {
+
+constexpr int kSwB = kSwitchProposals;  // threads per workgroup = proposals per round
+constexpr int kSwLds = 38 * 1024;       // LDS words for one graph: n + 1 offsets, m targets, n locks
+constexpr uint32_t kFree = 0xFFFFFFFFu;
+
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014) used as a counter-based generator: output i of
+// stream `key` is the finaliser applied to key + (i + 1) * gamma.
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+__host__ __device__ inline uint64_t sm64_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Row (source vertex) of arc slot i: the last v with off[v] <= i.
+__device__ __forceinline__ int32_t row_of(const int32_t* off, int32_t n, int32_t i) {
+  int32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Lock words: in LDS plain accesses; in global memory device-scope atomics,
+// which are performed in L2 (the per-CU L1 does not see them).
+template <bool LDS>
+__device__ __forceinline__ void lock_min(uint32_t* w, uint32_t v) {
+  if constexpr (LDS) atomicMin(w, v);
+  else __hip_atomic_fetch_min(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool LDS>
+__device__ __forceinline__ uint32_t lock_get(uint32_t* w) {
+  if constexpr (LDS) return *w;
+  else return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool LDS>
+__device__ __forceinline__ void lock_set(uint32_t* w, uint32_t v) {
+  if constexpr (LDS) *w = v;
+  else __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool LDS>
+__device__ __forceinline__ void sw_barrier() {
+  if constexpr (!LDS) __builtin_amdgcn_s_waitcnt(0);  // global atomics and stores of this wave done
+  __syncthreads();
+}
+
+// Randomise the graphs list[0..count) of gs, one workgroup per graph.  LDS:
+// the graph is held in LDS ((n + 1) + m + n <= kSwLds words).  Otherwise it
+// is switched in place in global memory with this workgroup's lock slice
+// glock + blockIdx.x * lock_stride (lock_stride >= n of every listed graph).
+template <bool LDS>
+__global__ __launch_bounds__(kSwB) void k_switch(const SwitchGraph* __restrict__ gs, const int32_t* __restrict__ list,
+                                                 int32_t count, uint32_t* __restrict__ glock, int64_t lock_stride,
+                                                 const int32_t* st) {
+  __shared__ int32_t lds[LDS ? kSwLds : 1];
+  if (st[kStatus] != 0) return;
+  const uint32_t tid = threadIdx.x;
+  for (int32_t q = blockIdx.x; q < count; q += gridDim.x) {
+    const SwitchGraph G = gs[list[q]];
+    const int32_t n = G.n, m = G.m;
+    if (m < 2 || n < 2) continue;  // nothing to switch (uniform over the workgroup)
+    const int32_t* off;
+    int32_t* idx;
+    uint32_t* lock;
+    if constexpr (LDS) {
+      int32_t* loff = lds;
+      int32_t* lidx = lds + (n + 1);
+      uint32_t* llock = reinterpret_cast<uint32_t*>(lidx + m);
+      for (int32_t i = tid; i <= n; i += kSwB) loff[i] = G.off[i];
+      for (int32_t i = tid; i < m; i += kSwB) lidx[i] = G.idx[i];
+      for (int32_t i = tid; i < n; i += kSwB) llock[i] = kFree;
+      off = loff;
+      idx = lidx;
+      lock = llock;
+    } else {
+      off = G.off;
+      idx = G.idx;
+      lock = glock + (int64_t)blockIdx.x * lock_stride;
+      for (int32_t i = tid; i < n; i += kSwB) lock_set<LDS>(&lock[i], kFree);
+    }
+    sw_barrier<LDS>();
+    for (int64_t r = 0; r < G.rounds; ++r) {
+      const uint64_t x = sm64_mix(G.key + (uint64_t)(r * kSwB + tid + 1) * kGamma);
+      const int32_t i = (int32_t)(((x & 0xFFFFFFFFull) * (uint64_t)m) >> 32);
+      const int32_t j = (int32_t)(((x >> 32) * (uint64_t)m) >> 32);
+      const int32_t a = row_of(off, n, i), c = row_of(off, n, j);
+      const bool cand = a != c;  // two arcs of one row: the switch changes nothing
+      if (cand) {
+        lock_min<LDS>(&lock[a], tid);
+        lock_min<LDS>(&lock[c], tid);
+      }
+      sw_barrier<LDS>();
+      if (cand && lock_get<LDS>(&lock[a]) == tid && lock_get<LDS>(&lock[c]) == tid) {
+        // rows a and c are this proposal's alone until the next barrier
+        const int32_t b = idx[i], d = idx[j];
+        bool ok = a != d && c != b && b != d;
+        for (int32_t p = off[a], pe = off[a + 1]; ok && p < pe; ++p) ok = idx[p] != d;
+        for (int32_t p = off[c], pe = off[c + 1]; ok && p < pe; ++p) ok = idx[p] != b;
+        if (ok) {
+          idx[i] = d;
+          idx[j] = b;
+        }
+      }
+      sw_barrier<LDS>();
+      if (cand) {
+        lock_set<LDS>(&lock[a], kFree);
+        lock_set<LDS>(&lock[c], kFree);
+      }
+      sw_barrier<LDS>();
+    }
+    if constexpr (LDS) {
+      for (int32_t i = tid; i < m; i += kSwB) G.idx[i] = idx[i];
+    }
+    sw_barrier<LDS>();
+  }
+}
+
+// Offsets of a graph whose rows will be switched: monotone, from 0 to m (the
+// switch kernel reads the rows they delimit).
+__global__ void k_check_rows(const int32_t* off, int32_t n, int64_t m, int32_t* st) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = off[v];
+    const bool bad = (v == 0 && a != 0) || (v == n && (int64_t)a != m) || (v < n && off[v + 1] < a);
+    if (bad) atomicMin(&st[kStatus], MOTIF_EINVAL_SHAPE);
+  }
+}
+
+// dst[g * m + i] = src[i] for g < copies.
+__global__ void k_replicate(const int32_t* __restrict__ src, int64_t m, int32_t copies, int32_t* __restrict__ dst,
+                            const int32_t* st) {
+  if (st[kStatus] != 0) return;
+  const int64_t total = m * copies;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x)
+    dst[t] = src[t % m];
+}
+
+// Unsigned 128-bit integers from 64-bit halves (exact sums of counts and of
+// their squares).
+struct U128 {
+  uint64_t lo = 0, hi = 0;
+};
+__device__ __forceinline__ U128 add(U128 a, U128 b) {
+  U128 r;
+  r.lo = a.lo + b.lo;
+  r.hi = a.hi + b.hi + (r.lo < a.lo ? 1u : 0u);
+  return r;
+}
+__device__ __forceinline__ U128 mul64(uint64_t a, uint64_t b) {
+  U128 r;
+  r.lo = a * b;
+  r.hi = __umul64hi(a, b);
+  return r;
+}
+// a * b for a < 2^64 and b < 2^128, assuming the product is below 2^128.
+__device__ __forceinline__ U128 mul(uint64_t a, U128 b) {
+  U128 r = mul64(a, b.lo);
+  r.hi += a * b.hi;
+  return r;
+}
+__device__ __forceinline__ bool less(U128 a, U128 b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
+__device__ __forceinline__ U128 sub(U128 a, U128 b) {  // a >= b
+  U128 r;
+  r.lo = a.lo - b.lo;
+  r.hi = a.hi - b.hi - (a.lo < b.lo ? 1u : 0u);
+  return r;
+}
+__device__ __forceinline__ double to_double(U128 a) { return (double)a.hi * 18446744073709551616.0 + (double)a.lo; }
+
+// z_c = (h_real,c - mean_c) / sd_c over the `count` randomised graphs, sample
+// standard deviation (ddof = 1), from exact integer sums:
+//   S1 = sum h, S2 = sum h^2, var_num = N S2 - S1^2 = N (N - 1) var,
+//   z = (N h_real - S1) / N / sqrt(var_num / (N (N - 1))).
+// NaN where N < 2, var = 0, or a count of the class reaches 2^40 (its sums
+// would then need more than 128 bits for N up to 2^16 graphs).
+__global__ void k_zscores(const uint64_t* __restrict__ hists, int32_t C, int32_t count, double* __restrict__ z,
+                          const int32_t* st) {
+  if (st[kStatus] != 0) return;
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const uint64_t real = hists[c];
+  const uint64_t N = (uint64_t)count;
+  bool exact = N >= 2 && N <= 65536 && real < (1ull << 40);
+  U128 s1, s2;
+  for (int32_t g = 1; g <= count; ++g) {
+    const uint64_t h = hists[(int64_t)g * C + c];
+    exact = exact && h < (1ull << 40);
+    s1 = add(s1, U128{h, 0});
+    s2 = add(s2, mul64(h, h));
+  }
+  double out = __builtin_nan("");
+  if (exact) {
+    const U128 a = mul(N, s2);
+    const U128 b = mul(s1.lo, s1);  // s1 < 2^56: one 64-bit half
+    if (less(b, a)) {
+      const double var = to_double(sub(a, b)) / ((double)N * (double)(N - 1));
+      const U128 nr = mul64(N, real);
+      const double num = less(nr, s1) ? -to_double(sub(s1, nr)) : to_double(sub(nr, s1));
+      out = num / (double)N / sqrt(var);
+    }
+  }
+  z[c] = out;
+}
+
+unsigned blocks(int64_t items, int b) {
+  const int64_t g = (items + b - 1) / b;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, g));
+}
+
+}  // namespace
+
+int32_t enqueue_switch(Pipeline& p, const SwitchGraph* host_graphs, int32_t count, hipStream_t s) {
+  // graphs held in LDS and graphs switched in global memory, each a list
+  std::vector<int32_t> lds_list, glob_list;
+  int64_t max_glob_n = 0;
+  for (int32_t g = 0; g < count; ++g) {
+    const SwitchGraph& G = host_graphs[g];
+    if ((int64_t)(G.n + 1) + G.m + G.n <= kSwLds) {
+      lds_list.push_back(g);
+    } else {
+      glob_list.push_back(g);
+      max_glob_n = std::max<int64_t>(max_glob_n, G.n);
+    }
+  }
+  SwitchGraph* dg = p.arena.take<SwitchGraph>(std::max(count, 1));
+  int32_t* dl = p.arena.take<int32_t>(std::max(count, 1));
+  if (hipMemcpyAsync(dg, host_graphs, sizeof(SwitchGraph) * count, hipMemcpyHostToDevice, s) != hipSuccess)
+    return MOTIF_EDEVICE;
+  std::vector<int32_t> lists(lds_list);
+  lists.insert(lists.end(), glob_list.begin(), glob_list.end());
+  if (!lists.empty() &&
+      hipMemcpyAsync(dl, lists.data(), sizeof(int32_t) * lists.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    return MOTIF_EDEVICE;
+  // the copies above read pageable host memory: wait before it goes out of scope
+  if (hipStreamSynchronize(s) != hipSuccess) return MOTIF_EDEVICE;
+  const int grid = std::max(1, p.num_cus);
+  if (!lds_list.empty())
+    hipLaunchKernelGGL((k_switch<true>), dim3(std::min<int64_t>(grid, (int64_t)lds_list.size())), dim3(kSwB), 0, s, dg,
+                       dl, (int32_t)lds_list.size(), nullptr, 0, p.status);
+  if (!glob_list.empty()) {
+    const int gw = (int)std::min<int64_t>(grid, (int64_t)glob_list.size());
+    uint32_t* locks = p.arena.take<uint32_t>((size_t)gw * (size_t)max_glob_n);
+    hipLaunchKernelGGL((k_switch<false>), dim3(gw), dim3(kSwB), 0, s, dg, dl + lds_list.size(),
+                       (int32_t)glob_list.size(), locks, max_glob_n, p.status);
+  }
+  return 0;
+}
+
+size_t switch_bytes(int32_t count, int64_t max_n, int num_cus) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return al(sizeof(SwitchGraph) * std::max(count, 1)) + al(sizeof(int32_t) * std::max(count, 1)) +
+         al(sizeof(uint32_t) * (size_t)std::max(1, num_cus) * (size_t)std::max<int64_t>(max_n, 1));
+}
+
+uint64_t switch_key(uint64_t seed, int64_t graph) { return sm64_mix(seed + (uint64_t)(graph + 1) * kGamma); }
+
+void enqueue_check_rows(const int32_t* off, int32_t n, int64_t m, int32_t* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_rows, dim3(blocks(n + 1, 256)), dim3(256), 0, s, off, n, m, st);
+}
+
+void enqueue_replicate(const int32_t* src, int64_t m, int32_t copies, int32_t* dst, const int32_t* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_replicate, dim3(blocks(m * copies, 256)), dim3(256), 0, s, src, m, copies, dst, st);
+}
+
+void enqueue_zscores(const uint64_t* hists, int32_t C, int32_t count, double* z, const int32_t* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_zscores, dim3(blocks(C, 256)), dim3(256), 0, s, hists, C, count, z, st);
+}
+
+}  // namespace motif

@@ -203,7 +203,8 @@ def test_async_census(pm):
         pm.census_async(off, idx, g.n, k, hist, status, stream=s)
         s.synchronize()
         assert int(status.item()) == 0
-        assert np.array_equal(hist.cpu().numpy().view(np.uint64), oracle.census(g, k))
+        # the method reference (pinned against ESU) stands in for ESU at this size
+        assert np.array_equal(hist.cpu().numpy().view(np.uint64), oracle.method_census(g, k))
     # an invalid graph: the status word carries the code, the histogram is untouched
     bo, bi = _dev(pm, np.asarray([0, 1, 2, 2], np.int32), np.asarray([1, 1], np.int32))
     hist = torch.full((13,), 7, dtype=torch.int64, device="cuda")
@@ -217,7 +218,7 @@ def test_async_census(pm):
     pm.census_async(off, idx, g.n, 4, hist4, status, stream=s)
     s.synchronize()
     assert int(status.item()) == 0
-    assert np.array_equal(hist4.cpu().numpy().view(np.uint64), oracle.census(g, 4))
+    assert np.array_equal(hist4.cpu().numpy().view(np.uint64), oracle.method_census(g, 4))
 
 
 @pytest.mark.parametrize("k", [3, 4, 5])
