@@ -72,6 +72,8 @@ extern "C" {
 #define MOTIF_EINVAL_ARG (-13)   /* other bad argument (NULL pointer, bad count...)   */
 #define MOTIF_EINTERNAL (-14)    /* self-check failed: a class total was not an exact
                                     multiple of its anchor multiplicity               */
+#define MOTIF_EPARSE (-15)       /* network file: malformed line or id out of range    */
+#define MOTIF_EIO (-16)          /* network file: cannot be opened or read             */
 
 /* One graph in int32 CSR.  in_off/in_idx may be NULL (the transpose is built
  * internally); when given they must describe exactly the transpose of the
@@ -119,6 +121,45 @@ int32_t motif_class_of_code(int32_t k, uint32_t code);
 
 /* Static description of an error code. */
 const char* motif_strerror(int32_t code);
+
+/* ---- reading networks (host) ----------------------------------------------- */
+
+#define MOTIF_FORMAT_AUTO 0       /* Pajek for a ".net" file name, else edge list      */
+#define MOTIF_FORMAT_PAJEK 1
+#define MOTIF_FORMAT_EDGE_LIST 2
+#define MOTIF_READ_UNDIRECTED 1   /* edge list: each line is an undirected edge        */
+#define MOTIF_READ_KEEP_ISOLATED 2 /* Pajek: keep the vertices of degree zero          */
+
+typedef struct motif_read_stats {
+  int64_t lines;              /* lines read                                          */
+  int64_t arcs_read;          /* arcs listed (an undirected edge counts twice)       */
+  int64_t self_loops_dropped; /* arcs u -> u                                          */
+  int64_t duplicates_merged;  /* arcs listed more than once                          */
+  int64_t isolated_dropped;   /* Pajek vertices with no neighbour, removed            */
+} motif_read_stats_t;
+
+/* Reads a network file into a HOST int32 out-CSR, as the paper prepares its
+ * instances (Section "Results and Discussion": networks from public Pajek
+ * and edge-list collections, vertices with no neighbours removed).
+ *  Pajek: "*Vertices N" then "*Arcs" / "*Edges" ("u v [w]"), "*Arcslist" /
+ *         "*Edgeslist" ("u v1 v2 ..."), or "*Matrix" sections; 1-based ids;
+ *         an edge is both arcs; other sections are skipped; "%" comments.
+ *  Edge list: "u v [anything]" per line, ids >= 0, each line the arc u -> v
+ *         (both arcs with MOTIF_READ_UNDIRECTED); "#" or "%" comments.
+ * Self-loops are dropped and repeated arcs merged (the census takes simple
+ * digraphs); the vertices that keep a neighbour are renumbered 0..n-1 in the
+ * order of their ids in the file; rows come out sorted.  *out_off ([n+1]),
+ * *out_idx ([m], at least one entry) and, when orig_ids is not NULL,
+ * *orig_ids ([n]: file id of each vertex, 0-based for Pajek) are malloc'ed
+ * by the library; free them with motif_free().  stats may be NULL.  Errors:
+ * MOTIF_EIO, MOTIF_EPARSE, MOTIF_EINVAL_ARG, MOTIF_EINVAL_SHAPE (n or m of
+ * 2^30 or more), MOTIF_ENOMEM; nothing is returned through the pointers on
+ * error.  Host-only; needs no device. */
+int32_t motif_read_network(const char* path, int32_t format, int32_t flags, int32_t* n, int64_t* m,
+                           int32_t** out_off, int32_t** out_idx, int64_t** orig_ids, motif_read_stats_t* stats);
+
+/* Frees memory returned by motif_read_network(). */
+void motif_free(void* p);
 
 /* ---- census --------------------------------------------------------------- */
 

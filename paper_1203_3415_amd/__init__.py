@@ -22,6 +22,7 @@ from .binding import (  # noqa: F401
     class_code,
     class_multiplicity,
     class_of_code,
+    read_network,
     get_tuning,
     set_tuning,
     autotune,

@@ -18,7 +18,7 @@ NUM_CLASSES = {3: 13, 4: 199, 5: 9364}
 _ERRORS = {
     -1: "EINVAL_K", -2: "EINVAL_SHAPE", -3: "EINDEX", -4: "ESELFLOOP", -5: "EDUP", -6: "ETRANSPOSE",
     -7: "ENOMEM", -8: "EDEVICE", -9: "EAGAIN", -10: "ETOOBIG", -11: "ETIMEOUT", -12: "ECANCELED",
-    -13: "EINVAL_ARG", -14: "EINTERNAL",
+    -13: "EINVAL_ARG", -14: "EINTERNAL", -15: "EPARSE", -16: "EIO",
 }
 
 
@@ -46,6 +46,11 @@ class _Tuning(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f in _TUNING_FIELDS}
+
+
+class _ReadStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("lines", "arcs_read", "self_loops_dropped", "duplicates_merged",
+                                              "isolated_dropped")]
 
 
 _LOCK = threading.Lock()
@@ -79,6 +84,10 @@ def lib():
             "motif_class_multiplicity": ([I32, I32], I32),
             "motif_class_of_code": ([I32, U32], I32),
             "motif_strerror": ([I32], ctypes.c_char_p),
+            "motif_read_network": ([ctypes.c_char_p, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I64),
+                                    ctypes.POINTER(ctypes.POINTER(I32)), ctypes.POINTER(ctypes.POINTER(I32)),
+                                    ctypes.POINTER(ctypes.POINTER(I64)), ctypes.POINTER(_ReadStats)], I32),
+            "motif_free": ([P], None),
             "motif_census": ([P, P, P, P, I32, I64, I32, P, P], I32),
             "motif_census_async": ([P, P, P, P, I32, I64, I32, P, P, P], I32),
             "motif_census_batch": ([P, I32, I32, P, P], I32),
@@ -136,6 +145,33 @@ def class_multiplicity(k: int, cls: int) -> int:
 
 def class_of_code(k: int, code: int) -> int:
     return int(lib().motif_class_of_code(k, code))
+
+
+_FORMATS = {"auto": 0, "pajek": 1, "edgelist": 2}
+
+
+def read_network(path: str, fmt: str = "auto", undirected: bool = False, keep_isolated: bool = False):
+    """Read a Pajek (.net) or edge-list file into a host CSR (numpy), the way
+    the paper prepares its instances: self-loops dropped, repeated arcs merged,
+    vertices without neighbours removed.  Returns (n, out_off int32 [n+1],
+    out_idx int32 [m], file_ids int64 [n], stats dict)."""
+    L = lib()
+    n, m = ctypes.c_int32(), ctypes.c_int64()
+    po, pi = ctypes.POINTER(ctypes.c_int32)(), ctypes.POINTER(ctypes.c_int32)()
+    pid = ctypes.POINTER(ctypes.c_int64)()
+    st = _ReadStats()
+    flags = (1 if undirected else 0) | (2 if keep_isolated else 0)
+    rc = L.motif_read_network(os.fsencode(path), _FORMATS[fmt], flags, ctypes.byref(n), ctypes.byref(m),
+                              ctypes.byref(po), ctypes.byref(pi), ctypes.byref(pid), ctypes.byref(st))
+    _check(rc, "motif_read_network")
+    try:
+        off = np.ctypeslib.as_array(po, shape=(n.value + 1,)).copy()
+        idx = np.ctypeslib.as_array(pi, shape=(max(1, m.value),))[: m.value].copy()
+        ids = np.ctypeslib.as_array(pid, shape=(max(1, n.value),))[: n.value].copy()
+    finally:
+        for p in (po, pi, pid):
+            L.motif_free(ctypes.cast(p, ctypes.c_void_p))
+    return n.value, off, idx, ids, {f: int(getattr(st, f)) for f, _ in _ReadStats._fields_}
 
 
 # ---------------------------------------------------------------- device --

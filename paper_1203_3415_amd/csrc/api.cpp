@@ -491,6 +491,8 @@ const char* motif_strerror(int32_t code) {
     case MOTIF_ECANCELED: return "cancelled";
     case MOTIF_EINVAL_ARG: return "invalid argument";
     case MOTIF_EINTERNAL: return "internal self-check failed";
+    case MOTIF_EPARSE: return "malformed network file";
+    case MOTIF_EIO: return "network file cannot be read";
     default: return "unknown error";
   }
 }

@@ -445,3 +445,19 @@ def test_dense_closed_forms(pm, k, n):
         cls = pm.class_of_code(k, code)
         assert int(h[cls]) == want, name
         assert int(h.sum()) == want, name
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_census_of_network_files(pm, k, tmp_path):
+    # A file read the way the paper prepares its instances, censused on the
+    # device and by the oracle from the same CSR.
+    import os
+    net = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "networks")
+    g = gg.gnm_reciprocal(120, 500, 0.3, seed=21)
+    path = str(tmp_path / "g.txt")
+    np.savetxt(path, g.arcs() * 3 + 1, fmt="%d")
+    for p in (os.path.join(net, "tiny_arcs.net"), path):
+        n, off, idx, _, _ = pm.read_network(p)
+        h = gg.Digraph(n, off, idx)
+        print(f"[case] network file {os.path.basename(p)} n={n} m={h.m} k={k}", flush=True)
+        assert_parity(pm, h, k, os.path.basename(p))
