@@ -190,6 +190,22 @@ int32_t motif_census_async(const int32_t* out_off, const int32_t* out_idx, const
                            const int32_t* in_idx, int32_t n, int64_t m, int32_t k, uint64_t* hist,
                            int32_t* status, void* stream);
 
+/* Allocation-free form of motif_census(), for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, result and errors as
+ * motif_census(); it calls no allocating routine.  Its workspace is a fixed
+ * 128 MiB device array of the library (every device the library is set up on
+ * holds it until the process ends); motif_init() must have run on the current
+ * device first, else MOTIF_EDEVICE.  A graph whose workspace does not fit
+ * returns MOTIF_ETOOBIG before any work is enqueued; for k = 4, 5 the
+ * per-anchor scheme (no per-workgroup tables) is used when the default
+ * scheme's workspace does not fit.  Calls on one device share the array:
+ * they are serialised by a lock and each returns only after its work on
+ * `stream` has finished, so they never overlap in it. */
+int32_t motif_census_noalloc(const int32_t* out_off, const int32_t* out_idx, const int32_t* in_off,
+                             const int32_t* in_idx, int32_t n, int64_t m, int32_t k, uint64_t* hist,
+                             void* stream);
+
 /* Census of one graph for several sizes: ks[0..nk) are distinct values of
  * {3, 4, 5} and hists[i] (device, motif_num_classes(ks[i]) uint64) receives
  * exactly what motif_census(..., ks[i], hists[i], ...) would write.  The

@@ -90,6 +90,7 @@ def lib():
             "motif_free": ([P], None),
             "motif_census": ([P, P, P, P, I32, I64, I32, P, P], I32),
             "motif_census_async": ([P, P, P, P, I32, I64, I32, P, P, P], I32),
+            "motif_census_noalloc": ([P, P, P, P, I32, I64, I32, P, P], I32),
             "motif_census_batch": ([P, I32, I32, P, P], I32),
             "motif_census_multi": ([P, I32, P, P, P], I32),
             "motif_census_batch_loop": ([P, I32, I32, P, P], I32),

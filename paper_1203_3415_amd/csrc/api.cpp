@@ -26,9 +26,19 @@ std::mutex g_mu;
 // total arc count)).
 using TuneKey = std::tuple<int32_t, int32_t, int32_t>;
 
+// Workspace of motif_census_noalloc(): a fixed device array, so that call
+// allocates nothing.  Host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (kept per device in
+// DeviceState::scratch); the array's name is not a device address on the host.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr size_t kScratchHead = 256;  // status words at the start, then the arena
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 struct DeviceState {
   bool ready = false;
   int num_cus = 0;
+  char* scratch = nullptr;           // device address of `scratch` on this device
+  int32_t* scratch_host = nullptr;   // pinned host copy of its status words
   std::string arch;  // gcnArchName up to the first ':'
   DevTables tables;
   std::vector<void*> owned;  // table buffers
@@ -76,6 +86,15 @@ int32_t init_device_locked(int dev) {
       return MOTIF_EDEVICE;
     d.tables.lut[k] = (const uint16_t*)lut;
     d.tables.mult[k] = (const uint8_t*)mult;
+  }
+  // the allocation-free entry point's workspace: this device's copy of the
+  // array, and a pinned word block its status is read back into
+  void* sp = nullptr;
+  if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) return MOTIF_EDEVICE;
+  d.scratch = static_cast<char*>(sp);
+  if (hipHostMalloc(&d.scratch_host, kStatusWords * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+    d.scratch_host = nullptr;
+    return MOTIF_ENOMEM;
   }
   d.ready = true;
   return 0;
@@ -264,8 +283,12 @@ std::vector<TuneAxis> tune_axes(int k) {
 
 }  // namespace
 
+// Set while motif_census_noalloc() runs on this thread: no profiling events
+// are created or recorded for it.
+thread_local bool t_no_events = false;
+
 void profile_mark(int k, int what, bool begin, hipStream_t s) {
-  if (!g_prof.on || k < 3 || k > 5) return;
+  if (!g_prof.on || t_no_events || k < 3 || k > 5) return;
   hipEvent_t& e = g_prof.ev[k][what * 2 + (begin ? 0 : 1)];
   if (!e && hipEventCreate(&e) != hipSuccess) {
     e = nullptr;
@@ -428,6 +451,7 @@ int32_t motif_shutdown(void) {
     (void)hipSetDevice(kv.first);
     (void)hipDeviceSynchronize();
     for (void* ptr : kv.second.owned) (void)hipFree(ptr);
+    if (kv.second.scratch_host) (void)hipHostFree(kv.second.scratch_host);
     for (auto& nc : kv.second.null_copies) (void)hipFree(nc.second.first);
     for (auto& pp : kv.second.pipes) {
       if (pp.second->side) (void)hipStreamDestroy(pp.second->side);
@@ -562,6 +586,64 @@ int32_t motif_census_async(const int32_t* out_off, const int32_t* out_idx, const
     return drain_after_error(*p, s);
   }
   return 0;
+}
+
+int32_t motif_census_noalloc(const int32_t* out_off, const int32_t* out_idx, const int32_t* in_off,
+                             const int32_t* in_idx, int32_t n, int64_t m, int32_t k, uint64_t* hist, void* stream) {
+  if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
+  if (!check_shape(n, m) || (n == 0 && m != 0)) return MOTIF_EINVAL_SHAPE;
+  if (!hist || !out_off || (m > 0 && !out_idx)) return MOTIF_EINVAL_ARG;
+  if (in_off && m > 0 && !in_idx) return MOTIF_EINVAL_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  int dev;
+  if (current_device(&dev)) return MOTIF_EDEVICE;
+  char* base = nullptr;
+  int32_t* host_status = nullptr;
+  int cus = 0;
+  {
+    // set up by motif_init(); nothing is initialised (allocated) here
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_dev.find(dev);
+    if (it == g_dev.end() || !it->second.ready || !it->second.scratch) return MOTIF_EDEVICE;
+    base = it->second.scratch;
+    host_status = it->second.scratch_host;
+    cus = it->second.num_cus;
+  }
+  // One workspace per device: calls are serialised here, and each returns
+  // only after its work has finished, so two calls never overlap in it.
+  static std::mutex scratch_mu;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  TuningSet tune = tuning_for_call(dev, 1, &k, false, m);
+  const size_t room = kScratchBytes - kScratchHead;
+  size_t need = pipeline_bytes(n, m, 1, false, k, cus, n, tune.k[k]);
+  if (need > room && (k == 4 || k == 5) && tune.k[k].heavy == 1) {
+    // the per-anchor scheme needs no per-workgroup W rows: same result, less room
+    tune.k[k].heavy = 0;
+    need = pipeline_bytes(n, m, 1, false, k, cus, n, tune.k[k]);
+  }
+  if (need > room) return MOTIF_ETOOBIG;
+  Pipeline p;
+  p.arena.base = base + kScratchHead;
+  p.arena.cap = room;
+  p.status = reinterpret_cast<int32_t*>(base);
+  p.host_status = host_status;
+  p.num_cus = cus;
+  p.tune = tune;
+  if (n == 0) {
+    enqueue_zero(hist, sizeof(uint64_t) * motif_num_classes(k), s);
+    return hipStreamSynchronize(s) == hipSuccess ? 0 : MOTIF_EDEVICE;
+  }
+  BuildInput in{};
+  in.out_off = out_off;
+  in.out_idx = out_idx;
+  in.in_off = in_off;
+  in.in_idx = in_off ? in_idx : nullptr;
+  in.n = n;
+  in.m = m;
+  t_no_events = true;
+  const int32_t rc = run_census_on(p, in, k, hist, s);
+  t_no_events = false;
+  return rc;
 }
 
 int32_t motif_census_multi(const motif_graph_t* g, int32_t nk, const int32_t* ks, uint64_t* const* hists,
