@@ -44,6 +44,8 @@ def make_graph(name: str):
     import graphgen as gg
     if name == "chunglu_n1e5_k34":
         return gg.chung_lu(100_000, 1_000_000, 2.1, 2.1, 0.2, seed=2), (3, 4)
+    if name in ("chunglu_n1e5_k3", "chunglu_n1e5_k4"):  # one size alone, for kernel timing
+        return gg.chung_lu(100_000, 1_000_000, 2.1, 2.1, 0.2, seed=2), (int(name[-1]),)
     if name == "gnm_n1000":
         return gg.gnm_reciprocal(1000, 5000, 0.1, seed=1), (3, 4, 5)
     if name == "chunglu_n2e4_k5":
@@ -342,6 +344,8 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, kname: str, workload: 
 def describe(name):
     return {
         "chunglu_n1e5_k34": "Chung-Lu n=100000 m=1000000 gamma_out=gamma_in=2.1 reciprocity=0.2 seed=2",
+        "chunglu_n1e5_k3": "Chung-Lu n=100000 m=1000000 gamma_out=gamma_in=2.1 reciprocity=0.2 seed=2, k=3 alone",
+        "chunglu_n1e5_k4": "Chung-Lu n=100000 m=1000000 gamma_out=gamma_in=2.1 reciprocity=0.2 seed=2, k=4 alone",
         "gnm_n1000": "G(n=1000, 5000 arcs) + 10% reciprocated, seed=1",
         "chunglu_n2e4_k5": "Chung-Lu n=20000 m=100000 gamma_out=2.2 gamma_in=2.5 reciprocity=0.1 seed=4",
     }.get(name, name)
@@ -674,7 +678,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="chunglu_n1e5_k34",
-                    choices=["chunglu_n1e5_k34", "gnm_n1000", "chunglu_n2e4_k5", "nullmodel_k4", "serving"])
+                    choices=["chunglu_n1e5_k34", "chunglu_n1e5_k3", "chunglu_n1e5_k4", "gnm_n1000", "chunglu_n2e4_k5",
+                             "nullmodel_k4", "serving"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--null-graphs", type=int, default=1000)

@@ -119,6 +119,19 @@ int32_t motif_class_multiplicity(int32_t k, int32_t cls);
  * version is disconnected.  Host-only. */
 int32_t motif_class_of_code(int32_t k, uint32_t code);
 
+/* Undirected classes: the connected undirected graphs on k vertices, 2, 6 or
+ * 21 for k = 3, 4, 5 (the undirected censuses of the paper, Sections
+ * "Counting isomorphic patterns of size 4" (Table "ept") and "Counting
+ * 5-sized patterns in undirected graphs").  Numbering: the edge {i, j},
+ * i < j, is bit i(2k - i - 1)/2 + (j - i - 1) of a k(k-1)/2-bit code; the
+ * canonical code is the minimum over all k! relabellings; class ids are the
+ * ranks of the canonical codes of connected graphs, ascending.  Host-only. */
+int32_t motif_num_undirected_classes(int32_t k);
+int32_t motif_undirected_class_code(int32_t k, int32_t cls, uint32_t* canon_code);
+/* Undirected class of directed class `cls` when every arc of its pattern is
+ * reciprocated, else -1.  Host-only. */
+int32_t motif_class_undirected(int32_t k, int32_t cls);
+
 /* Static description of an error code. */
 const char* motif_strerror(int32_t code);
 
@@ -205,6 +218,17 @@ int32_t motif_census_async(const int32_t* out_off, const int32_t* out_idx, const
 int32_t motif_census_noalloc(const int32_t* out_off, const int32_t* out_idx, const int32_t* in_off,
                              const int32_t* in_idx, int32_t n, int64_t m, int32_t k, uint64_t* hist,
                              void* stream);
+
+/* Undirected census: the connected k-vertex induced subgraphs of the
+ * undirected version G* of the graph (u, v adjacent when u -> v or v -> u is
+ * listed), grouped into the motif_num_undirected_classes(k) classes above.
+ * An undirected graph may be given with each edge listed once or in both
+ * directions.  Same pipeline as motif_census() with every edge of G* read as
+ * a pair of arcs, then the all-reciprocated directed classes summed into
+ * undirected ones.  hist: device, motif_num_undirected_classes(k) uint64.
+ * Errors as for motif_census(). */
+int32_t motif_census_undirected(const int32_t* out_off, const int32_t* out_idx, int32_t n, int64_t m, int32_t k,
+                                uint64_t* hist, void* stream);
 
 /* Census of one graph for several sizes: ks[0..nk) are distinct values of
  * {3, 4, 5} and hists[i] (device, motif_num_classes(ks[i]) uint64) receives

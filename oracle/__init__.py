@@ -211,6 +211,88 @@ def undirected4(g, threads: int = 0) -> np.ndarray:
     return out
 
 
+# -- undirected censuses --------------------------------------------------------
+
+def und_bit(k: int, i: int, j: int) -> int:
+    """Bit of the edge {i, j} (i < j) in a k-vertex undirected code."""
+    return i * (2 * k - i - 1) // 2 + (j - i - 1)
+
+
+def _und_connected(k: int, code: int) -> bool:
+    adj = [[False] * k for _ in range(k)]
+    for i in range(k):
+        for j in range(i + 1, k):
+            if code >> und_bit(k, i, j) & 1:
+                adj[i][j] = adj[j][i] = True
+    seen, stack = {0}, [0]
+    while stack:
+        a = stack.pop()
+        for b in range(k):
+            if adj[a][b] and b not in seen:
+                seen.add(b)
+                stack.append(b)
+    return len(seen) == k
+
+
+@functools.lru_cache(maxsize=4)
+def undirected_class_table(k: int):
+    """(canon: sorted canonical codes of the connected undirected graphs on k
+    vertices, cls_of_code: dict code -> class id for every connected code,
+    n_all_classes, n_connected_codes), by brute force over all
+    2^(k(k-1)/2) codes and all k! relabellings."""
+    import itertools
+    perms = list(itertools.permutations(range(k)))
+    nb = k * (k - 1) // 2
+    canon_of = {}
+    for code in range(1 << nb):
+        best = None
+        for p in perms:
+            c = 0
+            for i in range(k):
+                for j in range(i + 1, k):
+                    if code >> und_bit(k, i, j) & 1:
+                        a, b = min(p[i], p[j]), max(p[i], p[j])
+                        c |= 1 << und_bit(k, a, b)
+            best = c if best is None else min(best, c)
+        canon_of[code] = best
+    classes = sorted({c for x, c in canon_of.items() if _und_connected(k, x)})
+    rank = {c: i for i, c in enumerate(classes)}
+    cls = {x: rank[c] for x, c in canon_of.items() if c in rank}
+    return tuple(classes), cls, len(set(canon_of.values())), len(cls)
+
+
+def census_undirected(g, k: int, threads: int = 0, method: bool = False) -> np.ndarray:
+    """uint64 histogram over the undirected classes: the connected induced
+    k-subgraphs of the undirected version G* of g, by ESU on G* read as a
+    symmetric digraph (every pattern then has all arcs reciprocated), each
+    class mapped to the undirected class of its skeleton.  method=True takes
+    the method reference instead of ESU for the directed census (for sizes
+    ESU cannot finish)."""
+    a = np.asarray(g.arcs())
+    sym = np.unique(np.concatenate([a, a[:, ::-1]]), axis=0) if a.size else a.reshape(0, 2)
+
+    class _G:
+        pass
+    h = _G()
+    h.n = g.n
+    cnt = np.bincount(sym[:, 0], minlength=g.n) if sym.size else np.zeros(g.n, np.int64)
+    h.out_off = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)
+    h.out_idx = sym[:, 1].astype(np.int32) if sym.size else np.zeros(0, np.int32)
+    hd = method_census(h, k, threads=threads) if method else census(h, k, threads=threads)
+    _, canon, _, _ = class_table(k)
+    _, ucls, _, _ = undirected_class_table(k)
+    out = np.zeros(len(undirected_class_table(k)[0]), np.uint64)
+    for c in np.flatnonzero(hd):
+        code = int(canon[c])
+        u = 0
+        for i in range(k):
+            for j in range(i + 1, k):
+                if code >> (i * (k - 1) + (j - 1)) & 1:
+                    u |= 1 << und_bit(k, i, j)
+        out[ucls[u]] += hd[c]
+    return out
+
+
 def code_of(k: int, arcs) -> int:
     """Adjacency code of a k-vertex pattern given as (i, j) arcs."""
     code = 0

@@ -55,3 +55,30 @@ def census_by_canon(n: int, arcs, k: int) -> Counter:
         local = [(i, j) for i, a in enumerate(sub) for j, b in enumerate(sub) if i != j and (a, b) in arcs]
         out[canonical(k, local)] += 1
     return out
+
+
+def census_undirected_by_canon(n: int, edges, k: int) -> Counter:
+    """Counter {canonical undirected code: number of connected induced
+    k-subsets} of an undirected graph, by all k-subsets; an edge {i, j}, i < j,
+    is bit i(2k - i - 1)/2 + (j - i - 1) of the code."""
+    adj = {v: set() for v in range(n)}
+    for a, b in edges:
+        if a != b:
+            adj[int(a)].add(int(b))
+            adj[int(b)].add(int(a))
+    bit = lambda i, j: i * (2 * k - i - 1) // 2 + (j - i - 1)  # noqa: E731
+    out = Counter()
+    for sub in itertools.combinations(range(n), k):
+        if not _connected(sub, adj):
+            continue
+        best = None
+        for perm in itertools.permutations(range(k)):
+            c = 0
+            for x in range(k):
+                for y in range(x + 1, k):
+                    if sub[y] in adj[sub[x]]:
+                        a, b = min(perm[x], perm[y]), max(perm[x], perm[y])
+                        c |= 1 << bit(a, b)
+            best = c if best is None else min(best, c)
+        out[best] += 1
+    return out

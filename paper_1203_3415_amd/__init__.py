@@ -12,6 +12,11 @@ from .binding import (  # noqa: F401
     lib_path,
     census,
     census_async,
+    census_undirected,
+    num_undirected_classes,
+    undirected_class_code,
+    class_undirected,
+    NUM_UNDIRECTED_CLASSES,
     census_batch,
     census_multi,
     census_batch_loop,

@@ -83,6 +83,10 @@ def lib():
             "motif_class_code": ([I32, I32, ctypes.POINTER(U32)], I32),
             "motif_class_multiplicity": ([I32, I32], I32),
             "motif_class_of_code": ([I32, U32], I32),
+            "motif_num_undirected_classes": ([I32], I32),
+            "motif_undirected_class_code": ([I32, I32, ctypes.POINTER(U32)], I32),
+            "motif_class_undirected": ([I32, I32], I32),
+            "motif_census_undirected": ([P, P, I32, I64, I32, P, P], I32),
             "motif_strerror": ([I32], ctypes.c_char_p),
             "motif_read_network": ([ctypes.c_char_p, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I64),
                                     ctypes.POINTER(ctypes.POINTER(I32)), ctypes.POINTER(ctypes.POINTER(I32)),
@@ -224,6 +228,41 @@ def census(out_off, out_idx, n: int, k: int, in_off=None, in_idx=None, stream=No
     rc = lib().motif_census(_ptr(out_off), _ptr(out_idx), _ptr(in_off), _ptr(in_idx), int(n), m, int(k),
                             _ptr(hist), _stream_handle(stream))
     _check(rc, "motif_census")
+    if out is not None:
+        return out
+    return hist.cpu().numpy().view(np.uint64)
+
+
+NUM_UNDIRECTED_CLASSES = {3: 2, 4: 6, 5: 21}
+
+
+def num_undirected_classes(k: int) -> int:
+    return int(lib().motif_num_undirected_classes(k))
+
+
+def undirected_class_code(k: int, cls: int) -> int:
+    out = ctypes.c_uint32()
+    _check(lib().motif_undirected_class_code(k, cls, ctypes.byref(out)), "motif_undirected_class_code")
+    return int(out.value)
+
+
+def class_undirected(k: int, cls: int) -> int:
+    return int(lib().motif_class_undirected(k, cls))
+
+
+def census_undirected(out_off, out_idx, n: int, k: int, stream=None, out=None):
+    """Undirected census of the graph's undirected version: numpy uint64
+    [2 / 6 / 21] (or fills `out`, an int64 CUDA tensor of that size)."""
+    torch = _torch()
+    for t, nm in ((out_off, "out_off"), (out_idx, "out_idx")):
+        _check_dev(t, nm)
+    U = NUM_UNDIRECTED_CLASSES.get(k)
+    if U is None:
+        raise MotifError(-1, "census_undirected")
+    hist = out if out is not None else torch.empty(U, dtype=torch.int64, device=out_off.device)
+    rc = lib().motif_census_undirected(_ptr(out_off), _ptr(out_idx), int(n), int(out_idx.numel()), int(k),
+                                       _ptr(hist), _stream_handle(stream))
+    _check(rc, "motif_census_undirected")
     if out is not None:
         return out
     return hist.cpu().numpy().view(np.uint64)

@@ -76,16 +76,20 @@ int32_t init_device_locked(int dev) {
   d.arch = d.arch.substr(0, d.arch.find(':'));
   for (int k = 3; k <= 5; ++k) {
     const ClassTable* t = class_table(k);
-    void *lut = nullptr, *mult = nullptr;
+    void *lut = nullptr, *mult = nullptr, *und = nullptr;
     if (hipMalloc(&lut, t->lut.size() * sizeof(uint16_t)) != hipSuccess) return MOTIF_ENOMEM;
-    if (hipMalloc(&mult, t->mult.size()) != hipSuccess) return MOTIF_ENOMEM;
     d.owned.push_back(lut);
+    if (hipMalloc(&mult, t->mult.size()) != hipSuccess) return MOTIF_ENOMEM;
     d.owned.push_back(mult);
+    if (hipMalloc(&und, t->und_of.size() * sizeof(int16_t)) != hipSuccess) return MOTIF_ENOMEM;
+    d.owned.push_back(und);
     if (hipMemcpy(lut, t->lut.data(), t->lut.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(mult, t->mult.data(), t->mult.size(), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(mult, t->mult.data(), t->mult.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(und, t->und_of.data(), t->und_of.size() * sizeof(int16_t), hipMemcpyHostToDevice) != hipSuccess)
       return MOTIF_EDEVICE;
     d.tables.lut[k] = (const uint16_t*)lut;
     d.tables.mult[k] = (const uint8_t*)mult;
+    d.tables.und_of[k] = (const int16_t*)und;
   }
   // the allocation-free entry point's workspace: this device's copy of the
   // array, and a pinned word block its status is read back into
@@ -491,6 +495,26 @@ int32_t motif_class_multiplicity(int32_t k, int32_t cls) {
   return t->mult[cls];
 }
 
+int32_t motif_num_undirected_classes(int32_t k) {
+  const ClassTable* t = class_table(k);
+  return t ? (int32_t)t->und_canon.size() : MOTIF_EINVAL_K;
+}
+
+int32_t motif_undirected_class_code(int32_t k, int32_t cls, uint32_t* canon_code) {
+  const ClassTable* t = class_table(k);
+  if (!t) return MOTIF_EINVAL_K;
+  if (cls < 0 || cls >= (int32_t)t->und_canon.size() || !canon_code) return MOTIF_EINVAL_ARG;
+  *canon_code = t->und_canon[cls];
+  return 0;
+}
+
+int32_t motif_class_undirected(int32_t k, int32_t cls) {
+  const ClassTable* t = class_table(k);
+  if (!t) return MOTIF_EINVAL_K;
+  if (cls < 0 || cls >= (int32_t)t->und_of.size()) return MOTIF_EINVAL_ARG;
+  return t->und_of[cls];
+}
+
 int32_t motif_class_of_code(int32_t k, uint32_t code) {
   const ClassTable* t = class_table(k);
   if (!t) return MOTIF_EINVAL_K;
@@ -644,6 +668,48 @@ int32_t motif_census_noalloc(const int32_t* out_off, const int32_t* out_idx, con
   const int32_t rc = run_census_on(p, in, k, hist, s);
   t_no_events = false;
   return rc;
+}
+
+int32_t motif_census_undirected(const int32_t* out_off, const int32_t* out_idx, int32_t n, int64_t m, int32_t k,
+                                uint64_t* hist, void* stream) {
+  if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
+  if (!check_shape(n, m) || (n == 0 && m != 0)) return MOTIF_EINVAL_SHAPE;
+  if (!hist || !out_off || (m > 0 && !out_idx)) return MOTIF_EINVAL_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  int dev;
+  int32_t rc = ensure_init(&dev);
+  if (rc) return rc;
+  const ClassTable* ct = class_table(k);
+  const int32_t C = motif_num_classes(k), U = (int32_t)ct->und_canon.size();
+  if (n == 0) {
+    enqueue_zero(hist, sizeof(uint64_t) * U, s);
+    return hipStreamSynchronize(s) == hipSuccess ? 0 : MOTIF_EDEVICE;
+  }
+  const TuningSet tune = tuning_for_call(dev, 1, &k, false, m);
+  Pipeline* p = nullptr;
+  rc = get_pipeline(dev, s, pipeline_bytes(n, m, 1, false, k, device_cus(dev), n, tune.k[k]), &p);
+  if (rc) return rc;
+  p->tune = tune;
+  BuildInput in{};
+  in.out_off = out_off;
+  in.out_idx = out_idx;
+  in.n = n;
+  in.m = m;
+  try {
+    p->arena.reset();
+    enqueue_zero(p->status, sizeof(int32_t) * kStatusWords, s);
+    profile_mark(k, 0, true, s);
+    DevGraph g = enqueue_build(*p, in, s);
+    enqueue_all_bidirected(g, s, p->status);
+    profile_mark(k, 0, false, s);
+    uint64_t* acc = p->arena.take<uint64_t>((size_t)C);
+    uint64_t* dir = p->arena.take<uint64_t>((size_t)C);
+    enqueue_census(*p, g, k, acc, dir, s);
+    enqueue_project_undirected(dir, dev_tables().und_of[k], C, U, hist, p->status, s);
+  } catch (const WorkspaceError&) {
+    return drain_after_error(*p, s);
+  }
+  return read_status(*p, s);
 }
 
 int32_t motif_census_multi(const motif_graph_t* g, int32_t nk, const int32_t* ks, uint64_t* const* hists,

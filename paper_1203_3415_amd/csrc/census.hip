@@ -189,34 +189,36 @@ __device__ __forceinline__ int32_t find_row(const int32_t* off, int32_t lo, int3
 // pair of the other two corners leaves its open class, and the triangle class
 // gains one occurrence per corner (the division by 3 removes the repetition).
 //
-// Work unit = a tile of consecutive vertices (of one graph).  The type counts
-// of the tile's rows are summed by the whole workgroup (one G* entry per
-// thread, so a hub's row is spread over the workgroup), then each vertex's
-// closed form is added.  Triangles: one wave per vertex u of the tile; N+(u)
-// goes into a wave-private LDS hash (vertex -> type), the N+ rows of its
-// members are laid end to end over the lanes and every entry x is looked up.
-// A u with more than kTriHash / 2 higher-ranked neighbours takes the same
-// rows with a binary search of N+(u) instead of the hash.
+// One wave per vertex u, vertices handed out in chunks from a device counter
+// so that every wave of the chip stays busy and a heavy vertex delays only
+// its own wave.  The wave counts the types of u's row with ballots (a hub's
+// row is read 64 entries at a time), adds the six closed forms, puts N+(u)
+// into a wave-private LDS hash (vertex -> type), lays the N+ rows of its
+// members end to end over the lanes and looks every entry x up: a hit is a
+// triangle.  A u with more than kTriHash / 2 higher-ranked neighbours
+// binary-searches N+(u) instead of the hash.  Counts go to a per-wave LDS
+// histogram, flushed when the wave's vertex moves to another graph of a batch.
 constexpr int kTriHashBits = 10;
 constexpr int kTriHash = 1 << kTriHashBits;
-constexpr int kTriTileMax = 1024;  // vertices per k = 3 tile
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k3_kernel(DevGraph G, const uint16_t* __restrict__ lut_g,
-                                                   uint64_t* __restrict__ acc, const int32_t* st, int32_t tv) {
+                                                   uint64_t* __restrict__ acc, const int32_t* st,
+                                                   int32_t* __restrict__ queue, int32_t chunk) {
   constexpr int K = 3, C = 13, NW = BLOCK / 64;
-  __shared__ u64 hist[C];
+  __shared__ u64 whist[NW * 16];
   __shared__ uint16_t lut[64];
-  __shared__ int32_t tcnt[3 * kTriTileMax];
   __shared__ uint32_t th[NW * kTriHash];
+  __shared__ uint16_t tslot[NW * (kTriHash / 2)];  // slot of each key of N+(u), to empty exactly those
   if (st[kStatus] != 0) return;
   for (int i = threadIdx.x; i < 64; i += BLOCK) lut[i] = lut_g[i];
-  for (int i = threadIdx.x; i < C; i += BLOCK) hist[i] = 0;
-  for (int i = threadIdx.x; i < 3 * kTriTileMax; i += BLOCK) tcnt[i] = 0;
+  for (int i = threadIdx.x; i < NW * 16; i += BLOCK) whist[i] = 0;
   for (int i = threadIdx.x; i < NW * kTriHash; i += BLOCK) th[i] = kEmptySlot;
   __syncthreads();
   const int32_t lane = (int32_t)(threadIdx.x & 63u);
   uint32_t* H = th + (threadIdx.x >> 6) * kTriHash;
+  uint16_t* HS = tslot + (threadIdx.x >> 6) * (kTriHash / 2);
+  u64* hist = whist + (threadIdx.x >> 6) * 16;
   auto tri = [&](uint32_t tuw, uint32_t tux, uint32_t twx) {
     const uint32_t full = slot_code<K, 1>(tuw) | slot_code<K, 2>(tux) | rel_code<K>(twx);
     atomicAdd(&hist[lut[full]], 3ull);
@@ -224,132 +226,130 @@ __global__ __launch_bounds__(BLOCK) void k3_kernel(DevGraph G, const uint16_t* _
     atomicAdd(&hist[lut[slot_code<K, 1>(flip(tuw)) | slot_code<K, 2>(twx)]], kMinusOne);
     atomicAdd(&hist[lut[slot_code<K, 1>(flip(tux)) | slot_code<K, 2>(flip(twx))]], kMinusOne);
   };
+  auto flush = [&](int32_t g) {  // this wave's counts to graph g's accumulator
+    wave_sync();
+    if (g >= 0 && lane < C) {
+      const u64 v = hist[lane];
+      if (v) atomicAdd((u64*)&acc[(int64_t)g * C + lane], v);
+    }
+    if (lane < C) hist[lane] = 0;
+    wave_sync();
+  };
   const int32_t n = G.n;
-  const int32_t ntiles = (n + tv - 1) / tv;
   int32_t cur_g = -1;
-  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    int32_t v0 = t * tv;
-    const int32_t v1 = min(n, v0 + tv);
-    while (v0 < v1) {
-      const int32_t g = G.gid ? G.gid[v0] : 0;
-      int32_t end = v1;
-      if (G.gid) {  // first vertex of the tile in a later graph
-        int32_t lo = v0, hi = v1;
-        while (lo < hi) {
-          int32_t mid = (lo + hi) >> 1;
-          if (G.gid[mid] > g) hi = mid; else lo = mid + 1;
-        }
-        end = lo;
-      }
+  for (;;) {
+    int32_t v0 = 0;
+    if (lane == 0) v0 = atomicAdd(queue, chunk);
+    v0 = __shfl(v0, 0);
+    if (v0 >= n) break;
+    const int32_t v1 = min(n, v0 + chunk);
+    for (int32_t u = v0; u < v1; ++u) {
+      const int32_t g = G.gid ? G.gid[u] : 0;
       if (g != cur_g) {
-        __syncthreads();
-        hist_flush<C, BLOCK>(hist, acc, cur_g);
+        flush(cur_g);
         cur_g = g;
-        __syncthreads();
       }
-      // type counts of the rows of [v0, end), one entry per thread
-      for (int32_t j = G.gs_off[v0] + threadIdx.x; j < G.gs_off[end]; j += BLOCK)
-        atomicAdd(&tcnt[3 * (G.gs_row[j] - v0) + (int32_t)(G.gs_idx[j] >> kTypeShift) - 1], 1);
-      __syncthreads();
-      for (int32_t v = v0 + threadIdx.x; v < end; v += BLOCK) {
-        int32_t* tc = tcnt + 3 * (v - v0);
-        const u64 nb = (u64)tc[0], nc = (u64)tc[1], na = (u64)tc[2];  // types 1 = B, 2 = C, 3 = A
-        tc[0] = tc[1] = tc[2] = 0;
-        const u64 w[6] = {na * nb, na * nc, nb * nc, na * (na - (na > 0)) / 2, nb * (nb - (nb > 0)) / 2,
-                          nc * (nc - (nc > 0)) / 2};
-        const uint32_t ta[6] = {3, 3, 1, 3, 1, 2};
-        const uint32_t tb[6] = {1, 2, 2, 3, 1, 2};
-#pragma unroll
-        for (int q = 0; q < 6; ++q)
-          if (w[q]) atomicAdd(&hist[lut[slot_code<K, 1>(ta[q]) | slot_code<K, 2>(tb[q])]], w[q]);
+      // type counts of u's row: 1 = B, 2 = C, 3 = A
+      const int32_t ra = G.gs_off[u], rb = G.gs_off[u + 1];
+      uint32_t nb = 0, nc = 0, na = 0;
+      for (int32_t j0 = ra; j0 < rb; j0 += 64) {
+        const int32_t j = j0 + lane;
+        const uint32_t t = j < rb ? G.gs_idx[j] >> kTypeShift : 0u;
+        nb += (uint32_t)__popcll(__ballot(t == 1u));
+        nc += (uint32_t)__popcll(__ballot(t == 2u));
+        na += (uint32_t)__popcll(__ballot(t == 3u));
       }
-      // triangles u -> w -> x with u in [v0, end), one wave per u
-      for (int32_t u = v0 + (int32_t)(threadIdx.x >> 6); u < end; u += NW) {
-        const int32_t ua = G.np_off[u], du = G.np_off[u + 1] - ua;
-        if (du < 2) continue;
-        const bool hashed = du <= kTriHash / 2;
-        if (hashed) {
-          for (int32_t i = lane; i < du; i += 64) {
-            const uint32_t e = G.np_idx[ua + i];
-            uint32_t h = ((e & kIdMask) * 2654435761u) >> (32 - kTriHashBits);
-            const uint32_t ent = ((e & kIdMask) << 2) | (e >> kTypeShift);  // id < 2^30 - 1: never kEmptySlot
-            while (atomicCAS(&H[h], kEmptySlot, ent) != kEmptySlot) h = (h + 1) & (kTriHash - 1);
-          }
-          wave_sync();
+      if (lane < 6) {
+        const uint32_t ta = lane < 2 ? 3u : lane == 2 ? 1u : lane == 3 ? 3u : lane == 4 ? 1u : 2u;
+        const uint32_t tb = lane == 0 ? 1u : lane == 1 ? 2u : lane == 2 ? 2u : lane == 3 ? 3u : lane == 4 ? 1u : 2u;
+        const u64 x = lane == 0 ? (u64)na * nb : lane == 1 ? (u64)na * nc : lane == 2 ? (u64)nb * nc
+                    : lane == 3 ? (u64)na * (na - (na > 0)) / 2 : lane == 4 ? (u64)nb * (nb - (nb > 0)) / 2
+                                                                : (u64)nc * (nc - (nc > 0)) / 2;
+        if (x) atomicAdd(&hist[lut[slot_code<K, 1>(ta) | slot_code<K, 2>(tb)]], x);
+      }
+      // triangles u -> w -> x
+      const int32_t ua = G.np_off[u], du = G.np_off[u + 1] - ua;
+      if (du < 2) continue;
+      const bool hashed = du <= kTriHash / 2;
+      if (hashed) {
+        for (int32_t i = lane; i < du; i += 64) {
+          const uint32_t e = G.np_idx[ua + i];
+          uint32_t h = ((e & kIdMask) * 2654435761u) >> (32 - kTriHashBits);
+          const uint32_t ent = ((e & kIdMask) << 2) | (e >> kTypeShift);  // id < 2^30 - 1: never kEmptySlot
+          while (atomicCAS(&H[h], kEmptySlot, ent) != kEmptySlot) h = (h + 1) & (kTriHash - 1);
+          HS[i] = (uint16_t)h;  // du <= kTriHash / 2: i in range
         }
-        for (int32_t i0 = 0; i0 < du; i0 += 64) {
-          // lanes take members w of N+(u); their rows are laid end to end
-          const int32_t i = i0 + lane;
-          int32_t len = 0, rb = 0;
-          uint32_t tuw = 0;
-          if (i < du) {
-            const uint32_t e = G.np_idx[ua + i];
-            const int32_t w = (int32_t)(e & kIdMask);
-            tuw = e >> kTypeShift;
-            rb = G.np_off[w];
-            len = G.np_off[w + 1] - rb;
+        wave_sync();
+      }
+      for (int32_t i0 = 0; i0 < du; i0 += 64) {
+        // lanes take members w of N+(u); their rows are laid end to end
+        const int32_t i = i0 + lane;
+        int32_t len = 0, rb2 = 0;
+        uint32_t tuw = 0;
+        if (i < du) {
+          const uint32_t e = G.np_idx[ua + i];
+          const int32_t w = (int32_t)(e & kIdMask);
+          tuw = e >> kTypeShift;
+          rb2 = G.np_off[w];
+          len = G.np_off[w + 1] - rb2;
+        }
+        int32_t inc = len;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const int32_t tt = __shfl_up(inc, d);
+          if (lane >= d) inc += tt;
+        }
+        const int32_t tot = __shfl(inc, 63);
+        const int32_t rs = rb2 - (inc - len);
+        for (int32_t jb = 0; jb < tot; jb += 64 * kUnroll) {
+          uint32_t fs[kUnroll], ts[kUnroll];
+#pragma unroll
+          for (int uu = 0; uu < kUnroll; ++uu) {
+            const int32_t j = jb + uu * 64 + lane;
+            int32_t sl = 0;
+#pragma unroll
+            for (int st2 = 32; st2; st2 >>= 1)
+              if (__shfl(inc, sl + st2 - 1) <= j) sl += st2;
+            ts[uu] = (uint32_t)__shfl((int32_t)tuw, sl);
+            const int32_t srs = __shfl(rs, sl);
+            fs[uu] = j < tot ? G.np_idx[srs + j] : 0u;
           }
-          int32_t inc = len;
 #pragma unroll
-          for (int d = 1; d < 64; d <<= 1) {
-            const int32_t tt = __shfl_up(inc, d);
-            if (lane >= d) inc += tt;
-          }
-          const int32_t tot = __shfl(inc, 63);
-          const int32_t rs = rb - (inc - len);
-          for (int32_t jb = 0; jb < tot; jb += 64 * kUnroll) {
-            uint32_t fs[kUnroll], ts[kUnroll];
-#pragma unroll
-            for (int uu = 0; uu < kUnroll; ++uu) {
-              const int32_t j = jb + uu * 64 + lane;
-              int32_t sl = 0;
-#pragma unroll
-              for (int st2 = 32; st2; st2 >>= 1)
-                if (__shfl(inc, sl + st2 - 1) <= j) sl += st2;
-              ts[uu] = (uint32_t)__shfl((int32_t)tuw, sl);
-              const int32_t srs = __shfl(rs, sl);
-              fs[uu] = j < tot ? G.np_idx[srs + j] : 0u;
-            }
-#pragma unroll
-            for (int uu = 0; uu < kUnroll; ++uu) {
-              if (jb + uu * 64 + lane >= tot) continue;
-              const uint32_t f = fs[uu], x = f & kIdMask;
-              uint32_t tux = 0;
-              if (hashed) {
-                uint32_t h = (x * 2654435761u) >> (32 - kTriHashBits);
-                for (;;) {
-                  const uint32_t e = H[h];
-                  if (e == kEmptySlot) break;
-                  if ((e >> 2) == x) {
-                    tux = e & 3u;
-                    break;
-                  }
-                  h = (h + 1) & (kTriHash - 1);
+          for (int uu = 0; uu < kUnroll; ++uu) {
+            if (jb + uu * 64 + lane >= tot) continue;
+            const uint32_t f = fs[uu], x = f & kIdMask;
+            uint32_t tux = 0;
+            if (hashed) {
+              uint32_t h = (x * 2654435761u) >> (32 - kTriHashBits);
+              for (;;) {
+                const uint32_t e = H[h];
+                if (e == kEmptySlot) break;
+                if ((e >> 2) == x) {
+                  tux = e & 3u;
+                  break;
                 }
-              } else {
-                int32_t lo = ua, hi = ua + du;
-                while (lo < hi) {
-                  const int32_t mid = (lo + hi) >> 1;
-                  if ((G.np_idx[mid] & kIdMask) < x) lo = mid + 1; else hi = mid;
-                }
-                if (lo < ua + du && (G.np_idx[lo] & kIdMask) == x) tux = G.np_idx[lo] >> kTypeShift;
+                h = (h + 1) & (kTriHash - 1);
               }
-              if (tux) tri(ts[uu], tux, f >> kTypeShift);
+            } else {
+              int32_t lo = ua, hi = ua + du;
+              while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                if ((G.np_idx[mid] & kIdMask) < x) lo = mid + 1; else hi = mid;
+              }
+              if (lo < ua + du && (G.np_idx[lo] & kIdMask) == x) tux = G.np_idx[lo] >> kTypeShift;
             }
+            if (tux) tri(ts[uu], tux, f >> kTypeShift);
           }
         }
-        if (hashed) {
-          wave_sync();
-          for (int32_t i = lane; i < kTriHash; i += 64) H[i] = kEmptySlot;
-          wave_sync();
-        }
       }
-      __syncthreads();
-      v0 = end;
+      if (hashed) {
+        wave_sync();
+        for (int32_t i = lane; i < du; i += 64) H[HS[i]] = kEmptySlot;  // the slots this vertex filled
+        wave_sync();
+      }
     }
   }
-  __syncthreads();
-  hist_flush<C, BLOCK>(hist, acc, cur_g);
+  flush(cur_g);
 }
 
 // Closed form over the non-empty neighbour sets of one anchor: pairs within a
@@ -2248,10 +2248,10 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
   bool marked = false;  // the profiling events bracket the main census kernel only
   if (g.n > 0) {
     if (k == 3) {
-      const int tv = std::min(kTriTileMax, t.tile > 0 ? t.tile * 16 : 256);
       profile_mark(k, 1, true, s);
       marked = true;
-      hipLaunchKernelGGL((k3_kernel<256>), dim3(grid), dim3(256), 0, s, g, T.lut[3], acc, p.status, tv);
+      hipLaunchKernelGGL((k3_kernel<256>), dim3(grid), dim3(256), 0, s, g, T.lut[3], acc, p.status, queue,
+                         std::max(1, t.tile));
     } else {
       const bool reuse = t.heavy == 1;
       const int cap = k == 4 ? label_cap_k4(g.n) : label_cap_k5(g.n);

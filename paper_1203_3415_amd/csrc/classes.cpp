@@ -118,6 +118,42 @@ ClassTable build(int k) {
     size_t i = std::lower_bound(mins.begin(), mins.end(), orbit_min[x]) - mins.begin();
     if (id_of_min_index[i] >= 0) t.lut[x] = (uint16_t)id_of_min_index[i];
   }
+  // Undirected classes: the all-reciprocated directed classes.  Undirected
+  // code of such a class: edge {i, j} at und_bit(k, i, j); its canonical code
+  // is the minimum over all k! relabellings; ids are ranks of the canonical
+  // codes, ascending.
+  std::vector<int> p(k);
+  std::vector<uint32_t> und_code(t.canon.size(), 0);
+  std::vector<char> symmetric(t.canon.size(), 0);
+  for (size_t c = 0; c < t.canon.size(); ++c) {
+    const uint32_t x = t.canon[c];
+    bool sym = true;
+    for (int i = 0; i < k && sym; ++i)
+      for (int j = 0; j < k; ++j)
+        if (i != j && ((x >> code_bit(k, i, j)) & 1u) != ((x >> code_bit(k, j, i)) & 1u)) sym = false;
+    if (!sym) continue;
+    symmetric[c] = 1;
+    uint32_t best = UINT32_MAX;
+    for (int i = 0; i < k; ++i) p[i] = i;
+    do {
+      uint32_t u = 0;
+      for (int i = 0; i < k; ++i)
+        for (int j = i + 1; j < k; ++j)
+          if ((x >> code_bit(k, i, j)) & 1u) {
+            const int a = std::min(p[i], p[j]), b2 = std::max(p[i], p[j]);
+            u |= 1u << und_bit(k, a, b2);
+          }
+      best = std::min(best, u);
+    } while (std::next_permutation(p.begin(), p.end()));
+    und_code[c] = best;
+    t.und_canon.push_back(best);
+  }
+  std::sort(t.und_canon.begin(), t.und_canon.end());
+  t.und_of.assign(t.canon.size(), -1);
+  for (size_t c = 0; c < t.canon.size(); ++c)
+    if (symmetric[c])
+      t.und_of[c] = (int16_t)(std::lower_bound(t.und_canon.begin(), t.und_canon.end(), und_code[c]) -
+                              t.und_canon.begin());
   return t;
 }
 

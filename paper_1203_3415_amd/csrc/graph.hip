@@ -587,6 +587,56 @@ void enqueue_status_out(int32_t* dst, const int32_t* st, hipStream_t s) {
   hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, s, dst, st);
 }
 
+namespace {
+// Undirected census: every G* entry and every N+ entry becomes type A
+// (bidirected), so the directed census of the result is the census of the
+// undirected version G* with each edge read as a pair of arcs.
+__global__ void k_all_bidirected(const int32_t* gs_off, uint32_t* gs_idx, const int32_t* np_off, uint32_t* np_idx,
+                                 int32_t n, const int32_t* st) {
+  if (st[kStatus] != 0) return;
+  const int64_t ng = gs_off[n], nn = np_off[n];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ng; i += (int64_t)gridDim.x * blockDim.x) {
+    gs_idx[i] |= 3u << kTypeShift;
+    if (i < nn) np_idx[i] |= 3u << kTypeShift;
+  }
+}
+
+// out[u] = sum of dir[c] over the directed classes c of undirected class u;
+// a count in a class with a one-way arc is impossible after the override
+// and is reported as a self-check failure (nothing written then).
+__global__ void k_project_undirected(const uint64_t* dir, const int16_t* und_of, int32_t C, int32_t U, uint64_t* out,
+                                     int32_t* st) {
+  __shared__ unsigned long long acc[32];
+  __shared__ int32_t bad;
+  if (st[kStatus] != 0) return;
+  if (threadIdx.x < 32) acc[threadIdx.x] = 0;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int32_t c = threadIdx.x; c < C; c += blockDim.x) {
+    const uint64_t v = dir[c];
+    if (!v) continue;
+    if (und_of[c] < 0) bad = 1;
+    else atomicAdd(&acc[und_of[c]], (unsigned long long)v);
+  }
+  __syncthreads();
+  if (bad) {
+    if (threadIdx.x == 0) atomicMin(&st[kStatus], MOTIF_EINTERNAL);
+    return;
+  }
+  if (threadIdx.x < U) out[threadIdx.x] = acc[threadIdx.x];
+}
+}  // namespace
+
+void enqueue_all_bidirected(const DevGraph& g, hipStream_t s, const int32_t* st) {
+  hipLaunchKernelGGL(k_all_bidirected, dim3(grid_for(g.gs_cap)), dim3(kB), 0, s, g.gs_off,
+                     const_cast<uint32_t*>(g.gs_idx), g.np_off, const_cast<uint32_t*>(g.np_idx), g.n, st);
+}
+
+void enqueue_project_undirected(const uint64_t* dir, const int16_t* und_of, int32_t C, int32_t U, uint64_t* out,
+                                int32_t* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_project_undirected, dim3(1), dim3(1024), 0, s, dir, und_of, C, U, out, st);
+}
+
 size_t build_bytes(int64_t N, int64_t M, int32_t G, bool batch) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   size_t b = 0;

@@ -49,6 +49,7 @@ struct DevGraph {
 struct DevTables {
   const uint16_t* lut[6] = {};   // index k
   const uint8_t* mult[6] = {};
+  const int16_t* und_of[6] = {};  // undirected class of each directed class, -1 if an arc is one-way
 };
 const DevTables& dev_tables();
 
@@ -159,6 +160,11 @@ BuildInput enqueue_pack(Pipeline& p, const motif_graph_t* graphs, int32_t count,
 void enqueue_zero(void* ptr, size_t bytes, hipStream_t s);
 // dst[0] = st[kStatus], stream-ordered (a kernel).
 void enqueue_status_out(int32_t* dst, const int32_t* st, hipStream_t s);
+// Undirected census: every entry of the built G* and N+ becomes type A; then
+// the directed class totals dir[C] are summed into the U undirected classes.
+void enqueue_all_bidirected(const DevGraph& g, hipStream_t s, const int32_t* st);
+void enqueue_project_undirected(const uint64_t* dir, const int16_t* und_of, int32_t C, int32_t U, uint64_t* out,
+                                int32_t* st, hipStream_t s);
 
 // In-place exclusive scan of int32 data[0..len) on the device; `scratch`
 // holds scan_scratch(len) ints.

@@ -14,6 +14,9 @@ defined by the oracle's canonical-code numbering):
   these same workloads (tests/test_method_ref.py), which are "esu" goldens.
   k = 4 method goldens also store the undirected skeleton counts of
   Algorithm "und4" (oracle.undirected4), an independent projection check.
+* "esu_undirected" / "method_ref_undirected": the undirected census of the
+  graph's undirected version (oracle.census_undirected), its directed
+  census of the symmetric digraph taken by ESU or by the method reference.
 
 Nothing here calls the GPU library.
 """
@@ -47,6 +50,10 @@ RECIPES = {
                              "method_ref"),
     "chunglu_n2e4_m1e5_k5": (CL, dict(n=20_000, m=100_000, gamma_out=2.2, gamma_in=2.5, r=0.1, seed=4), 5,
                              "method_ref"),
+    # undirected censuses (21 classes for k = 5) of the same workloads' undirected versions
+    "chunglu_n2e4_m1e5_und5": (CL, dict(n=20_000, m=100_000, gamma_out=2.2, gamma_in=2.5, r=0.1, seed=4), 5,
+                               "method_ref_undirected"),
+    "gnm_n1000_und5": ("gnm_reciprocal", dict(n=1000, m0=5000, frac=0.1, seed=1), 5, "esu_undirected"),
 }
 
 
@@ -59,7 +66,12 @@ def make(name, threads=0):
     gen, kw, k, route = RECIPES[name]
     g = getattr(gg, gen)(**kw)
     t = time.time()
-    h = oracle.census(g, k, threads=threads) if route == "esu" else oracle.method_census(g, k, threads=threads)
+    if route == "esu":
+        h = oracle.census(g, k, threads=threads)
+    elif route == "method_ref":
+        h = oracle.method_census(g, k, threads=threads)
+    else:  # undirected census (classes of oracle.undirected_class_table)
+        h = oracle.census_undirected(g, k, threads=threads, method=route == "method_ref_undirected")
     dt = time.time() - t
     out = {"name": name, "generator": gen, "params": kw, "k": k, "n": g.n, "m": g.m, "sha256": g.sha256(),
            "route": route, "oracle_seconds": round(dt, 1), "total": int(h.sum()),

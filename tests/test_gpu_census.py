@@ -461,3 +461,24 @@ def test_census_of_network_files(pm, k, tmp_path):
         h = gg.Digraph(n, off, idx)
         print(f"[case] network file {os.path.basename(p)} n={n} m={h.m} k={k}", flush=True)
         assert_parity(pm, h, k, os.path.basename(p))
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_undirected_census(pm, k):
+    # the undirected version of each graph, by the oracle's ESU on it
+    rng = np.random.default_rng(70 + k)
+    graphs = [gg.random_small(int(rng.integers(k, 20)), float(rng.uniform(0.1, 0.6)), float(rng.uniform(0, 1)),
+                              seed=7100 + 10 * k + t) for t in range(8)]
+    graphs += [gg.chung_lu(300 if k < 5 else 120, 1200 if k < 5 else 400, 2.2, 2.4, 0.2, seed=72 + k),
+               gg.star(3, 4, 2), gg.complete_digraph(7), gg.from_arcs(5, [])]
+    for t, g in enumerate(graphs):
+        off, idx = _dev(pm, g.out_off, g.out_idx)
+        print(f"[case] undirected k={k} graph {t} n={g.n} m={g.m}", flush=True)
+        got = pm.census_undirected(off, idx, g.n, k)
+        assert np.array_equal(got, oracle.census_undirected(g, k)), t
+    # an undirected graph listed with each edge once or in both directions
+    g = gg.chung_lu(200, 700, 2.3, 2.3, 0.0, seed=75)
+    both = gg.from_arcs(g.n, np.unique(np.concatenate([g.arcs(), g.arcs()[:, ::-1]]), axis=0))
+    o1, i1 = _dev(pm, g.out_off, g.out_idx)
+    o2, i2 = _dev(pm, both.out_off, both.out_idx)
+    assert np.array_equal(pm.census_undirected(o1, i1, g.n, k), pm.census_undirected(o2, i2, both.n, k))

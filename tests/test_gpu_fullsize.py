@@ -48,7 +48,9 @@ def _golden(name):
     if not os.path.exists(path):
         pytest.skip(f"golden {name} not generated")
     d = json.load(open(path))
-    h = np.zeros(oracle.N_CLASSES[d["k"]], np.uint64)
+    undirected = d.get("route", "esu").endswith("_undirected")
+    size = len(oracle.undirected_class_table(d["k"])[0]) if undirected else oracle.N_CLASSES[d["k"]]
+    h = np.zeros(size, np.uint64)
     for c, v in d["hist"].items():
         h[int(c)] = v
     key = (d["generator"], json.dumps(d["params"], sort_keys=True))
@@ -121,6 +123,26 @@ def test_per_anchor_kernels_at_full_size(pm, name):
     finally:
         pm.set_tuning(k, **saved)
     assert np.array_equal(got, want), _diff(got, want)
+
+
+def test_undirected_census_at_full_size(pm):
+    # k = 4: the bench graph's undirected version against Algorithm "und4" /
+    # Table "ept" (stored with the k = 4 golden); k = 5: the n = 2e4 graph
+    # against the method reference on its symmetric version; k = 5 on the
+    # n = 1e3 graph against ESU.
+    g, _, _, d4 = _golden("chunglu_n1e5_m1e6_k4")
+    off, idx = pm.to_device(g.out_off, g.out_idx)
+    print("[case] undirected k=4 n=1e5", flush=True)
+    h = pm.census_undirected(off, idx, g.n, 4)
+    canon = oracle.undirected_class_table(4)[0]
+    name = {7: "claw", 13: "P4", 15: "tailed_triangle", 30: "C4", 31: "diamond", 63: "K4"}
+    assert {name[int(c)]: int(h[i]) for i, c in enumerate(canon)} == d4["undirected4"]
+    for gname in ("chunglu_n2e4_m1e5_und5", "gnm_n1000_und5"):
+        g, k, want, _ = _golden(gname)
+        off, idx = pm.to_device(g.out_off, g.out_idx)
+        print(f"[case] undirected {gname}", flush=True)
+        got = pm.census_undirected(off, idx, g.n, k)
+        assert np.array_equal(got, want), _diff(got, want)
 
 
 def test_bench_graph_k4_invariants(pm):
