@@ -167,6 +167,21 @@ def kr5_kernel_bytes(st) -> float:
     return pairs - inter + core - shared
 
 
+def k5_method_bytes(st) -> float:
+    """The survey's per-anchor byte model for k = 5 (the paper's method, one
+    connected triple at a time): per triple (a, b, c) its three rows and the
+    N+ rows of adj(T): 4 (d_a + d_b + d_c) + 4 sum over x in N(a), N(b), N(c)
+    of d+(x).  Neighbourhood overlaps are not subtracted, so this is an upper
+    estimate; triples are counted at their centre (a triangle three times)."""
+    import scipy.sparse as sp
+    n, u, v = st["n"], st["u"], st["v"]
+    deg = st["deg"].astype(np.float64)
+    A = sp.csr_matrix((np.ones(2 * len(u)), (np.r_[u, v], np.r_[v, u])), shape=(n, n))
+    f = 4.0 * deg + 4.0 * st["splus"]
+    pairs = deg * (deg - 1.0) / 2.0
+    return float((pairs * f + (deg - 1.0) * (A @ f)).sum())
+
+
 def k3_kernel_bytes(st) -> float:
     """Algorithmic bytes of one k = 3 census kernel launch: every typed G*
     entry with its row index (8 B, type counts), and per vertex u its row
@@ -233,6 +248,15 @@ def bench_census(args):
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(kname, args.workload),
                     "kernel": kname, "kernel_ms": round(kms, 3), "algorithmic_bytes": kbytes}
+        # The survey's per-anchor byte model (what the paper's method, one
+        # anchor at a time, must read).  The core-reuse kernel reads far fewer
+        # bytes than that, from a working set that sits in the caches, so the
+        # model's rate can exceed the HBM peak: it is reported beside the
+        # kernel's own floor, and the counters below say what binds.
+        method = {4: k4_kernel_bytes, 5: k5_method_bytes, 3: k3_kernel_bytes}[dominant](st)
+        roofline["method_model_bytes"] = method
+        roofline["method_model_frac"] = round(method / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)
+        roofline["binding"] = stored_counters(kname, args.workload)
     if args.calibration_copy_mib > 0:  # a copy of known size for the counter runs
         a = torch.empty(args.calibration_copy_mib << 18, dtype=torch.float32, device=dev)
         torch.empty_like(a).copy_(a)
@@ -337,6 +361,68 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, kname: str, workload: 
            "census_src_sha256": _src_digest()}
     os.makedirs(TRAFFIC_DIR, exist_ok=True)
     with open(_traffic_file(kname, workload), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+def _counters_file(kname: str, workload: str) -> str:
+    safe = kname.replace("<", "").replace(">", "")
+    return os.path.join(TRAFFIC_DIR, f"counters_{safe}_{workload}.json")
+
+
+def stored_counters(kname: str, workload: str):
+    """Occupancy, issue and cache figures of the kernel from the committed
+    counter runs (see counters_from_csv), or None when there are none or the
+    census kernels changed since they were taken."""
+    path = _counters_file(kname, workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("census_src_sha256") != _src_digest():
+        return None
+    return rec["derived"]
+
+
+def counters_from_csv(dirs: dict, kname: str, workload: str):
+    """Per-launch averages of the kernel's counters from rocprofv3 --pmc csv
+    runs (dirs: pass name -> counter_collection.csv), and the figures derived
+    from them: L2 hit rate, the fractions of resident wave-cycles issuing
+    VALU / LDS / vector-memory instructions or waiting, LDS bank conflicts."""
+    import csv
+    stem, kk = kname.split("<")[0], kname[len(kname.split("<")[0]):]
+    vals = {}
+    for _, path in dirs.items():
+        per = {}
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"]
+            if not ((f"{stem}<{kk[1:-1]}," in name) if kk else (f"{stem}<" in name)):
+                continue
+            key = (r["Counter_Name"], r["Dispatch_Id"])
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        by = {}
+        for (cn, _), v in per.items():
+            by.setdefault(cn, []).append(v)
+        for cn, vs in by.items():
+            vals[cn] = float(np.mean(vs))
+    d = {}
+    if "TCC_HIT_sum" in vals and "TCC_MISS_sum" in vals:
+        d["l2_hit_rate"] = round(vals["TCC_HIT_sum"] / max(1.0, vals["TCC_HIT_sum"] + vals["TCC_MISS_sum"]), 3)
+    if vals.get("SQ_WAVE_CYCLES", 0) > 0:
+        # each SQ_ACTIVE_INST_* and SQ_WAIT_INST_ANY count wave-cycles like
+        # SQ_WAVE_CYCLES, so their ratios are the fractions of the resident
+        # waves' time spent issuing that kind of instruction, or waiting
+        wc = vals["SQ_WAVE_CYCLES"]
+        for cn, nm in (("SQ_ACTIVE_INST_VALU", "valu_issue_frac"), ("SQ_ACTIVE_INST_LDS", "lds_issue_frac"),
+                       ("SQ_ACTIVE_INST_VMEM", "vmem_issue_frac"), ("SQ_WAIT_INST_ANY", "wait_frac")):
+            if cn in vals:
+                d[nm] = round(vals[cn] / wc, 3)
+    if "SQ_INSTS_LDS" in vals and "SQ_LDS_BANK_CONFLICT" in vals:
+        d["lds_bank_conflict_cycles_per_lds_inst"] = round(vals["SQ_LDS_BANK_CONFLICT"] / max(1.0, vals["SQ_INSTS_LDS"]), 3)
+    rec = {"kernel": kname, "workload": workload, "counters_per_launch": vals, "derived": d,
+           "census_src_sha256": _src_digest()}
+    os.makedirs(TRAFFIC_DIR, exist_ok=True)
+    with open(_counters_file(kname, workload), "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
 
@@ -589,7 +675,7 @@ def bench_serving(args):
     import paper_1203_3415_amd as pm
 
     t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as p:
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as p:  # workers touch no GPU
         pool = p.starmap(_serving_graph, [(j, args.serve_log_m_max) for j in range(args.pool)])
     print(f"[serving] pool of {len(pool)} graphs generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
           flush=True)
@@ -697,8 +783,13 @@ def main():
                     help="after the timed steps, copy this many MiB on the device (reference for HBM counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU: turn two rocprofv3 --pmc csv files into the stored traffic record")
-    ap.add_argument("--kernel", default="kr_kernel<4>", help="kernel of --traffic-from")
+    ap.add_argument("--kernel", default="kr_kernel<4>", help="kernel of --traffic-from / --counters-from")
+    ap.add_argument("--counters-from", nargs="+", metavar="CSV",
+                    help="no GPU: turn rocprofv3 --pmc csv files into the stored counter record")
     args = ap.parse_args()
+    if args.counters_from:
+        counters_from_csv({str(i): p for i, p in enumerate(args.counters_from)}, args.kernel, args.workload)
+        return
     if args.traffic_from:
         traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.kernel, args.workload,
                               args.calibration_copy_mib)

@@ -55,8 +55,11 @@ int32_t g_init_err = 0;
 TuningSet g_tuning = {{
     {256, 4, 16, 1}, {256, 4, 16, 1}, {256, 4, 16, 1},
     {256, 4, 16, 1},    // k = 3: tile*16 vertices per tile (at most 1024)
-    {1024, 1, 3, 1},    // k = 4: core reuse (tile = cost tiles per workgroup)
-    {1024, 1, 64, 1},   // k = 5: core reuse (tile = cost tiles per workgroup)
+    // k = 4: core reuse (tile = cost tiles per workgroup); solo / light limits
+    // from a sweep on the n = 1e5, m = 1e6 workload
+    {1024, 1, 4, 1, 48, 224, 512},
+    // k = 5: core reuse, light-partner limit from a sweep on the n = 2e4 workload
+    {1024, 1, 128, 1, 64, 192, 384},
 }};
 
 int32_t current_device(int* dev) {
@@ -155,6 +158,27 @@ int32_t get_pipeline(int dev, hipStream_t s, size_t bytes, Pipeline** out) {
   }
   p->arena.reset();
   *out = p;
+  return 0;
+}
+
+// Grow the pipeline's zeroed W-row pool to at least `bytes` (see
+// Pipeline::wpool); waits for the stream before replacing an old pool.
+int32_t ensure_wpool(Pipeline* p, hipStream_t s, size_t bytes) {
+  if (bytes == 0 || p->wpool_bytes >= bytes) return 0;
+  if (p->wpool) {
+    (void)hipStreamSynchronize(s);  // a failure here shows up as a failed allocation below
+    (void)hipFree(p->wpool);
+    p->wpool = nullptr;
+    p->wpool_bytes = 0;
+  }
+  void* w = nullptr;
+  if (hipMalloc(&w, bytes) != hipSuccess) return 0;  // the census then takes its W rows from the arena
+  if (hipMemsetAsync(w, 0, bytes, s) != hipSuccess) {
+    (void)hipFree(w);
+    return 0;
+  }
+  p->wpool = static_cast<uint32_t*>(w);
+  p->wpool_bytes = bytes;
   return 0;
 }
 
@@ -327,7 +351,7 @@ int32_t run_census_on(Pipeline& p, const BuildInput& in, int32_t k, uint64_t* hi
     DevGraph g = enqueue_build(p, in, s);
     profile_mark(k, 0, false, s);
     uint64_t* acc = p.arena.take<uint64_t>((size_t)in.ngraphs * C);
-    enqueue_census(p, g, k, acc, hist, s);
+    enqueue_census(p, g, k, acc, hist, s, true);
   } catch (const WorkspaceError&) {
     return drain_after_error(p, s);
   }
@@ -365,14 +389,20 @@ int32_t run_census_multi_enqueue(Pipeline& p, const BuildInput& in, int32_t nk, 
       return MOTIF_EDEVICE;
   }
   uint64_t* acc = p.arena.take<uint64_t>((size_t)in.ngraphs * motif_num_classes(ks[top]));
-  enqueue_census(p, g, ks[top], acc, hists[top], s);
+  enqueue_census(p, g, ks[top], acc, hists[top], s, true);
+  uint64_t* side_acc[3] = {};  // nk <= 3 (checked by the entry point)
   for (int32_t i = 0; i < nk; ++i) {
     if (i == top) continue;
-    uint64_t* a = p.arena.take<uint64_t>((size_t)in.ngraphs * motif_num_classes(ks[i]));
-    enqueue_census(p, g, ks[i], a, hists[i], p.side);
+    side_acc[i] = p.arena.take<uint64_t>((size_t)in.ngraphs * motif_num_classes(ks[i]));
+    enqueue_census(p, g, ks[i], side_acc[i], nullptr, p.side, false);
   }
   if (nk > 1 && (hipEventRecord(p.ev_join, p.side) != hipSuccess || hipStreamWaitEvent(s, p.ev_join, 0) != hipSuccess))
     return MOTIF_EDEVICE;
+  // The side censuses' divisions run after the join, on the caller's stream:
+  // launched on the side stream they would wait for compute units that the
+  // largest census holds until its end.
+  for (int32_t i = 0; i < nk; ++i)
+    if (i != top) enqueue_finalise(p, ks[i], in.ngraphs, side_acc[i], hists[i], s);
   return read_status(p, s);
 }
 
@@ -385,6 +415,7 @@ int32_t run_census(const BuildInput& in, int32_t k, uint64_t* hist, hipStream_t 
   rc = get_pipeline(dev, s, pipeline_bytes(in.n, in.m, in.ngraphs, false, k, device_cus(dev), in.n, tune.k[k]), &p);
   if (rc) return rc;
   p->tune = tune;
+  ensure_wpool(p, s, w_slice_bytes(k, in.n, tune.k[k], device_cus(dev)));
   return run_census_on(*p, in, k, hist, s);
 }
 
@@ -419,6 +450,7 @@ int32_t census_batch_with(const motif_graph_t* graphs, int32_t count, int32_t k,
                     pipeline_bytes(voff[count], aoff[count], count, true, k, device_cus(dev), maxn, tune.k[k]), &p);
   if (rc) return rc;
   p->tune = tune;
+  ensure_wpool(p, s, w_slice_bytes(k, maxn, tune.k[k], device_cus(dev)));
   try {
     p->arena.reset();
     enqueue_zero(p->status, sizeof(int32_t) * kStatusWords, s);
@@ -431,7 +463,7 @@ int32_t census_batch_with(const motif_graph_t* graphs, int32_t count, int32_t k,
     DevGraph g = enqueue_build(*p, in, s);
     profile_mark(k, 0, false, s);
     uint64_t* acc = p->arena.take<uint64_t>((size_t)count * C);
-    enqueue_census(*p, g, k, acc, hists, s);
+    enqueue_census(*p, g, k, acc, hists, s, true);
   } catch (const WorkspaceError&) {
     return drain_after_error(*p, s);
   }
@@ -462,6 +494,7 @@ int32_t motif_shutdown(void) {
       if (pp.second->ev_fork) (void)hipEventDestroy(pp.second->ev_fork);
       if (pp.second->ev_join) (void)hipEventDestroy(pp.second->ev_join);
       if (pp.second->arena.base) (void)hipFree(pp.second->arena.base);
+      if (pp.second->wpool) (void)hipFree(pp.second->wpool);
       if (pp.second->status) (void)hipFree(pp.second->status);
       if (pp.second->host_status) (void)hipHostFree(pp.second->host_status);
       delete pp.second;
@@ -586,6 +619,7 @@ int32_t motif_census_async(const int32_t* out_off, const int32_t* out_idx, const
   rc = get_pipeline(dev, s, pipeline_bytes(n, m, 1, false, k, device_cus(dev), n, tune.k[k]), &p);
   if (rc) return rc;
   p->tune = tune;
+  ensure_wpool(p, s, w_slice_bytes(k, n, tune.k[k], device_cus(dev)));
   BuildInput in{};
   in.out_off = out_off;
   in.out_idx = out_idx;
@@ -603,7 +637,7 @@ int32_t motif_census_async(const int32_t* out_off, const int32_t* out_idx, const
       DevGraph g = enqueue_build(*p, in, s);
       profile_mark(k, 0, false, s);
       uint64_t* acc = p->arena.take<uint64_t>((size_t)motif_num_classes(k));
-      enqueue_census(*p, g, k, acc, hist, s);
+      enqueue_census(*p, g, k, acc, hist, s, true);
     }
     enqueue_status_out(status, p->status, s);
   } catch (const WorkspaceError&) {
@@ -690,6 +724,7 @@ int32_t motif_census_undirected(const int32_t* out_off, const int32_t* out_idx, 
   rc = get_pipeline(dev, s, pipeline_bytes(n, m, 1, false, k, device_cus(dev), n, tune.k[k]), &p);
   if (rc) return rc;
   p->tune = tune;
+  ensure_wpool(p, s, w_slice_bytes(k, n, tune.k[k], device_cus(dev)));
   BuildInput in{};
   in.out_off = out_off;
   in.out_idx = out_idx;
@@ -704,7 +739,7 @@ int32_t motif_census_undirected(const int32_t* out_off, const int32_t* out_idx, 
     profile_mark(k, 0, false, s);
     uint64_t* acc = p->arena.take<uint64_t>((size_t)C);
     uint64_t* dir = p->arena.take<uint64_t>((size_t)C);
-    enqueue_census(*p, g, k, acc, dir, s);
+    enqueue_census(*p, g, k, acc, dir, s, true);
     enqueue_project_undirected(dir, dev_tables().und_of[k], C, U, hist, p->status, s);
   } catch (const WorkspaceError&) {
     return drain_after_error(*p, s);
@@ -750,6 +785,10 @@ int32_t motif_census_multi(const motif_graph_t* g, int32_t nk, const int32_t* ks
   rc = get_pipeline(dev, s, bytes, &p);
   if (rc) return rc;
   p->tune = tune;
+  int32_t top = 0;  // the largest size runs on `stream` and may use the pool
+  for (int32_t i = 1; i < nk; ++i)
+    if (ks[i] > ks[top]) top = i;
+  ensure_wpool(p, s, w_slice_bytes(ks[top], in.n, tune.k[ks[top]], device_cus(dev)));
   return run_census_multi_on(*p, in, nk, ks, hists, s);
 }
 
@@ -1073,7 +1112,7 @@ bool enqueue_plan(motif_batch_plan* b) {
     BuildInput in = enqueue_pack(b->p, b->graphs, b->count, b->voff, b->aoff, b->stream);
     DevGraph g = enqueue_build(b->p, in, b->stream);
     uint64_t* acc = b->p.arena.take<uint64_t>((size_t)b->count * C);
-    enqueue_census(b->p, g, b->k, acc, b->hists, b->stream);
+    enqueue_census(b->p, g, b->k, acc, b->hists, b->stream, false);
     return !in.copy_error;
   } catch (const WorkspaceError&) {
     return false;

@@ -2234,7 +2234,13 @@ size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int nu
   hipLaunchKernelGGL((k5_kernel<BLOCK, CAP>), dim3(grid), dim3(BLOCK), 0, s, g, T.lut[5], acc, p.status, queue, \
                      glabels, lw, t.tile)
 
-void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64_t* out, hipStream_t s) {
+size_t w_slice_bytes(int k, int64_t maxn, const Tuning& t, int num_cus) {
+  if (!((k == 4 || k == 5) && t.heavy == 1)) return 0;
+  return sizeof(uint32_t) * kBigRow * (size_t)(maxn > 0 ? maxn : 1) * (size_t)grid_size(t, num_cus);
+}
+
+void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64_t* out, hipStream_t s,
+                    bool use_wpool) {
   const DevTables& T = dev_tables();
   const int C = num_classes(k);
   const int64_t total = (int64_t)g.ngraphs * C;
@@ -2281,8 +2287,12 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
       }
       if (reuse) {
         ws = kBigRow * (int64_t)(g.max_graph_n > 0 ? g.max_graph_n : g.n);
-        wg = p.arena.take<uint32_t>((size_t)ws * grid);
-        enqueue_zero(wg, sizeof(uint32_t) * (size_t)ws * grid, s);
+        if (use_wpool && p.wpool && p.wpool_bytes >= sizeof(uint32_t) * (size_t)ws * grid) {
+          wg = p.wpool;  // all zero: every earlier census cleared the rows it used
+        } else {
+          wg = p.arena.take<uint32_t>((size_t)ws * grid);
+          enqueue_zero(wg, sizeof(uint32_t) * (size_t)ws * grid, s);
+        }
         hub_id = p.arena.take<int32_t>(g.n + 1);
         int32_t* hs = p.arena.take<int32_t>(64);
         enqueue_zero(hs, 64 * sizeof(int32_t), s);
@@ -2344,6 +2354,13 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
   }
   if (!marked) profile_mark(k, 1, true, s);
   profile_mark(k, 1, false, s);
+  if (out) enqueue_finalise(p, k, g.ngraphs, acc, out, s);
+}
+
+void enqueue_finalise(Pipeline& p, int k, int32_t ngraphs, const uint64_t* acc, uint64_t* out, hipStream_t s) {
+  const DevTables& T = dev_tables();
+  const int C = num_classes(k);
+  const int64_t total = (int64_t)ngraphs * C;
   hipLaunchKernelGGL(k_div_check, dim3(blocks_for(total, 256)), dim3(256), 0, s, acc, T.mult[k], C, total, p.status);
   hipLaunchKernelGGL(k_div_write, dim3(blocks_for(total, 256)), dim3(256), 0, s, acc, T.mult[k], C, total, out,
                      p.status);

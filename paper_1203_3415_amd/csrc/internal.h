@@ -117,6 +117,12 @@ struct Pipeline {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   TuningSet tune;  // the tuning this call was sized with (set before any enqueue)
+  // Per-workgroup W rows of the k = 4, 5 core-reuse kernels for the census
+  // on this pipeline's own stream: zeroed once when allocated, and left zero
+  // by every census (each core's tear-down clears the rows it touched), so
+  // no call has to clear them.  Null where the W rows come from the arena.
+  uint32_t* wpool = nullptr;
+  size_t wpool_bytes = 0;
 };
 
 // Bytes the arena needs for a union graph of N vertices, M arcs, G graphs
@@ -146,10 +152,16 @@ struct BuildInput {
 DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s);
 
 // Enqueue the census of k into acc[ngraphs * C] (accumulators, zeroed here)
-// and the exact division into out[ngraphs * C] (written only if every
-// remainder is zero).
-void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64_t* out,
-                    hipStream_t s);
+// and, unless out is null, the exact division into out[ngraphs * C] (written
+// only if every remainder is zero).  use_wpool: the W rows may come from
+// p.wpool (only for work on the pipeline's own stream, one census at a time).
+void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64_t* out, hipStream_t s,
+                    bool use_wpool);
+// The exact division alone: out[i] = acc[i] / multiplicity, after a check
+// that every remainder is zero (Fact "correction").
+void enqueue_finalise(Pipeline& p, int k, int32_t ngraphs, const uint64_t* acc, uint64_t* out, hipStream_t s);
+// Bytes of the per-workgroup W rows of a k = 4, 5 core-reuse census (0 otherwise).
+size_t w_slice_bytes(int k, int64_t maxn, const Tuning& t, int num_cus);
 
 // Pack `count` device graphs into one union CSR inside the arena.
 // Host arrays voff/aoff are the prefix sums of n and m.

@@ -58,6 +58,21 @@ __device__ __forceinline__ int32_t row_of(const int32_t* off, int32_t n, int32_t
   return lo;
 }
 
+// Does row [p, pe) of idx hold x?  Eight loads per step, issued together, so a
+// long (hub) row is not a chain of dependent loads.
+__device__ __forceinline__ bool row_has(const int32_t* idx, int32_t p, int32_t pe, int32_t x) {
+  bool hit = false;
+  for (; p + 8 <= pe && !hit; p += 8) {
+    int32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = idx[p + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) hit |= v[u] == x;
+  }
+  for (; p < pe && !hit; ++p) hit = idx[p] == x;
+  return hit;
+}
+
 // Lock words: in LDS plain accesses; in global memory device-scope atomics,
 // which are performed in L2 (the per-CU L1 does not see them).
 template <bool LDS>
@@ -131,9 +146,8 @@ __global__ __launch_bounds__(kSwB) void k_switch(const SwitchGraph* __restrict__
       if (cand && lock_get<LDS>(&lock[a]) == tid && lock_get<LDS>(&lock[c]) == tid) {
         // rows a and c are this proposal's alone until the next barrier
         const int32_t b = idx[i], d = idx[j];
-        bool ok = a != d && c != b && b != d;
-        for (int32_t p = off[a], pe = off[a + 1]; ok && p < pe; ++p) ok = idx[p] != d;
-        for (int32_t p = off[c], pe = off[c + 1]; ok && p < pe; ++p) ok = idx[p] != b;
+        const bool ok = a != d && c != b && b != d && !row_has(idx, off[a], off[a + 1], d) &&
+                        !row_has(idx, off[c], off[c + 1], b);
         if (ok) {
           idx[i] = d;
           idx[j] = b;

@@ -482,3 +482,21 @@ def test_undirected_census(pm, k):
     o1, i1 = _dev(pm, g.out_off, g.out_idx)
     o2, i2 = _dev(pm, both.out_off, both.out_idx)
     assert np.array_equal(pm.census_undirected(o1, i1, g.n, k), pm.census_undirected(o2, i2, both.n, k))
+
+
+def test_w_rows_reused_across_calls(pm):
+    # The W rows of the core-reuse kernels are kept per stream and must be
+    # left all zero by every census: alternate graphs of different sizes and
+    # k on one stream and compare each result with the CPU reference.
+    import torch
+    s = torch.cuda.Stream()
+    a = gg.chung_lu(3000, 20000, 2.1, 2.1, 0.2, seed=91)
+    b = gg.chung_lu(800, 4000, 2.2, 2.3, 0.1, seed=92)
+    want = {(id(a), 4): oracle.method_census(a, 4), (id(b), 4): oracle.method_census(b, 4),
+            (id(b), 5): oracle.method_census(b, 5)}
+    dev = {id(g): _dev(pm, g.out_off, g.out_idx) for g in (a, b)}
+    for rnd, (g, k) in enumerate([(a, 4), (b, 4), (b, 5), (a, 4), (b, 5), (b, 4), (a, 4)]):
+        off, idx = dev[id(g)]
+        print(f"[case] W rows reuse round {rnd} n={g.n} k={k}", flush=True)
+        got = pm.census(off, idx, g.n, k, stream=s)
+        assert np.array_equal(got, want[(id(g), k)]), rnd
