@@ -279,7 +279,45 @@ motif_batch_plan_t* motif_batch_plan_create(const motif_graph_t* graphs, int32_t
 int32_t motif_batch_plan_run(motif_batch_plan_t* plan);
 int32_t motif_batch_plan_destroy(motif_batch_plan_t* plan);
 
+/* ---- motifs of size 6 ------------------------------------------------------ */
+
+/* The paper's method taken to k = 6, its stated extension to larger motifs
+ * (Section "Our approach"): anchors are the connected 4-sets (as edges anchor
+ * k = 4 and connected triples k = 5), each other vertex adjacent to the
+ * anchor is labelled by its types towards the four anchor vertices, label
+ * pairs are counted in closed form and every edge between two labelled
+ * vertices moves one occurrence to its class; a 6-set is seen once per
+ * connected 4-subset that dominates its other two vertices, which the exact
+ * division removes.
+ * Classes: the 1,530,843 weakly connected digraphs on 6 vertices, numbered as
+ * for k <= 5 (arc i->j at bit 5i + (j < i ? j : j - 1) of a 30-bit code,
+ * canonical = minimum over the 720 relabellings, ids = ranks of the
+ * canonical codes).  The class table is built on the device on first use
+ * (a few seconds; it keeps 4 GiB of device memory until motif_shutdown). */
+#define MOTIF_NUM_CLASSES6 1530843
+
+/* Census of the connected 6-sets of a simple digraph (arguments as for
+ * motif_census; hist: device, MOTIF_NUM_CLASSES6 uint64).  Research-grade:
+ * the connected 4-sets are listed first (16 bytes each, device memory), so
+ * the graph's connected 4-sets must number below 2^31; an anchor edge whose
+ * ends have more than 1,024 neighbours in all, or an anchor with more than
+ * 4,096 labelled vertices, returns MOTIF_ETOOBIG.  Waits for the stream.
+ * Errors as for motif_census, plus MOTIF_ETOOBIG and MOTIF_ENOMEM. */
+int32_t motif_census6(const int32_t* out_off, const int32_t* out_idx, const int32_t* in_off, const int32_t* in_idx,
+                      int32_t n, int64_t m, uint64_t* hist, void* stream);
+
+/* Host copies of the k = 6 class table: the canonical code of every class
+ * (codes: host, MOTIF_NUM_CLASSES6 uint32, increasing) and its multiplicity
+ * (mult: host, MOTIF_NUM_CLASSES6 bytes: connected 4-subsets dominating the
+ * other two vertices).  Build the table on the current device if needed. */
+int32_t motif_class6_codes(uint32_t* codes);
+int32_t motif_class6_multiplicities(uint8_t* mult);
+
 /* ---- null-model ensembles on the device ------------------------------------ */
+
+/* flags of the null-model calls */
+#define MOTIF_SWITCH_MUTUAL 1 /* also keep every vertex's numbers of reciprocated,
+                                 one-way-out and one-way-in neighbours        */
 
 /* Degree-preserving randomisation of `count` graphs in place (the random
  * graphs of the paper's significance step (iii), Section "Implementation";
@@ -290,17 +328,27 @@ int32_t motif_batch_plan_destroy(motif_batch_plan_t* plan);
  * to a->d, c->b unless that makes a self-loop or a repeated arc.  Every arc
  * keeps its slot in its source's row, so out_off and all out- and in-degrees
  * are unchanged; rows are left unsorted; in_off/in_idx are ignored (the
- * graph's transpose changes).  Random numbers: SplitMix64 on a counter, one
- * stream per (seed, graph index), so the result depends only on the input,
- * switches_per_arc and seed.  Errors: MOTIF_EINVAL_SHAPE (offsets not
- * monotone from 0 to m), MOTIF_EINVAL_ARG.  Waits for the stream. */
-int32_t motif_null_randomize(const motif_graph_t* graphs, int32_t count, int32_t switches_per_arc,
+ * graph's transpose changes).
+ * flags = MOTIF_SWITCH_MUTUAL: one-way arcs are switched only with one-way
+ * arcs (and only if no arc joins a and d, or c and b, in either direction),
+ * reciprocated pairs only with reciprocated pairs (a<->b, c<->d become
+ * a<->d, c<->b), so the numbers of reciprocated and one-way neighbours of
+ * every vertex are kept as well.  Either way the chain's stationary
+ * distribution is uniform over the graphs it can reach.
+ * The input must be a simple digraph (rows may be unsorted); repeated arcs
+ * are not detected here and leave the result unspecified.
+ * Random numbers: SplitMix64 on a counter, one stream per (seed, graph
+ * index), so the result depends only on the input, switches_per_arc, flags
+ * and seed.  Errors (nothing is rewritten): MOTIF_EINVAL_SHAPE (offsets not
+ * monotone from 0 to m), MOTIF_EINDEX (a target outside [0, n)),
+ * MOTIF_ESELFLOOP, MOTIF_EINVAL_ARG (unknown flags).  Waits for the stream. */
+int32_t motif_null_randomize(const motif_graph_t* graphs, int32_t count, int32_t switches_per_arc, int32_t flags,
                              uint64_t seed, void* stream);
 
 /* The whole null-model job on the device: `count` randomisations of the real
  * graph (device pointers; its in-CSR, if given, is validated for the real
  * graph), each made as by motif_null_randomize(real copy, switches_per_arc,
- * seed; graph i uses stream i of seed), then one fused census of the real
+ * flags, seed; graph i uses stream i of seed), then one fused census of the real
  * graph and its copies (motif_census_batch), then the z-scores.
  *  hists : device, (count + 1) * motif_num_classes(k) uint64; row 0 is the
  *          real graph, row i the i-th randomisation.
@@ -310,7 +358,7 @@ int32_t motif_null_randomize(const motif_graph_t* graphs, int32_t count, int32_t
  * The library keeps a device buffer of count * m int32 per stream for the
  * copies.  Errors as for motif_census() and motif_null_randomize(). */
 int32_t motif_null_model(const motif_graph_t* real, int32_t count, int32_t k, int32_t switches_per_arc,
-                         uint64_t seed, uint64_t* hists, double* z, void* stream);
+                         int32_t flags, uint64_t seed, uint64_t* hists, double* z, void* stream);
 
 /* ---- tuning ---------------------------------------------------------------- */
 

@@ -71,6 +71,10 @@ def _lib():
     lib.mref_census_sample.restype = ctypes.c_int
     lib.mref_undirected4.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int32]
     lib.mref_undirected4.restype = ctypes.c_int
+    lib.oracle_canon6.argtypes = [ctypes.c_uint32]
+    lib.oracle_canon6.restype = ctypes.c_uint32
+    lib.oracle_census6.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, P, P, ctypes.c_int64, P]
+    lib.oracle_census6.restype = ctypes.c_int
     return lib
 
 
@@ -304,3 +308,32 @@ def code_of(k: int, arcs) -> int:
 def class_of(k: int, arcs) -> int:
     """Class id of the k-vertex pattern with these arcs (0xFFFF if disconnected)."""
     return int(class_table(k)[0][code_of(k, arcs)])
+
+
+# ---------------------------------------------------------------- k = 6 --
+# The paper's stated extension to larger motifs (Section "Our approach").
+# 2^30 codes are too many for a class table here, so k = 6 classes are named
+# by their canonical code (minimum over the 720 relabellings).
+
+N_CLASSES6 = 1_530_843  # weakly connected digraphs on 6 vertices
+
+
+def canon6(code: int) -> int:
+    """Canonical code of a 6-vertex code (minimum over all 720 relabellings)."""
+    return int(_lib().oracle_canon6(ctypes.c_uint32(code)))
+
+
+def census6(g, threads: int = 0) -> dict:
+    """Connected 6-sets of the digraph g by ESU, as {canonical code: count}."""
+    cap = N_CLASSES6 + 1
+    codes = np.zeros(cap, np.uint32)
+    counts = np.zeros(cap, np.uint64)
+    nout = np.zeros(1, np.int64)
+    off = np.ascontiguousarray(g.out_off, np.int32)
+    idx = np.ascontiguousarray(g.out_idx, np.int32)
+    rc = _lib().oracle_census6(int(g.n), _ptr(off), _ptr(idx), int(threads), _ptr(codes), _ptr(counts), cap,
+                               _ptr(nout))
+    if rc:
+        raise RuntimeError(f"oracle_census6 failed: {rc}")
+    k = int(nout[0])
+    return {int(c): int(v) for c, v in zip(codes[:k], counts[:k])}

@@ -28,7 +28,14 @@
  * dominate the rest (every vertex outside T is adjacent to a vertex of T).
  * This is the number of anchors -- a vertex for k=3 (v-Patterns), an edge for
  * k=4 (e-Patterns, Fact "correction"), a connected triple for k=5
- * (Delta-Patterns) -- whose pattern set contains the k-set.
+ * (Delta-Patterns), a connected 4-set for k=6 -- whose pattern set contains
+ * the k-set.
+ *
+ * k = 6 (the paper's stated extension to larger motifs, Section "Our
+ * approach"): 2^30 codes are too many for a brute-force class table, so the
+ * k = 6 census (oracle_census6) reports each class by its canonical code
+ * (minimum over the 720 relabellings, computed for each distinct code met,
+ * and remembered), with the number of connected 6-sets of that class.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -148,7 +155,7 @@ int oracle_class_table(int k, uint16_t* cls_of_code, uint32_t* canon_of_class,
 /* Number of (k-2)-subsets of the code's vertices that induce a connected G*
  * and dominate the remaining two vertices. */
 int oracle_multiplicity(int k, uint32_t code) {
-    if (k < 3 || k > 5) return OR_EINVAL;
+    if (k < 3 || k > 6) return OR_EINVAL;
     int adj[8][8] = {{0}};
     for (int i = 0; i < k; ++i)
         for (int j = 0; j < k; ++j)
@@ -177,6 +184,83 @@ int oracle_multiplicity(int k, uint32_t code) {
     return count;
 }
 
+/* ------------------------------------------------ k = 6 canonical codes -- */
+
+/* Relabelling of 30-bit codes one byte at a time: the permuted code is the OR
+ * of the images of its four bytes (each bit is one arc), so tab[p][b][v] =
+ * permute_code(6, v << 8b, perm p) gives the image in four lookups. */
+static uint32_t (*perm6_tab)[4][256] = NULL;
+
+static void perm6_init(void) {
+#pragma omp critical(perm6)
+    if (!perm6_tab) {
+        static int perms[720 * 6];
+        all_perms(6, perms);
+        uint32_t (*t)[4][256] = malloc(sizeof(uint32_t) * 720 * 4 * 256);
+        for (int p = 0; p < 720; ++p)
+            for (int b = 0; b < 4; ++b)
+                for (int v = 0; v < 256; ++v)
+                    t[p][b][v] = ((uint32_t)v << (8 * b)) >> 30 ? 0u
+                                 : permute_code(6, (uint32_t)v << (8 * b), perms + p * 6);
+        perm6_tab = t;
+    }
+}
+
+/* Canonical code of a 6-vertex code: the minimum over all 720 relabellings. */
+uint32_t oracle_canon6(uint32_t code) {
+    if (!perm6_tab) perm6_init();
+    uint32_t best = code;
+    for (int p = 0; p < 720; ++p) {
+        const uint32_t y = perm6_tab[p][0][code & 255u] | perm6_tab[p][1][(code >> 8) & 255u] |
+                           perm6_tab[p][2][(code >> 16) & 255u] | perm6_tab[p][3][code >> 24];
+        if (y < best) best = y;
+    }
+    return best;
+}
+
+/* Open-addressing maps of one thread: code -> canonical code (a cache), and
+ * canonical code -> number of sets.  Keys are codes + 1 (0 = empty). */
+struct map6 {
+    uint32_t* ck; uint32_t* cv; size_t ccap;      /* cache */
+    uint32_t* hk; uint64_t* hv; size_t hcap, hn;  /* counts */
+};
+
+static size_t h6(uint32_t x, size_t cap) { return (size_t)((x * 2654435761u) ^ (x >> 15)) & (cap - 1); }
+
+static void map6_add(struct map6* m, uint32_t canon, uint64_t add) {
+    if (2 * (m->hn + 1) > m->hcap) {  /* grow: rehash into twice the room */
+        size_t cap = m->hcap ? 2 * m->hcap : 1024;
+        uint32_t* k = calloc(cap, sizeof(uint32_t));
+        uint64_t* v = calloc(cap, sizeof(uint64_t));
+        for (size_t i = 0; i < m->hcap; ++i)
+            if (m->hk[i]) {
+                size_t h = h6(m->hk[i], cap);
+                while (k[h]) h = (h + 1) & (cap - 1);
+                k[h] = m->hk[i];
+                v[h] = m->hv[i];
+            }
+        free(m->hk); free(m->hv);
+        m->hk = k; m->hv = v; m->hcap = cap;
+    }
+    size_t h = h6(canon + 1u, m->hcap);
+    while (m->hk[h] && m->hk[h] != canon + 1u) h = (h + 1) & (m->hcap - 1);
+    if (!m->hk[h]) { m->hk[h] = canon + 1u; ++m->hn; }
+    m->hv[h] += add;
+}
+
+static void canon6_count(struct map6* m, uint32_t code) {
+    size_t h = h6(code + 1u, m->ccap);
+    uint32_t canon;
+    if (m->ck[h] == code + 1u) {
+        canon = m->cv[h];
+    } else {  /* a direct-mapped cache: a miss recomputes and replaces */
+        canon = oracle_canon6(code);
+        m->ck[h] = code + 1u;
+        m->cv[h] = canon;
+    }
+    map6_add(m, canon, 1);
+}
+
 /* ---------------------------------------------------------------- ESU ---- */
 
 typedef struct {
@@ -191,6 +275,7 @@ typedef struct {
     double deadline;       /* omp wall-clock deadline, <= 0: none */
     volatile int* stop;    /* set once the deadline has passed */
     uint64_t emitted;
+    struct map6* map6;     /* k = 6: this thread's canonical-code counts */
 } esu_ctx;
 
 static int has_edge_u(const esu_ctx* c, int a, int b) {
@@ -206,15 +291,19 @@ static int has_arc(const esu_ctx* c, int a, int b) {
 }
 
 static void emit(esu_ctx* c, const int* sub) {
-    int k = c->k, v[5];
+    int k = c->k, v[6];
     memcpy(v, sub, sizeof(int) * k);
     for (int i = 1; i < k; ++i) { int t = v[i], j = i - 1; while (j >= 0 && v[j] > t) { v[j + 1] = v[j]; --j; } v[j + 1] = t; }
     uint32_t code = 0;
     for (int i = 0; i < k; ++i)
         for (int j = 0; j < k; ++j)
             if (i != j && has_arc(c, v[i], v[j])) code |= 1u << bitpos(k, i, j);
-    uint16_t cl = c->cls[code];
-    if (cl != 0xFFFF) c->hist[cl] += 1;   /* ESU only emits connected sets */
+    if (c->k == 6) {
+        canon6_count(c->map6, code);
+    } else {
+        uint16_t cl = c->cls[code];
+        if (cl != 0xFFFF) c->hist[cl] += 1;   /* ESU only emits connected sets */
+    }
 #ifdef _OPENMP
     if (c->deadline > 0 && (++c->emitted & 0xFFFF) == 0 && omp_get_wtime() > c->deadline) *c->stop = 1;
 #endif
@@ -261,11 +350,11 @@ static int cmp_i32(const void* a, const void* b) {
  */
 static int census_impl(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32_t k,
                        const uint16_t* cls_of_code, int32_t n_classes, uint64_t* hist, int32_t threads,
-                       const int32_t* roots, int32_t n_roots, double seconds);
+                       const int32_t* roots, int32_t n_roots, double seconds, struct map6* result6);
 
 int oracle_census(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32_t k,
                   const uint16_t* cls_of_code, int32_t n_classes, uint64_t* hist, int32_t threads) {
-    return census_impl(n, out_off, out_idx, k, cls_of_code, n_classes, hist, threads, NULL, n, 0.0);
+    return census_impl(n, out_off, out_idx, k, cls_of_code, n_classes, hist, threads, NULL, n, 0.0, NULL);
 }
 
 /*
@@ -279,7 +368,7 @@ int oracle_census_roots(int32_t n, const int32_t* out_off, const int32_t* out_id
                         const int32_t* roots, int32_t n_roots) {
     for (int32_t i = 0; i < n_roots; ++i)
         if (roots[i] < 0 || roots[i] >= n) return OR_EINVAL;
-    return census_impl(n, out_off, out_idx, k, cls_of_code, n_classes, hist, threads, roots, n_roots, 0.0);
+    return census_impl(n, out_off, out_idx, k, cls_of_code, n_classes, hist, threads, roots, n_roots, 0.0, NULL);
 }
 
 /*
@@ -295,14 +384,14 @@ int oracle_census_timed(int32_t n, const int32_t* out_off, const int32_t* out_id
     for (int32_t i = 0; i < n_roots; ++i)
         if (roots[i] < 0 || roots[i] >= n) return OR_EINVAL;
     return census_impl(n, out_off, out_idx, k, cls_of_code, n_classes, hist, threads, roots, n_roots,
-                       seconds > 0 ? seconds : 1e-9);
+                       seconds > 0 ? seconds : 1e-9, NULL);
 }
 
 static int census_impl(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32_t k,
                        const uint16_t* cls_of_code, int32_t n_classes, uint64_t* hist, int32_t threads,
-                       const int32_t* roots, int32_t n_roots, double seconds) {
-    if (k < 3 || k > 5 || n < 0) return OR_EINVAL;
-    memset(hist, 0, sizeof(uint64_t) * (size_t)n_classes);
+                       const int32_t* roots, int32_t n_roots, double seconds, struct map6* result6) {
+    if (k < 3 || k > 6 || n < 0 || (k == 6) != (result6 != NULL)) return OR_EINVAL;
+    if (hist) memset(hist, 0, sizeof(uint64_t) * (size_t)n_classes);
     if (n == 0) return 0;
     int64_t m = out_off[n];
     int64_t* aoff = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
@@ -338,7 +427,17 @@ static int census_impl(int32_t n, const int32_t* out_off, const int32_t* out_idx
 #ifdef _OPENMP
     nthreads = threads > 0 ? threads : omp_get_max_threads();
 #endif
-    uint64_t* th = (uint64_t*)calloc((size_t)nthreads * (size_t)n_classes, sizeof(uint64_t));
+    uint64_t* th = (uint64_t*)calloc((size_t)nthreads * (size_t)(n_classes > 0 ? n_classes : 1), sizeof(uint64_t));
+    struct map6* maps = NULL;
+    if (k == 6) {
+        perm6_init();
+        maps = (struct map6*)calloc((size_t)nthreads, sizeof(struct map6));
+        for (int t = 0; t < nthreads; ++t) {
+            maps[t].ccap = (size_t)1 << 18;
+            maps[t].ck = (uint32_t*)calloc(maps[t].ccap, sizeof(uint32_t));
+            maps[t].cv = (uint32_t*)calloc(maps[t].ccap, sizeof(uint32_t));
+        }
+    }
     volatile int stop = 0;
     double deadline = 0.0;
 #ifdef _OPENMP
@@ -352,8 +451,9 @@ static int census_impl(int32_t n, const int32_t* out_off, const int32_t* out_idx
         tid = omp_get_thread_num();
 #endif
         if (stop) continue;
-        esu_ctx c = { n, uoff2, uidx, aoff, aidx, k, cls_of_code, th + (size_t)tid * n_classes, deadline, &stop, 0 };
-        int sub[5];
+        esu_ctx c = { n, uoff2, uidx, aoff, aidx, k, cls_of_code, th + (size_t)tid * n_classes, deadline, &stop, 0,
+                      maps ? maps + tid : NULL };
+        int sub[6];
         sub[0] = root;
         int64_t d = uoff2[root + 1] - uoff2[root];
         int* ext = (int*)malloc(sizeof(int) * (size_t)(d + 1));
@@ -363,8 +463,46 @@ static int census_impl(int32_t n, const int32_t* out_off, const int32_t* out_idx
         extend(&c, sub, 1, ext, ne, root);
         free(ext);
     }
-    for (int t = 0; t < nthreads; ++t)
-        for (int cl = 0; cl < n_classes; ++cl) hist[cl] += th[(size_t)t * n_classes + cl];
+    if (k == 6) {
+        for (int t = 0; t < nthreads; ++t) {
+            for (size_t i = 0; i < maps[t].hcap; ++i)
+                if (maps[t].hk[i]) map6_add(result6, maps[t].hk[i] - 1u, maps[t].hv[i]);
+            free(maps[t].ck); free(maps[t].cv); free(maps[t].hk); free(maps[t].hv);
+        }
+        free(maps);
+    } else {
+        for (int t = 0; t < nthreads; ++t)
+            for (int cl = 0; cl < n_classes; ++cl) hist[cl] += th[(size_t)t * n_classes + cl];
+    }
     free(th); free(aoff); free(aidx); free(deg); free(uoff); free(uoff2); free(uidx);
+    return 0;
+}
+
+/*
+ * k = 6 census by canonical code: the connected 6-sets of the digraph, each
+ * found once by ESU, grouped by the canonical code of their induced digraph.
+ * Writes up to max_out (canonical code, count) pairs in increasing code
+ * order and their number to *n_out (OR_ENOMEM if more than max_out classes
+ * occur).
+ */
+static int cmp_pair(const void* a, const void* b) {
+    const uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return x < y ? -1 : x > y;
+}
+
+int oracle_census6(int32_t n, const int32_t* out_off, const int32_t* out_idx, int32_t threads,
+                   uint32_t* codes, uint64_t* counts, int64_t max_out, int64_t* n_out) {
+    struct map6 res = {0};
+    int rc = census_impl(n, out_off, out_idx, 6, NULL, 0, NULL, threads, NULL, n, 0.0, &res);
+    if (rc) { free(res.hk); free(res.hv); return rc; }
+    if ((int64_t)res.hn > max_out) { free(res.hk); free(res.hv); return OR_ENOMEM; }
+    uint64_t* kv = (uint64_t*)malloc(sizeof(uint64_t) * 2 * (res.hn + 1));
+    size_t w = 0;
+    for (size_t i = 0; i < res.hcap; ++i)
+        if (res.hk[i]) { kv[2 * w] = res.hk[i] - 1u; kv[2 * w + 1] = res.hv[i]; ++w; }
+    qsort(kv, w, 2 * sizeof(uint64_t), cmp_pair);
+    for (size_t i = 0; i < w; ++i) { codes[i] = (uint32_t)kv[2 * i]; counts[i] = kv[2 * i + 1]; }
+    *n_out = (int64_t)w;
+    free(kv); free(res.hk); free(res.hv);
     return 0;
 }

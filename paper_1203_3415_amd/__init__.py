@@ -1,4 +1,4 @@
-"""MI355X (gfx950) exact directed motif census for k = 3, 4, 5.
+"""MI355X (gfx950) exact directed motif census for k = 3, 4, 5 (and 6).
 
 Thin Python binding over the C ABI of ``libmotif.so`` (declared in
 ``include/motif.h``).  Every step of the census runs in the library's HIP
@@ -11,6 +11,10 @@ from .binding import (  # noqa: F401
     lib,
     lib_path,
     census,
+    census6,
+    class6_codes,
+    class6_multiplicities,
+    NUM_CLASSES6,
     census_async,
     census_undirected,
     num_undirected_classes,

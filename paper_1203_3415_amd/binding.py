@@ -93,6 +93,9 @@ def lib():
                                     ctypes.POINTER(ctypes.POINTER(I64)), ctypes.POINTER(_ReadStats)], I32),
             "motif_free": ([P], None),
             "motif_census": ([P, P, P, P, I32, I64, I32, P, P], I32),
+            "motif_census6": ([P, P, P, P, I32, I64, P, P], I32),
+            "motif_class6_codes": ([P], I32),
+            "motif_class6_multiplicities": ([P], I32),
             "motif_census_async": ([P, P, P, P, I32, I64, I32, P, P, P], I32),
             "motif_census_noalloc": ([P, P, P, P, I32, I64, I32, P, P], I32),
             "motif_census_batch": ([P, I32, I32, P, P], I32),
@@ -103,8 +106,8 @@ def lib():
             "motif_autotune": ([P, I32, I32, P, P, ctypes.POINTER(_Tuning)], I32),
             "motif_tune_cache_save": ([ctypes.c_char_p], I32),
             "motif_tune_cache_load": ([ctypes.c_char_p], I32),
-            "motif_null_randomize": ([P, I32, I32, ctypes.c_uint64, P], I32),
-            "motif_null_model": ([P, I32, I32, I32, ctypes.c_uint64, P, P, P], I32),
+            "motif_null_randomize": ([P, I32, I32, I32, ctypes.c_uint64, P], I32),
+            "motif_null_model": ([P, I32, I32, I32, I32, ctypes.c_uint64, P, P, P], I32),
             "motif_batch_plan_create": ([P, I32, I32, P, P, ctypes.POINTER(I32)], P),
             "motif_batch_plan_run": ([P], I32),
             "motif_batch_plan_destroy": ([P], I32),
@@ -233,6 +236,38 @@ def census(out_off, out_idx, n: int, k: int, in_off=None, in_idx=None, stream=No
     return hist.cpu().numpy().view(np.uint64)
 
 
+NUM_CLASSES6 = 1_530_843
+
+
+def census6(out_off, out_idx, n: int, in_off=None, in_idx=None, stream=None, out=None):
+    """Census of the connected 6-sets (motif_census6).  Returns numpy uint64
+    [NUM_CLASSES6] (or fills `out`, an int64 CUDA tensor, and returns it)."""
+    torch = _torch()
+    for t, nm in ((out_off, "out_off"), (out_idx, "out_idx"), (in_off, "in_off"), (in_idx, "in_idx")):
+        _check_dev(t, nm)
+    hist = out if out is not None else torch.empty(NUM_CLASSES6, dtype=torch.int64, device=out_off.device)
+    rc = lib().motif_census6(_ptr(out_off), _ptr(out_idx), _ptr(in_off), _ptr(in_idx), int(n),
+                             int(out_idx.numel()), _ptr(hist), _stream_handle(stream))
+    _check(rc, "motif_census6")
+    if out is not None:
+        return out
+    return hist.cpu().numpy().view(np.uint64)
+
+
+def class6_codes() -> np.ndarray:
+    """Canonical code of every k = 6 class (uint32, increasing)."""
+    out = np.zeros(NUM_CLASSES6, np.uint32)
+    _check(lib().motif_class6_codes(out.ctypes.data), "motif_class6_codes")
+    return out
+
+
+def class6_multiplicities() -> np.ndarray:
+    """Anchors per occurrence of every k = 6 class (uint8)."""
+    out = np.zeros(NUM_CLASSES6, np.uint8)
+    _check(lib().motif_class6_multiplicities(out.ctypes.data), "motif_class6_multiplicities")
+    return out
+
+
 NUM_UNDIRECTED_CLASSES = {3: 2, 4: 6, 5: 21}
 
 
@@ -351,20 +386,26 @@ def census_batch_loop(graphs, k: int, stream=None, out=None):
     return census_batch(graphs, k, stream=stream, out=out, loop=True)
 
 
-def null_randomize(graphs, switches_per_arc: int, seed: int, stream=None) -> None:
+SWITCH_MUTUAL = 1
+
+
+def null_randomize(graphs, switches_per_arc: int, seed: int, stream=None, mutual: bool = False) -> None:
     """Randomise device graphs [(out_off, out_idx, n), ...] in place by
     switches_per_arc * m degree-preserving arc switches each (out_idx is
-    rewritten; rows end up unsorted)."""
+    rewritten; rows end up unsorted).  mutual: one-way arcs and reciprocated
+    pairs are switched separately (MOTIF_SWITCH_MUTUAL)."""
     arr = _graph_array([g[:3] for g in graphs])
     _check(lib().motif_null_randomize(ctypes.cast(arr, ctypes.c_void_p), len(graphs), int(switches_per_arc),
-                                      ctypes.c_uint64(seed), _stream_handle(stream)), "motif_null_randomize")
+                                      SWITCH_MUTUAL if mutual else 0, ctypes.c_uint64(seed), _stream_handle(stream)),
+           "motif_null_randomize")
 
 
 def null_model(out_off, out_idx, n: int, count: int, k: int, switches_per_arc: int = 100, seed: int = 0,
-               in_off=None, in_idx=None, stream=None, out=None, z_out=None):
+               in_off=None, in_idx=None, stream=None, out=None, z_out=None, mutual: bool = False):
     """Randomise, census and score on the device: returns (hists, z) as numpy
     (uint64 [count + 1, C], row 0 the real graph; float64 [C]), or fills the
-    CUDA tensors `out` (int64 [count + 1, C]) and `z_out` (float64 [C])."""
+    CUDA tensors `out` (int64 [count + 1, C]) and `z_out` (float64 [C]).
+    mutual: the mutual-preserving switch (MOTIF_SWITCH_MUTUAL)."""
     torch = _torch()
     C = NUM_CLASSES.get(k)
     if C is None:
@@ -373,7 +414,8 @@ def null_model(out_off, out_idx, n: int, count: int, k: int, switches_per_arc: i
     hist = out if out is not None else torch.empty((count + 1, C), dtype=torch.int64, device=out_off.device)
     z = z_out if z_out is not None else torch.empty(C, dtype=torch.float64, device=out_off.device)
     _check(lib().motif_null_model(ctypes.cast(g, ctypes.c_void_p), int(count), int(k), int(switches_per_arc),
-                                  ctypes.c_uint64(seed), _ptr(hist), _ptr(z), _stream_handle(stream)),
+                                  SWITCH_MUTUAL if mutual else 0, ctypes.c_uint64(seed), _ptr(hist), _ptr(z),
+                                  _stream_handle(stream)),
            "motif_null_model")
     if out is not None:
         return out, z

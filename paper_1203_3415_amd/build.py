@@ -13,7 +13,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmotif.so")
-SOURCES = ["classes.cpp", "graph.hip", "census.hip", "nullmodel.hip", "api.cpp", "server.cpp", "ingest.cpp"]
+SOURCES = ["classes.cpp", "graph.hip", "census.hip", "census6.hip", "nullmodel.hip", "api.cpp", "server.cpp",
+           "ingest.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -46,6 +46,9 @@ struct DeviceState {
   std::map<TuneKey, Tuning> tuned;  // filled by motif_autotune / motif_tune_cache_load
   // per-stream buffer of the randomised copies made by motif_null_model
   std::map<hipStream_t, std::pair<int32_t*, size_t>> null_copies;
+  // k = 6 class table, built on first use; t6_rc: 1 = not built yet, else its outcome
+  Tables6 t6;
+  int32_t t6_rc = 1;
 };
 
 std::map<int, DeviceState> g_dev;
@@ -489,6 +492,7 @@ int32_t motif_shutdown(void) {
     for (void* ptr : kv.second.owned) (void)hipFree(ptr);
     if (kv.second.scratch_host) (void)hipHostFree(kv.second.scratch_host);
     for (auto& nc : kv.second.null_copies) (void)hipFree(nc.second.first);
+    free_tables6(&kv.second.t6);
     for (auto& pp : kv.second.pipes) {
       if (pp.second->side) (void)hipStreamDestroy(pp.second->side);
       if (pp.second->ev_fork) (void)hipEventDestroy(pp.second->ev_fork);
@@ -601,6 +605,115 @@ int32_t motif_census(const int32_t* out_off, const int32_t* out_idx, const int32
   in.n = n;
   in.m = m;
   return run_census(in, k, hist, s);
+}
+
+// ---- k = 6 ----
+
+// The k = 6 class table of device dev (current), built once.
+static int32_t ensure_tables6(int dev, const Tables6** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceState& d = g_dev[dev];
+  if (d.t6_rc == 1) d.t6_rc = build_tables6(&d.t6);
+  if (d.t6_rc) return d.t6_rc;
+  *out = &d.t6;
+  return 0;
+}
+
+int32_t motif_census6(const int32_t* out_off, const int32_t* out_idx, const int32_t* in_off, const int32_t* in_idx,
+                      int32_t n, int64_t m, uint64_t* hist, void* stream) {
+  if (!check_shape(n, m) || (n == 0 && m != 0)) return MOTIF_EINVAL_SHAPE;
+  if (!hist || !out_off || (m > 0 && !out_idx)) return MOTIF_EINVAL_ARG;
+  if (in_off && m > 0 && !in_idx) return MOTIF_EINVAL_ARG;
+  int dev;
+  if (int32_t rc = ensure_init(&dev)) return rc;
+  const Tables6* T = nullptr;
+  if (int32_t rc = ensure_tables6(dev, &T)) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (n == 0) {
+    enqueue_zero(hist, sizeof(uint64_t) * kClasses6, s);
+    return hipStreamSynchronize(s) == hipSuccess ? 0 : MOTIF_EDEVICE;
+  }
+  BuildInput in{};
+  in.out_off = out_off;
+  in.out_idx = out_idx;
+  in.in_off = in_off;
+  in.in_idx = in_off ? in_idx : nullptr;
+  in.n = n;
+  in.m = m;
+  const int cus = device_cus(dev);
+  Pipeline* p = nullptr;
+  if (int32_t rc = get_pipeline(dev, s, build_bytes(n, m, 1, false), &p)) return rc;
+  DevGraph g;
+  try {
+    p->arena.reset();
+    enqueue_zero(p->status, sizeof(int32_t) * kStatusWords, s);
+    g = enqueue_build(*p, in, s);
+  } catch (const WorkspaceError&) {
+    return drain_after_error(*p, s);
+  }
+  if (int32_t rc = read_status(*p, s)) return rc;
+  // the anchors: counted, then listed (each connected 4-set once)
+  unsigned long long* ctr = nullptr;
+  int4* anchors = nullptr;
+  uint64_t* acc = nullptr;
+  uint32_t* labels = nullptr;
+  int32_t rc = 0;
+  const int grid = 2 * cus;
+  const int64_t label_words = ((int64_t)n + 3) / 4;
+  do {
+    unsigned long long host_ctr[2] = {0, 0};
+    if (hipMalloc(&ctr, sizeof(host_ctr)) != hipSuccess) { rc = MOTIF_ENOMEM; break; }
+    enqueue_zero(ctr, sizeof(host_ctr), s);
+    if ((rc = enqueue_anchors6(g, nullptr, ctr, 0, false, cus, p->status, s))) break;
+    if (hipMemcpyAsync(host_ctr, ctr, sizeof(host_ctr), hipMemcpyDeviceToHost, s) != hipSuccess) {
+      rc = MOTIF_EDEVICE;
+      break;
+    }
+    if ((rc = read_status(*p, s))) break;  // also waits for the count
+    const unsigned long long na = host_ctr[1];
+    if (na >= (1ull << 31)) { rc = MOTIF_ETOOBIG; break; }
+    if (hipMalloc(&acc, sizeof(uint64_t) * kClasses6) != hipSuccess ||
+        hipMalloc(&labels, sizeof(uint32_t) * (size_t)grid * (size_t)label_words) != hipSuccess ||
+        (na > 0 && hipMalloc(&anchors, sizeof(int4) * na) != hipSuccess)) {
+      rc = MOTIF_ENOMEM;
+      break;
+    }
+    enqueue_zero(acc, sizeof(uint64_t) * kClasses6, s);
+    enqueue_zero(labels, sizeof(uint32_t) * (size_t)grid * (size_t)label_words, s);
+    if (na > 0) {
+      enqueue_zero(ctr, sizeof(host_ctr), s);
+      if ((rc = enqueue_anchors6(g, anchors, ctr, na, true, cus, p->status, s))) break;
+      enqueue_census6(g, anchors, (int64_t)na, *T, acc, labels, label_words, grid, p->status, s);
+    }
+    enqueue_divide(acc, T->mult, kClasses6, kClasses6, hist, p->status, s);
+    rc = read_status(*p, s);
+  } while (false);
+  (void)hipStreamSynchronize(s);  // the buffers below are released after the work that uses them
+  (void)hipFree(ctr);
+  (void)hipFree(anchors);
+  (void)hipFree(acc);
+  (void)hipFree(labels);
+  return rc;
+}
+
+int32_t motif_class6_codes(uint32_t* codes) {
+  if (!codes) return MOTIF_EINVAL_ARG;
+  int dev;
+  if (int32_t rc = ensure_init(&dev)) return rc;
+  const Tables6* T = nullptr;
+  if (int32_t rc = ensure_tables6(dev, &T)) return rc;
+  std::copy(T->host_codes.begin(), T->host_codes.end(), codes);
+  return 0;
+}
+
+int32_t motif_class6_multiplicities(uint8_t* mult) {
+  if (!mult) return MOTIF_EINVAL_ARG;
+  int dev;
+  if (int32_t rc = ensure_init(&dev)) return rc;
+  const Tables6* T = nullptr;
+  if (int32_t rc = ensure_tables6(dev, &T)) return rc;
+  std::copy(T->host_mult.begin(), T->host_mult.end(), mult);
+  return 0;
 }
 
 int32_t motif_census_async(const int32_t* out_off, const int32_t* out_idx, const int32_t* in_off,
@@ -965,10 +1078,11 @@ namespace {
 
 // Validate the descriptors of graphs to randomise and fill the switch list.
 int32_t switch_list(const motif_graph_t* graphs, int32_t count, int32_t switches_per_arc, uint64_t seed,
-                    int64_t first_index, std::vector<SwitchGraph>* out, int64_t* max_n) {
+                    int64_t first_index, std::vector<SwitchGraph>* out, int64_t* max_n, int64_t* max_m) {
   if (switches_per_arc < 0) return MOTIF_EINVAL_ARG;
   out->clear();
   *max_n = 0;
+  *max_m = 0;
   for (int32_t g = 0; g < count; ++g) {
     const motif_graph_t& G = graphs[g];
     if (!check_shape(G.n, G.m) || (G.n == 0 && G.m != 0)) return MOTIF_EINVAL_SHAPE;
@@ -982,18 +1096,17 @@ int32_t switch_list(const motif_graph_t* graphs, int32_t count, int32_t switches
     sg.rounds = ((int64_t)switches_per_arc * G.m + kSwitchProposals - 1) / kSwitchProposals;
     out->push_back(sg);
     *max_n = std::max<int64_t>(*max_n, G.n);
+    *max_m = std::max<int64_t>(*max_m, G.m);
   }
   return 0;
 }
 
-// Check every graph's rows, then switch; one host wait at the end.
-int32_t run_switch(Pipeline& p, const std::vector<SwitchGraph>& sg, hipStream_t s) {
+// Check every graph (one launch), then switch; one host wait at the end.
+int32_t run_switch(Pipeline& p, const std::vector<SwitchGraph>& sg, bool mutual, hipStream_t s) {
   p.arena.reset();
   try {
     enqueue_zero(p.status, sizeof(int32_t) * kStatusWords, s);
-    for (const SwitchGraph& G : sg)
-      if (G.n > 0) enqueue_check_rows(G.off, G.n, G.m, p.status, s);
-    if (int32_t rc = enqueue_switch(p, sg.data(), (int32_t)sg.size(), s)) {
+    if (int32_t rc = enqueue_switch(p, sg.data(), (int32_t)sg.size(), mutual, s)) {
       (void)hipStreamSynchronize(s);  // best effort: the error is what the caller acts on
       return rc;
     }
@@ -1007,25 +1120,26 @@ int32_t run_switch(Pipeline& p, const std::vector<SwitchGraph>& sg, hipStream_t 
 
 extern "C" {
 
-int32_t motif_null_randomize(const motif_graph_t* graphs, int32_t count, int32_t switches_per_arc, uint64_t seed,
-                             void* stream) {
-  if (count < 0 || (count > 0 && !graphs)) return MOTIF_EINVAL_ARG;
+int32_t motif_null_randomize(const motif_graph_t* graphs, int32_t count, int32_t switches_per_arc, int32_t flags,
+                             uint64_t seed, void* stream) {
+  if (count < 0 || (count > 0 && !graphs) || (flags & ~MOTIF_SWITCH_MUTUAL)) return MOTIF_EINVAL_ARG;
   if (count == 0) return 0;
   int dev;
   if (int32_t rc = ensure_init(&dev)) return rc;
   std::vector<SwitchGraph> sg;
-  int64_t max_n = 0;
-  if (int32_t rc = switch_list(graphs, count, switches_per_arc, seed, 0, &sg, &max_n)) return rc;
+  int64_t max_n = 0, max_m = 0;
+  if (int32_t rc = switch_list(graphs, count, switches_per_arc, seed, 0, &sg, &max_n, &max_m)) return rc;
   hipStream_t s = (hipStream_t)stream;
   Pipeline* p = nullptr;
-  if (int32_t rc = get_pipeline(dev, s, switch_bytes(count, max_n, device_cus(dev)), &p)) return rc;
-  return run_switch(*p, sg, s);
+  if (int32_t rc = get_pipeline(dev, s, switch_bytes(count, max_n, max_m, device_cus(dev)), &p)) return rc;
+  return run_switch(*p, sg, (flags & MOTIF_SWITCH_MUTUAL) != 0, s);
 }
 
-int32_t motif_null_model(const motif_graph_t* real, int32_t count, int32_t k, int32_t switches_per_arc, uint64_t seed,
-                         uint64_t* hists, double* z, void* stream) {
+int32_t motif_null_model(const motif_graph_t* real, int32_t count, int32_t k, int32_t switches_per_arc, int32_t flags,
+                         uint64_t seed, uint64_t* hists, double* z, void* stream) {
   if (motif_num_classes(k) < 0) return MOTIF_EINVAL_K;
   if (!real || !hists || !z || count < 1 || switches_per_arc < 0) return MOTIF_EINVAL_ARG;
+  if (flags & ~MOTIF_SWITCH_MUTUAL) return MOTIF_EINVAL_ARG;
   if (!check_shape(real->n, real->m) || (real->n == 0 && real->m != 0)) return MOTIF_EINVAL_SHAPE;
   if ((real->n > 0 && !real->out_off) || (real->m > 0 && !real->out_idx)) return MOTIF_EINVAL_ARG;
   if (real->in_off && real->m > 0 && !real->in_idx) return MOTIF_EINVAL_ARG;
@@ -1063,15 +1177,15 @@ int32_t motif_null_model(const motif_graph_t* real, int32_t count, int32_t k, in
     all[g].in_idx = nullptr;
   }
   std::vector<SwitchGraph> sg;
-  int64_t max_n = 0;
-  if (int32_t rc = switch_list(all.data() + 1, count, switches_per_arc, seed, 0, &sg, &max_n)) return rc;
+  int64_t max_n = 0, max_m = 0;
+  if (int32_t rc = switch_list(all.data() + 1, count, switches_per_arc, seed, 0, &sg, &max_n, &max_m)) return rc;
   Pipeline* p = nullptr;
-  if (int32_t rc = get_pipeline(dev, s, switch_bytes(count, max_n, device_cus(dev)), &p)) return rc;
+  if (int32_t rc = get_pipeline(dev, s, switch_bytes(count, max_n, max_m, device_cus(dev)), &p)) return rc;
   // 1. copy the real graph's targets into every slot, 2. randomise the slots
   enqueue_zero(p->status, sizeof(int32_t) * kStatusWords, s);
   if (real->n > 0) enqueue_check_rows(real->out_off, real->n, real->m, p->status, s);
   if (real->m > 0) enqueue_replicate(real->out_idx, real->m, count, copies, p->status, s);
-  if (int32_t rc = run_switch(*p, sg, s)) return rc;
+  if (int32_t rc = run_switch(*p, sg, (flags & MOTIF_SWITCH_MUTUAL) != 0, s)) return rc;
   // 3. one fused census of the real graph and its copies
   int32_t rc = census_batch_with(all.data(), count + 1, k, hists, s,
                                  tuning_for_call(dev, 1, &k, true, real->m * (count + 1)));

@@ -71,6 +71,14 @@ __device__ __forceinline__ uint32_t rel_code(uint32_t t) {
 
 __device__ __forceinline__ uint32_t flip(uint32_t t) { return ((t & 1u) << 1) | ((t & 2u) >> 1); }
 
+// k = 4: slot of the label pair (a, b), 1 <= a <= b <= 15, among the 120 such
+// pairs (row-major upper triangle).
+constexpr int kPairs4 = 120;
+__device__ __forceinline__ uint32_t pair_slot4(uint32_t a, uint32_t b) {
+  const uint32_t a0 = a - 1u;
+  return a0 * 15u - (a0 * (a0 - 1u)) / 2u + (b - a);
+}
+
 constexpr int num_classes(int k) { return k == 3 ? 13 : k == 4 ? 199 : 9364; }
 
 constexpr int kMaxHubs = 512;  // rows of the per-core W table in LDS
@@ -670,8 +678,21 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   __shared__ int32_t ncore[4];
   __shared__ int32_t sh_j0, sh_j1;
   __shared__ u64 seg_ctr[2];  // (rows << 32) | entries of the chunk being laid out
-  __shared__ int32_t seg_v[BLOCK], seg_start[BLOCK], seg_base[BLOCK], seg_at[kBuckets];
   constexpr int NW = BLOCK / 64;
+  // k = 4: per anchor, the inner-edge moves counted per label pair (a <= b)
+  // and arc type, 32-bit wrapping (per anchor they stay far inside int32);
+  // the classes and the no-edge halves are added once, in the closed form.
+  // The wave paths' tables share the row-scan layout's words: the two are
+  // never in use at the same time (workgroup phases are barrier-separated).
+  constexpr int TW = K == 4 ? kPairs4 * 3 : 0;
+  constexpr int SEGW = 3 * BLOCK + kBuckets;
+  constexpr int POOLW = NW * TW > SEGW ? NW * TW : SEGW;
+  __shared__ __align__(16) int32_t seg_pool[POOLW];
+  int32_t* const seg_v = seg_pool;
+  int32_t* const seg_start = seg_pool + BLOCK;
+  int32_t* const seg_base = seg_pool + 2 * BLOCK;
+  int32_t* const seg_at = seg_pool + 3 * BLOCK;
+  uint32_t* const wT = reinterpret_cast<uint32_t*>(seg_pool);
   constexpr int WH = K == 4 ? kWaveHash : 0;  // per-wave hash words
   constexpr int NCN = K == 4 ? NW : kNP5;     // set-size rows: one per wave (k = 4), per light partner (k = 5)
   __shared__ uint32_t wh[K == 4 ? NW * WH : 1];  // light anchors: per-wave hashes of the sides' neighbourhoods
@@ -690,10 +711,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   __shared__ int32_t p5_vb[2][P5], p5_rowb[2][P5], p5_offb[2][P5], p5_ctlb[2][5], p5_dc[P5];
   __shared__ uint16_t tlist[K == 5 ? kT5Load : 1];  // slots of the table's keys
   __shared__ uint32_t p5_baseb[2][P5], p5_db[P5];
-  // k = 4: the no-edge half of every edge move, per label pair (min, max),
-  // summed for the current anchor and added in its closed form (per wave for
-  // the wave paths, one table for the workgroup path)
-  __shared__ uint32_t wE[K == 4 ? NW * NL * NL : 1], bE[K == 4 ? NL * NL : 1];
+  // k = 4: the workgroup path's move table (kept zero between anchors)
+  __shared__ __align__(16) uint32_t bT[K == 4 ? TW : 1];
   __shared__ int32_t unit_list[BLOCK], unit_ctr[3];
   __shared__ int32_t lbk[K == 4 ? 32 : 1];  // k = 4 light units: counts and fills per log2 degree bucket
   __shared__ uint32_t lds_labels[LCAP > 0 ? LCAP / 4 : 1];
@@ -720,10 +739,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     for (int i = threadIdx.x; i < kU5; i += BLOCK) U5[i] = 0u;
     if (threadIdx.x < 32) cnUb[threadIdx.x >> 4][threadIdx.x & 15] = 0;
   }
-  if (K == 4) {
-    for (int i = threadIdx.x; i < NW * NL * NL; i += BLOCK) wE[i] = 0u;
-    for (int i = threadIdx.x; i < NL * NL; i += BLOCK) bE[i] = 0u;
-  }
+  if (K == 4)
+    for (int i = threadIdx.x; i < TW; i += BLOCK) bT[i] = 0u;
   if (LCAP > 0)
     for (int i = threadIdx.x; i < LCAP / 4; i += BLOCK) lds_labels[i] = 0u;
   __syncthreads();
@@ -768,21 +785,39 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     atomicAdd(&hist[lut[c0 | rel_code<K>(r)]], w);
     atomicAdd(&hist[lut[c0]], (u64)0 - w);
   };
-  // k = 4: the same move with its no-edge half kept in E (the class of a
-  // member pair without an edge does not depend on which member is in which
-  // slot); per anchor and pair the sum stays far inside int32, so 32-bit
-  // wrapping counters are exact after sign extension
-  auto edge4 = [&](uint32_t* E, uint32_t base, uint32_t Lx, uint32_t Ly, uint32_t r, u64 w) {
-    atomicAdd(&hist[lut[base | slot_code<K, S1>(Lx) | slot_code<K, S2>(Ly) | rel_code<K>(r)]], w);
-    atomicAdd(&E[min(Lx, Ly) * NL + max(Lx, Ly)], (uint32_t)((u64)0 - w));
+  // k = 4: the same move counted in the anchor's table T at (min label, max
+  // label, arc type seen from the smaller label's member): swapping the two
+  // members flips the arc type and keeps the class.  The no-edge half is the
+  // negated sum of a pair's three counts (the class of a member pair without
+  // an edge does not depend on which member is in which slot).
+  auto edge4 = [&](uint32_t* T, uint32_t, uint32_t Lx, uint32_t Ly, uint32_t r, u64 w) {
+    const bool sw = Lx > Ly;
+    const uint32_t a = sw ? Ly : Lx, b = sw ? Lx : Ly, rr = sw ? flip(r) : r;
+    atomicAdd(&T[pair_slot4(a, b) * 3u + rr - 1u], (uint32_t)w);
   };
-  // closed form of one pair (La <= Lb) plus its deferred no-edge moves
-  auto pair_total = [&](const int32_t* cntv, uint32_t* E, int32_t La, int32_t Lb) -> u64 {
+  // Closed form of label pair slot t with the anchor's moves: the pair's
+  // member pairs go to its no-edge class, then each counted move takes one
+  // from there to the class with the edge.  zero: clear the pair's counts.
+  auto t_close = [&](const int32_t* cntv, uint32_t* T, uint32_t base, int32_t t, bool zero) {
+    int32_t a0 = 0, rem = t;
+    while (rem >= 15 - a0) {
+      rem -= 15 - a0;
+      ++a0;
+    }
+    const uint32_t La = (uint32_t)a0 + 1u, Lb = La + (uint32_t)rem;
     const u64 na = (u64)cntv[La], nb = (u64)cntv[Lb];
-    const u64 w = La == Lb ? na * (na - (na > 0)) / 2 : na * nb;
-    const uint32_t e = E[La * NL + Lb];
-    E[La * NL + Lb] = 0u;
-    return w + (u64)(int64_t)(int32_t)e;
+    const int32_t s1 = (int32_t)T[3 * t], s2 = (int32_t)T[3 * t + 1], s3 = (int32_t)T[3 * t + 2];
+    if (zero) {
+      T[3 * t] = 0u;
+      T[3 * t + 1] = 0u;
+      T[3 * t + 2] = 0u;
+    }
+    const u64 w0 = (La == Lb ? na * (na - (na > 0)) / 2 : na * nb) - (u64)((int64_t)s1 + s2 + s3);
+    const uint32_t c0 = base | slot_code<K, S1>(La) | slot_code<K, S2>(Lb);
+    if (w0) atomicAdd(&hist[lut[c0]], w0);
+    if (s1) atomicAdd(&hist[lut[c0 | rel_code<K>(1u)]], (u64)(int64_t)s1);
+    if (s2) atomicAdd(&hist[lut[c0 | rel_code<K>(2u)]], (u64)(int64_t)s2);
+    if (s3) atomicAdd(&hist[lut[c0 | rel_code<K>(3u)]], (u64)(int64_t)s3);
   };
   // Flattened scan of the N+ rows of the vertices pick(0 .. items-1): pick
   // returns a vertex (or -1) and does the per-vertex work, visit(v, f) handles
@@ -922,7 +957,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   // One anchor: core c, sides s0 (and s1 for k = 5) whose labels are set.
   auto anchor = [&](int32_t c, int32_t s0, int32_t s1, uint32_t base) {
     auto EDGE = [&](uint32_t bs, uint32_t Lx, uint32_t Ly, uint32_t r, u64 w) {
-      if constexpr (K == 4) edge4(bE, bs, Lx, Ly, r, w);
+      if constexpr (K == 4) edge4(bT, bs, Lx, Ly, r, w);
       else edge(bs, Lx, Ly, r, w);
     };
     const int32_t a0 = G.gs_off[s0], d0 = G.gs_off[s0 + 1] - a0;
@@ -968,12 +1003,12 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       const uint32_t Lq = lab.get((uint32_t)q);
       const bool mq = !is_side(q), my = !sy;
       const uint32_t r = f >> kTypeShift, cq = Lq & 3u, cy = Ly & 3u;
-      if (cq && cy) EDGE(base, cq, cy, r, kMinusOne);
+      // (cq, cy) takes -1, and +1 back when p = q is also counted in W[y]
+      // (y a side neighbour or a side): only the net is added
+      const bool inw = sy || (Ly >> 2);
+      if (cq && cy && !inw) EDGE(base, cq, cy, r, kMinusOne);
       if (mq && my) EDGE(base, Lq, Ly, r, 1ull);
-      if (cq && (sy || (Ly >> 2))) {  // p = q is also counted in W[y]
-        if (cy) EDGE(base, cq, cy, r, 1ull);
-        if (my) EDGE(base, cq, Ly, r, kMinusOne);
-      }
+      if (cq && my && inw) EDGE(base, cq, Ly, r, kMinusOne);
     };
     flat_rows(nsides + d0 + d1, pick, visit);
     // edges inside N(core) with core-only labels
@@ -996,13 +1031,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       cnt[a] = v;
     }
     bar<GL>();
-    if constexpr (K == 4) {  // every pair once: some deferred moves sit on empty sets
-      for (int32_t t = threadIdx.x; t < NL * NL; t += BLOCK) {
-        const int32_t La = t / NL, Lb = t % NL;
-        if (La == 0 || La > Lb) continue;
-        const u64 w = pair_total(cnt, bE, La, Lb);
-        if (w) atomicAdd(&hist[lut[base | slot_code<K, K - 2>((uint32_t)La) | slot_code<K, K - 1>((uint32_t)Lb)]], w);
-      }
+    if constexpr (K == 4) {  // every pair once: some moves sit on empty sets
+      for (int32_t t = threadIdx.x; t < kPairs4; t += BLOCK) t_close(cnt, bT, base, t, true);
     } else {
       closed_form<K, NL, BLOCK>(hist, lut, cnt, nzl, &nz_count, base);
     }
@@ -1022,7 +1052,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     const int32_t lane = (int32_t)(threadIdx.x & 63u);
     uint32_t* H = wh + (threadIdx.x >> 6) * WH;
     int32_t* cn = wcnt + (threadIdx.x >> 6) * NL;
-    uint32_t* E = wE + (threadIdx.x >> 6) * NL * NL;
+    uint32_t* E = wT + (threadIdx.x >> 6) * TW;
+    for (int32_t i = lane; i < TW / 4; i += 64) reinterpret_cast<uint4*>(E)[i] = make_uint4(0u, 0u, 0u, 0u);
     const int32_t a0 = G.gs_off[s], d0 = G.gs_off[s + 1] - a0;
     const uint32_t Ls = lab.get((uint32_t)s) & 3u;
     for (int32_t i = lane; i < d0; i += 64) {
@@ -1112,12 +1143,12 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
             if (Ly || sy) {
               const bool mq = sq != s, my = !sy;
               const uint32_t r = f >> kTypeShift, cq = sL & 3u, cy = Ly & 3u;
-              if (cq && cy) edge4(E, base, cq, cy, r, kMinusOne);
+              // (cq, cy) takes -1, and +1 back when p = sq is also counted in
+              // W[y] (y a side neighbour or the side): only the net is added
+              const bool inw = sy || (Ly >> 2);
+              if (cq && cy && !inw) edge4(E, base, cq, cy, r, kMinusOne);
               if (mq && my) edge4(E, base, sL, Ly, r, 1ull);
-              if (cq && (sy || (Ly >> 2))) {  // p = sq is also counted in W[y]
-                if (cy) edge4(E, base, cq, cy, r, 1ull);
-                if (my) edge4(E, base, cq, Ly, r, kMinusOne);
-              }
+              if (cq && my && inw) edge4(E, base, cq, Ly, r, kMinusOne);
             }
           }
         }
@@ -1137,12 +1168,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       cn[lane] = v;
     }
     wave_sync();
-    for (int32_t pq = lane; pq < NL * NL; pq += 64) {
-      const int32_t La = pq / NL, Lb = pq % NL;
-      if (La == 0 || La > Lb) continue;
-      const u64 w = pair_total(cn, E, La, Lb);
-      if (w) atomicAdd(&hist[lut[base | slot_code<K, K - 2>((uint32_t)La) | slot_code<K, K - 1>((uint32_t)Lb)]], w);
-    }
+    for (int32_t t = lane; t < kPairs4; t += 64) t_close(cn, E, base, t, false);
     wave_sync();
     if (lane < NL) cn[lane] = 0;
     for (int32_t i = lane; i < WH; i += 64) H[i] = kEmptySlot;
@@ -1159,7 +1185,8 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     uint32_t* key = wh + (threadIdx.x >> 6) * WH;
     uint32_t* nlab = key + kSoloHash;
     int32_t* cn = wcnt + (threadIdx.x >> 6) * NL;
-    uint32_t* E = wE + (threadIdx.x >> 6) * NL * NL;
+    uint32_t* E = wT + (threadIdx.x >> 6) * TW;
+    for (int32_t i = lane; i < TW / 4; i += 64) reinterpret_cast<uint4*>(E)[i] = make_uint4(0u, 0u, 0u, 0u);
     auto slot = [](uint32_t x) { return (x * 2654435761u) >> (32 - kSoloHashBits); };
     auto insert = [&](uint32_t x, uint32_t bits) {
       uint32_t h = slot(x);
@@ -1233,12 +1260,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       }
     }
     wave_sync();
-    for (int32_t pq = lane; pq < NL * NL; pq += 64) {
-      const int32_t La = pq / NL, Lb = pq % NL;
-      if (La == 0 || La > Lb) continue;
-      const u64 w = pair_total(cn, E, La, Lb);
-      if (w) atomicAdd(&hist[lut[base | slot_code<K, K - 2>((uint32_t)La) | slot_code<K, K - 1>((uint32_t)Lb)]], w);
-    }
+    for (int32_t t = lane; t < kPairs4; t += 64) t_close(cn, E, base, t, false);
     wave_sync();
     if (lane < NL) cn[lane] = 0;
     for (int32_t i = lane; i < WH; i += 64) key[i] = kEmptySlot;
@@ -2358,12 +2380,14 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
 }
 
 void enqueue_finalise(Pipeline& p, int k, int32_t ngraphs, const uint64_t* acc, uint64_t* out, hipStream_t s) {
-  const DevTables& T = dev_tables();
   const int C = num_classes(k);
-  const int64_t total = (int64_t)ngraphs * C;
-  hipLaunchKernelGGL(k_div_check, dim3(blocks_for(total, 256)), dim3(256), 0, s, acc, T.mult[k], C, total, p.status);
-  hipLaunchKernelGGL(k_div_write, dim3(blocks_for(total, 256)), dim3(256), 0, s, acc, T.mult[k], C, total, out,
-                     p.status);
+  enqueue_divide(acc, dev_tables().mult[k], C, (int64_t)ngraphs * C, out, p.status, s);
+}
+
+void enqueue_divide(const uint64_t* acc, const uint8_t* mult, int32_t C, int64_t total, uint64_t* out,
+                    int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_div_check, dim3(blocks_for(total, 256)), dim3(256), 0, s, acc, mult, C, total, status);
+  hipLaunchKernelGGL(k_div_write, dim3(blocks_for(total, 256)), dim3(256), 0, s, acc, mult, C, total, out, status);
 }
 
 }  // namespace motif

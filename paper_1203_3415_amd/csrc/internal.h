@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <stdexcept>
+#include <vector>
 
 #include "../../include/motif.h"
 
@@ -160,6 +161,31 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
 // The exact division alone: out[i] = acc[i] / multiplicity, after a check
 // that every remainder is zero (Fact "correction").
 void enqueue_finalise(Pipeline& p, int k, int32_t ngraphs, const uint64_t* acc, uint64_t* out, hipStream_t s);
+// The same for any table: out[i] = acc[i] / mult[i % C], i < total.
+void enqueue_divide(const uint64_t* acc, const uint8_t* mult, int32_t C, int64_t total, uint64_t* out,
+                    int32_t* status, hipStream_t s);
+
+// ---- k = 6 (census6.hip) ----
+constexpr int32_t kClasses6 = 1530843;  // weakly connected digraphs on 6 vertices
+struct Tables6 {
+  uint32_t* lut = nullptr;    // device [2^30]: class of each code, 0xFFFFFFFF when disconnected
+  uint32_t* codes = nullptr;  // device [kClasses6]: canonical code of each class, increasing
+  uint8_t* mult = nullptr;    // device [kClasses6]: anchors (connected dominating 4-subsets) per occurrence
+  std::vector<uint32_t> host_codes;
+  std::vector<uint8_t> host_mult;
+};
+// Classify all 2^30 codes on the current device (synchronous, a few seconds;
+// 4 GiB for the table).  MOTIF_EINTERNAL if the class counts come out wrong.
+int32_t build_tables6(Tables6* T);
+void free_tables6(Tables6* T);
+// Connected 4-sets of g, each once: count into ctr[1] (fill = false) or write
+// them to out[0 .. cap) with ctr[0] as the cursor (fill = true).
+int32_t enqueue_anchors6(const DevGraph& g, int4* out, unsigned long long* ctr, unsigned long long cap, bool fill,
+                         int num_cus, int32_t* status, hipStream_t s);
+// acc[class] += every 6-set of each anchor, counted once per anchor (labels:
+// `grid` zeroed slices of label_words words).
+void enqueue_census6(const DevGraph& g, const int4* anchors, int64_t nanchors, const Tables6& T, uint64_t* acc,
+                     uint32_t* labels, int64_t label_words, int grid, int32_t* status, hipStream_t s);
 // Bytes of the per-workgroup W rows of a k = 4, 5 core-reuse census (0 otherwise).
 size_t w_slice_bytes(int k, int64_t maxn, const Tuning& t, int num_cus);
 
@@ -208,10 +234,13 @@ struct SwitchGraph {
   int64_t rounds;
 };
 constexpr int kSwitchProposals = 1024;  // proposals (attempted switches) per round
-// Enqueue the randomisation of host_graphs[0..count) (descriptors copied to
-// the arena; waits for that copy).  Graphs are skipped if the status word is set.
-int32_t enqueue_switch(Pipeline& p, const SwitchGraph* host_graphs, int32_t count, hipStream_t s);
-size_t switch_bytes(int32_t count, int64_t max_n, int num_cus);
+// Enqueue the check and the randomisation of host_graphs[0..count)
+// (descriptors copied to the arena; waits for that copy).  The check sets
+// MOTIF_EINVAL_SHAPE (offsets), MOTIF_EINDEX or MOTIF_ESELFLOOP (targets) in
+// the status word, and nothing is switched once it is set.  mutual: the
+// mutual-preserving switch.
+int32_t enqueue_switch(Pipeline& p, const SwitchGraph* host_graphs, int32_t count, bool mutual, hipStream_t s);
+size_t switch_bytes(int32_t count, int64_t max_n, int64_t max_m, int num_cus);
 // Key of graph `graph`'s random stream under `seed`.
 uint64_t switch_key(uint64_t seed, int64_t graph);
 // Sets MOTIF_EINVAL_SHAPE unless off[0..n] is monotone from 0 to m.

@@ -22,6 +22,29 @@
 // graphs of the same degrees: the chain keeps the uniform distribution over
 // them, as the one-switch-at-a-time chain does.  Every proposal counts as an
 // attempt, whether it loses its reservation, is rejected or is executed.
+//
+// Mutual-preserving switch (optional): one-way arcs are exchanged only with
+// one-way arcs and reciprocated pairs only with reciprocated pairs, so each
+// vertex also keeps its numbers of reciprocated, one-way-out and one-way-in
+// neighbours.  A one-way pair a->b, c->d becomes a->d, c->b; a reciprocated
+// pair a<->b, c<->d becomes a<->d, c<->b.  Either is rejected if a and d, or
+// c and b, are already joined in either direction (or on a self-loop or a
+// repeated target).  Each slot's kind (bit 31 of its target while the kernel
+// runs) never changes.  These switches also read (one-way) or write
+// (reciprocated) the target rows b and d, so a proposal that holds its two
+// source rows marks them as held and claims b and d (atomicMin of its index,
+// among such proposals); it runs only if it wins both claims and neither b
+// nor d is a row held by another proposal.  A proposal draws its first slot
+// uniformly and its second uniformly among the slots of the same kind (from a
+// list of the slots ordered by kind, fixed for the run), so each kind gets
+// switches_per_arc attempts per arc whatever the reciprocity, and the
+// proposals still do not depend on the current graph.  Everything that decides whether a
+// proposal runs is the same before and after the round's switches (the
+// reservations and so the held rows, the slots' kinds, and the set {b, d} of
+// every proposal that holds its source rows), and the running proposals touch
+// disjoint rows, so
+// the round stays a symmetric move and the chain keeps the uniform
+// distribution over the graphs with the same three degree sequences.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,6 +60,9 @@ namespace {
 constexpr int kSwB = kSwitchProposals;  // threads per workgroup = proposals per round
 constexpr int kSwLds = 38 * 1024;       // LDS words for one graph: n + 1 offsets, m targets, n locks
 constexpr uint32_t kFree = 0xFFFFFFFFu;
+// lock word index | kHeld: the row's winning proposal holds both its rows
+// (indices are below 1024; a free word has both top bits set)
+constexpr uint32_t kHeld = 0x40000000u, kHeldMask = 0xC0000000u;
 
 // SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
 // generators", OOPSLA 2014) used as a counter-based generator: output i of
@@ -60,6 +86,10 @@ __device__ __forceinline__ int32_t row_of(const int32_t* off, int32_t n, int32_t
 
 // Does row [p, pe) of idx hold x?  Eight loads per step, issued together, so a
 // long (hub) row is not a chain of dependent loads.
+// Targets are compared without bit 31 (the slot kind of the mutual-preserving
+// switch).
+constexpr int32_t kTarget = 0x7FFFFFFF;
+constexpr int32_t kMutualBit = (int32_t)0x80000000u;
 __device__ __forceinline__ bool row_has(const int32_t* idx, int32_t p, int32_t pe, int32_t x) {
   bool hit = false;
   for (; p + 8 <= pe && !hit; p += 8) {
@@ -67,10 +97,16 @@ __device__ __forceinline__ bool row_has(const int32_t* idx, int32_t p, int32_t p
 #pragma unroll
     for (int u = 0; u < 8; ++u) v[u] = idx[p + u];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) hit |= v[u] == x;
+    for (int u = 0; u < 8; ++u) hit |= (v[u] & kTarget) == x;
   }
-  for (; p < pe && !hit; ++p) hit = idx[p] == x;
+  for (; p < pe && !hit; ++p) hit = (idx[p] & kTarget) == x;
   return hit;
+}
+
+// Position of target x in row [p, pe) (present by construction).
+__device__ __forceinline__ int32_t row_find(const int32_t* idx, int32_t p, int32_t pe, int32_t x) {
+  while (p < pe - 1 && (idx[p] & kTarget) != x) ++p;
+  return p;
 }
 
 // Lock words: in LDS plain accesses; in global memory device-scope atomics,
@@ -98,14 +134,17 @@ __device__ __forceinline__ void sw_barrier() {
 }
 
 // Randomise the graphs list[0..count) of gs, one workgroup per graph.  LDS:
-// the graph is held in LDS ((n + 1) + m + n <= kSwLds words).  Otherwise it
-// is switched in place in global memory with this workgroup's lock slice
-// glock + blockIdx.x * lock_stride (lock_stride >= n of every listed graph).
-template <bool LDS>
+// the graph is held in LDS ((n + 1) + m + n words, + n target claims when
+// MUT).  Otherwise it is switched in place in global memory with this
+// workgroup's lock slice glock + blockIdx.x * lock_stride (lock_stride >= n,
+// or 2n when MUT, of every listed graph).  MUT: the slots ordered by kind go
+// to gperm + blockIdx.x * perm_stride (perm_stride >= m of every listed graph).
+template <bool LDS, bool MUT>
 __global__ __launch_bounds__(kSwB) void k_switch(const SwitchGraph* __restrict__ gs, const int32_t* __restrict__ list,
                                                  int32_t count, uint32_t* __restrict__ glock, int64_t lock_stride,
-                                                 const int32_t* st) {
+                                                 int32_t* __restrict__ gperm, int64_t perm_stride, const int32_t* st) {
   __shared__ int32_t lds[LDS ? kSwLds : 1];
+  __shared__ int32_t wsum[2][kSwB / 64];
   if (st[kStatus] != 0) return;
   const uint32_t tid = threadIdx.x;
   for (int32_t q = blockIdx.x; q < count; q += gridDim.x) {
@@ -115,27 +154,90 @@ __global__ __launch_bounds__(kSwB) void k_switch(const SwitchGraph* __restrict__
     const int32_t* off;
     int32_t* idx;
     uint32_t* lock;
+    uint32_t* claim = nullptr;  // MUT: target-row claims
     if constexpr (LDS) {
       int32_t* loff = lds;
       int32_t* lidx = lds + (n + 1);
       uint32_t* llock = reinterpret_cast<uint32_t*>(lidx + m);
       for (int32_t i = tid; i <= n; i += kSwB) loff[i] = G.off[i];
       for (int32_t i = tid; i < m; i += kSwB) lidx[i] = G.idx[i];
-      for (int32_t i = tid; i < n; i += kSwB) llock[i] = kFree;
+      for (int32_t i = tid; i < (MUT ? 2 * n : n); i += kSwB) llock[i] = kFree;
       off = loff;
       idx = lidx;
       lock = llock;
+      if constexpr (MUT) claim = llock + n;
     } else {
       off = G.off;
       idx = G.idx;
       lock = glock + (int64_t)blockIdx.x * lock_stride;
-      for (int32_t i = tid; i < n; i += kSwB) lock_set<LDS>(&lock[i], kFree);
+      for (int32_t i = tid; i < (MUT ? 2 * n : n); i += kSwB) lock_set<LDS>(&lock[i], kFree);
+      if constexpr (MUT) claim = lock + n;
     }
     sw_barrier<LDS>();
+    int32_t* perm = nullptr;  // MUT: slot indices, reciprocated first, each kind in slot order
+    int32_t nmut = 0;         // MUT: reciprocated slots
+    if constexpr (MUT) {
+      // slot kinds: bit 31 set on a->b when b->a exists (each slot is
+      // written by one thread; readers compare without bit 31)
+      const int32_t lane = (int32_t)(tid & 63u), wv = (int32_t)(tid >> 6);
+      int32_t mine = 0;
+      for (int32_t i = tid; i < m; i += kSwB) {
+        const int32_t a = row_of(off, n, i), b = idx[i] & kTarget;
+        if (row_has(idx, off[b], off[b + 1], a)) {
+          idx[i] |= kMutualBit;
+          ++mine;
+        }
+      }
+      for (int o = 32; o; o >>= 1) mine += __shfl_xor(mine, o);
+      if (lane == 0) wsum[0][wv] = mine;
+      sw_barrier<LDS>();
+      for (int w = 0; w < kSwB / 64; ++w) nmut += wsum[0][w];
+      // stable partition of the slots by kind, kSwB slots at a time
+      perm = gperm + (int64_t)blockIdx.x * perm_stride;
+      const uint64_t below = (1ull << lane) - 1ull;
+      int32_t next_m = 0, next_s = nmut;
+      for (int32_t c0 = 0; c0 < m; c0 += kSwB) {
+        const int32_t i = c0 + (int32_t)tid;
+        const bool live = i < m, f = live && (idx[i] & kMutualBit);
+        const uint64_t bm = __ballot(f), bl = __ballot(live);
+        sw_barrier<LDS>();  // the previous chunk's counts have been read
+        if (lane == 0) {
+          wsum[0][wv] = __popcll(bm);
+          wsum[1][wv] = __popcll(bl);
+        }
+        sw_barrier<LDS>();
+        int32_t om = 0, ol = 0, tm = 0, tl = 0;
+        for (int w = 0; w < kSwB / 64; ++w) {
+          if (w < wv) {
+            om += wsum[0][w];
+            ol += wsum[1][w];
+          }
+          tm += wsum[0][w];
+          tl += wsum[1][w];
+        }
+        if (live) {
+          const int32_t rm = om + __popcll(bm & below), rl = ol + __popcll(bl & below);
+          perm[f ? next_m + rm : next_s + (rl - rm)] = i;
+        }
+        next_m += tm;
+        next_s += tl - tm;
+      }
+      // the list was written to global memory by other threads of this
+      // workgroup: wait for the stores, then drop stale L1 lines
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
     for (int64_t r = 0; r < G.rounds; ++r) {
       const uint64_t x = sm64_mix(G.key + (uint64_t)(r * kSwB + tid + 1) * kGamma);
-      const int32_t i = (int32_t)(((x & 0xFFFFFFFFull) * (uint64_t)m) >> 32);
-      const int32_t j = (int32_t)(((x >> 32) * (uint64_t)m) >> 32);
+      int32_t i = (int32_t)(((x & 0xFFFFFFFFull) * (uint64_t)m) >> 32);
+      int32_t j = (int32_t)(((x >> 32) * (uint64_t)m) >> 32);
+      if constexpr (MUT) {  // first slot uniform, second uniform among the slots of its kind
+        const bool km = i < nmut;
+        const int32_t lo = km ? 0 : nmut, nk = km ? nmut : m - nmut;
+        j = perm[lo + (int32_t)(((x >> 32) * (uint64_t)nk) >> 32)];
+        i = perm[i];
+      }
       const int32_t a = row_of(off, n, i), c = row_of(off, n, j);
       const bool cand = a != c;  // two arcs of one row: the switch changes nothing
       if (cand) {
@@ -143,27 +245,101 @@ __global__ __launch_bounds__(kSwB) void k_switch(const SwitchGraph* __restrict__
         lock_min<LDS>(&lock[c], tid);
       }
       sw_barrier<LDS>();
-      if (cand && lock_get<LDS>(&lock[a]) == tid && lock_get<LDS>(&lock[c]) == tid) {
-        // rows a and c are this proposal's alone until the next barrier
-        const int32_t b = idx[i], d = idx[j];
-        const bool ok = a != d && c != b && b != d && !row_has(idx, off[a], off[a + 1], d) &&
-                        !row_has(idx, off[c], off[c + 1], b);
-        if (ok) {
-          idx[i] = d;
-          idx[j] = b;
+      if constexpr (!MUT) {
+        if (cand && lock_get<LDS>(&lock[a]) == tid && lock_get<LDS>(&lock[c]) == tid) {
+          // rows a and c are this proposal's alone until the next barrier
+          const int32_t b = idx[i], d = idx[j];
+          const bool ok = a != d && c != b && b != d && !row_has(idx, off[a], off[a + 1], d) &&
+                          !row_has(idx, off[c], off[c + 1], b);
+          if (ok) {
+            idx[i] = d;
+            idx[j] = b;
+          }
         }
-      }
-      sw_barrier<LDS>();
-      if (cand) {
-        lock_set<LDS>(&lock[a], kFree);
-        lock_set<LDS>(&lock[c], kFree);
+        sw_barrier<LDS>();
+        if (cand) {
+          lock_set<LDS>(&lock[a], kFree);
+          lock_set<LDS>(&lock[c], kFree);
+        }
+      } else {
+        // holds both source rows (then marked as held) and the two slots are of one kind
+        int32_t wi = 0, wj = 0;
+        bool held = cand && lock_get<LDS>(&lock[a]) == tid && lock_get<LDS>(&lock[c]) == tid;
+        if (held) {
+          lock_set<LDS>(&lock[a], tid | kHeld);
+          lock_set<LDS>(&lock[c], tid | kHeld);
+          wi = idx[i];
+          wj = idx[j];
+          held = (wi & kMutualBit) == (wj & kMutualBit);
+        }
+        const int32_t b = wi & kTarget, d = wj & kTarget;
+        if (held) {
+          lock_min<LDS>(&claim[b], tid);
+          lock_min<LDS>(&claim[d], tid);
+        }
+        sw_barrier<LDS>();
+        auto held_by_other = [&](int32_t row) {
+          return row != a && row != c && (lock_get<LDS>(&lock[row]) & kHeldMask) == kHeld;
+        };
+        if (held && lock_get<LDS>(&claim[b]) == tid && lock_get<LDS>(&claim[d]) == tid && !held_by_other(b) &&
+            !held_by_other(d)) {
+          // rows a, b, c and d are this proposal's alone until the next barrier
+          const bool ok = a != d && c != b && b != d && !row_has(idx, off[a], off[a + 1], d) &&
+                          !row_has(idx, off[d], off[d + 1], a) && !row_has(idx, off[c], off[c + 1], b) &&
+                          !row_has(idx, off[b], off[b + 1], c);
+          if (ok) {
+            const int32_t kind = wi & kMutualBit;
+            idx[i] = d | kind;
+            idx[j] = b | kind;
+            if (kind) {  // the reverse arcs: b->a becomes b->c, d->c becomes d->a
+              idx[row_find(idx, off[b], off[b + 1], a)] = c | kind;
+              idx[row_find(idx, off[d], off[d + 1], c)] = a | kind;
+            }
+          }
+        }
+        sw_barrier<LDS>();
+        if (cand) {
+          lock_set<LDS>(&lock[a], kFree);
+          lock_set<LDS>(&lock[c], kFree);
+        }
+        if (held) {
+          lock_set<LDS>(&claim[b], kFree);
+          lock_set<LDS>(&claim[d], kFree);
+        }
       }
       sw_barrier<LDS>();
     }
     if constexpr (LDS) {
-      for (int32_t i = tid; i < m; i += kSwB) G.idx[i] = idx[i];
+      for (int32_t i = tid; i < m; i += kSwB) G.idx[i] = idx[i] & kTarget;
+    } else if constexpr (MUT) {
+      for (int32_t i = tid; i < m; i += kSwB) idx[i] &= kTarget;
     }
     sw_barrier<LDS>();
+  }
+}
+
+// Every listed graph before it is switched.  Pass 0: offsets monotone from
+// 0 to m (the kernel reads the rows they delimit).  Pass 1, run only when
+// every graph passed pass 0: targets in [0, n) (the mutual-preserving switch
+// reads the rows they name) and no self-loops.  Graph q = blockIdx.y +
+// t gridDim.y; rows spread over x.
+__global__ void k_check_graphs(const SwitchGraph* __restrict__ gs, int32_t count, int32_t pass, int32_t* st) {
+  if (pass == 1 && st[kStatus] != 0) return;
+  for (int32_t q = blockIdx.y; q < count; q += gridDim.y) {
+    const SwitchGraph G = gs[q];
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= G.n; v += (int64_t)gridDim.x * blockDim.x) {
+      if (pass == 0) {
+        const int32_t a = G.off[v];
+        if ((v == 0 && a != 0) || (v == G.n && a != G.m) || (v < G.n && G.off[v + 1] < a))
+          atomicMin(&st[kStatus], MOTIF_EINVAL_SHAPE);
+      } else if (v < G.n) {
+        for (int32_t i = G.off[v], e = G.off[v + 1]; i < e; ++i) {
+          const int32_t t = G.idx[i];
+          if (t < 0 || t >= G.n) atomicMin(&st[kStatus], MOTIF_EINDEX);
+          else if (t == (int32_t)v) atomicMin(&st[kStatus], MOTIF_ESELFLOOP);
+        }
+      }
+    }
   }
 }
 
@@ -260,13 +436,13 @@ unsigned blocks(int64_t items, int b) {
 
 }  // namespace
 
-int32_t enqueue_switch(Pipeline& p, const SwitchGraph* host_graphs, int32_t count, hipStream_t s) {
+int32_t enqueue_switch(Pipeline& p, const SwitchGraph* host_graphs, int32_t count, bool mutual, hipStream_t s) {
   // graphs held in LDS and graphs switched in global memory, each a list
   std::vector<int32_t> lds_list, glob_list;
   int64_t max_glob_n = 0;
   for (int32_t g = 0; g < count; ++g) {
     const SwitchGraph& G = host_graphs[g];
-    if ((int64_t)(G.n + 1) + G.m + G.n <= kSwLds) {
+    if ((int64_t)(G.n + 1) + G.m + (mutual ? 2 : 1) * (int64_t)G.n <= kSwLds) {
       lds_list.push_back(g);
     } else {
       glob_list.push_back(g);
@@ -284,23 +460,49 @@ int32_t enqueue_switch(Pipeline& p, const SwitchGraph* host_graphs, int32_t coun
     return MOTIF_EDEVICE;
   // the copies above read pageable host memory: wait before it goes out of scope
   if (hipStreamSynchronize(s) != hipSuccess) return MOTIF_EDEVICE;
+  int64_t max_n = 0;
+  for (int32_t g = 0; g < count; ++g) max_n = std::max<int64_t>(max_n, host_graphs[g].n);
+  if (count > 0) {
+    const dim3 cg((unsigned)std::min<int64_t>(64, (max_n + 256) / 256), (unsigned)std::min(count, 4096));
+    for (int32_t pass = 0; pass < 2; ++pass)
+      hipLaunchKernelGGL(k_check_graphs, cg, dim3(256), 0, s, dg, count, pass, p.status);
+  }
   const int grid = std::max(1, p.num_cus);
-  if (!lds_list.empty())
-    hipLaunchKernelGGL((k_switch<true>), dim3(std::min<int64_t>(grid, (int64_t)lds_list.size())), dim3(kSwB), 0, s, dg,
-                       dl, (int32_t)lds_list.size(), nullptr, 0, p.status);
+  // MUT: one slot list per workgroup (both launches run one after the other)
+  int64_t max_m = 1;
+  for (int32_t g = 0; g < count; ++g) max_m = std::max<int64_t>(max_m, host_graphs[g].m);
+  int32_t* perm = mutual ? p.arena.take<int32_t>((size_t)grid * (size_t)max_m) : nullptr;
+  if (!lds_list.empty()) {
+    const dim3 gl((unsigned)std::min<int64_t>(grid, (int64_t)lds_list.size()));
+    if (mutual)
+      hipLaunchKernelGGL((k_switch<true, true>), gl, dim3(kSwB), 0, s, dg, dl, (int32_t)lds_list.size(), nullptr, 0,
+                         perm, max_m, p.status);
+    else
+      hipLaunchKernelGGL((k_switch<true, false>), gl, dim3(kSwB), 0, s, dg, dl, (int32_t)lds_list.size(), nullptr, 0,
+                         nullptr, 0, p.status);
+  }
   if (!glob_list.empty()) {
     const int gw = (int)std::min<int64_t>(grid, (int64_t)glob_list.size());
-    uint32_t* locks = p.arena.take<uint32_t>((size_t)gw * (size_t)max_glob_n);
-    hipLaunchKernelGGL((k_switch<false>), dim3(gw), dim3(kSwB), 0, s, dg, dl + lds_list.size(),
-                       (int32_t)glob_list.size(), locks, max_glob_n, p.status);
+    const int64_t stride = (mutual ? 2 : 1) * max_glob_n;
+    uint32_t* locks = p.arena.take<uint32_t>((size_t)gw * (size_t)stride);
+    if (mutual)
+      hipLaunchKernelGGL((k_switch<false, true>), dim3(gw), dim3(kSwB), 0, s, dg, dl + lds_list.size(),
+                         (int32_t)glob_list.size(), locks, stride, perm, max_m, p.status);
+    else
+      hipLaunchKernelGGL((k_switch<false, false>), dim3(gw), dim3(kSwB), 0, s, dg, dl + lds_list.size(),
+                         (int32_t)glob_list.size(), locks, stride, nullptr, 0, p.status);
   }
   return 0;
 }
 
-size_t switch_bytes(int32_t count, int64_t max_n, int num_cus) {
+size_t switch_bytes(int32_t count, int64_t max_n, int64_t max_m, int num_cus) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  // lock slices and slot lists sized for the mutual-preserving switch (two
+  // words per vertex, one per arc)
+  const size_t wg = (size_t)std::max(1, num_cus);
   return al(sizeof(SwitchGraph) * std::max(count, 1)) + al(sizeof(int32_t) * std::max(count, 1)) +
-         al(sizeof(uint32_t) * (size_t)std::max(1, num_cus) * (size_t)std::max<int64_t>(max_n, 1));
+         al(2 * sizeof(uint32_t) * wg * (size_t)std::max<int64_t>(max_n, 1)) +
+         al(sizeof(int32_t) * wg * (size_t)std::max<int64_t>(max_m, 1));
 }
 
 uint64_t switch_key(uint64_t seed, int64_t graph) { return sm64_mix(seed + (uint64_t)(graph + 1) * kGamma); }
