@@ -391,21 +391,42 @@ def counters_from_csv(dirs: dict, kname: str, workload: str):
     VALU / LDS / vector-memory instructions or waiting, LDS bank conflicts."""
     import csv
     stem, kk = kname.split("<")[0], kname[len(kname.split("<")[0]):]
-    vals = {}
+    vals, copy_vals = {}, {}
     for _, path in dirs.items():
-        per = {}
+        per, cper = {}, {}
         for r in csv.DictReader(open(path)):
             name = r["Kernel_Name"]
+            key = (r["Counter_Name"], r["Dispatch_Id"])
+            if "copy" in name.lower():  # the reference copy of --calibration-copy-mib
+                cper[key] = cper.get(key, 0.0) + float(r["Counter_Value"])
             if not ((f"{stem}<{kk[1:-1]}," in name) if kk else (f"{stem}<" in name)):
                 continue
-            key = (r["Counter_Name"], r["Dispatch_Id"])
             per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
         by = {}
         for (cn, _), v in per.items():
             by.setdefault(cn, []).append(v)
         for cn, vs in by.items():
             vals[cn] = float(np.mean(vs))
+        for (cn, _), v in cper.items():
+            copy_vals[cn] = max(copy_vals.get(cn, 0.0), v)
     d = {}
+    # bytes from the request counts by size (no calibration needed): reads of
+    # 32, 64 and 128 bytes, writes of 64 bytes and the rest of 32 bytes
+    def by_size(v):
+        out = {}
+        if all(c in v for c in ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum")):
+            out["read_bytes_by_request_size"] = (32 * v["TCC_EA0_RDREQ_32B_sum"] + 64 * v["TCC_EA0_RDREQ_64B_sum"] +
+                                                 128 * v["TCC_EA0_RDREQ_128B_sum"])
+            if "TCC_EA0_RDREQ_sum" in v:
+                out["read_requests_other_sizes"] = v["TCC_EA0_RDREQ_sum"] - (
+                    v["TCC_EA0_RDREQ_32B_sum"] + v["TCC_EA0_RDREQ_64B_sum"] + v["TCC_EA0_RDREQ_128B_sum"])
+        if "TCC_EA0_WRREQ_sum" in v and "TCC_EA0_WRREQ_64B_sum" in v:
+            out["write_bytes_by_request_size"] = (64 * v["TCC_EA0_WRREQ_64B_sum"] +
+                                                  32 * (v["TCC_EA0_WRREQ_sum"] - v["TCC_EA0_WRREQ_64B_sum"]))
+        return out
+    d.update(by_size(vals))
+    if copy_vals:
+        d.update({"copy_" + k2: v2 for k2, v2 in by_size(copy_vals).items()})
     if "TCC_HIT_sum" in vals and "TCC_MISS_sum" in vals:
         d["l2_hit_rate"] = round(vals["TCC_HIT_sum"] / max(1.0, vals["TCC_HIT_sum"] + vals["TCC_MISS_sum"]), 3)
     if vals.get("SQ_WAVE_CYCLES", 0) > 0:

@@ -369,7 +369,9 @@ typedef struct motif_tuning {
   int32_t tile;         /* work-queue granularity (1..4096): G* entries per tile,
                            except for the k = 4 and k = 5 core-reuse schemes,
                            where the queue is cut by estimated cost into about
-                           `tile` tiles per workgroup                           */
+                           `tile` tiles per workgroup (fewer on small graphs:
+                           a tile holds at least 128 (k = 4) or 512 (k = 5)
+                           cost units)                                         */
   int32_t heavy;        /* census scheme for k = 4, 5: 1 = core reuse (neighbourhood
                            of the highest-ranked anchor vertex scanned once per
                            work unit), 2 = per-anchor scan; 0 = keep              */

@@ -87,6 +87,12 @@ constexpr int kBigMinDeg = 256;      // ... among vertices of at least this degr
 constexpr int64_t kBigBytes = 512ll << 20;  // ... within this many bytes of tables
 constexpr int kBigRow = 12;          // words per W row (9 used, 16-byte aligned), big-core tables and WG slices
 constexpr int kUnroll = 4;
+// Smallest cost of a work-queue tile of the core-reuse kernels: on small
+// graphs `tile` tiles per workgroup would cut below one core's units, and
+// every tile sets its cores up again (measured best tile costs: about 135
+// for k = 4 and 370-850 for k = 5 on graphs of 10^3-10^5 arcs).
+constexpr int32_t kMinTileCost4 = 128;
+constexpr int32_t kMinTileCost5 = 512;
 constexpr int kBucketShift = 6;     // the row-scan layout records the row at every 64th entry ...
 constexpr int kBuckets = 1024;      // ... for layouts of up to 64 K entries (else plain binary search)         // N+ entries per lane and pass of the flattened scans
 constexpr int kLightDegMax = 256;  // cap of the k = 4 light-side limit (wave hash load <= 1/2)
@@ -1603,7 +1609,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     // and light units (one wave each).
     const int32_t tot_cost = cpre[total];
     const int64_t parts = (int64_t)gridDim.x * (tile > 0 ? tile : 1);
-    const int32_t tc = (int32_t)max((int64_t)1, ((int64_t)tot_cost + parts - 1) / parts);
+    const int32_t tc = (int32_t)max((int64_t)kMinTileCost4, ((int64_t)tot_cost + parts - 1) / parts);
     // The last quarter of the cost is cut four times finer (second counter),
     // so the tiles still running at the end are small.
     const int32_t split = tot_cost - tot_cost / 4, tc_end = max(1, tc / 4);
@@ -1741,7 +1747,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   // light core stay together (one core set-up), a heavy core's are spread.
   const int32_t tot_cost = cpre[total];
   const int64_t parts = (int64_t)gridDim.x * (tile > 0 ? tile : 1);
-  const int32_t tc = (int32_t)max((int64_t)1, ((int64_t)tot_cost + parts - 1) / parts);
+  const int32_t tc = (int32_t)max((int64_t)kMinTileCost5, ((int64_t)tot_cost + parts - 1) / parts);
   const int32_t split = tot_cost - tot_cost / 4, tc_end = max(1, tc / 4);
   for (;;) {
     pull_tile(tot_cost, tc, split, tc_end);
