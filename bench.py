@@ -779,6 +779,53 @@ def bench_serving(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_census6(args):
+    """The k = 6 census (connected 4-set anchors) of a small power-law
+    digraph: one step = one motif_census6 call (validation, G* build, anchor
+    count and list, census, exact division), host-timed; the CPU baseline is
+    the oracle's full ESU census of the same graph on all host cores."""
+    import torch
+    import graphgen as gg
+    import paper_1203_3415_amd as pm
+
+    g = gg.chung_lu(300, 700, 2.3, 2.4, 0.2, seed=62)
+    dev = torch.device("cuda:0")
+    off, idx = pm.to_device(g.out_off, g.out_idx, dev)
+    out = torch.empty(pm.NUM_CLASSES6, dtype=torch.int64, device=dev)
+    for _ in range(max(1, args.warmup)):  # the first call also builds the class table
+        pm.census6(off, idx, g.n, out=out)
+    torch.cuda.synchronize()
+    ref = out.cpu().numpy().view(np.uint64).copy()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pm.census6(off, idx, g.n, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    stable = bool(np.array_equal(out.cpu().numpy().view(np.uint64), ref))
+    line = {"metric": "arcs censused/sec", "value": round(g.m / (ms * 1e-3), 1), "unit": "arcs/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": "chunglu_n300_k6", "n": g.n, "m": g.m, "k": [6],
+                       "generator": "Chung-Lu n=300 m=700 gamma_out=2.3 gamma_in=2.4 reciprocity=0.2 seed=62"},
+            "detail": {"k6": {"connected_sets": int(ref.sum()), "classes_seen": int(np.count_nonzero(ref)),
+                              "step": "whole motif_census6 call"}},
+            "checks": {"stable_across_steps": stable},
+            "roofline": None, "cpu_baseline": None}
+    if not args.no_cpu:
+        import oracle
+        threads = _threads()
+        t = time.perf_counter()
+        d = oracle.census6(g, threads=threads)
+        sec = time.perf_counter() - t
+        by_code = dict(zip((int(c) for c in pm.class6_codes()[np.flatnonzero(ref)]),
+                           (int(v) for v in ref[np.flatnonzero(ref)])))
+        line["checks"]["equals_oracle"] = by_code == d
+        line["cpu_baseline"] = {"value": round(g.m / sec, 1), "unit": "arcs/s", "cores": threads,
+                                "kind": "oracle", "sample": "the full ESU census of the same graph by canonical code",
+                                "seconds": round(sec, 2), "cpu_model": cpu_model()}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -786,7 +833,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="chunglu_n1e5_k34",
                     choices=["chunglu_n1e5_k34", "chunglu_n1e5_k3", "chunglu_n1e5_k4", "gnm_n1000", "chunglu_n2e4_k5",
-                             "nullmodel_k4", "serving"])
+                             "nullmodel_k4", "serving", "chunglu_n300_k6"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--null-graphs", type=int, default=1000)
@@ -826,6 +873,8 @@ def main():
         bench_nullmodel(args)
     elif args.workload == "serving":
         bench_serving(args)
+    elif args.workload == "chunglu_n300_k6":
+        bench_census6(args)
     else:
         bench_census(args)
 
