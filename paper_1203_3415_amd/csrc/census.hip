@@ -691,13 +691,14 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   // The wave paths' tables share the row-scan layout's words: the two are
   // never in use at the same time (workgroup phases are barrier-separated).
   constexpr int TW = K == 4 ? kPairs4 * 3 : 0;
-  constexpr int SEGW = 3 * BLOCK + kBuckets;
+  constexpr int SEGW = (K == 4 ? 4 : 3) * BLOCK + kBuckets;  // k = 4 also keeps each row's label
   constexpr int POOLW = NW * TW > SEGW ? NW * TW : SEGW;
   __shared__ __align__(16) int32_t seg_pool[POOLW];
   int32_t* const seg_v = seg_pool;
   int32_t* const seg_start = seg_pool + BLOCK;
   int32_t* const seg_base = seg_pool + 2 * BLOCK;
   int32_t* const seg_at = seg_pool + 3 * BLOCK;
+  int32_t* const seg_lab = seg_pool + 3 * BLOCK + kBuckets;  // k = 4 only
   uint32_t* const wT = reinterpret_cast<uint32_t*>(seg_pool);
   constexpr int WH = K == 4 ? kWaveHash : 0;  // per-wave hash words
   constexpr int NCN = K == 4 ? NW : kNP5;     // set-size rows: one per wave (k = 4), per light partner (k = 5)
@@ -826,8 +827,10 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     if (s3) atomicAdd(&hist[lut[c0 | rel_code<K>(3u)]], (u64)(int64_t)s3);
   };
   // Flattened scan of the N+ rows of the vertices pick(0 .. items-1): pick
-  // returns a vertex (or -1) and does the per-vertex work, visit(v, f) handles
-  // one entry f of N+(v).  Uniform across the workgroup; ends with a barrier.
+  // returns a vertex (or -1) and does the per-vertex work, visit(v, f, Lv)
+  // handles one entry f of N+(v); for k = 4, Lv is v's label read once per
+  // row after pick (0 for k = 5).  Uniform across the workgroup; ends with a
+  // barrier.
   // seg_ctr alternates between two words so that one of them can be cleared
   // while the other is read.
   // pre() runs once on every thread before the first rows are laid out
@@ -850,6 +853,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
             const int32_t sl = (int32_t)(old >> 32);
             const int32_t start = (int32_t)(uint32_t)old;
             seg_v[sl] = v;
+            if constexpr (K == 4) seg_lab[sl] = (int32_t)lab.get((uint32_t)v);
             seg_start[sl] = start;
             seg_base[sl] = G.np_off[v] - start;  // entry j of the layout is np_idx[seg_base + j]
             // this row holds the bucket boundaries b * 64 in [start, start + len)
@@ -868,11 +872,12 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       // kUnroll entries per thread and pass, their loads issued together
       for (int32_t jb = threadIdx.x; jb < tot; jb += kUnroll * BLOCK) {
         int32_t vv[kUnroll];
-        uint32_t ff[kUnroll];
+        uint32_t ff[kUnroll], ll[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const int32_t j = jb + u * BLOCK;
           vv[u] = -1;
+          ll[u] = 0u;
           if (j < tot) {
             // the row of j lies between the rows of the bucket boundaries around j
             const int32_t b = j >> kBucketShift;
@@ -883,12 +888,13 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
               if (seg_start[mid] <= j) lo = mid; else hi = mid - 1;
             }
             vv[u] = seg_v[lo];
+            if constexpr (K == 4) ll[u] = (uint32_t)seg_lab[lo];
             ff[u] = G.np_idx[seg_base[lo] + j];
           }
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
-          if (vv[u] >= 0) visit(vv[u], ff[u]);
+          if (vv[u] >= 0) visit(vv[u], ff[u], ll[u]);
       }
       bar<GL>();
       par ^= 1;
@@ -912,10 +918,10 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     bar<GL>();
     flat_rows(
         dcn, [&](int32_t i) { return (int32_t)(G.gs_idx[ca + i] & kIdMask); },
-        [&](int32_t y, uint32_t f) {
+        [&](int32_t y, uint32_t f, uint32_t Ly) {
           const int32_t x = (int32_t)(f & kIdMask);
           if (x == c) return;
-          const uint32_t r = f >> kTypeShift, ty = lab.get((uint32_t)y) & 3u;
+          const uint32_t r = f >> kTypeShift, ty = (K == 4 ? Ly : lab.get((uint32_t)y)) & 3u;
           const int32_t h = hub(x);
           if (h >= 0) atomicAdd(&W[h * 9 + (ty - 1) * 3 + (r - 1)], 1u);
           else atomicAdd(&wrow(x)[(ty - 1) * 3 + (r - 1)], 1u);
@@ -945,7 +951,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
           lab.clear_bits((uint32_t)y, 3u);
           return y;
         },
-        [&](int32_t, uint32_t f) {
+        [&](int32_t, uint32_t f, uint32_t) {
           const int32_t x = (int32_t)(f & kIdMask);
           if (x == c || hub(x) >= 0) return;
           uint4* w4 = reinterpret_cast<uint4*>(wrow(x));
@@ -1000,13 +1006,13 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       return q;
     };
     // one edge q -> y of N+(q) with q in R'
-    auto visit = [&](int32_t q, uint32_t f) {
+    auto visit = [&](int32_t q, uint32_t f, uint32_t Lrow) {
       const int32_t y = (int32_t)(f & kIdMask);
       if (y == c) return;
       const uint32_t Ly = lab.get((uint32_t)y);
       const bool sy = is_side(y);
       if (!Ly && !sy) return;
-      const uint32_t Lq = lab.get((uint32_t)q);
+      const uint32_t Lq = K == 4 ? Lrow : lab.get((uint32_t)q);
       const bool mq = !is_side(q), my = !sy;
       const uint32_t r = f >> kTypeShift, cq = Lq & 3u, cy = Ly & 3u;
       // (cq, cy) takes -1, and +1 back when p = q is also counted in W[y]
@@ -1974,7 +1980,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                   flat_rows_pre(
                       na + p5_ctlb[sb][4], pairs,
                       [&](int32_t i) { return i < na ? u5_pick(c, x, xa, i) : c5_pick(x, i - na); },
-                      [&](int32_t q, uint32_t f) { s5_visit(c, x, q, f); });
+                      [&](int32_t q, uint32_t f, uint32_t) { s5_visit(c, x, q, f); });
                 }
                 {
                   const int32_t nd = p5_ctlb[sb][3];

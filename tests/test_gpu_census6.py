@@ -84,3 +84,31 @@ def test_errors(pm):
     with pytest.raises(pm.MotifError) as e:
         pm.census6(off, idx, 2)
     assert e.value.name == "ESELFLOOP"
+
+
+def test_in_csr_checked(pm, codes):
+    g = gg.chung_lu(60, 150, 2.3, 2.3, 0.2, seed=64)
+    off, idx = pm.to_device(g.out_off, g.out_idx)
+    ioff, iidx = pm.to_device(*g.in_csr())
+    h = pm.census6(off, idx, g.n, in_off=ioff, in_idx=iidx)
+    assert {int(codes[c]): int(h[c]) for c in np.flatnonzero(h)} == oracle.census6(g)
+    # one in-arc replaced by an arc that is not in the graph
+    ioff_h, iidx_h = g.in_csr()
+    t = int(np.flatnonzero(np.diff(ioff_h))[0])
+    row = set(iidx_h[ioff_h[t]:ioff_h[t + 1]].tolist())
+    bad = iidx_h.copy()
+    bad[ioff_h[t]] = next(x for x in range(g.n) if x not in row and x != t)
+    ioff2, iidx2 = pm.to_device(ioff_h, bad)
+    with pytest.raises(pm.MotifError) as e:
+        pm.census6(off, idx, g.n, in_off=ioff2, in_idx=iidx2)
+    assert e.value.name == "ETRANSPOSE"
+
+
+def test_too_big_anchor_edge(pm):
+    # a star with 1,100 leaves: every anchor edge has more than 1,024 members
+    star = np.array([(0, i) for i in range(1, 1101)])
+    g = gg.from_arcs(1101, star)
+    off, idx = pm.to_device(g.out_off, g.out_idx)
+    with pytest.raises(pm.MotifError) as e:
+        pm.census6(off, idx, g.n)
+    assert e.value.name == "ETOOBIG"
