@@ -674,7 +674,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   constexpr int C = K == 4 ? 199 : 9364, NL = K == 4 ? 16 : 64, LB = K == 4 ? 4 : 8;
   constexpr int S1 = K - 2, S2 = K - 1;  // member slots
   // LDS rows of W: fewer where the k = 5 counters and labels leave no room
-  constexpr int HUBS = (K == 5 && LCAP == 32768) ? 200 : (K == 4 && LCAP == 65536) ? 384 : kMaxHubs;
+  constexpr int HUBS = (K == 5 && LCAP == 32768) ? 80 : (K == 4 && LCAP == 65536) ? 384 : kMaxHubs;
   constexpr bool GL = LCAP == 0;
   __shared__ u64 hist[C];
   __shared__ uint16_t lut_lds[K == 4 ? 4096 : 1];
@@ -691,14 +691,14 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   // The wave paths' tables share the row-scan layout's words: the two are
   // never in use at the same time (workgroup phases are barrier-separated).
   constexpr int TW = K == 4 ? kPairs4 * 3 : 0;
-  constexpr int SEGW = (K == 4 ? 4 : 3) * BLOCK + kBuckets;  // k = 4 also keeps each row's label
+  constexpr int SEGW = 4 * BLOCK + kBuckets;  // with one word of row information per row
   constexpr int POOLW = NW * TW > SEGW ? NW * TW : SEGW;
   __shared__ __align__(16) int32_t seg_pool[POOLW];
   int32_t* const seg_v = seg_pool;
   int32_t* const seg_start = seg_pool + BLOCK;
   int32_t* const seg_base = seg_pool + 2 * BLOCK;
   int32_t* const seg_at = seg_pool + 3 * BLOCK;
-  int32_t* const seg_lab = seg_pool + 3 * BLOCK + kBuckets;  // k = 4 only
+  int32_t* const seg_lab = seg_pool + 3 * BLOCK + kBuckets;  // rowinfo of each laid-out row
   uint32_t* const wT = reinterpret_cast<uint32_t*>(seg_pool);
   constexpr int WH = K == 4 ? kWaveHash : 0;  // per-wave hash words
   constexpr int NCN = K == 4 ? NW : kNP5;     // set-size rows: one per wave (k = 4), per light partner (k = 5)
@@ -827,15 +827,15 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     if (s3) atomicAdd(&hist[lut[c0 | rel_code<K>(3u)]], (u64)(int64_t)s3);
   };
   // Flattened scan of the N+ rows of the vertices pick(0 .. items-1): pick
-  // returns a vertex (or -1) and does the per-vertex work, visit(v, f, Lv)
-  // handles one entry f of N+(v); for k = 4, Lv is v's label read once per
-  // row after pick (0 for k = 5).  Uniform across the workgroup; ends with a
-  // barrier.
+  // returns a vertex (or -1) and does the per-vertex work, visit(v, f, info)
+  // handles one entry f of N+(v), where info = rowinfo(v) is computed once
+  // per row when the rows are laid out (by default v's label for k = 4, 0 for
+  // k = 5).  Uniform across the workgroup; ends with a barrier.
   // seg_ctr alternates between two words so that one of them can be cleared
   // while the other is read.
   // pre() runs once on every thread before the first rows are laid out
   // (independent work that can share the first pass's latency).
-  auto flat_rows_pre = [&](int32_t items, auto&& pre, auto&& pick, auto&& visit) {
+  auto flat_rows_pre = [&](int32_t items, auto&& pre, auto&& pick, auto&& visit, auto&& rowinfo) {
     if (items <= 0) {
       pre();
       bar<GL>();
@@ -853,7 +853,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
             const int32_t sl = (int32_t)(old >> 32);
             const int32_t start = (int32_t)(uint32_t)old;
             seg_v[sl] = v;
-            if constexpr (K == 4) seg_lab[sl] = (int32_t)lab.get((uint32_t)v);
+            seg_lab[sl] = (int32_t)rowinfo(v);
             seg_start[sl] = start;
             seg_base[sl] = G.np_off[v] - start;  // entry j of the layout is np_idx[seg_base + j]
             // this row holds the bucket boundaries b * 64 in [start, start + len)
@@ -888,7 +888,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
               if (seg_start[mid] <= j) lo = mid; else hi = mid - 1;
             }
             vv[u] = seg_v[lo];
-            if constexpr (K == 4) ll[u] = (uint32_t)seg_lab[lo];
+            ll[u] = (uint32_t)seg_lab[lo];
             ff[u] = G.np_idx[seg_base[lo] + j];
           }
         }
@@ -900,7 +900,9 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       par ^= 1;
     }
   };
-  auto flat_rows = [&](int32_t items, auto&& pick, auto&& visit) { flat_rows_pre(items, [] {}, pick, visit); };
+  auto flat_rows = [&](int32_t items, auto&& pick, auto&& visit) {
+    flat_rows_pre(items, [] {}, pick, visit, [&](int32_t v) { return K == 4 ? lab.get((uint32_t)v) : 0u; });
+  };
   // per-core set-up (labels of N(core), type counts, M, W) and tear-down
   auto core_setup = [&](int32_t c) {
     const int32_t ca = G.gs_off[c], dcn = G.gs_off[c + 1] - ca;
@@ -1450,14 +1452,25 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     return q == a || ((lab.get((uint32_t)q) >> 2) & 3u) ? -1 : q;
   };
   // entry (y, r) of N+(q) for an item q of either part
-  auto s5_visit = [&](int32_t b, int32_t a, int32_t q, uint32_t f) {
+  // row information of q for the merged scan: label << 16 | table slot + 1
+  // (0 when q is no key), found once per row
+  auto s5_rowinfo = [&](int32_t q) -> uint32_t {
+    const uint32_t lq = lab.get((uint32_t)q);
+    const uint32_t h = (lq & kInT5) ? t5_find((uint32_t)q) : (uint32_t)kT5;
+    return (lq << 16) | (h < kT5 ? h + 1u : 0u);
+  };
+  auto s5_visit = [&](int32_t b, int32_t a, int32_t q, uint32_t f, uint32_t qinfo) {
     const int32_t y = (int32_t)(f & kIdMask);
     if (y == b) return;
     const uint32_t r = f >> kTypeShift;
-    const uint32_t lq = lab.get((uint32_t)q), ly = lab.get((uint32_t)y);
-    u64 tq, ty;
-    int32_t pq, py;
-    t5_get((uint32_t)q, lq, tq, pq);
+    const uint32_t lq = qinfo >> 16, ly = lab.get((uint32_t)y);
+    u64 tq = 0ull, ty;
+    int32_t pq = -1, py;
+    if (qinfo & 0xFFFFu) {
+      const uint32_t hq = (qinfo & 0xFFFFu) - 1u;
+      tq = ttyp[hq];
+      pq = (int32_t)tpid[hq] - 1;
+    }
     t5_get((uint32_t)y, ly, ty, py);
     if (q != a && !((lq >> 2) & 3u)) {  // c-part: q is outside N[a]
       const uint32_t cq = lq & 3u;
@@ -1980,7 +1993,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                   flat_rows_pre(
                       na + p5_ctlb[sb][4], pairs,
                       [&](int32_t i) { return i < na ? u5_pick(c, x, xa, i) : c5_pick(x, i - na); },
-                      [&](int32_t q, uint32_t f, uint32_t) { s5_visit(c, x, q, f); });
+                      [&](int32_t q, uint32_t f, uint32_t qi) { s5_visit(c, x, q, f, qi); }, s5_rowinfo);
                 }
                 {
                   const int32_t nd = p5_ctlb[sb][3];
