@@ -718,8 +718,10 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   __shared__ int32_t p5_vb[2][P5], p5_rowb[2][P5], p5_offb[2][P5], p5_ctlb[2][5], p5_dc[P5];
   __shared__ uint16_t tlist[K == 5 ? kT5Load : 1];  // slots of the table's keys
   __shared__ uint32_t p5_baseb[2][P5], p5_db[P5];
-  // k = 4: the workgroup path's move table (kept zero between anchors)
+  // k = 4: the workgroup path's move table (kept zero between anchors), and
+  // the label pair (a, b) of each table slot
   __shared__ __align__(16) uint32_t bT[K == 4 ? TW : 1];
+  __shared__ uint8_t pair_a[K == 4 ? kPairs4 : 1], pair_b[K == 4 ? kPairs4 : 1];
   __shared__ int32_t unit_list[BLOCK], unit_ctr[3];
   __shared__ int32_t lbk[K == 4 ? 32 : 1];  // k = 4 light units: counts and fills per log2 degree bucket
   __shared__ uint32_t lds_labels[LCAP > 0 ? LCAP / 4 : 1];
@@ -746,8 +748,15 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     for (int i = threadIdx.x; i < kU5; i += BLOCK) U5[i] = 0u;
     if (threadIdx.x < 32) cnUb[threadIdx.x >> 4][threadIdx.x & 15] = 0;
   }
-  if (K == 4)
+  if (K == 4) {
     for (int i = threadIdx.x; i < TW; i += BLOCK) bT[i] = 0u;
+    if (threadIdx.x < 15)  // pairs (a, b), 1 <= a <= b <= 15, row a from slot pair_slot4(a, a)
+      for (uint32_t b = threadIdx.x + 1u; b <= 15u; ++b) {
+        const uint32_t t = pair_slot4(threadIdx.x + 1u, b);
+        pair_a[t] = (uint8_t)(threadIdx.x + 1u);
+        pair_b[t] = (uint8_t)b;
+      }
+  }
   if (LCAP > 0)
     for (int i = threadIdx.x; i < LCAP / 4; i += BLOCK) lds_labels[i] = 0u;
   __syncthreads();
@@ -806,12 +815,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   // member pairs go to its no-edge class, then each counted move takes one
   // from there to the class with the edge.  zero: clear the pair's counts.
   auto t_close = [&](const int32_t* cntv, uint32_t* T, uint32_t base, int32_t t, bool zero) {
-    int32_t a0 = 0, rem = t;
-    while (rem >= 15 - a0) {
-      rem -= 15 - a0;
-      ++a0;
-    }
-    const uint32_t La = (uint32_t)a0 + 1u, Lb = La + (uint32_t)rem;
+    const uint32_t La = pair_a[t], Lb = pair_b[t];
     const u64 na = (u64)cntv[La], nb = (u64)cntv[Lb];
     const int32_t s1 = (int32_t)T[3 * t], s2 = (int32_t)T[3 * t + 1], s3 = (int32_t)T[3 * t + 2];
     if (zero) {
