@@ -46,7 +46,7 @@ struct DeviceState {
   std::map<TuneKey, Tuning> tuned;  // filled by motif_autotune / motif_tune_cache_load
   // per-stream buffer of the randomised copies made by motif_null_model
   std::map<hipStream_t, std::pair<int32_t*, size_t>> null_copies;
-  // k = 6 class table, built on first use; t6_rc: 1 = not built yet, else its outcome
+  // k = 6 class table, built on first use (t6_rc 0 once built)
   Tables6 t6;
   int32_t t6_rc = 1;
 };
@@ -609,12 +609,16 @@ int32_t motif_census(const int32_t* out_off, const int32_t* out_idx, const int32
 
 // ---- k = 6 ----
 
-// The k = 6 class table of device dev (current), built once.
+// The k = 6 class table of device dev (current), built once; a failed build
+// (say, out of device memory) is tried again by the next call.
 static int32_t ensure_tables6(int dev, const Tables6** out) {
   std::lock_guard<std::mutex> lk(g_mu);
   DeviceState& d = g_dev[dev];
-  if (d.t6_rc == 1) d.t6_rc = build_tables6(&d.t6);
-  if (d.t6_rc) return d.t6_rc;
+  if (d.t6_rc != 0) {
+    const int32_t rc = build_tables6(&d.t6);
+    d.t6_rc = rc == 0 ? 0 : 1;
+    if (rc) return rc;
+  }
   *out = &d.t6;
   return 0;
 }
