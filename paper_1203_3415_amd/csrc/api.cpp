@@ -377,19 +377,25 @@ int32_t run_census_multi_on(Pipeline& p, const BuildInput& in, int32_t nk, const
 int32_t run_census_multi_enqueue(Pipeline& p, const BuildInput& in, int32_t nk, const int32_t* ks,
                                  uint64_t* const* hists, hipStream_t s) {
   p.arena.reset();
-  enqueue_zero(p.status, sizeof(int32_t) * kStatusWords, s);
-  for (int32_t i = 0; i < nk; ++i) profile_mark(ks[i], 0, true, s);  // the shared build, seen by every k
-  DevGraph g = enqueue_build(p, in, s);
-  for (int32_t i = 0; i < nk; ++i) profile_mark(ks[i], 0, false, s);
-  int32_t top = 0;
-  for (int32_t i = 1; i < nk; ++i)
-    if (ks[i] > ks[top]) top = i;
   if (nk > 1) {
     if (!p.side && hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) != hipSuccess) return MOTIF_EDEVICE;
     if (!p.ev_fork && hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming) != hipSuccess) return MOTIF_EDEVICE;
     if (!p.ev_join && hipEventCreateWithFlags(&p.ev_join, hipEventDisableTiming) != hipSuccess) return MOTIF_EDEVICE;
-    if (hipEventRecord(p.ev_fork, s) != hipSuccess || hipStreamWaitEvent(p.side, p.ev_fork, 0) != hipSuccess)
-      return MOTIF_EDEVICE;
+  }
+  enqueue_zero(p.status, sizeof(int32_t) * kStatusWords, s);
+  for (int32_t i = 0; i < nk; ++i) profile_mark(ks[i], 0, true, s);  // the shared build, seen by every k
+  // the second stream starts as soon as G* and N+ are written: the in-CSR
+  // check and the largest size's set-up overlap its census (a failed check
+  // still blocks every output: the divisions run after the join)
+  bool ready_ok = true;
+  DevGraph g = enqueue_build(p, in, s, nk > 1 ? p.ev_fork : nullptr, &ready_ok);
+  for (int32_t i = 0; i < nk; ++i) profile_mark(ks[i], 0, false, s);
+  int32_t top = 0;
+  for (int32_t i = 1; i < nk; ++i)
+    if (ks[i] > ks[top]) top = i;
+  if (nk > 1 && (!ready_ok || hipStreamWaitEvent(p.side, p.ev_fork, 0) != hipSuccess)) {
+    (void)hipStreamSynchronize(s);  // best effort: the error is what the caller acts on
+    return MOTIF_EDEVICE;
   }
   uint64_t* acc = p.arena.take<uint64_t>((size_t)in.ngraphs * motif_num_classes(ks[top]));
   enqueue_census(p, g, ks[top], acc, hists[top], s, true);

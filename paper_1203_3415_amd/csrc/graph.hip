@@ -700,7 +700,7 @@ BuildInput enqueue_pack(Pipeline& p, const motif_graph_t* graphs, int32_t count,
   return in;
 }
 
-DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s) {
+DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s, hipEvent_t graph_ready, bool* ready_ok) {
   Arena& A = p.arena;
   const int32_t n = in.n;
   const int64_t m = in.m;
@@ -736,7 +736,10 @@ DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s) {
   g.max_graph_n = in.gid ? in.max_graph_n : n;
   g.gs_row = gs_row;
   g.gs_cap = 2 * m + 1;
-  if (n == 0) return g;
+  if (n == 0) {
+    if (graph_ready) *ready_ok = hipEventRecord(graph_ready, s) == hipSuccess;
+    return g;
+  }
 
   enqueue_zero(in_cnt, sizeof(int32_t) * (n + 1), s);
   if (!in.gid) hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.out_off, n, m, st);
@@ -766,6 +769,8 @@ DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_off, dim3(grid_for(n + 1)), dim3(kB), 0, s, flags, gs_off, n, np_off, st);
   hipLaunchKernelGGL(k_write_plus, dim3(grid_for(2 * m)), dim3(kB), 0, s, gs_idx, flags, gs_row, deg, gs_off, n,
                      np_idx, st);
+  // G* and N+ are complete here; the in-CSR check below only compares
+  if (graph_ready) *ready_ok = hipEventRecord(graph_ready, s) == hipSuccess;
   if (in.in_off) {
     if (!in.gid) hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.in_off, n, m, st);
     hipLaunchKernelGGL(k_check_in_rows, dim3(grid_for(n)), dim3(kB), 0, s, in.in_off, in_cnt, n, in.gid, in.has_in,

@@ -148,9 +148,12 @@ struct BuildInput {
   bool copy_error = false;          // a host-to-device copy could not be enqueued
 };
 
-// Enqueue validation + G* + N+ build.  Returns the built view (device pointers
-// into the arena).  Does not wait.
-DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s);
+// Enqueue validation + G* + N+ build, then the in-CSR check when an in-CSR
+// is given.  Returns the built view (device pointers into the arena).  Does
+// not wait.  graph_ready (optional): recorded on s once G* and N+ are
+// written, before the in-CSR check (*ready_ok: whether the record succeeded).
+DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s, hipEvent_t graph_ready = nullptr,
+                       bool* ready_ok = nullptr);
 
 // Enqueue the census of k into acc[ngraphs * C] (accumulators, zeroed here)
 // and, unless out is null, the exact division into out[ngraphs * C] (written
