@@ -2169,13 +2169,19 @@ __global__ void k_big_labels(DevGraph G, const int32_t* hs, const int32_t* big_l
 
 // W rows and M counts of each big core (the per-core set-up of the core-reuse
 // kernel, done once): thread (entry y of the core's row, lane s of 4) takes
-// every fourth entry of N+(y).
+// every fourth entry of N+(y).  The rows of hub vertices, which many entries
+// hit, are summed in LDS first and added once per workgroup (their global
+// atomics otherwise queue up on a few addresses).
 __global__ __launch_bounds__(256) void k_core_tables(DevGraph G, const int32_t* hs, const int32_t* big_list,
                                                      const uint32_t* lbig, int64_t lstride, uint32_t* wbig,
-                                                     int64_t wstride, uint32_t* mbig, const int32_t* st) {
+                                                     int64_t wstride, uint32_t* mbig, const int32_t* hub_id,
+                                                     const int32_t* st) {
   __shared__ uint32_t M[27];
+  __shared__ uint32_t Wh[kMaxHubs * 9];
+  __shared__ int32_t hubx[kMaxHubs];
   if (st[kStatus] != 0 || (int32_t)blockIdx.y >= min(hs[35], kMaxBig)) return;
   if (threadIdx.x < 27) M[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < kMaxHubs * 9; i += 256) Wh[i] = 0u;
   __syncthreads();
   const int32_t b = blockIdx.y, c = big_list[b];
   const int64_t wbase = G.voff ? G.voff[G.gid[c]] : 0;
@@ -2193,13 +2199,21 @@ __global__ __launch_bounds__(256) void k_core_tables(DevGraph G, const int32_t* 
       if (x == c) continue;
       const uint32_t r = f >> kTypeShift;
       const int64_t xl = (int64_t)x - wbase;
-      atomicAdd(&Wb[xl * kBigRow + (ty - 1) * 3 + (r - 1)], 1u);
+      const int32_t h = hub_id[x];
+      if (h >= 0) {
+        hubx[h] = x;
+        atomicAdd(&Wh[h * 9 + (ty - 1) * 3 + (r - 1)], 1u);
+      } else {
+        atomicAdd(&Wb[xl * kBigRow + (ty - 1) * 3 + (r - 1)], 1u);
+      }
       const uint32_t tx = (L[xl >> 4] >> (2 * (xl & 15))) & 3u;
       if (tx) atomicAdd(&M[(ty - 1) * 9 + (tx - 1) * 3 + (r - 1)], 1u);
     }
   }
   __syncthreads();
   if (threadIdx.x < 27 && M[threadIdx.x]) atomicAdd(&mbig[b * 32 + threadIdx.x], M[threadIdx.x]);
+  for (int i = threadIdx.x; i < kMaxHubs * 9; i += 256)
+    if (Wh[i]) atomicAdd(&Wb[((int64_t)hubx[i / 9] - wbase) * kBigRow + i % 9], Wh[i]);
 }
 
 // =========================================================== finalise ==
@@ -2354,7 +2368,7 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
         if (nbig > 0) {
           hipLaunchKernelGGL(k_big_labels, dim3(16, nbig), dim3(256), 0, s, g, hs, big_list, lbig, lstride, p.status);
           hipLaunchKernelGGL(k_core_tables, dim3(64, nbig), dim3(256), 0, s, g, hs, big_list, lbig, lstride, wbig,
-                             wbig_stride, mbig, p.status);
+                             wbig_stride, mbig, hub_id, p.status);
         }
       }
       const int32_t* cpre = nullptr;

@@ -30,6 +30,8 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kB * kScanItems;
 constexpr int kSmallRow = 64;     // rows up to this length: sorted by one thread, in registers
 constexpr int kMidRow = 4096;     // rows up to this length: LDS bitonic sort
+constexpr int kWaveRow = 1024;    // ... by one wave when at most this long, else by the workgroup
+constexpr int kLdsBitmapWords = 16384;  // big rows: the key bitmap sits in LDS when 2n bits fit in 64 KB
 constexpr int kBigSlots = 32;     // concurrent bitmap sorts
 
 __device__ __forceinline__ void set_status(int32_t* st, int32_t code) { atomicMin(&st[kStatus], code); }
@@ -332,11 +334,50 @@ __global__ __launch_bounds__(kB) void k_sort_small(const int32_t* hoff, int32_t 
 __global__ __launch_bounds__(kB) void k_sort_mid(const int32_t* hoff, uint32_t* keys, const int32_t* midq,
                                                  const int32_t* st) {
   __shared__ uint32_t s[kMidRow];
+  static_assert(kB / 64 * kWaveRow <= kMidRow, "one LDS slice per wave");
   if (st[kStatus] != 0) return;
   const int32_t count = st[kMidCount];
+  // rows of at most kWaveRow keys: one wave each, in its own LDS slice, with
+  // no workgroup barrier (most mid rows are a few hundred keys)
+  {
+    const int32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t* ws = s + wv * kWaveRow;
+    auto wave_sync = [] {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    for (int32_t q = blockIdx.x * (kB / 64) + wv; q < count; q += gridDim.x * (kB / 64)) {
+      const int32_t v = midq[q];
+      const int32_t a = hoff[v], len = hoff[v + 1] - a;
+      if (len > kWaveRow) continue;
+      int P = 1;
+      while (P < len) P <<= 1;
+      for (int i = lane; i < P; i += 64) ws[i] = i < len ? keys[a + i] : 0xFFFFFFFFu;
+      wave_sync();
+      for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          for (int i = lane; i < P; i += 64) {
+            const int ij = i ^ j;
+            if (ij > i) {
+              const uint32_t x = ws[i], y = ws[ij];
+              const bool up = (i & k) == 0;
+              if ((x > y) == up) { ws[i] = y; ws[ij] = x; }
+            }
+          }
+          wave_sync();
+        }
+      }
+      for (int i = lane; i < len; i += 64) keys[a + i] = ws[i];
+      wave_sync();
+    }
+  }
+  __syncthreads();
+  // longer rows: the whole workgroup
   for (int32_t q = blockIdx.x; q < count; q += gridDim.x) {
     const int32_t v = midq[q];
     const int32_t a = hoff[v], len = hoff[v + 1] - a;
+    if (len <= kWaveRow) continue;
     int P = 1;
     while (P < len) P <<= 1;
     for (int i = threadIdx.x; i < P; i += kB) s[i] = i < len ? keys[a + i] : 0xFFFFFFFFu;
@@ -361,13 +402,15 @@ __global__ __launch_bounds__(kB) void k_sort_mid(const int32_t* hoff, uint32_t* 
 
 // Big rows: set one bit per key in a bitmap over [0, 2n), then compact in
 // order.  A key seen twice is a repeated arc.
+template <bool LDS>
 __global__ __launch_bounds__(kB) void k_sort_big(const int32_t* hoff, int32_t n, uint32_t* keys,
                                                  const int32_t* bigq, uint32_t* bitmaps, int32_t* st) {
   __shared__ int32_t sh[kB / 64];
+  __shared__ uint32_t lbm[LDS ? kLdsBitmapWords : 1];
   if (st[kStatus] != 0) return;
   const int32_t count = st[kBigCount];
   const int64_t words = ((int64_t)2 * n + 31) / 32;
-  uint32_t* bm = bitmaps + (int64_t)blockIdx.x * words;
+  uint32_t* bm = LDS ? lbm : bitmaps + (int64_t)blockIdx.x * words;
   const int64_t per = (words + kB - 1) / kB;
   for (int32_t q = blockIdx.x; q < count; q += gridDim.x) {
     const int32_t v = bigq[q];
@@ -754,7 +797,10 @@ DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s, hipEven
                        hrow, st);
   hipLaunchKernelGGL(k_sort_small, dim3(grid_for(n)), dim3(kB), 0, s, hoff, n, keys, midq, bigq, st);
   hipLaunchKernelGGL(k_sort_mid, dim3(512), dim3(kB), 0, s, hoff, keys, midq, st);
-  hipLaunchKernelGGL(k_sort_big, dim3(kBigSlots), dim3(kB), 0, s, hoff, n, keys, bigq, bitmaps, st);
+  if ((2 * (int64_t)n + 31) / 32 <= kLdsBitmapWords)
+    hipLaunchKernelGGL((k_sort_big<true>), dim3(kBigSlots), dim3(kB), 0, s, hoff, n, keys, bigq, bitmaps, st);
+  else
+    hipLaunchKernelGGL((k_sort_big<false>), dim3(kBigSlots), dim3(kB), 0, s, hoff, n, keys, bigq, bitmaps, st);
   // merge: flags over the 2m sorted half-edges, one scan gives offsets and positions
   hipLaunchKernelGGL(k_entry_flags, dim3(grid_for(2 * m + 1)), dim3(kB), 0, s, keys, hrow, hoff, 2 * m, flags, st);
   scan_excl(flags, 2 * m + 1, scratch, s);
