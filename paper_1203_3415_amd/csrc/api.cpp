@@ -377,41 +377,53 @@ int32_t run_census_multi_on(Pipeline& p, const BuildInput& in, int32_t nk, const
 int32_t run_census_multi_enqueue(Pipeline& p, const BuildInput& in, int32_t nk, const int32_t* ks,
                                  uint64_t* const* hists, hipStream_t s) {
   p.arena.reset();
-  if (nk > 1) {
+  // A second stream takes the in-CSR check and every size but the largest,
+  // so that neither delays the largest census on the caller's stream.
+  const bool fork = nk > 1 || in.in_off != nullptr;
+  if (fork) {
     if (!p.side && hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) != hipSuccess) return MOTIF_EDEVICE;
     if (!p.ev_fork && hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming) != hipSuccess) return MOTIF_EDEVICE;
     if (!p.ev_join && hipEventCreateWithFlags(&p.ev_join, hipEventDisableTiming) != hipSuccess) return MOTIF_EDEVICE;
   }
   enqueue_zero(p.status, sizeof(int32_t) * kStatusWords, s);
   for (int32_t i = 0; i < nk; ++i) profile_mark(ks[i], 0, true, s);  // the shared build, seen by every k
-  // the second stream starts as soon as G* and N+ are written: the in-CSR
-  // check and the largest size's set-up overlap its census (a failed check
-  // still blocks every output: the divisions run after the join)
-  bool ready_ok = true;
-  DevGraph g = enqueue_build(p, in, s, nk > 1 ? p.ev_fork : nullptr, &ready_ok);
+  InCheck check;
+  DevGraph g = enqueue_build(p, in, s, nullptr, nullptr, fork ? &check : nullptr);
   for (int32_t i = 0; i < nk; ++i) profile_mark(ks[i], 0, false, s);
   int32_t top = 0;
   for (int32_t i = 1; i < nk; ++i)
     if (ks[i] > ks[top]) top = i;
-  if (nk > 1 && (!ready_ok || hipStreamWaitEvent(p.side, p.ev_fork, 0) != hipSuccess)) {
+  uint64_t* acc[3] = {};  // nk <= 3 (checked by the entry point)
+  acc[top] = p.arena.take<uint64_t>((size_t)in.ngraphs * motif_num_classes(ks[top]));
+  // the second stream starts once the largest census has done the clears
+  // and small kernels of its set-up (G* and N+ are complete by then)
+  bool side_ok = true;
+  enqueue_census(p, g, ks[top], acc[top], fork ? nullptr : hists[top], s, true, fork ? p.ev_fork : nullptr,
+                 &side_ok);
+  if (fork && (!side_ok || hipStreamWaitEvent(p.side, p.ev_fork, 0) != hipSuccess)) {
     (void)hipStreamSynchronize(s);  // best effort: the error is what the caller acts on
+    (void)hipStreamSynchronize(p.side);
     return MOTIF_EDEVICE;
   }
-  uint64_t* acc = p.arena.take<uint64_t>((size_t)in.ngraphs * motif_num_classes(ks[top]));
-  enqueue_census(p, g, ks[top], acc, hists[top], s, true);
-  uint64_t* side_acc[3] = {};  // nk <= 3 (checked by the entry point)
   for (int32_t i = 0; i < nk; ++i) {
     if (i == top) continue;
-    side_acc[i] = p.arena.take<uint64_t>((size_t)in.ngraphs * motif_num_classes(ks[i]));
-    enqueue_census(p, g, ks[i], side_acc[i], nullptr, p.side, false);
+    acc[i] = p.arena.take<uint64_t>((size_t)in.ngraphs * motif_num_classes(ks[i]));
+    enqueue_census(p, g, ks[i], acc[i], nullptr, p.side, false);
   }
-  if (nk > 1 && (hipEventRecord(p.ev_join, p.side) != hipSuccess || hipStreamWaitEvent(s, p.ev_join, 0) != hipSuccess))
+  if (!fork) return read_status(p, s);
+  // after the smaller sizes: the check then runs beside the largest census
+  // rather than beside its set-up
+  enqueue_check_in(in, g, check, p.status, p.side, true);
+  if (hipEventRecord(p.ev_join, p.side) != hipSuccess || hipStreamWaitEvent(s, p.ev_join, 0) != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(p.side);
     return MOTIF_EDEVICE;
-  // The side censuses' divisions run after the join, on the caller's stream:
-  // launched on the side stream they would wait for compute units that the
+  }
+  // Every division runs after the join, on the caller's stream: a failed
+  // in-CSR check then leaves every output unwritten, and the side sizes'
+  // divisions do not wait on the second stream for compute units that the
   // largest census holds until its end.
-  for (int32_t i = 0; i < nk; ++i)
-    if (i != top) enqueue_finalise(p, ks[i], in.ngraphs, side_acc[i], hists[i], s);
+  for (int32_t i = 0; i < nk; ++i) enqueue_finalise(p, ks[i], in.ngraphs, acc[i], hists[i], s);
   return read_status(p, s);
 }
 

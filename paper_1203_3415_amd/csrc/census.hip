@@ -37,6 +37,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "scan.h"
 
 namespace motif {
 
@@ -1625,7 +1626,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
 
   if constexpr (K == 4) {
     // Tiles of G* entries cut by estimated cost: cpre is the exclusive prefix
-    // sum of a per-entry cost (k_unit_cost4), and a tile is the run of
+    // sum of a per-entry cost (UnitCost4), and a tile is the run of
     // entries whose prefix falls in one cost interval of the queue, about
     // `tile` tiles per workgroup.  Within a tile, the entries of one core
     // row are sorted into heavy units (whole workgroup, one after another)
@@ -1765,7 +1766,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     return;
   }
 
-  // Tiles of units cut by estimated cost (k_unit_cost5) as for k = 4, about
+  // Tiles of units cut by estimated cost (UnitCost5) as for k = 4, about
   // `tile` per workgroup, the last quarter four times finer: the units of a
   // light core stay together (one core set-up), a heavy core's are spread.
   const int32_t tot_cost = cpre[total];
@@ -2060,45 +2061,42 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
 // Per-entry cost estimate of the k = 4 core-reuse kernel, for cutting its
 // work queue into tiles of similar cost: 1 for an entry that is not a unit,
 // else a fixed part (larger for a heavy unit, which takes the whole
-// workgroup) plus a quarter of the side's degree.  Clamped to cmax so that
-// the prefix sum stays below 2^31; any positive costs give a correct tiling.
-__global__ void k_unit_cost4(DevGraph G, int32_t cmax, int32_t light_deg, int32_t* cost, const int32_t* st) {
-  if (st[kStatus] != 0) return;
-  const int32_t total = G.gs_off[G.n];
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < G.gs_cap; j += (int64_t)gridDim.x * blockDim.x) {
-    int32_t c = 0;
-    if (j < total) {
-      const int32_t r = G.gs_row[j], x = (int32_t)(G.gs_idx[j] & kIdMask);
-      const int32_t dr = G.gs_off[r + 1] - G.gs_off[r], dx = G.gs_off[x + 1] - G.gs_off[x];
-      c = 1;
-      if (dx < dr || (dx == dr && x < r)) c = min(cmax, (dx > light_deg ? 40 : 4) + (dx >> 2));
-    }
-    cost[j] = c;
+// workgroup) plus a quarter of the side's degree; 0 past the last entry.
+// Clamped to cmax so that the prefix sum stays below 2^31; any positive costs
+// give a correct tiling.  The values are scanned as they are computed.
+struct UnitCost4 {
+  DevGraph G;
+  int32_t cmax, light_deg;
+  __device__ int32_t operator()(int64_t j) const {
+    if (j >= G.gs_off[G.n]) return 0;
+    const int32_t r = G.gs_row[j], x = (int32_t)(G.gs_idx[j] & kIdMask);
+    const int32_t dr = G.gs_off[r + 1] - G.gs_off[r], dx = G.gs_off[x + 1] - G.gs_off[x];
+    if (dx < dr || (dx == dr && x < r)) return min(cmax, (dx > light_deg ? 40 : 4) + (dx >> 2));
+    return 1;
   }
-}
+};
 
 // The same for the k = 5 core-reuse kernel: every G* entry (b, a) is a unit
 // whose partners are about half of b's row, taken in sub-chunks, so its cost
 // grows with d*(b); the fixed part covers the unit's labels and barriers.
-__global__ void k_unit_cost5(DevGraph G, int32_t cmax, int32_t* cost, const int32_t* st) {
-  if (st[kStatus] != 0) return;
-  const int32_t total = G.gs_off[G.n];
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < G.gs_cap; j += (int64_t)gridDim.x * blockDim.x) {
-    int32_t c = 0;
-    if (j < total) {
-      const int32_t r = G.gs_row[j];
-      c = min(cmax, 8 + (G.gs_off[r + 1] - G.gs_off[r]));
-    }
-    cost[j] = c;
+struct UnitCost5 {
+  DevGraph G;
+  int32_t cmax;
+  __device__ int32_t operator()(int64_t j) const {
+    if (j >= G.gs_off[G.n]) return 0;
+    const int32_t r = G.gs_row[j];
+    return min(cmax, 8 + (G.gs_off[r + 1] - G.gs_off[r]));
   }
-}
+};
 
 // Hub slots for the core-reuse scheme: the vertices of largest degree get one
 // of kMaxHubs rows of the per-core W table; the threshold is the smallest
 // power of two whose degree bucket and all above hold at most kMaxHubs
-// vertices (and at least 32).  hs[0..31] = counts per floor(log2 d),
-// hs[32] = threshold, hs[33] = slot counter.  Which vertices get slots never
-// changes the result, only where the work goes.
+// vertices (and at least 32).  The same buckets choose the big cores (at most
+// nbig, degree >= kBigMinDeg).  hs[0..31] = counts per floor(log2 d),
+// hs[33] = hub slot counter, hs[35] = big-core slot counter (all zero at the
+// start).  Which vertices get slots never changes the result, only where the
+// work goes.
 __global__ void k_degree_buckets(const int32_t* gs_off, int32_t n, int32_t* hs, const int32_t* st) {
   __shared__ int32_t b[32];
   if (st[kStatus] != 0) return;
@@ -2112,26 +2110,23 @@ __global__ void k_degree_buckets(const int32_t* gs_off, int32_t n, int32_t* hs, 
   if (threadIdx.x < 32 && b[threadIdx.x]) atomicAdd(&hs[threadIdx.x], b[threadIdx.x]);
 }
 
-//
-// The same buckets choose the big cores (at most nbig, degree >= kBigMinDeg):
-// hs[34] = their threshold, hs[35] = their slot counter.
-__global__ void k_hub_threshold(int32_t* hs, int32_t nbig, const int32_t* st) {
-  if (st[kStatus] != 0 || threadIdx.x != 0) return;
-  int32_t cum = 0, b = 30;
-  while (b > 5 && cum + hs[b] <= kMaxHubs) cum += hs[b--];
-  hs[32] = 1 << (b + 1);
-  hs[33] = 0;
-  cum = 0;
-  b = 30;
-  while ((1 << b) >= kBigMinDeg && cum + hs[b] <= nbig) cum += hs[b--];
-  hs[34] = b == 30 ? 0x7fffffff : 1 << (b + 1);
-  hs[35] = 0;
-}
-
+// Every workgroup derives both thresholds from the buckets, then hands out
+// the slots.
 __global__ void k_assign_hubs(const int32_t* gs_off, int32_t n, int32_t* hs, int32_t* hub_id, int32_t nbig,
                               int32_t* big_id, int32_t* big_list, const int32_t* st) {
+  __shared__ int32_t thr[2];
   if (st[kStatus] != 0) return;
-  const int32_t t = hs[32], tb = hs[34];
+  if (threadIdx.x == 0) {
+    int32_t cum = 0, b = 30;
+    while (b > 5 && cum + hs[b] <= kMaxHubs) cum += hs[b--];
+    thr[0] = 1 << (b + 1);
+    cum = 0;
+    b = 30;
+    while ((1 << b) >= kBigMinDeg && cum + hs[b] <= nbig) cum += hs[b--];
+    thr[1] = b == 30 ? 0x7fffffff : 1 << (b + 1);
+  }
+  __syncthreads();
+  const int32_t t = thr[0], tb = thr[1];
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const int32_t d = gs_off[v + 1] - gs_off[v];
     int32_t h = -1;
@@ -2272,8 +2267,8 @@ size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int nu
   if (reuse)
     b += al(sizeof(int32_t) * (N + 1)) + al(64 * sizeof(int32_t)) +
          al(sizeof(uint32_t) * kBigRow * (size_t)(maxn > 0 ? maxn : N) * grid_size(t, num_cus));
-  if (reuse)  // cost prefix of the G* entries and its scan scratch
-    b += al(sizeof(int32_t) * (2 * M + 1)) + al(sizeof(int32_t) * (size_t)scan_scratch(2 * M + 1));
+  if (reuse)  // cost prefix of the G* entries and its look-back words
+    b += al(sizeof(int32_t) * (2 * M + 1)) + scan1_bytes(2 * M + 1);
   if (reuse) {
     const int64_t mn = maxn > 0 ? maxn : N;
     const int nb = big_slots(mn);
@@ -2305,13 +2300,22 @@ size_t w_slice_bytes(int k, int64_t maxn, const Tuning& t, int num_cus) {
 }
 
 void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64_t* out, hipStream_t s,
-                    bool use_wpool) {
+                    bool use_wpool, hipEvent_t side_start, bool* side_ok) {
+  bool forked = side_start == nullptr;
+  auto fork_side = [&] {
+    if (forked) return;
+    forked = true;
+    *side_ok = hipEventRecord(side_start, s) == hipSuccess;
+  };
   const DevTables& T = dev_tables();
   const int C = num_classes(k);
   const int64_t total = (int64_t)g.ngraphs * C;
-  enqueue_zero(acc, sizeof(uint64_t) * total, s);
+  // every region the set-up needs cleared goes into one batch, launched
+  // before the first kernel that reads any of them
+  ZeroBatch z;
+  z.add(acc, sizeof(uint64_t) * total);
   int32_t* queue = p.arena.take<int32_t>(64);
-  enqueue_zero(queue, 64 * sizeof(int32_t), s);
+  z.add(queue, 64 * sizeof(int32_t));
   const Tuning& t = p.tune.k[k];
   const int grid = grid_size(t, p.num_cus);
   const Limits lim{std::min(t.solo_deg, kSoloDegMax), std::min(t.light_deg, kLightDegMax),
@@ -2319,6 +2323,8 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
   bool marked = false;  // the profiling events bracket the main census kernel only
   if (g.n > 0) {
     if (k == 3) {
+      enqueue_zero_batch(z, s);
+      fork_side();
       profile_mark(k, 1, true, s);
       marked = true;
       hipLaunchKernelGGL((k3_kernel<256>), dim3(grid), dim3(256), 0, s, g, T.lut[3], acc, p.status, queue,
@@ -2330,7 +2336,7 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
       uint32_t* glabels = nullptr;
       if (cap == 0) {
         glabels = p.arena.take<uint32_t>((size_t)lw * grid);
-        enqueue_zero(glabels, sizeof(uint32_t) * (size_t)lw * grid, s);
+        z.add(glabels, sizeof(uint32_t) * (size_t)lw * grid);
       }
       int32_t* hub_id = nullptr;
       uint32_t* wg = nullptr;
@@ -2346,44 +2352,47 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
         lbig = p.arena.take<uint32_t>((size_t)nbig * lstride);
         wbig = p.arena.take<uint32_t>((size_t)nbig * wbig_stride);
         mbig = p.arena.take<uint32_t>(32 * kMaxBig);
-        enqueue_zero(lbig, sizeof(uint32_t) * (size_t)nbig * lstride, s);
-        enqueue_zero(wbig, sizeof(uint32_t) * (size_t)nbig * wbig_stride, s);
-        enqueue_zero(mbig, sizeof(uint32_t) * 32 * kMaxBig, s);
+        z.add(lbig, sizeof(uint32_t) * (size_t)nbig * lstride);
+        z.add(wbig, sizeof(uint32_t) * (size_t)nbig * wbig_stride);
+        z.add(mbig, sizeof(uint32_t) * 32 * kMaxBig);
       }
+      int32_t* hs = nullptr;
+      int32_t* cost = nullptr;
+      Scan1 sc_cost;
       if (reuse) {
         ws = kBigRow * (int64_t)(g.max_graph_n > 0 ? g.max_graph_n : g.n);
         if (use_wpool && p.wpool && p.wpool_bytes >= sizeof(uint32_t) * (size_t)ws * grid) {
           wg = p.wpool;  // all zero: every earlier census cleared the rows it used
         } else {
           wg = p.arena.take<uint32_t>((size_t)ws * grid);
-          enqueue_zero(wg, sizeof(uint32_t) * (size_t)ws * grid, s);
+          z.add(wg, sizeof(uint32_t) * (size_t)ws * grid);
         }
         hub_id = p.arena.take<int32_t>(g.n + 1);
-        int32_t* hs = p.arena.take<int32_t>(64);
-        enqueue_zero(hs, 64 * sizeof(int32_t), s);
+        hs = p.arena.take<int32_t>(64);
+        z.add(hs, 64 * sizeof(int32_t));
+        cost = p.arena.take<int32_t>((size_t)g.gs_cap);
+        sc_cost = scan1_take(p.arena, g.gs_cap, z);
+      }
+      enqueue_zero_batch(z, s);
+      if (reuse) {
         hipLaunchKernelGGL(k_degree_buckets, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.gs_off, g.n, hs, p.status);
-        hipLaunchKernelGGL(k_hub_threshold, dim3(1), dim3(64), 0, s, hs, nbig, p.status);
         hipLaunchKernelGGL(k_assign_hubs, dim3(blocks_for(g.n, 256)), dim3(256), 0, s, g.gs_off, g.n, hs, hub_id,
                            nbig, big_id, big_list, p.status);
-        if (nbig > 0) {
+        const int32_t cmax = cost_cap(g.gs_cap);
+        if (k == 4)
+          enqueue_scan1(sc_cost, cost, UnitCost4{g, cmax, lim.light}, p.status, s);
+        else
+          enqueue_scan1(sc_cost, cost, UnitCost5{g, cmax}, p.status, s);
+        if (nbig > 0)
           hipLaunchKernelGGL(k_big_labels, dim3(16, nbig), dim3(256), 0, s, g, hs, big_list, lbig, lstride, p.status);
+        fork_side();
+        if (nbig > 0) {
           hipLaunchKernelGGL(k_core_tables, dim3(64, nbig), dim3(256), 0, s, g, hs, big_list, lbig, lstride, wbig,
                              wbig_stride, mbig, hub_id, p.status);
         }
       }
-      const int32_t* cpre = nullptr;
-      if (reuse) {
-        int32_t* cost = p.arena.take<int32_t>((size_t)g.gs_cap);
-        int32_t* scr = p.arena.take<int32_t>((size_t)scan_scratch(g.gs_cap));
-        const int32_t cmax = cost_cap(g.gs_cap);
-        if (k == 4)
-          hipLaunchKernelGGL(k_unit_cost4, dim3(blocks_for(g.gs_cap, 256)), dim3(256), 0, s, g, cmax, lim.light, cost,
-                             p.status);
-        else
-          hipLaunchKernelGGL(k_unit_cost5, dim3(blocks_for(g.gs_cap, 256)), dim3(256), 0, s, g, cmax, cost, p.status);
-        scan_excl(cost, g.gs_cap, scr, s);
-        cpre = cost;
-      }
+      const int32_t* cpre = reuse ? cost : nullptr;
+      fork_side();
       profile_mark(k, 1, true, s);
       marked = true;
       if (k == 4 && reuse) {
@@ -2417,6 +2426,8 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
       }
     }
   }
+  if (g.n == 0) enqueue_zero_batch(z, s);
+  fork_side();
   if (!marked) profile_mark(k, 1, true, s);
   profile_mark(k, 1, false, s);
   if (out) enqueue_finalise(p, k, g.ngraphs, acc, out, s);

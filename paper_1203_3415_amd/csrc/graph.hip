@@ -20,19 +20,22 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "scan.h"
 
 namespace motif {
 
 namespace {
 
 constexpr int kB = 256;           // threads per block for streaming kernels
-constexpr int kScanItems = 8;
-constexpr int kScanTile = kB * kScanItems;
 constexpr int kSmallRow = 64;     // rows up to this length: sorted by one thread, in registers
 constexpr int kMidRow = 4096;     // rows up to this length: LDS bitonic sort
 constexpr int kWaveRow = 1024;    // ... by one wave when at most this long, else by the workgroup
 constexpr int kLdsBitmapWords = 16384;  // big rows: the key bitmap sits in LDS when 2n bits fit in 64 KB
-constexpr int kBigSlots = 32;     // concurrent bitmap sorts
+constexpr int kLdsBitmapRow = 256;  // ... and then takes every row longer than this
+constexpr int kLdsBitmapBlock = 1024;  // threads of an LDS bitmap sort
+constexpr int kLdsBitmapGrid = 512;    // LDS bitmap sorts in flight (two 64 KB workgroups per CU)
+constexpr int kBigSlots = 32;     // concurrent bitmap sorts with the bitmaps in global memory
+constexpr int kCheckGrid = 256;   // workgroups of an in-CSR check run beside a census
 
 __device__ __forceinline__ void set_status(int32_t* st, int32_t code) { atomicMin(&st[kStatus], code); }
 
@@ -66,82 +69,25 @@ __global__ void k_zero16(uint4* p, size_t n) {
     p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// Exclusive block scan of one value per thread (wave64 shuffles + LDS).
-__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* sh, int32_t* total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  int32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[w] = x;
-  __syncthreads();
-  if (w == 0) {
-    int32_t s = lane < nw ? sh[lane] : 0;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      int32_t y = __shfl_up(s, o, 64);
-      if (lane >= o) s += y;
-    }
-    if (lane < nw) sh[lane] = s;
-  }
-  __syncthreads();
-  int32_t r = x - v + (w ? sh[w - 1] : 0);
-  *total = sh[nw - 1];
-  __syncthreads();
-  return r;
-}
+// The regions of a ZeroBatch: a 16-byte part and a tail of at most 3 words.
+struct ZeroRanges {
+  uint4* p16[ZeroBatch::kMax];
+  size_t n16[ZeroBatch::kMax];
+  uint32_t* tail[ZeroBatch::kMax];
+  int32_t ntail[ZeroBatch::kMax];
+  int32_t n;
+};
 
-__global__ __launch_bounds__(kB) void k_scan_local(int32_t* data, int64_t len, int32_t* bsum) {
-  __shared__ int32_t sh[kB / 64];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  int32_t vals[kScanItems];
-  int32_t sum = 0;
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    vals[i] = base + i < len ? data[base + i] : 0;
-    sum += vals[i];
-  }
-  int32_t total;
-  int32_t run = block_excl_scan(sum, sh, &total);
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    if (base + i < len) data[base + i] = run;
-    run += vals[i];
-  }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
-}
 
-__global__ __launch_bounds__(kB) void k_scan_add(int32_t* data, int64_t len, const int32_t* bsum) {
-  const int32_t add = bsum[blockIdx.x];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  for (int i = threadIdx.x; i < kScanTile; i += kB)
-    if (base + i < len) data[base + i] += add;
+__global__ void k_zero_many(ZeroRanges r) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x, t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  for (int k = 0; k < r.n; ++k) {
+    for (size_t i = t; i < r.n16[k]; i += stride) r.p16[k][i] = make_uint4(0u, 0u, 0u, 0u);
+    if (t < (size_t)r.ntail[k]) r.tail[k][t] = 0u;
+  }
 }
 
 }  // namespace
-
-// In-place exclusive scan of data[0..len); scratch needs scan_scratch(len) ints.
-void scan_excl(int32_t* data, int64_t len, int32_t* scratch, hipStream_t s) {
-  if (len <= 0) return;
-  const int64_t nb = (len + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kB), 0, s, data, len, scratch);
-  if (nb > 1) {
-    scan_excl(scratch, nb, scratch + ((nb + 63) & ~int64_t(63)), s);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kB), 0, s, data, len, scratch);
-  }
-}
-
-int64_t scan_scratch(int64_t len) {
-  int64_t total = 64;
-  while (len > 1) {
-    int64_t nb = (len + kScanTile - 1) / kScanTile;
-    total += (nb + 63) & ~int64_t(63);
-    len = nb;
-  }
-  return total;
-}
 
 namespace {
 
@@ -215,15 +161,14 @@ __global__ __launch_bounds__(kB) void k_count_in(const int32_t* off, const int32
   }
 }
 
-// hcnt[v] = out-degree + in-degree (half-edges of row v); hcnt[n] = 0.
-__global__ void k_half_counts(const int32_t* off, const int32_t* in_cnt, int32_t n, int32_t* hcnt,
-                              int32_t* fill, const int32_t* st) {
-  if (st[kStatus] != 0) return;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += (int64_t)gridDim.x * blockDim.x) {
-    hcnt[v] = v < n ? (off[v + 1] - off[v]) + in_cnt[v] : 0;
-    if (v < n) fill[v] = 0;
-  }
-}
+// Half-edges of row v (out-degree + in-degree), the values whose exclusive
+// scan gives the half-edge offsets; 0 at v = n.
+struct HalfCount {
+  const int32_t* off;
+  const int32_t* in_cnt;
+  int32_t n;
+  __device__ int32_t operator()(int64_t v) const { return v < n ? (off[v + 1] - off[v]) + in_cnt[v] : 0; }
+};
 
 // Half-edge keys: row u gets (d<<1|0) for arc u->d, row d gets (u<<1|1).
 // Half-edge scatter with the same per-block aggregation: each arc takes a
@@ -290,10 +235,10 @@ __global__ __launch_bounds__(kB) void k_scatter(const int32_t* off, const int32_
   }
 }
 
-// Small rows sorted by their own thread; longer rows queued.
+// Small rows sorted by their own thread; longer rows queued: up to mid_max
+// keys for the bitonic sort, longer ones for the bitmap sort.
 __global__ __launch_bounds__(kB) void k_sort_small(const int32_t* hoff, int32_t n, uint32_t* keys, int32_t* midq,
-                                                   int32_t* bigq,
-                             int32_t* st) {
+                                                   int32_t* bigq, int32_t mid_max, int32_t* st) {
   if (st[kStatus] != 0) return;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const int32_t a = hoff[v], len = hoff[v + 1] - a;
@@ -322,7 +267,7 @@ __global__ __launch_bounds__(kB) void k_sort_small(const int32_t* hoff, int32_t 
 #pragma unroll
       for (int i = 0; i < kSmallRow; ++i)
         if (i < len) r[i] = x[i];
-    } else if (len <= kMidRow) {
+    } else if (len <= mid_max) {
       midq[atomicAdd(&st[kMidCount], 1)] = (int32_t)v;
     } else {
       bigq[atomicAdd(&st[kBigCount], 1)] = (int32_t)v;
@@ -401,23 +346,25 @@ __global__ __launch_bounds__(kB) void k_sort_mid(const int32_t* hoff, uint32_t* 
 }
 
 // Big rows: set one bit per key in a bitmap over [0, 2n), then compact in
-// order.  A key seen twice is a repeated arc.
-template <bool LDS>
-__global__ __launch_bounds__(kB) void k_sort_big(const int32_t* hoff, int32_t n, uint32_t* keys,
+// order.  A key seen twice is a repeated arc.  The bitmap is cleared once at
+// the start and each word again as the compaction reads it.
+template <bool LDS, int BS>
+__global__ __launch_bounds__(BS) void k_sort_big(const int32_t* hoff, int32_t n, uint32_t* keys,
                                                  const int32_t* bigq, uint32_t* bitmaps, int32_t* st) {
-  __shared__ int32_t sh[kB / 64];
+  __shared__ int32_t sh[BS / 64];
   __shared__ uint32_t lbm[LDS ? kLdsBitmapWords : 1];
   if (st[kStatus] != 0) return;
   const int32_t count = st[kBigCount];
+  if ((int32_t)blockIdx.x >= count) return;
   const int64_t words = ((int64_t)2 * n + 31) / 32;
   uint32_t* bm = LDS ? lbm : bitmaps + (int64_t)blockIdx.x * words;
-  const int64_t per = (words + kB - 1) / kB;
+  const int64_t per = (words + BS - 1) / BS;
+  for (int64_t w = threadIdx.x; w < words; w += BS) bm[w] = 0u;
+  __syncthreads();
   for (int32_t q = blockIdx.x; q < count; q += gridDim.x) {
     const int32_t v = bigq[q];
     const int32_t a = hoff[v], len = hoff[v + 1] - a;
-    for (int64_t w = threadIdx.x; w < words; w += kB) bm[w] = 0u;
-    __syncthreads();
-    for (int i = threadIdx.x; i < len; i += kB) {
+    for (int i = threadIdx.x; i < len; i += BS) {
       uint32_t key = keys[a + i];
       uint32_t bit = 1u << (key & 31u);
       uint32_t old = atomicOr(&bm[key >> 5], bit);
@@ -431,6 +378,7 @@ __global__ __launch_bounds__(kB) void k_sort_big(const int32_t* hoff, int32_t n,
     int32_t pos = block_excl_scan(cnt, sh, &total);
     for (int64_t w = w0; w < w1; ++w) {
       uint32_t b = bm[w];
+      if (b) bm[w] = 0u;
       while (b) {
         int t = __ffs(b) - 1;
         b &= b - 1;
@@ -445,24 +393,32 @@ __global__ __launch_bounds__(kB) void k_sort_big(const int32_t* hoff, int32_t n,
 // Element-parallel merge of the sorted half-edges of every row: a half-edge
 // opens a new G* entry unless it carries the same neighbour as its
 // predecessor in the row (the pair id<<1, id<<1|1 is one bidirected
-// neighbour); equal keys are a repeated arc.  flag[2m] = 0 closes the scan.
-__global__ void k_entry_flags(const uint32_t* keys, const int32_t* hrow, const int32_t* hoff, int64_t h,
-                              int32_t* flag, int32_t* st) {
-  if (st[kStatus] != 0) return;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= h; i += (int64_t)gridDim.x * blockDim.x) {
-    if (i == h) { flag[i] = 0; continue; }
+// neighbour); equal keys are a repeated arc.  Position h closes the scan.
+struct EntryFlag {
+  const uint32_t* keys;
+  const int32_t* hrow;
+  const int32_t* hoff;
+  int64_t h;
+  int32_t* st;
+  __device__ int32_t operator()(int64_t i) const {
+    if (i == h) return 0;
     const uint32_t k = keys[i];
     const bool first = i == hoff[hrow[i]];
     if (!first && keys[i - 1] == k) set_status(st, MOTIF_EDUP);
-    flag[i] = (first || (keys[i - 1] >> 1) != (k >> 1)) ? 1 : 0;
+    return (first || (keys[i - 1] >> 1) != (k >> 1)) ? 1 : 0;
   }
-}
+};
 
-// gs_off[v] = position of row v's first half-edge in the scanned flags.
-__global__ void k_gather_off(const int32_t* pos, const int32_t* hoff, int32_t n, int32_t* gs_off, const int32_t* st) {
+// gs_off[v] = position of row v's first half-edge in the scanned flags;
+// with deg given, also the row's length.
+__global__ void k_gather_off(const int32_t* pos, const int32_t* hoff, int32_t n, int32_t* gs_off, int32_t* deg,
+                             const int32_t* st) {
   if (st[kStatus] != 0) return;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += (int64_t)gridDim.x * blockDim.x)
-    gs_off[v] = pos[hoff[v]];
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = pos[hoff[v]];
+    gs_off[v] = a;
+    if (deg && v < n) deg[v] = pos[hoff[v + 1]] - a;
+  }
 }
 
 // Typed G* entries, plus the row of each entry and the degree of each row.
@@ -480,25 +436,21 @@ __global__ void k_write_gstar(const uint32_t* keys, const int32_t* hrow, const i
   }
 }
 
-__global__ void k_degree(const int32_t* gs_off, int32_t n, int32_t* deg, const int32_t* st) {
-  if (st[kStatus] != 0) return;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    deg[v] = gs_off[v + 1] - gs_off[v];
-}
-
-// flag[j] = 1 when entry j of row v points to a neighbour of higher rank;
-// entries past the last G* entry (up to `cap`) get 0.
-__global__ void k_plus_flags(const uint32_t* gs_idx, const int32_t* gs_row, const int32_t* deg,
-                             const int32_t* gs_off, int32_t n, int64_t cap, int32_t* flag, const int32_t* st) {
-  if (st[kStatus] != 0) return;
-  const int64_t e = gs_off[n];
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= cap; j += (int64_t)gridDim.x * blockDim.x) {
-    if (j >= e) { flag[j] = 0; continue; }
+// 1 for entry j of row v when it points to a neighbour of higher rank (an
+// entry of N+(v)); 0 past the last G* entry.
+struct PlusFlag {
+  const uint32_t* gs_idx;
+  const int32_t* gs_row;
+  const int32_t* deg;
+  const int32_t* gs_off;
+  int32_t n;
+  __device__ int32_t operator()(int64_t j) const {
+    if (j >= gs_off[n]) return 0;
     const int32_t v = gs_row[j];
     const int32_t w = (int32_t)(gs_idx[j] & kIdMask);
-    flag[j] = rank_less(deg[v], v, deg[w], w) ? 1 : 0;
+    return rank_less(deg[v], v, deg[w], w) ? 1 : 0;
   }
-}
+};
 
 __global__ void k_write_plus(const uint32_t* gs_idx, const int32_t* flag_pos, const int32_t* gs_row,
                              const int32_t* deg, const int32_t* gs_off, int32_t n, uint32_t* np_idx,
@@ -620,6 +572,22 @@ void enqueue_zero(void* ptr, size_t bytes, hipStream_t s) {
   hipLaunchKernelGGL(k_zero, dim3(grid_for((int64_t)words)), dim3(kB), 0, s, (uint32_t*)ptr, words);
 }
 
+void enqueue_zero_batch(const ZeroBatch& z, hipStream_t s) {
+  if (!z.n) return;
+  ZeroRanges r{};
+  size_t most = 1;
+  for (int k = 0; k < z.n; ++k) {
+    const size_t words = (z.bytes[k] + 3) / 4;
+    r.p16[k] = (uint4*)z.ptr[k];
+    r.n16[k] = words / 4;
+    r.tail[k] = (uint32_t*)z.ptr[k] + (words / 4) * 4;
+    r.ntail[k] = (int32_t)(words % 4);
+    most = std::max(most, r.n16[k]);
+  }
+  r.n = z.n;
+  hipLaunchKernelGGL(k_zero_many, dim3(grid_for((int64_t)most)), dim3(kB), 0, s, r);
+}
+
 namespace {
 __global__ void k_status_out(int32_t* dst, const int32_t* st) {
   if (threadIdx.x == 0) dst[0] = st[kStatus];
@@ -692,7 +660,7 @@ size_t build_bytes(int64_t N, int64_t M, int32_t G, bool batch) {
   b += 2 * al(sizeof(int32_t) * (N + 1));          // sort queues
   b += al(sizeof(uint32_t) * kBigSlots * ((2 * N + 31) / 32 + 1));
   b += al(sizeof(uint32_t) * ((2 * M + 31) / 32 + 1));  // transpose marks
-  b += al(sizeof(int32_t) * scan_scratch(std::max<int64_t>(N + 1, 2 * M + 1)));
+  b += scan1_bytes(N + 1) + 2 * scan1_bytes(2 * M + 1);  // look-back words of the three scans
   b += 3 * al(sizeof(int32_t) * (2 * M + 1));      // half-edge rows, merge flags, G* entry rows
   if (batch) {
     b += 2 * al(sizeof(int32_t) * (N + 1)) + 2 * al(sizeof(int32_t) * (M + 1)) + al(sizeof(int32_t) * (N + 1));
@@ -743,7 +711,8 @@ BuildInput enqueue_pack(Pipeline& p, const motif_graph_t* graphs, int32_t count,
   return in;
 }
 
-DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s, hipEvent_t graph_ready, bool* ready_ok) {
+DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s, hipEvent_t graph_ready, bool* ready_ok,
+                       InCheck* deferred) {
   Arena& A = p.arena;
   const int32_t n = in.n;
   const int64_t m = in.m;
@@ -765,7 +734,12 @@ DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s, hipEven
   const int64_t bm_words = (2 * (int64_t)n + 31) / 32 + 1;
   uint32_t* bitmaps = A.take<uint32_t>(kBigSlots * bm_words);
   uint32_t* marks = A.take<uint32_t>((2 * m + 31) / 32 + 1);
-  int32_t* scratch = A.take<int32_t>(scan_scratch(std::max<int64_t>(n + 1, 2 * m + 1)));
+  ZeroBatch z;
+  z.add(in_cnt, sizeof(int32_t) * (n + 1));
+  z.add(fill, sizeof(int32_t) * (n + 1));
+  const Scan1 sc_half = scan1_take(A, n + 1, z);
+  const Scan1 sc_entry = scan1_take(A, 2 * m + 1, z);
+  const Scan1 sc_plus = scan1_take(A, 2 * m + 1, z);
 
   DevGraph g;
   g.n = n;
@@ -784,49 +758,62 @@ DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s, hipEven
     return g;
   }
 
-  enqueue_zero(in_cnt, sizeof(int32_t) * (n + 1), s);
+  enqueue_zero_batch(z, s);
   if (!in.gid) hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.out_off, n, m, st);
   if (m > 0)
     hipLaunchKernelGGL(k_count_in, dim3(grid_for((m + kArcsPerThread - 1) / kArcsPerThread)), dim3(kB), 0, s,
                        in.out_off, in.out_idx, n, m, in_cnt, st);  // grid_for caps at 65536 blocks
-  hipLaunchKernelGGL(k_half_counts, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.out_off, in_cnt, n, hoff, fill, st);
-  scan_excl(hoff, n + 1, scratch, s);
+  enqueue_scan1(sc_half, hoff, HalfCount{in.out_off, in_cnt, n}, st, s);
   if (m > 0)
     hipLaunchKernelGGL(k_scatter, dim3(grid_for((m + kArcsPerThread - 1) / kArcsPerThread)), dim3(kB), 0, s,
                        in.out_off, in.out_idx, n, m, hoff, fill, keys,
                        hrow, st);
-  hipLaunchKernelGGL(k_sort_small, dim3(grid_for(n)), dim3(kB), 0, s, hoff, n, keys, midq, bigq, st);
+  // With the bitmap in LDS a row costs about the same whatever its length
+  // (a few words per thread to clear, count and compact), which beats the
+  // bitonic sort's log^2 stages from a few hundred keys on.
+  const bool lds_bitmap = (2 * (int64_t)n + 31) / 32 <= kLdsBitmapWords;
+  hipLaunchKernelGGL(k_sort_small, dim3(grid_for(n)), dim3(kB), 0, s, hoff, n, keys, midq, bigq,
+                     lds_bitmap ? kLdsBitmapRow : kMidRow, st);
   hipLaunchKernelGGL(k_sort_mid, dim3(512), dim3(kB), 0, s, hoff, keys, midq, st);
-  if ((2 * (int64_t)n + 31) / 32 <= kLdsBitmapWords)
-    hipLaunchKernelGGL((k_sort_big<true>), dim3(kBigSlots), dim3(kB), 0, s, hoff, n, keys, bigq, bitmaps, st);
+  if (lds_bitmap)
+    hipLaunchKernelGGL((k_sort_big<true, kLdsBitmapBlock>), dim3(kLdsBitmapGrid), dim3(kLdsBitmapBlock), 0, s, hoff,
+                       n, keys, bigq, bitmaps, st);
   else
-    hipLaunchKernelGGL((k_sort_big<false>), dim3(kBigSlots), dim3(kB), 0, s, hoff, n, keys, bigq, bitmaps, st);
-  // merge: flags over the 2m sorted half-edges, one scan gives offsets and positions
-  hipLaunchKernelGGL(k_entry_flags, dim3(grid_for(2 * m + 1)), dim3(kB), 0, s, keys, hrow, hoff, 2 * m, flags, st);
-  scan_excl(flags, 2 * m + 1, scratch, s);
-  hipLaunchKernelGGL(k_gather_off, dim3(grid_for(n + 1)), dim3(kB), 0, s, flags, hoff, n, gs_off, st);
+    hipLaunchKernelGGL((k_sort_big<false, kB>), dim3(kBigSlots), dim3(kB), 0, s, hoff, n, keys, bigq, bitmaps, st);
+  // merge: entry flags over the 2m sorted half-edges, scanned into positions
+  enqueue_scan1(sc_entry, flags, EntryFlag{keys, hrow, hoff, 2 * m, st}, st, s);
+  hipLaunchKernelGGL(k_gather_off, dim3(grid_for(n + 1)), dim3(kB), 0, s, flags, hoff, n, gs_off, deg, st);
   hipLaunchKernelGGL(k_write_gstar, dim3(grid_for(2 * m)), dim3(kB), 0, s, keys, hrow, hoff, 2 * m, flags, gs_idx,
                      gs_row, st);
-  hipLaunchKernelGGL(k_degree, dim3(grid_for(n)), dim3(kB), 0, s, gs_off, n, deg, st);
-  // oriented rows N+: flags over the G* entries (at most 2m of them), one scan
-  hipLaunchKernelGGL(k_plus_flags, dim3(grid_for(2 * m + 1)), dim3(kB), 0, s, gs_idx, gs_row, deg, gs_off, n,
-                     2 * m, flags, st);
-  scan_excl(flags, 2 * m + 1, scratch, s);
-  hipLaunchKernelGGL(k_gather_off, dim3(grid_for(n + 1)), dim3(kB), 0, s, flags, gs_off, n, np_off, st);
+  // oriented rows N+: flags over the G* entries (at most 2m of them), scanned
+  enqueue_scan1(sc_plus, flags, PlusFlag{gs_idx, gs_row, deg, gs_off, n}, st, s);
+  hipLaunchKernelGGL(k_gather_off, dim3(grid_for(n + 1)), dim3(kB), 0, s, flags, gs_off, n, np_off, nullptr, st);
   hipLaunchKernelGGL(k_write_plus, dim3(grid_for(2 * m)), dim3(kB), 0, s, gs_idx, flags, gs_row, deg, gs_off, n,
                      np_idx, st);
   // G* and N+ are complete here; the in-CSR check below only compares
   if (graph_ready) *ready_ok = hipEventRecord(graph_ready, s) == hipSuccess;
-  if (in.in_off) {
-    if (!in.gid) hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.in_off, n, m, st);
-    hipLaunchKernelGGL(k_check_in_rows, dim3(grid_for(n)), dim3(kB), 0, s, in.in_off, in_cnt, n, in.gid, in.has_in,
-                       st);
-    enqueue_zero(marks, sizeof(uint32_t) * ((2 * m + 31) / 32 + 1), s);
-    if (m > 0)
-      hipLaunchKernelGGL(k_check_in_arcs, dim3(grid_for(m)), dim3(kB), 0, s, in.in_off, in.in_idx, n, m, gs_off,
-                         gs_idx, in.gid, in.has_in, marks, st);
-  }
+  InCheck c{in_cnt, marks};
+  if (deferred) *deferred = c;
+  else enqueue_check_in(in, g, c, st, s, false);
   return g;
+}
+
+void enqueue_check_in(const BuildInput& in, const DevGraph& g, const InCheck& c, int32_t* st, hipStream_t s,
+                      bool background) {
+  if (!in.in_off || g.n == 0) return;
+  const int32_t n = in.n;
+  const int64_t m = in.m;
+  if (!in.gid) hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.in_off, n, m, st);
+  hipLaunchKernelGGL(k_check_in_rows, dim3(grid_for(n)), dim3(kB), 0, s, in.in_off, c.in_cnt, n, in.gid, in.has_in,
+                     st);
+  enqueue_zero(c.marks, sizeof(uint32_t) * ((2 * m + 31) / 32 + 1), s);
+  // beside a census, a few waves per CU: the search chains are latency-bound
+  // and a full grid would hold back the census's own launches
+  unsigned grid = grid_for(m);
+  if (background) grid = std::min(grid, (unsigned)kCheckGrid);
+  if (m > 0)
+    hipLaunchKernelGGL(k_check_in_arcs, dim3(grid), dim3(kB), 0, s, in.in_off, in.in_idx, n, m, g.gs_off, g.gs_idx,
+                       in.gid, in.has_in, c.marks, st);
 }
 
 }  // namespace motif

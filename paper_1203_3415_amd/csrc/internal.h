@@ -151,16 +151,31 @@ struct BuildInput {
 // Enqueue validation + G* + N+ build, then the in-CSR check when an in-CSR
 // is given.  Returns the built view (device pointers into the arena).  Does
 // not wait.  graph_ready (optional): recorded on s once G* and N+ are
-// written, before the in-CSR check (*ready_ok: whether the record succeeded).
+// written, before the in-CSR check (*ready_ok: whether the record
+// succeeded).  deferred (optional): the in-CSR check is not enqueued; what it
+// needs is returned there for enqueue_check_in on another stream.
+struct InCheck {
+  const int32_t* in_cnt = nullptr;  // in-degrees counted from the out-CSR
+  uint32_t* marks = nullptr;        // one bit per G* entry
+};
 DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s, hipEvent_t graph_ready = nullptr,
-                       bool* ready_ok = nullptr);
+                       bool* ready_ok = nullptr, InCheck* deferred = nullptr);
+// The in-CSR check of a build (nothing when no in-CSR was given); its verdict
+// lands in the status word.  background: a bounded grid, for a stream that
+// runs beside a census.
+void enqueue_check_in(const BuildInput& in, const DevGraph& g, const InCheck& c, int32_t* status, hipStream_t s,
+                      bool background);
 
 // Enqueue the census of k into acc[ngraphs * C] (accumulators, zeroed here)
 // and, unless out is null, the exact division into out[ngraphs * C] (written
 // only if every remainder is zero).  use_wpool: the W rows may come from
 // p.wpool (only for work on the pipeline's own stream, one census at a time).
+// side_start (optional) is recorded on s once the set-up has done its
+// bandwidth-heavy clears and the small kernels before the core tables: work
+// on a second stream that waits for it then runs beside the rest of this
+// census instead of crowding those steps.
 void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64_t* out, hipStream_t s,
-                    bool use_wpool);
+                    bool use_wpool, hipEvent_t side_start = nullptr, bool* side_ok = nullptr);
 // The exact division alone: out[i] = acc[i] / multiplicity, after a check
 // that every remainder is zero (Fact "correction").
 void enqueue_finalise(Pipeline& p, int k, int32_t ngraphs, const uint64_t* acc, uint64_t* out, hipStream_t s);
@@ -199,6 +214,23 @@ BuildInput enqueue_pack(Pipeline& p, const motif_graph_t* graphs, int32_t count,
 
 // Zero fill helper (a kernel, so it is safe inside captured graphs).
 void enqueue_zero(void* ptr, size_t bytes, hipStream_t s);
+// Several regions cleared by one kernel launch.
+struct ZeroBatch {
+  static constexpr int kMax = 16;
+  void* ptr[kMax] = {};
+  size_t bytes[kMax] = {};
+  int n = 0;
+  // Regions must be 16-byte aligned (arena regions are); a full batch is an
+  // internal sizing error, reported like a workspace error.
+  void add(void* p, size_t b) {
+    if (!b) return;
+    if (n == kMax || ((uintptr_t)p & 15u)) throw WorkspaceError();
+    ptr[n] = p;
+    bytes[n] = b;
+    ++n;
+  }
+};
+void enqueue_zero_batch(const ZeroBatch& z, hipStream_t s);
 // dst[0] = st[kStatus], stream-ordered (a kernel).
 void enqueue_status_out(int32_t* dst, const int32_t* st, hipStream_t s);
 // Undirected census: every entry of the built G* and N+ becomes type A; then
@@ -207,10 +239,6 @@ void enqueue_all_bidirected(const DevGraph& g, hipStream_t s, const int32_t* st)
 void enqueue_project_undirected(const uint64_t* dir, const int16_t* und_of, int32_t C, int32_t U, uint64_t* out,
                                 int32_t* st, hipStream_t s);
 
-// In-place exclusive scan of int32 data[0..len) on the device; `scratch`
-// holds scan_scratch(len) ints.
-void scan_excl(int32_t* data, int64_t len, int32_t* scratch, hipStream_t s);
-int64_t scan_scratch(int64_t len);
 
 // Device setup (class tables) for the current device; returns the device id.
 int32_t ensure_init(int* dev);

@@ -122,6 +122,32 @@ def test_global_label_path(pm, k):
     assert_parity(pm, g, k, "global_labels")
 
 
+def _shuffled_rows(g, seed):
+    rng = np.random.default_rng(seed)
+    idx = g.out_idx.copy()
+    for v in range(g.n):
+        a, b = g.out_off[v], g.out_off[v + 1]
+        idx[a:b] = rng.permutation(idx[a:b])
+    return idx
+
+
+def test_row_sort_paths(pm):
+    """Rows of every sort path, given unsorted: in registers (up to 64
+    half-edges), bitonic in LDS (65-256), bitmap in LDS (longer, while 2n bits
+    fit in 64 KB) and bitmap in global memory (n = 300,000 after padding with
+    isolated vertices and relabelling)."""
+    g = gg.chung_lu(2500, 10000, 2.1, 2.1, 0.2, seed=24)
+    h = np.diff(g.out_off) + np.bincount(g.out_idx, minlength=g.n)
+    assert (h > 256).sum() >= 3 and ((h > 64) & (h <= 256)).sum() >= 10
+    big = gg.pad_relabel(g, 300000, seed=25)
+    want = {3: oracle.census(g, 3), 4: oracle.method_census(g, 4)}  # the method reference: ESU takes 30 s here
+    for name, G in (("lds", g), ("global", big)):
+        off_d, idx_d = _dev(pm, G.out_off, _shuffled_rows(G, 26))
+        for k in (3, 4):
+            print(f"[case] row sort paths, {name} bitmap, k={k}", flush=True)
+            assert np.array_equal(pm.census(off_d, idx_d, G.n, k), want[k]), (name, k)
+
+
 @pytest.mark.parametrize("k", [3, 4])
 def test_unsorted_rows_and_in_csr(pm, k):
     g = gg.chung_lu(800, 4000, 2.2, 2.2, 0.3, seed=31)
@@ -177,10 +203,12 @@ def test_errors(pm):
     _expect_error(pm, [1, 1, 2, 2], [1, 2], 3, 4, "EINVAL_SHAPE")
     _expect_error(pm, [0, 1, 2, 3], [1, 2], 3, 4, "EINVAL_SHAPE")
     _expect_error(pm, [0, 1, 2, 2], [1, 0], 3, 6, "EINVAL_K")
-    # a repeated arc in a mid-size row (LDS sort) and in a big row (bitmap sort)
-    for deg in (100, 5000):
+    # a repeated arc in a row of each sort path: bitonic in LDS (100 keys),
+    # bitmap in LDS (300, 2,000 and 5,000 keys), and bitmap in global memory
+    # (n = 300,000: 2n bits no longer fit in LDS)
+    for deg, n in ((100, 101), (300, 301), (2000, 2001), (5000, 5001), (5000, 300000)):
         idx = list(range(1, deg + 1)) + [7]
-        _expect_error(pm, [0, deg + 1] + [deg + 1] * deg, idx, deg + 1, 4, "EDUP")
+        _expect_error(pm, [0, deg + 1] + [deg + 1] * (n - 1), idx, n, 4, "EDUP")
     # histogram untouched on error
     import torch
     off_d, idx_d = _dev(pm, np.asarray([0, 1, 2, 2], np.int32), np.asarray([1, 1], np.int32))
@@ -421,6 +449,36 @@ def test_census_multi_matches_single(pm):
     assert e.value.name == "ESELFLOOP"
     with pytest.raises(pm.MotifError):
         pm.census_multi(off, idx, g.n, (3, 3))
+
+
+@pytest.mark.gpu
+def test_census_multi_in_csr(pm):
+    """With an in-CSR the multi-size call checks it on its second stream,
+    beside the censuses: a good one changes nothing, for one size as for
+    several, and a bad one fails the call with every output left as it was."""
+    import torch
+    g = gg.chung_lu(1500, 7000, 2.2, 2.4, 0.15, seed=22)
+    off, idx = pm.to_device(g.out_off, g.out_idx)
+    in_off, in_idx = g.in_csr()
+    io, ii = pm.to_device(in_off, in_idx)
+    singles = {k: pm.census(off, idx, g.n, k) for k in (3, 4, 5)}
+    for ks in ((3, 4), (4,), (5, 3, 4)):
+        print(f"[case] census_multi in-CSR ks={ks}", flush=True)
+        outs = pm.census_multi(off, idx, g.n, ks, in_off=io, in_idx=ii)
+        for k, h in zip(ks, outs):
+            assert np.array_equal(h, singles[k]), (ks, k)
+    bad = in_idx.copy()
+    v = int(np.argmax(np.diff(in_off)))
+    present = set(bad[in_off[v]:in_off[v + 1]].tolist())
+    bad[in_off[v]] = next(x for x in range(g.n) if x != v and x not in present)
+    bo, bi = pm.to_device(in_off, bad)
+    for ks in ((3, 4), (4,)):
+        print(f"[case] census_multi bad in-CSR ks={ks}", flush=True)
+        outs = [torch.full((pm.NUM_CLASSES[k],), 7, dtype=torch.int64, device="cuda") for k in ks]
+        with pytest.raises(pm.MotifError) as e:
+            pm.census_multi(off, idx, g.n, ks, in_off=bo, in_idx=bi, outs=outs)
+        assert e.value.name == "ETRANSPOSE"
+        assert all(bool((h == 7).all()) for h in outs)
 
 
 @pytest.mark.gpu
