@@ -384,27 +384,45 @@ int32_t run_census_multi_enqueue(Pipeline& p, const BuildInput& in, int32_t nk, 
     if (!p.side && hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) != hipSuccess) return MOTIF_EDEVICE;
     if (!p.ev_fork && hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming) != hipSuccess) return MOTIF_EDEVICE;
     if (!p.ev_join && hipEventCreateWithFlags(&p.ev_join, hipEventDisableTiming) != hipSuccess) return MOTIF_EDEVICE;
+    if (!p.ev_pre && hipEventCreateWithFlags(&p.ev_pre, hipEventDisableTiming) != hipSuccess) return MOTIF_EDEVICE;
+  }
+  int32_t top = 0;
+  for (int32_t i = 1; i < nk; ++i)
+    if (ks[i] > ks[top]) top = i;
+  // The largest census's big-core tables (307 MB on the n = 10^5 graph) are
+  // cleared on the second stream while the build runs: the build is a chain
+  // of latency-bound kernels that leaves the bandwidth free.  (The previous
+  // call on this pipeline has ended on both streams, so the region is idle.)
+  auto device_error = [&] {
+    (void)hipStreamSynchronize(s);  // best effort: the error is what the caller acts on
+    (void)hipStreamSynchronize(p.side);
+    return MOTIF_EDEVICE;
+  };
+  BigTables pre;
+  bool pre_on_side = false;
+  if (fork) {
+    ZeroBatch zb;
+    pre = take_big_tables(p, ks[top], in.n, in.gid ? in.max_graph_n : in.n, p.tune.k[ks[top]], zb);
+    if (pre.nbig > 0) {
+      enqueue_zero_batch(zb, p.side);
+      if (hipEventRecord(p.ev_pre, p.side) != hipSuccess) return device_error();
+      pre_on_side = true;
+    }
   }
   enqueue_zero(p.status, sizeof(int32_t) * kStatusWords, s);
   for (int32_t i = 0; i < nk; ++i) profile_mark(ks[i], 0, true, s);  // the shared build, seen by every k
   InCheck check;
   DevGraph g = enqueue_build(p, in, s, nullptr, nullptr, fork ? &check : nullptr);
   for (int32_t i = 0; i < nk; ++i) profile_mark(ks[i], 0, false, s);
-  int32_t top = 0;
-  for (int32_t i = 1; i < nk; ++i)
-    if (ks[i] > ks[top]) top = i;
+  if (pre_on_side && hipStreamWaitEvent(s, p.ev_pre, 0) != hipSuccess) return device_error();
   uint64_t* acc[3] = {};  // nk <= 3 (checked by the entry point)
   acc[top] = p.arena.take<uint64_t>((size_t)in.ngraphs * motif_num_classes(ks[top]));
   // the second stream starts once the largest census has done the clears
   // and small kernels of its set-up (G* and N+ are complete by then)
   bool side_ok = true;
   enqueue_census(p, g, ks[top], acc[top], fork ? nullptr : hists[top], s, true, fork ? p.ev_fork : nullptr,
-                 &side_ok);
-  if (fork && (!side_ok || hipStreamWaitEvent(p.side, p.ev_fork, 0) != hipSuccess)) {
-    (void)hipStreamSynchronize(s);  // best effort: the error is what the caller acts on
-    (void)hipStreamSynchronize(p.side);
-    return MOTIF_EDEVICE;
-  }
+                 &side_ok, fork ? &pre : nullptr);
+  if (fork && (!side_ok || hipStreamWaitEvent(p.side, p.ev_fork, 0) != hipSuccess)) return device_error();
   for (int32_t i = 0; i < nk; ++i) {
     if (i == top) continue;
     acc[i] = p.arena.take<uint64_t>((size_t)in.ngraphs * motif_num_classes(ks[i]));
@@ -414,11 +432,8 @@ int32_t run_census_multi_enqueue(Pipeline& p, const BuildInput& in, int32_t nk, 
   // after the smaller sizes: the check then runs beside the largest census
   // rather than beside its set-up
   enqueue_check_in(in, g, check, p.status, p.side, true);
-  if (hipEventRecord(p.ev_join, p.side) != hipSuccess || hipStreamWaitEvent(s, p.ev_join, 0) != hipSuccess) {
-    (void)hipStreamSynchronize(s);
-    (void)hipStreamSynchronize(p.side);
-    return MOTIF_EDEVICE;
-  }
+  if (hipEventRecord(p.ev_join, p.side) != hipSuccess || hipStreamWaitEvent(s, p.ev_join, 0) != hipSuccess)
+    return device_error();
   // Every division runs after the join, on the caller's stream: a failed
   // in-CSR check then leaves every output unwritten, and the side sizes'
   // divisions do not wait on the second stream for compute units that the
@@ -515,6 +530,7 @@ int32_t motif_shutdown(void) {
       if (pp.second->side) (void)hipStreamDestroy(pp.second->side);
       if (pp.second->ev_fork) (void)hipEventDestroy(pp.second->ev_fork);
       if (pp.second->ev_join) (void)hipEventDestroy(pp.second->ev_join);
+      if (pp.second->ev_pre) (void)hipEventDestroy(pp.second->ev_pre);
       if (pp.second->arena.base) (void)hipFree(pp.second->arena.base);
       if (pp.second->wpool) (void)hipFree(pp.second->wpool);
       if (pp.second->status) (void)hipFree(pp.second->status);

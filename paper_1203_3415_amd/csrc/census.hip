@@ -2299,8 +2299,25 @@ size_t w_slice_bytes(int k, int64_t maxn, const Tuning& t, int num_cus) {
   return sizeof(uint32_t) * kBigRow * (size_t)(maxn > 0 ? maxn : 1) * (size_t)grid_size(t, num_cus);
 }
 
+BigTables take_big_tables(Pipeline& p, int k, int32_t n, int64_t maxn, const Tuning& t, ZeroBatch& z) {
+  BigTables b;
+  const bool reuse = (k == 4 || k == 5) && t.heavy == 1;
+  b.nbig = reuse && n > 0 ? big_slots(maxn) : 0;
+  if (b.nbig == 0) return b;
+  const int64_t lstride = big_label_words(maxn), wstride = (int64_t)kBigRow * maxn;
+  b.big_id = p.arena.take<int32_t>(n + 1);
+  b.big_list = p.arena.take<int32_t>(kMaxBig);
+  b.lbig = p.arena.take<uint32_t>((size_t)b.nbig * lstride);
+  b.wbig = p.arena.take<uint32_t>((size_t)b.nbig * wstride);
+  b.mbig = p.arena.take<uint32_t>(32 * kMaxBig);
+  z.add(b.lbig, sizeof(uint32_t) * (size_t)b.nbig * lstride);
+  z.add(b.wbig, sizeof(uint32_t) * (size_t)b.nbig * wstride);
+  z.add(b.mbig, sizeof(uint32_t) * 32 * kMaxBig);
+  return b;
+}
+
 void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64_t* out, hipStream_t s,
-                    bool use_wpool, hipEvent_t side_start, bool* side_ok) {
+                    bool use_wpool, hipEvent_t side_start, bool* side_ok, const BigTables* pre) {
   bool forked = side_start == nullptr;
   auto fork_side = [&] {
     if (forked) return;
@@ -2342,20 +2359,11 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
       uint32_t* wg = nullptr;
       int64_t ws = 0;
       const int64_t maxn = g.max_graph_n > 0 ? g.max_graph_n : g.n;
-      const int nbig = reuse ? big_slots(maxn) : 0;
-      int32_t *big_id = nullptr, *big_list = nullptr;
-      uint32_t *lbig = nullptr, *wbig = nullptr, *mbig = nullptr;
+      const BigTables bt = pre ? *pre : take_big_tables(p, k, g.n, maxn, t, z);
+      const int nbig = bt.nbig;
+      int32_t *big_id = bt.big_id, *big_list = bt.big_list;
+      uint32_t *lbig = bt.lbig, *wbig = bt.wbig, *mbig = bt.mbig;
       const int64_t lstride = big_label_words(maxn), wbig_stride = (int64_t)kBigRow * maxn;
-      if (nbig > 0) {
-        big_id = p.arena.take<int32_t>(g.n + 1);
-        big_list = p.arena.take<int32_t>(kMaxBig);
-        lbig = p.arena.take<uint32_t>((size_t)nbig * lstride);
-        wbig = p.arena.take<uint32_t>((size_t)nbig * wbig_stride);
-        mbig = p.arena.take<uint32_t>(32 * kMaxBig);
-        z.add(lbig, sizeof(uint32_t) * (size_t)nbig * lstride);
-        z.add(wbig, sizeof(uint32_t) * (size_t)nbig * wbig_stride);
-        z.add(mbig, sizeof(uint32_t) * 32 * kMaxBig);
-      }
       int32_t* hs = nullptr;
       int32_t* cost = nullptr;
       Scan1 sc_cost;

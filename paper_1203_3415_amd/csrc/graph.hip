@@ -52,6 +52,7 @@ __device__ __forceinline__ int32_t row_of(const int32_t* off, int32_t n, int64_t
 // Arcs are taken kArcsPerThread consecutive ones per thread: one binary
 // search for the row of the first, then a forward walk over the offsets.
 constexpr int kArcsPerThread = 8;
+constexpr int kPlaceArcs = 2;  // elements per thread of the sorted-input placement
 
 __device__ __forceinline__ bool rank_less(int32_t dv, int32_t v, int32_t dw, int32_t w) {
   return dv < dw || (dv == dw && v < w);
@@ -128,10 +129,15 @@ __device__ __forceinline__ int32_t agg_insert(uint32_t* keys, uint32_t d) {
 }
 
 __global__ __launch_bounds__(kB) void k_count_in(const int32_t* off, const int32_t* idx, int32_t n, int64_t m,
-                                                 int32_t* in_cnt, int32_t* st) {
+                                                 int32_t* in_cnt, int32_t* st, const int32_t* skip) {
   __shared__ uint32_t akey[kAggSlots];
   __shared__ int32_t acnt[kAggSlots];
   if (st[kStatus] != 0) return;
+  if (skip && *skip == 0) {
+    // every row was in order: the in-CSR lookups of the placement stand
+    if (blockIdx.x == 0 && threadIdx.x == 0 && st[kInMismatch]) set_status(st, MOTIF_ETRANSPOSE);
+    return;
+  }
   for (int i = threadIdx.x; i < kAggSlots; i += kB) {
     akey[i] = kAggEmpty;
     acnt[i] = 0;
@@ -177,10 +183,10 @@ struct HalfCount {
 // order inside a row is arbitrary; rows are sorted next).
 __global__ __launch_bounds__(kB) void k_scatter(const int32_t* off, const int32_t* idx, int32_t n, int64_t m,
                                                 const int32_t* hoff, int32_t* fill, uint32_t* keys, int32_t* hrow,
-                                                const int32_t* st) {
+                                                const int32_t* st, const int32_t* skip) {
   __shared__ uint32_t akey[kAggSlots];
   __shared__ int32_t acnt[kAggSlots];
-  if (st[kStatus] != 0) return;
+  if (st[kStatus] != 0 || (skip && *skip == 0)) return;
   for (int i = threadIdx.x; i < kAggSlots; i += kB) {
     akey[i] = kAggEmpty;
     acnt[i] = 0;
@@ -235,11 +241,73 @@ __global__ __launch_bounds__(kB) void k_scatter(const int32_t* off, const int32_
   }
 }
 
+// Placement from a caller's in-CSR whose rows, like the out-CSR's, are
+// strictly increasing: the half-edges of row v in key order are then the
+// merge of its out row (keys x<<1) and its in row (keys s<<1|1), so an
+// element's slot is its index in its own row plus the number of keys of the
+// other row below its own (a binary search), and no sort is needed.  Each
+// thread takes kPlaceArcs consecutive elements of the out rows or of the in
+// rows (few, so that the chains of dependent searches stay short).  Indices are checked as the arc check does; a row found out of
+// order sets st[kUnsorted], and then the general counting, scatter and sort
+// run instead (they return at once otherwise).  Every slot stays inside its
+// row whatever the input, since the rank is at most the other row's length.
+//
+// The in-CSR is checked here too, so that no census ever sees a G* whose
+// in-entries do not mirror out-arcs: each in-arc s -> v is looked up in the
+// out row of s.  With both CSRs strictly increasing (no repeats) and m arcs
+// each, in-arcs that are all out-arcs make the in-CSR the transpose.  A miss
+// is only recorded (st[kInMismatch]): a search in an out row that is itself
+// out of order proves nothing, so the verdict waits until the order is known.
+__global__ __launch_bounds__(kB) void k_place_sorted(const int32_t* off, const int32_t* idx, const int32_t* in_off,
+                                                     const int32_t* in_idx, int32_t n, int64_t m, int32_t* hoff,
+                                                     uint32_t* keys, int32_t* hrow, int32_t* st) {
+  if (st[kStatus] != 0) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x, t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t v = t0; v <= n; v += stride) hoff[v] = off[v] + in_off[v];
+  const int64_t chunks = (m + kPlaceArcs - 1) / kPlaceArcs;
+  for (int64_t t = t0; t < 2 * chunks; t += stride) {
+    const uint32_t side = t >= chunks ? 1u : 0u;  // 0: out rows, 1: in rows
+    const int32_t* O = side ? in_off : off;
+    const int32_t* I = side ? in_idx : idx;
+    const int32_t* O2 = side ? off : in_off;
+    const int32_t* I2 = side ? idx : in_idx;
+    const int64_t i0 = (t - (side ? chunks : 0)) * kPlaceArcs, i1 = min(m, i0 + kPlaceArcs);
+    int32_t u = row_of(O, n, i0);
+    for (int64_t i = i0; i < i1; ++i) {
+      while (u < n - 1 && O[u + 1] <= i) ++u;
+      const int32_t x = I[i];
+      if (x < 0 || x >= n) { set_status(st, MOTIF_EINDEX); continue; }
+      if (x == u) { set_status(st, MOTIF_ESELFLOOP); continue; }
+      if (i > O[u] && I[i - 1] >= x) { st[kUnsorted] = 1; continue; }
+      // keys of the other row below this one: s < x for an out key x<<1,
+      // x <= s for an in key s<<1|1
+      int32_t lo = O2[u], hi = O2[u + 1];
+      const int32_t base = lo;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        const int32_t y = I2[mid];
+        if (side ? y <= x : y < x) lo = mid + 1; else hi = mid;
+      }
+      const int64_t pos = (int64_t)off[u] + in_off[u] + (i - O[u]) + (lo - base);
+      keys[pos] = ((uint32_t)x << 1) | side;
+      hrow[pos] = u;
+      if (side) {  // in-arc x -> u: u in the out row of x
+        int32_t a = off[x], b = off[x + 1];
+        while (a < b) {
+          const int32_t mid = (a + b) >> 1;
+          if (idx[mid] < u) a = mid + 1; else b = mid;
+        }
+        if (a >= off[x + 1] || idx[a] != u) st[kInMismatch] = 1;
+      }
+    }
+  }
+}
+
 // Small rows sorted by their own thread; longer rows queued: up to mid_max
 // keys for the bitonic sort, longer ones for the bitmap sort.
 __global__ __launch_bounds__(kB) void k_sort_small(const int32_t* hoff, int32_t n, uint32_t* keys, int32_t* midq,
-                                                   int32_t* bigq, int32_t mid_max, int32_t* st) {
-  if (st[kStatus] != 0) return;
+                                                   int32_t* bigq, int32_t mid_max, int32_t* st, const int32_t* skip) {
+  if (st[kStatus] != 0 || (skip && *skip == 0)) return;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const int32_t a = hoff[v], len = hoff[v + 1] - a;
     if (len <= 1) continue;
@@ -277,10 +345,10 @@ __global__ __launch_bounds__(kB) void k_sort_small(const int32_t* hoff, int32_t 
 
 // Mid rows: bitonic sort in LDS, one workgroup per row (persistent grid).
 __global__ __launch_bounds__(kB) void k_sort_mid(const int32_t* hoff, uint32_t* keys, const int32_t* midq,
-                                                 const int32_t* st) {
+                                                 const int32_t* st, const int32_t* skip) {
   __shared__ uint32_t s[kMidRow];
   static_assert(kB / 64 * kWaveRow <= kMidRow, "one LDS slice per wave");
-  if (st[kStatus] != 0) return;
+  if (st[kStatus] != 0 || (skip && *skip == 0)) return;
   const int32_t count = st[kMidCount];
   // rows of at most kWaveRow keys: one wave each, in its own LDS slice, with
   // no workgroup barrier (most mid rows are a few hundred keys)
@@ -350,10 +418,11 @@ __global__ __launch_bounds__(kB) void k_sort_mid(const int32_t* hoff, uint32_t* 
 // the start and each word again as the compaction reads it.
 template <bool LDS, int BS>
 __global__ __launch_bounds__(BS) void k_sort_big(const int32_t* hoff, int32_t n, uint32_t* keys,
-                                                 const int32_t* bigq, uint32_t* bitmaps, int32_t* st) {
+                                                 const int32_t* bigq, uint32_t* bitmaps, int32_t* st,
+                                                 const int32_t* skip) {
   __shared__ int32_t sh[BS / 64];
   __shared__ uint32_t lbm[LDS ? kLdsBitmapWords : 1];
-  if (st[kStatus] != 0) return;
+  if (st[kStatus] != 0 || (skip && *skip == 0)) return;
   const int32_t count = st[kBigCount];
   if ((int32_t)blockIdx.x >= count) return;
   const int64_t words = ((int64_t)2 * n + 31) / 32;
@@ -496,6 +565,34 @@ __global__ void k_check_in_arcs(const int32_t* in_off, const int32_t* in_idx, in
       continue;
     }
     uint32_t bit = 1u << (lo & 31);
+    if (atomicOr(&marks[lo >> 5], bit) & bit) set_status(st, MOTIF_ETRANSPOSE);
+  }
+}
+
+// In-CSR check of a single graph against the built G*: every listed in-arc
+// s -> v must be an arc of the out-CSR (entry v of G* row s carries the out
+// bit, which only the out-CSR sets) and no entry may be claimed twice.  With
+// the in-CSR's offsets checked (m arcs in all) and the out-CSR free of
+// repeats, that makes the in-CSR the transpose, whichever CSR the G* in-bits
+// were taken from.
+__global__ void k_check_in_arcs_out(const int32_t* in_off, const int32_t* in_idx, int32_t n, int64_t m,
+                                    const int32_t* gs_off, const uint32_t* gs_idx, uint32_t* marks, int32_t* st,
+                                    const int32_t* skip) {
+  if (st[kStatus] != 0 || (skip && *skip == 0)) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = row_of(in_off, n, i);
+    const int32_t s = in_idx[i];
+    if (s < 0 || s >= n) { set_status(st, MOTIF_EINDEX); continue; }
+    int32_t lo = gs_off[s], hi = gs_off[s + 1];
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if ((int32_t)(gs_idx[mid] & kIdMask) < v) lo = mid + 1; else hi = mid;
+    }
+    if (lo >= gs_off[s + 1] || (int32_t)(gs_idx[lo] & kIdMask) != v || !((gs_idx[lo] >> kTypeShift) & 1u)) {
+      set_status(st, MOTIF_ETRANSPOSE);
+      continue;
+    }
+    const uint32_t bit = 1u << (lo & 31);
     if (atomicOr(&marks[lo >> 5], bit) & bit) set_status(st, MOTIF_ETRANSPOSE);
   }
 }
@@ -759,27 +856,38 @@ DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s, hipEven
   }
 
   enqueue_zero_batch(z, s);
+  // A single graph with an in-CSR whose rows (and the out-CSR's) are
+  // strictly increasing is placed by merging each row's two halves; the
+  // counting, scatter and sort below then return at once.  Any other input
+  // takes them.
+  const bool from_in = !in.gid && in.in_off && m > 0;
+  const int32_t* skip = from_in ? st + kUnsorted : nullptr;
+  const unsigned arc_grid = grid_for((m + kArcsPerThread - 1) / kArcsPerThread);  // caps at 65536 blocks
   if (!in.gid) hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.out_off, n, m, st);
+  if (from_in) {
+    hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.in_off, n, m, st);
+    hipLaunchKernelGGL(k_place_sorted, dim3(grid_for(2 * ((m + kPlaceArcs - 1) / kPlaceArcs))), dim3(kB), 0, s,
+                       in.out_off, in.out_idx, in.in_off, in.in_idx, n, m, hoff, keys, hrow, st);
+  }
   if (m > 0)
-    hipLaunchKernelGGL(k_count_in, dim3(grid_for((m + kArcsPerThread - 1) / kArcsPerThread)), dim3(kB), 0, s,
-                       in.out_off, in.out_idx, n, m, in_cnt, st);  // grid_for caps at 65536 blocks
-  enqueue_scan1(sc_half, hoff, HalfCount{in.out_off, in_cnt, n}, st, s);
+    hipLaunchKernelGGL(k_count_in, dim3(arc_grid), dim3(kB), 0, s, in.out_off, in.out_idx, n, m, in_cnt, st, skip);
+  enqueue_scan1(sc_half, hoff, HalfCount{in.out_off, in_cnt, n}, st, s, skip);
   if (m > 0)
-    hipLaunchKernelGGL(k_scatter, dim3(grid_for((m + kArcsPerThread - 1) / kArcsPerThread)), dim3(kB), 0, s,
-                       in.out_off, in.out_idx, n, m, hoff, fill, keys,
-                       hrow, st);
+    hipLaunchKernelGGL(k_scatter, dim3(arc_grid), dim3(kB), 0, s, in.out_off, in.out_idx, n, m, hoff, fill, keys,
+                       hrow, st, skip);
   // With the bitmap in LDS a row costs about the same whatever its length
   // (a few words per thread to clear, count and compact), which beats the
   // bitonic sort's log^2 stages from a few hundred keys on.
   const bool lds_bitmap = (2 * (int64_t)n + 31) / 32 <= kLdsBitmapWords;
   hipLaunchKernelGGL(k_sort_small, dim3(grid_for(n)), dim3(kB), 0, s, hoff, n, keys, midq, bigq,
-                     lds_bitmap ? kLdsBitmapRow : kMidRow, st);
-  hipLaunchKernelGGL(k_sort_mid, dim3(512), dim3(kB), 0, s, hoff, keys, midq, st);
+                     lds_bitmap ? kLdsBitmapRow : kMidRow, st, skip);
+  hipLaunchKernelGGL(k_sort_mid, dim3(512), dim3(kB), 0, s, hoff, keys, midq, st, skip);
   if (lds_bitmap)
     hipLaunchKernelGGL((k_sort_big<true, kLdsBitmapBlock>), dim3(kLdsBitmapGrid), dim3(kLdsBitmapBlock), 0, s, hoff,
-                       n, keys, bigq, bitmaps, st);
+                       n, keys, bigq, bitmaps, st, skip);
   else
-    hipLaunchKernelGGL((k_sort_big<false, kB>), dim3(kBigSlots), dim3(kB), 0, s, hoff, n, keys, bigq, bitmaps, st);
+    hipLaunchKernelGGL((k_sort_big<false, kB>), dim3(kBigSlots), dim3(kB), 0, s, hoff, n, keys, bigq, bitmaps, st,
+                       skip);
   // merge: entry flags over the 2m sorted half-edges, scanned into positions
   enqueue_scan1(sc_entry, flags, EntryFlag{keys, hrow, hoff, 2 * m, st}, st, s);
   hipLaunchKernelGGL(k_gather_off, dim3(grid_for(n + 1)), dim3(kB), 0, s, flags, hoff, n, gs_off, deg, st);
@@ -792,7 +900,7 @@ DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s, hipEven
                      np_idx, st);
   // G* and N+ are complete here; the in-CSR check below only compares
   if (graph_ready) *ready_ok = hipEventRecord(graph_ready, s) == hipSuccess;
-  InCheck c{in_cnt, marks};
+  InCheck c{in_cnt, marks, from_in};
   if (deferred) *deferred = c;
   else enqueue_check_in(in, g, c, st, s, false);
   return g;
@@ -803,14 +911,23 @@ void enqueue_check_in(const BuildInput& in, const DevGraph& g, const InCheck& c,
   if (!in.in_off || g.n == 0) return;
   const int32_t n = in.n;
   const int64_t m = in.m;
-  if (!in.gid) hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.in_off, n, m, st);
-  hipLaunchKernelGGL(k_check_in_rows, dim3(grid_for(n)), dim3(kB), 0, s, in.in_off, c.in_cnt, n, in.gid, in.has_in,
-                     st);
-  enqueue_zero(c.marks, sizeof(uint32_t) * ((2 * m + 31) / 32 + 1), s);
   // beside a census, a few waves per CU: the search chains are latency-bound
   // and a full grid would hold back the census's own launches
   unsigned grid = grid_for(m);
   if (background) grid = std::min(grid, (unsigned)kCheckGrid);
+  if (!in.gid) {
+    if (!c.offsets_checked)
+      hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n + 1)), dim3(kB), 0, s, in.in_off, n, m, st);
+    enqueue_zero(c.marks, sizeof(uint32_t) * ((2 * m + 31) / 32 + 1), s);
+    // after a placement from sorted rows the in-CSR is already checked
+    if (m > 0)
+      hipLaunchKernelGGL(k_check_in_arcs_out, dim3(grid), dim3(kB), 0, s, in.in_off, in.in_idx, n, m, g.gs_off,
+                         g.gs_idx, c.marks, st, c.offsets_checked ? st + kUnsorted : nullptr);
+    return;
+  }
+  hipLaunchKernelGGL(k_check_in_rows, dim3(grid_for(n)), dim3(kB), 0, s, in.in_off, c.in_cnt, n, in.gid, in.has_in,
+                     st);
+  enqueue_zero(c.marks, sizeof(uint32_t) * ((2 * m + 31) / 32 + 1), s);
   if (m > 0)
     hipLaunchKernelGGL(k_check_in_arcs, dim3(grid), dim3(kB), 0, s, in.in_off, in.in_idx, n, m, g.gs_off, g.gs_idx,
                        in.gid, in.has_in, c.marks, st);

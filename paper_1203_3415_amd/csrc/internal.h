@@ -28,6 +28,8 @@ enum StatusSlot : int {
   kBigCount = 2,     // number of big segments queued for sorting
   kQueue = 3,        // anchor work-queue cursor
   kQueue2 = 4,       // second work-queue cursor
+  kUnsorted = 5,     // build from an in-CSR: 1 when a row is not strictly increasing
+  kInMismatch = 6,   // build from an in-CSR: 1 when an in-arc was not found among the out-arcs
   kStatusWords = 16,
 };
 
@@ -117,6 +119,7 @@ struct Pipeline {
   // the shared build and joined before the status is read (default priority)
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_pre = nullptr;  // the largest census's big-core tables are clear (cleared on `side`)
   TuningSet tune;  // the tuning this call was sized with (set before any enqueue)
   // Per-workgroup W rows of the k = 4, 5 core-reuse kernels for the census
   // on this pipeline's own stream: zeroed once when allocated, and left zero
@@ -155,8 +158,9 @@ struct BuildInput {
 // succeeded).  deferred (optional): the in-CSR check is not enqueued; what it
 // needs is returned there for enqueue_check_in on another stream.
 struct InCheck {
-  const int32_t* in_cnt = nullptr;  // in-degrees counted from the out-CSR
+  const int32_t* in_cnt = nullptr;  // in-degrees counted from the out-CSR (batch builds)
   uint32_t* marks = nullptr;        // one bit per G* entry
+  bool offsets_checked = false;     // the build already checked the in-CSR offsets
 };
 DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s, hipEvent_t graph_ready = nullptr,
                        bool* ready_ok = nullptr, InCheck* deferred = nullptr);
@@ -170,12 +174,29 @@ void enqueue_check_in(const BuildInput& in, const DevGraph& g, const InCheck& c,
 // and, unless out is null, the exact division into out[ngraphs * C] (written
 // only if every remainder is zero).  use_wpool: the W rows may come from
 // p.wpool (only for work on the pipeline's own stream, one census at a time).
+struct ZeroBatch;
+
+// Big-core tables of a k = 4, 5 core-reuse census (nbig = 0: none).
+struct BigTables {
+  int nbig = 0;
+  int32_t* big_id = nullptr;    // [n + 1]
+  int32_t* big_list = nullptr;  // [kMaxBig]
+  uint32_t* lbig = nullptr;     // labels, zeroed
+  uint32_t* wbig = nullptr;     // W rows, zeroed
+  uint32_t* mbig = nullptr;     // M counts, zeroed
+};
+// Takes the tables of a census of k on graphs of n vertices (at most maxn
+// each) from the arena and adds the regions to clear to z.
+BigTables take_big_tables(Pipeline& p, int k, int32_t n, int64_t maxn, const Tuning& t, ZeroBatch& z);
+
 // side_start (optional) is recorded on s once the set-up has done its
 // bandwidth-heavy clears and the small kernels before the core tables: work
 // on a second stream that waits for it then runs beside the rest of this
-// census instead of crowding those steps.
+// census instead of crowding those steps.  pre (optional): big-core tables
+// taken before the build and already cleared in stream order.
 void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64_t* out, hipStream_t s,
-                    bool use_wpool, hipEvent_t side_start = nullptr, bool* side_ok = nullptr);
+                    bool use_wpool, hipEvent_t side_start = nullptr, bool* side_ok = nullptr,
+                    const BigTables* pre = nullptr);
 // The exact division alone: out[i] = acc[i] / multiplicity, after a check
 // that every remainder is zero (Fact "correction").
 void enqueue_finalise(Pipeline& p, int k, int32_t ngraphs, const uint64_t* acc, uint64_t* out, hipStream_t s);

@@ -75,13 +75,17 @@ constexpr int kScanLds = kScanTile1 + kScanTile1 / 16;
 // its status word is set, the workgroups that see it scan zeros instead of
 // calling f (f may read data that a failed earlier step left unwritten);
 // every tile still publishes, so the look-back always ends.
+//
+// skip (optional): when *skip is 0 at launch the whole scan returns at once
+// (the word is final before the launch, so every workgroup agrees).
 template <class F>
 __global__ __launch_bounds__(kScanBlock) void k_scan1(int32_t* out, int64_t len, F f, uint64_t* tiles,
-                                                      uint32_t* ticket, const int32_t* st) {
+                                                      uint32_t* ticket, const int32_t* st, const int32_t* skip) {
   __shared__ int32_t sh[kScanBlock / 64];
   __shared__ int32_t stage[kScanLds];
   __shared__ uint32_t tile_s;
   __shared__ int32_t excl_s;
+  if (skip && *skip == 0) return;
   if (threadIdx.x == 0) tile_s = atomicAdd(ticket, 1u);
   __syncthreads();
   const uint32_t tile = tile_s;
@@ -178,11 +182,12 @@ inline Scan1 scan1_take(Arena& A, int64_t len, ZeroBatch& z) {
 inline size_t scan1_bytes(int64_t len) { return sizeof(uint64_t) * (size_t)(scan1_tiles(len) + 1) + 256; }
 
 template <class F>
-void enqueue_scan1(const Scan1& sc, int32_t* out, const F& f, const int32_t* st, hipStream_t s) {
+void enqueue_scan1(const Scan1& sc, int32_t* out, const F& f, const int32_t* st, hipStream_t s,
+                   const int32_t* skip = nullptr) {
   if (sc.len <= 0) return;
   const int64_t nt = scan1_tiles(sc.len);
   hipLaunchKernelGGL((k_scan1<F>), dim3((unsigned)nt), dim3(kScanBlock), 0, s, out, sc.len, f, sc.tiles,
-                     (uint32_t*)(sc.tiles + nt), st);
+                     (uint32_t*)(sc.tiles + nt), st, skip);
 }
 
 }  // namespace motif

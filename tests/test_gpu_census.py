@@ -148,6 +148,73 @@ def test_row_sort_paths(pm):
             assert np.array_equal(pm.census(off_d, idx_d, G.n, k), want[k]), (name, k)
 
 
+def test_in_csr_placement(pm):
+    """A single graph with an in-CSR is placed by merging each row's out and
+    in halves when every row of both CSRs is strictly increasing, and takes
+    the counting scatter and sort otherwise.  Both routes give the oracle's
+    census for a good in-CSR, in any mix of sorted and unsorted rows, and
+    both reject a bad one before any census runs on it."""
+    g = gg.chung_lu(1200, 6000, 2.2, 2.2, 0.25, seed=41)
+    want = {k: oracle.census(g, k) for k in (3, 4)}
+    in_off, in_idx = g.in_csr()
+    off_d, idx_d = _dev(pm, g.out_off, g.out_idx)
+    shuf_d = _dev(pm, g.out_off, _shuffled_rows(g, 42))[1]
+    io_d, ii_d = _dev(pm, in_off, in_idx)
+    rng = np.random.default_rng(43)
+    ii_shuf = in_idx.copy()
+    for v in range(g.n):
+        a, b = in_off[v], in_off[v + 1]
+        ii_shuf[a:b] = rng.permutation(ii_shuf[a:b])
+    iis_d = _dev(pm, in_off, ii_shuf)[1]
+    # good in-CSR: both sorted (merge placement), out rows unsorted (an
+    # in-arc lookup in an unsorted out row must not count as a miss), in rows
+    # unsorted, both unsorted
+    for name, od, ind in (("sorted", idx_d, ii_d), ("out unsorted", shuf_d, ii_d), ("in unsorted", idx_d, iis_d),
+                          ("both unsorted", shuf_d, iis_d)):
+        for k in (3, 4):
+            print(f"[case] in-CSR placement, good, {name}, k={k}", flush=True)
+            assert np.array_equal(pm.census(off_d, od, g.n, k, in_off=io_d, in_idx=ind), want[k]), (name, k)
+            outs = pm.census_multi(off_d, od, g.n, (k,), in_off=io_d, in_idx=ind)
+            assert np.array_equal(outs[0], want[k]), (name, k)
+
+    def expect(name, in_off_bad, in_idx_bad, code, od=idx_d):
+        bo, bi = _dev(pm, np.asarray(in_off_bad, np.int32), np.asarray(in_idx_bad, np.int32))
+        for k in (3, 4):
+            print(f"[case] in-CSR placement, bad, {name}, k={k}", flush=True)
+            with pytest.raises(pm.MotifError) as e:
+                pm.census(off_d, od, g.n, k, in_off=bo, in_idx=bi)
+            assert e.value.name == code, (name, k, e.value.name)
+            with pytest.raises(pm.MotifError) as e:
+                pm.census_multi(off_d, od, g.n, (3, k) if k == 4 else (k,), in_off=bo, in_idx=bi)
+            assert e.value.name == code, (name, k, e.value.name)
+
+    # a non-arc that keeps its row strictly increasing: found by the merge
+    # placement's own lookups
+    v = next(v for v in range(g.n) if in_off[v + 1] - in_off[v] >= 2 and in_idx[in_off[v]] > 0)
+    present = set(in_idx[in_off[v]:in_off[v + 1]].tolist())
+    x = next(x for x in range(in_idx[in_off[v]]) if x != v and x not in present)
+    bad = in_idx.copy()
+    bad[in_off[v]] = x
+    expect("non-arc, rows sorted", in_off, bad, "ETRANSPOSE")
+    expect("non-arc, out rows unsorted", in_off, bad, "ETRANSPOSE", od=shuf_d)
+    # a repeated in-arc (its row is no longer increasing: the general route)
+    dup = in_idx.copy()
+    dup[in_off[v] + 1] = dup[in_off[v]]
+    expect("repeated in-arc", in_off, dup, "ETRANSPOSE")
+    # the right arcs in the wrong rows: every row sorted, m arcs in all
+    moved = in_off.copy()
+    w = next(w for w in range(g.n - 1) if moved[w + 1] - moved[w] >= 1 and moved[w + 2] - moved[w + 1] >= 1)
+    moved[w + 1] -= 1
+    expect("arc in the wrong row", moved, in_idx, "ETRANSPOSE")
+    # an index out of range, and offsets that do not end at m
+    oob = in_idx.copy()
+    oob[-1] = g.n
+    expect("index out of range", in_off, oob, "EINDEX")
+    short = in_off.copy()
+    short[-1] -= 1
+    expect("offsets end below m", short, in_idx, "EINVAL_SHAPE")
+
+
 @pytest.mark.parametrize("k", [3, 4])
 def test_unsorted_rows_and_in_csr(pm, k):
     g = gg.chung_lu(800, 4000, 2.2, 2.2, 0.3, seed=31)
