@@ -415,12 +415,16 @@ int32_t motif_tune_cache_load(const char* path);
 
 /* ---- measurement ------------------------------------------------------------ */
 
-/* When enabled, every census call records HIP events on its stream around the
- * G* build and around the main census kernel of k.  Off by default. */
+/* on = 1: every census call records HIP events on its stream around the G*
+ * build and around the main census kernel of k.  on = 2: around the census
+ * kernel only (two events per size, so that timing a step perturbs it as
+ * little as possible).  on = 0: off (the default).  Other values:
+ * MOTIF_EINVAL_ARG. */
 int32_t motif_profile_enable(int32_t on);
 
 /* Durations in ms of the census kernel and of the build in the most recent
- * profiled call for k (waits for those events).  MOTIF_EINVAL_ARG if none. */
+ * profiled call for k (waits for those events); *build_ms = -1 when that call
+ * recorded no build events.  MOTIF_EINVAL_ARG if none. */
 int32_t motif_profile_read(int32_t k, float* kernel_ms, float* build_ms);
 
 /* ---- serving ---------------------------------------------------------------- */

@@ -496,8 +496,11 @@ def autotune(graphs, k: int, stream=None) -> dict:
     return t.as_dict()
 
 
-def profile_enable(on: bool = True):
-    lib().motif_profile_enable(1 if on else 0)
+def profile_enable(on: bool = True, census_only: bool = False):
+    """Record HIP events around the build and the census kernel of every
+    call (census_only: around the census kernel only; the build time then
+    reads as -1)."""
+    _check(lib().motif_profile_enable((2 if census_only else 1) if on else 0), "motif_profile_enable")
 
 
 def profile_read(k: int):

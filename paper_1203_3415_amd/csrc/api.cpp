@@ -203,8 +203,10 @@ bool check_shape(int32_t n, int64_t m) { return n >= 0 && m >= 0 && n < kMaxN &&
 // ---- profiling ----
 struct ProfState {
   bool on = false;
+  bool build = false;  // build events too
   hipEvent_t ev[6][4] = {};
   bool have[6] = {};
+  bool have_build[6] = {};
 };
 ProfState g_prof;
 
@@ -319,7 +321,7 @@ std::vector<TuneAxis> tune_axes(int k) {
 thread_local bool t_no_events = false;
 
 void profile_mark(int k, int what, bool begin, hipStream_t s) {
-  if (!g_prof.on || t_no_events || k < 3 || k > 5) return;
+  if (!g_prof.on || t_no_events || k < 3 || k > 5 || (what == 0 && !g_prof.build)) return;
   hipEvent_t& e = g_prof.ev[k][what * 2 + (begin ? 0 : 1)];
   if (!e && hipEventCreate(&e) != hipSuccess) {
     e = nullptr;
@@ -327,6 +329,7 @@ void profile_mark(int k, int what, bool begin, hipStream_t s) {
   }
   (void)hipEventRecord(e, s);
   if (what == 1 && !begin) g_prof.have[k] = true;
+  if (what == 0 && !begin) g_prof.have_build[k] = true;
 }
 
 // A workspace sizing error stopped an enqueue half way: the kernels already
@@ -1396,8 +1399,11 @@ int32_t motif_batch_plan_destroy(motif_batch_plan_t* b) {
 }
 
 int32_t motif_profile_enable(int32_t on) {
+  if (on < 0 || on > 2) return MOTIF_EINVAL_ARG;
   g_prof.on = on != 0;
+  g_prof.build = on == 1;
   for (bool& h : g_prof.have) h = false;
+  for (bool& h : g_prof.have_build) h = false;
   return 0;
 }
 
@@ -1407,7 +1413,10 @@ int32_t motif_profile_read(int32_t k, float* kernel_ms, float* build_ms) {
   hipEvent_t* e = g_prof.ev[k];
   if (hipEventSynchronize(e[3]) != hipSuccess) return MOTIF_EDEVICE;
   if (kernel_ms && hipEventElapsedTime(kernel_ms, e[2], e[3]) != hipSuccess) return MOTIF_EDEVICE;
-  if (build_ms && hipEventElapsedTime(build_ms, e[0], e[1]) != hipSuccess) return MOTIF_EDEVICE;
+  if (build_ms) {
+    if (!g_prof.have_build[k]) *build_ms = -1.0f;
+    else if (hipEventElapsedTime(build_ms, e[0], e[1]) != hipSuccess) return MOTIF_EDEVICE;
+  }
   return 0;
 }
 

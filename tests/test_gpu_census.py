@@ -625,3 +625,25 @@ def test_w_rows_reused_across_calls(pm):
         print(f"[case] W rows reuse round {rnd} n={g.n} k={k}", flush=True)
         got = pm.census(off, idx, g.n, k, stream=s)
         assert np.array_equal(got, want[(id(g), k)]), rnd
+
+
+def test_profile_modes(pm):
+    """Events around build and census kernel (mode 1), around the census
+    kernel only (mode 2: the build reads -1), and no other modes."""
+    g = gg.chung_lu(900, 4500, 2.2, 2.3, 0.15, seed=44)
+    off, idx = _dev(pm, g.out_off, g.out_idx)
+    try:
+        pm.profile_enable(True)
+        pm.census(off, idx, g.n, 4)
+        km, bm = pm.profile_read(4)
+        assert km > 0 and bm > 0
+        pm.profile_enable(True, census_only=True)
+        with pytest.raises(pm.MotifError):
+            pm.profile_read(4)  # nothing recorded since the mode was set
+        pm.census_multi(off, idx, g.n, (3, 4))
+        for k in (3, 4):
+            km, bm = pm.profile_read(k)
+            assert km > 0 and bm == -1.0
+    finally:
+        pm.profile_enable(False)
+    assert pm.lib().motif_profile_enable(3) == -13  # MOTIF_EINVAL_ARG
