@@ -59,6 +59,7 @@ namespace {
 
 constexpr int kSwB = kSwitchProposals;  // threads per workgroup = proposals per round
 constexpr int kSwLds = 38 * 1024;       // LDS words for one graph: n + 1 offsets, m targets, n locks
+constexpr int kSwPerCu = 2;             // switch workgroups per CU when their graphs fit in half the LDS
 constexpr uint32_t kFree = 0xFFFFFFFFu;
 // lock word index | kHeld: the row's winning proposal holds both its rows
 // (indices are below 1024; a free word has both top bits set)
@@ -135,15 +136,22 @@ __device__ __forceinline__ void sw_barrier() {
 
 // Randomise the graphs list[0..count) of gs, one workgroup per graph.  LDS:
 // the graph is held in LDS ((n + 1) + m + n words, + n target claims when
-// MUT).  Otherwise it is switched in place in global memory with this
+// MUT), kSwLds / PER_CU words: with PER_CU = 2 two workgroups share a CU
+// (a round is a short chain of LDS reads between barriers, and a second
+// workgroup fills the gaps), for lists whose graphs all fit in half.
+// Otherwise it is switched in place in global memory with this
 // workgroup's lock slice glock + blockIdx.x * lock_stride (lock_stride >= n,
 // or 2n when MUT, of every listed graph).  MUT: the slots ordered by kind go
 // to gperm + blockIdx.x * perm_stride (perm_stride >= m of every listed graph).
-template <bool LDS, bool MUT>
-__global__ __launch_bounds__(kSwB) void k_switch(const SwitchGraph* __restrict__ gs, const int32_t* __restrict__ list,
-                                                 int32_t count, uint32_t* __restrict__ glock, int64_t lock_stride,
-                                                 int32_t* __restrict__ gperm, int64_t perm_stride, const int32_t* st) {
-  __shared__ int32_t lds[LDS ? kSwLds : 1];
+// (the second launch bound is in waves per SIMD: PER_CU workgroups of
+// kSwB / 64 waves over the CU's four SIMDs)
+template <bool LDS, bool MUT, int PER_CU>
+__global__ __launch_bounds__(kSwB, PER_CU * kSwB / 256) void k_switch(const SwitchGraph* __restrict__ gs,
+                                                           const int32_t* __restrict__ list, int32_t count,
+                                                           uint32_t* __restrict__ glock, int64_t lock_stride,
+                                                           int32_t* __restrict__ gperm, int64_t perm_stride,
+                                                           const int32_t* st) {
+  __shared__ int32_t lds[LDS ? kSwLds / PER_CU : 1];
   __shared__ int32_t wsum[2][kSwB / 64];
   if (st[kStatus] != 0) return;
   const uint32_t tid = threadIdx.x;
@@ -468,28 +476,44 @@ int32_t enqueue_switch(Pipeline& p, const SwitchGraph* host_graphs, int32_t coun
       hipLaunchKernelGGL(k_check_graphs, cg, dim3(256), 0, s, dg, count, pass, p.status);
   }
   const int grid = std::max(1, p.num_cus);
+  // two workgroups per CU when every LDS graph fits in half the array
+  int64_t lds_words = 1;
+  for (int32_t g : lds_list) {
+    const SwitchGraph& G = host_graphs[g];
+    lds_words = std::max<int64_t>(lds_words, (int64_t)(G.n + 1) + G.m + (mutual ? 2 : 1) * (int64_t)G.n);
+  }
+  const int per_cu = lds_words <= kSwLds / kSwPerCu ? kSwPerCu : 1;
+  const int grid_lds = (int)std::min<int64_t>((int64_t)grid * per_cu, (int64_t)lds_list.size());
   // MUT: one slot list per workgroup (both launches run one after the other)
   int64_t max_m = 1;
   for (int32_t g = 0; g < count; ++g) max_m = std::max<int64_t>(max_m, host_graphs[g].m);
-  int32_t* perm = mutual ? p.arena.take<int32_t>((size_t)grid * (size_t)max_m) : nullptr;
+  int32_t* perm =
+      mutual ? p.arena.take<int32_t>((size_t)std::max(grid, grid_lds) * (size_t)max_m) : nullptr;
   if (!lds_list.empty()) {
-    const dim3 gl((unsigned)std::min<int64_t>(grid, (int64_t)lds_list.size()));
-    if (mutual)
-      hipLaunchKernelGGL((k_switch<true, true>), gl, dim3(kSwB), 0, s, dg, dl, (int32_t)lds_list.size(), nullptr, 0,
-                         perm, max_m, p.status);
-    else
-      hipLaunchKernelGGL((k_switch<true, false>), gl, dim3(kSwB), 0, s, dg, dl, (int32_t)lds_list.size(), nullptr, 0,
+    const dim3 gl((unsigned)grid_lds);
+    const int32_t nl = (int32_t)lds_list.size();
+    if (mutual && per_cu == kSwPerCu)
+      hipLaunchKernelGGL((k_switch<true, true, kSwPerCu>), gl, dim3(kSwB), 0, s, dg, dl, nl, nullptr, 0, perm,
+                         max_m, p.status);
+    else if (mutual)
+      hipLaunchKernelGGL((k_switch<true, true, 1>), gl, dim3(kSwB), 0, s, dg, dl, nl, nullptr, 0, perm, max_m,
+                         p.status);
+    else if (per_cu == kSwPerCu)
+      hipLaunchKernelGGL((k_switch<true, false, kSwPerCu>), gl, dim3(kSwB), 0, s, dg, dl, nl, nullptr, 0,
                          nullptr, 0, p.status);
+    else
+      hipLaunchKernelGGL((k_switch<true, false, 1>), gl, dim3(kSwB), 0, s, dg, dl, nl, nullptr, 0, nullptr, 0,
+                         p.status);
   }
   if (!glob_list.empty()) {
     const int gw = (int)std::min<int64_t>(grid, (int64_t)glob_list.size());
     const int64_t stride = (mutual ? 2 : 1) * max_glob_n;
     uint32_t* locks = p.arena.take<uint32_t>((size_t)gw * (size_t)stride);
     if (mutual)
-      hipLaunchKernelGGL((k_switch<false, true>), dim3(gw), dim3(kSwB), 0, s, dg, dl + lds_list.size(),
+      hipLaunchKernelGGL((k_switch<false, true, 1>), dim3(gw), dim3(kSwB), 0, s, dg, dl + lds_list.size(),
                          (int32_t)glob_list.size(), locks, stride, perm, max_m, p.status);
     else
-      hipLaunchKernelGGL((k_switch<false, false>), dim3(gw), dim3(kSwB), 0, s, dg, dl + lds_list.size(),
+      hipLaunchKernelGGL((k_switch<false, false, 1>), dim3(gw), dim3(kSwB), 0, s, dg, dl + lds_list.size(),
                          (int32_t)glob_list.size(), locks, stride, nullptr, 0, p.status);
   }
   return 0;
@@ -502,7 +526,7 @@ size_t switch_bytes(int32_t count, int64_t max_n, int64_t max_m, int num_cus) {
   const size_t wg = (size_t)std::max(1, num_cus);
   return al(sizeof(SwitchGraph) * std::max(count, 1)) + al(sizeof(int32_t) * std::max(count, 1)) +
          al(2 * sizeof(uint32_t) * wg * (size_t)std::max<int64_t>(max_n, 1)) +
-         al(sizeof(int32_t) * wg * (size_t)std::max<int64_t>(max_m, 1));
+         al(sizeof(int32_t) * wg * kSwPerCu * (size_t)std::max<int64_t>(max_m, 1));
 }
 
 uint64_t switch_key(uint64_t seed, int64_t graph) { return sm64_mix(seed + (uint64_t)(graph + 1) * kGamma); }
