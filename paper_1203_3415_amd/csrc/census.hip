@@ -150,9 +150,16 @@ __device__ __forceinline__ void hist_flush(u64* hist, uint64_t* acc, int32_t g) 
 // barrier.  In a private global slice (GLOBAL = true) the updates are device
 // atomics performed in L2, so reads also go to L2 (agent-scope atomic loads
 // bypass the per-CU L1, which those atomics do not update).
+//
+// Vertices are indexed from `base`, the first vertex of the graph being
+// worked on, so that a batch of small graphs needs label room for its
+// largest graph only (and keeps the labels in LDS); a kernel moves `base`
+// when it moves to another graph, with every label of the previous one
+// cleared.
 template <int BITS, bool GLOBAL = false>
 struct Labels {
   uint32_t* w;
+  uint32_t base = 0;
   static constexpr int kPer = 32 / BITS;
   static constexpr uint32_t kMask = (1u << BITS) - 1u;
   __device__ __forceinline__ uint32_t word(uint32_t i) const {
@@ -160,15 +167,19 @@ struct Labels {
     else return w[i];
   }
   __device__ __forceinline__ uint32_t get(uint32_t x) const {
+    x -= base;
     return (word(x / kPer) >> ((x % kPer) * BITS)) & kMask;
   }
   __device__ __forceinline__ void set_bits(uint32_t x, uint32_t v) const {
+    x -= base;
     atomicOr(&w[x / kPer], v << ((x % kPer) * BITS));
   }
   __device__ __forceinline__ void clear_bits(uint32_t x, uint32_t v) const {
+    x -= base;
     atomicAnd(&w[x / kPer], ~(v << ((x % kPer) * BITS)));
   }
   __device__ __forceinline__ void clear_all(uint32_t x) const {
+    x -= base;
     if constexpr (GLOBAL) __hip_atomic_store(&w[x / kPer], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else w[x / kPer] = 0u;
   }
@@ -439,6 +450,7 @@ __global__ __launch_bounds__(BLOCK) void k4_kernel(DevGraph G, const uint16_t* _
       if (g != cur_g) {
         hist_flush<C, BLOCK>(hist, acc, cur_g);
         cur_g = g;
+        lab.base = G.voff ? (uint32_t)G.voff[g] : 0u;  // every label of the previous anchor is cleared
         bar<LCAP == 0>();
       }
       const uint32_t tuv = ev >> kTypeShift;
@@ -548,6 +560,7 @@ __global__ __launch_bounds__(BLOCK) void k5_kernel(DevGraph G, const uint16_t* _
             lab.clear_bits(G.gs_idx[i] & kIdMask, 3u);
         }
         bar<LCAP == 0>();
+        lab.base = G.voff ? (uint32_t)G.voff[G.gid[b]] : 0u;  // the previous centre's labels are cleared
         for (int32_t i = ba + threadIdx.x; i < bend; i += BLOCK) {
           const uint32_t e = G.gs_idx[i];
           lab.set_bits(e & kIdMask, e >> kTypeShift);
@@ -1572,6 +1585,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     if (c == core) return;
     if (core >= 0) core_teardown(core);
     wbase = G.voff ? G.voff[g] : 0;
+    lab.base = (uint32_t)wbase;  // the previous core's labels are cleared
     core = c;
     core_setup(c);
   };
@@ -1804,6 +1818,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
           bar<GL>();
         }
         wbase = G.voff ? G.voff[g] : 0;
+        lab.base = (uint32_t)wbase;  // the previous core's labels are cleared
         core = c;
         core_setup(c);
       }
@@ -2279,8 +2294,10 @@ size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int nu
   }
   b += 2 * al(sizeof(uint64_t) * (size_t)G * num_classes(k));  // accumulators (+ output staging)
   b += al(64 * sizeof(int32_t));                               // queue counters
-  const int cap = k == 4 ? label_cap_k4((int32_t)N) : k == 5 ? label_cap_k5((int32_t)N) : 1;
-  if (cap == 0) b += al(sizeof(uint32_t) * (size_t)label_words(k, (int32_t)N) * grid_size(t, num_cus));
+  // labels are indexed within one graph: room for the largest one
+  const int32_t ln = (int32_t)(maxn > 0 ? maxn : N);
+  const int cap = k == 4 ? label_cap_k4(ln) : k == 5 ? label_cap_k5(ln) : 1;
+  if (cap == 0) b += al(sizeof(uint32_t) * (size_t)label_words(k, ln) * grid_size(t, num_cus));
   return b + 4096;
 }
 
@@ -2348,8 +2365,10 @@ void enqueue_census(Pipeline& p, const DevGraph& g, int k, uint64_t* acc, uint64
                          std::max(1, t.tile));
     } else {
       const bool reuse = t.heavy == 1;
-      const int cap = k == 4 ? label_cap_k4(g.n) : label_cap_k5(g.n);
-      const int64_t lw = label_words(k, g.n);
+      // labels are indexed within one graph (Labels::base): room for the largest
+      const int32_t ln = g.max_graph_n > 0 ? g.max_graph_n : g.n;
+      const int cap = k == 4 ? label_cap_k4(ln) : label_cap_k5(ln);
+      const int64_t lw = label_words(k, ln);
       uint32_t* glabels = nullptr;
       if (cap == 0) {
         glabels = p.arena.take<uint32_t>((size_t)lw * grid);
