@@ -445,23 +445,35 @@ unsigned blocks(int64_t items, int b) {
 }  // namespace
 
 int32_t enqueue_switch(Pipeline& p, const SwitchGraph* host_graphs, int32_t count, bool mutual, hipStream_t s) {
-  // graphs held in LDS and graphs switched in global memory, each a list
-  std::vector<int32_t> lds_list, glob_list;
+  // three lists: graphs that fit in half the LDS array (two workgroups per
+  // CU), graphs that need all of it (one per CU), graphs switched in global
+  // memory; each list largest graph first, so that the graphs taken last by
+  // the persistent workgroups are the short ones
+  auto words = [&](const SwitchGraph& G) { return (int64_t)(G.n + 1) + G.m + (mutual ? 2 : 1) * (int64_t)G.n; };
+  std::vector<int32_t> half_list, full_list, glob_list;
   int64_t max_glob_n = 0;
   for (int32_t g = 0; g < count; ++g) {
     const SwitchGraph& G = host_graphs[g];
-    if ((int64_t)(G.n + 1) + G.m + (mutual ? 2 : 1) * (int64_t)G.n <= kSwLds) {
-      lds_list.push_back(g);
+    const int64_t w = words(G);
+    if (w <= kSwLds / kSwPerCu) {
+      half_list.push_back(g);
+    } else if (w <= kSwLds) {
+      full_list.push_back(g);
     } else {
       glob_list.push_back(g);
       max_glob_n = std::max<int64_t>(max_glob_n, G.n);
     }
   }
+  auto larger_first = [&](int32_t a, int32_t b) { return host_graphs[a].m > host_graphs[b].m; };
+  std::stable_sort(half_list.begin(), half_list.end(), larger_first);
+  std::stable_sort(full_list.begin(), full_list.end(), larger_first);
+  std::stable_sort(glob_list.begin(), glob_list.end(), larger_first);
   SwitchGraph* dg = p.arena.take<SwitchGraph>(std::max(count, 1));
   int32_t* dl = p.arena.take<int32_t>(std::max(count, 1));
   if (hipMemcpyAsync(dg, host_graphs, sizeof(SwitchGraph) * count, hipMemcpyHostToDevice, s) != hipSuccess)
     return MOTIF_EDEVICE;
-  std::vector<int32_t> lists(lds_list);
+  std::vector<int32_t> lists(full_list);
+  lists.insert(lists.end(), half_list.begin(), half_list.end());
   lists.insert(lists.end(), glob_list.begin(), glob_list.end());
   if (!lists.empty() &&
       hipMemcpyAsync(dl, lists.data(), sizeof(int32_t) * lists.size(), hipMemcpyHostToDevice, s) != hipSuccess)
@@ -476,45 +488,43 @@ int32_t enqueue_switch(Pipeline& p, const SwitchGraph* host_graphs, int32_t coun
       hipLaunchKernelGGL(k_check_graphs, cg, dim3(256), 0, s, dg, count, pass, p.status);
   }
   const int grid = std::max(1, p.num_cus);
-  // two workgroups per CU when every LDS graph fits in half the array
-  int64_t lds_words = 1;
-  for (int32_t g : lds_list) {
-    const SwitchGraph& G = host_graphs[g];
-    lds_words = std::max<int64_t>(lds_words, (int64_t)(G.n + 1) + G.m + (mutual ? 2 : 1) * (int64_t)G.n);
-  }
-  const int per_cu = lds_words <= kSwLds / kSwPerCu ? kSwPerCu : 1;
-  const int grid_lds = (int)std::min<int64_t>((int64_t)grid * per_cu, (int64_t)lds_list.size());
-  // MUT: one slot list per workgroup (both launches run one after the other)
+  const int grid_full = (int)std::min<int64_t>(grid, (int64_t)full_list.size());
+  const int grid_half = (int)std::min<int64_t>((int64_t)grid * kSwPerCu, (int64_t)half_list.size());
+  // MUT: one slot list per workgroup (the launches run one after the other)
   int64_t max_m = 1;
   for (int32_t g = 0; g < count; ++g) max_m = std::max<int64_t>(max_m, host_graphs[g].m);
   int32_t* perm =
-      mutual ? p.arena.take<int32_t>((size_t)std::max(grid, grid_lds) * (size_t)max_m) : nullptr;
-  if (!lds_list.empty()) {
-    const dim3 gl((unsigned)grid_lds);
-    const int32_t nl = (int32_t)lds_list.size();
-    if (mutual && per_cu == kSwPerCu)
-      hipLaunchKernelGGL((k_switch<true, true, kSwPerCu>), gl, dim3(kSwB), 0, s, dg, dl, nl, nullptr, 0, perm,
+      mutual ? p.arena.take<int32_t>((size_t)std::max(grid, grid_half) * (size_t)max_m) : nullptr;
+  if (!full_list.empty()) {
+    const int32_t nl = (int32_t)full_list.size();
+    if (mutual)
+      hipLaunchKernelGGL((k_switch<true, true, 1>), dim3(grid_full), dim3(kSwB), 0, s, dg, dl, nl, nullptr, 0, perm,
                          max_m, p.status);
-    else if (mutual)
-      hipLaunchKernelGGL((k_switch<true, true, 1>), gl, dim3(kSwB), 0, s, dg, dl, nl, nullptr, 0, perm, max_m,
-                         p.status);
-    else if (per_cu == kSwPerCu)
-      hipLaunchKernelGGL((k_switch<true, false, kSwPerCu>), gl, dim3(kSwB), 0, s, dg, dl, nl, nullptr, 0,
-                         nullptr, 0, p.status);
     else
-      hipLaunchKernelGGL((k_switch<true, false, 1>), gl, dim3(kSwB), 0, s, dg, dl, nl, nullptr, 0, nullptr, 0,
-                         p.status);
+      hipLaunchKernelGGL((k_switch<true, false, 1>), dim3(grid_full), dim3(kSwB), 0, s, dg, dl, nl, nullptr, 0,
+                         nullptr, 0, p.status);
+  }
+  if (!half_list.empty()) {
+    const int32_t nl = (int32_t)half_list.size();
+    const int32_t* hl = dl + full_list.size();
+    if (mutual)
+      hipLaunchKernelGGL((k_switch<true, true, kSwPerCu>), dim3(grid_half), dim3(kSwB), 0, s, dg, hl, nl, nullptr, 0,
+                         perm, max_m, p.status);
+    else
+      hipLaunchKernelGGL((k_switch<true, false, kSwPerCu>), dim3(grid_half), dim3(kSwB), 0, s, dg, hl, nl, nullptr,
+                         0, nullptr, 0, p.status);
   }
   if (!glob_list.empty()) {
     const int gw = (int)std::min<int64_t>(grid, (int64_t)glob_list.size());
     const int64_t stride = (mutual ? 2 : 1) * max_glob_n;
     uint32_t* locks = p.arena.take<uint32_t>((size_t)gw * (size_t)stride);
+    const int32_t* gl = dl + full_list.size() + half_list.size();
     if (mutual)
-      hipLaunchKernelGGL((k_switch<false, true, 1>), dim3(gw), dim3(kSwB), 0, s, dg, dl + lds_list.size(),
-                         (int32_t)glob_list.size(), locks, stride, perm, max_m, p.status);
+      hipLaunchKernelGGL((k_switch<false, true, 1>), dim3(gw), dim3(kSwB), 0, s, dg, gl, (int32_t)glob_list.size(),
+                         locks, stride, perm, max_m, p.status);
     else
-      hipLaunchKernelGGL((k_switch<false, false, 1>), dim3(gw), dim3(kSwB), 0, s, dg, dl + lds_list.size(),
-                         (int32_t)glob_list.size(), locks, stride, nullptr, 0, p.status);
+      hipLaunchKernelGGL((k_switch<false, false, 1>), dim3(gw), dim3(kSwB), 0, s, dg, gl, (int32_t)glob_list.size(),
+                         locks, stride, nullptr, 0, p.status);
   }
   return 0;
 }

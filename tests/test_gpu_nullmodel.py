@@ -88,6 +88,30 @@ def test_randomize_keeps_degrees_and_simplicity(pm, shape, mutual):
     assert np.array_equal(again.cpu().numpy(), outs[1])   # a function of (input, seed, graph index)
 
 
+@pytest.mark.parametrize("mutual", [False, True])
+def test_randomize_mixed_sizes(pm, mutual):
+    """One call over graphs of every placement: small enough for two
+    workgroups per CU, needing a CU's whole LDS, and switched in global
+    memory (three launches, each list largest first).  Every graph keeps its
+    degrees and stays simple, and the call is a function of its inputs."""
+    import torch
+    bases = [gg.chung_lu(1500, 6000, 2.3, 2.3, 0.05, seed=21),    # fits in half the LDS
+             gg.chung_lu(5000, 20000, 2.3, 2.3, 0.3, seed=22),    # needs all of it
+             gg.chung_lu(20000, 60000, 2.2, 2.2, 0.1, seed=23),   # global memory
+             gg.chung_lu(800, 3200, 2.3, 2.3, 0.05, seed=24)]     # half again, smaller
+    devs = [pm.to_device(b.out_off, b.out_idx) for b in bases]
+    outs = []
+    for rep in range(2):
+        print(f"[case] randomise mixed sizes mutual={mutual} rep={rep}", flush=True)
+        copies = [idx.clone() for _, idx in devs]
+        pm.null_randomize([(off, c, b.n) for (off, _), c, b in zip(devs, copies, bases)], 100, seed=31, mutual=mutual)
+        torch.cuda.synchronize()
+        outs.append([c.cpu().numpy() for c in copies])
+    for b, c0, c1 in zip(bases, outs[0], outs[1]):
+        assert np.array_equal(c0, c1)
+        assert _check_same_degrees(b, _host(b, torch.from_numpy(c0)), mutual) > 0.5
+
+
 # Tiny start graphs with 73 graphs reachable by plain switches and 48 by
 # mutual-preserving ones (enumerated by switch_space.reachable).
 UNIFORM = {False: (5, [(0, 1), (1, 0), (2, 3), (3, 2), (0, 2), (1, 3), (4, 0), (2, 4)]),
