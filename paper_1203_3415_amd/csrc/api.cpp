@@ -699,7 +699,12 @@ int32_t motif_census6(const int32_t* out_off, const int32_t* out_idx, const int3
   uint64_t* acc = nullptr;
   uint32_t* labels = nullptr;
   int32_t rc = 0;
-  const int grid = 2 * cus;
+  // a census workgroup's anchor is a short chain of dependent reads, so the
+  // chip wants all the workgroups it can hold (five per CU by LDS; the grid
+  // must not exceed what is resident, since the workgroups stride over the
+  // anchor list); each needs its own byte labels, n bytes, hence fewer for
+  // large n
+  const int grid = (n <= 65536 ? 4 : 2) * cus;
   const int64_t label_words = ((int64_t)n + 3) / 4;
   do {
     unsigned long long host_ctr[2] = {0, 0};

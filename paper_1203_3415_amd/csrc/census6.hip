@@ -389,18 +389,27 @@ __device__ __forceinline__ uint32_t slot6(uint32_t L) {
 
 constexpr int kB6 = 256;           // threads per workgroup of k6_census
 constexpr int kMemCap6 = 4096;     // labelled vertices per anchor
+constexpr int kAggBits6 = 10;      // class sums kept in LDS: 1,024 slots
+constexpr int kAgg6 = 1 << kAggBits6;
+constexpr int kAggProbe6 = 16;     // probes before a class goes straight to the accumulator
 
 // One workgroup per anchor 4-set of the list: labels in the workgroup's byte
-// slice lab (n bytes, all zero between anchors), the 255 label counts in LDS,
-// the anchor's contributions added to acc[lut[code]] (global atomics).
+// slice lab (n bytes, all zero between anchors), the 255 label counts in LDS.
+// The anchors' contributions are summed per class in an LDS table and added
+// to acc once per class when the table is half full and at the end: many
+// anchors hit the same few classes (those of two vertices joined to the
+// anchor and not to each other above all), and one global atomic per
+// contribution queued on those few addresses.
 __global__ __launch_bounds__(kB6) void k6_census(DevGraph G, const int4* __restrict__ anchors, int64_t nanchors,
                                                  const uint32_t* __restrict__ lut, uint64_t* __restrict__ acc,
                                                  uint32_t* __restrict__ labels, int64_t label_words, int32_t* st) {
   __shared__ int32_t cnt[256];
   __shared__ int32_t mem[kMemCap6];
-  __shared__ int32_t nmem, nz;
+  __shared__ int32_t nmem, nz, nagg;
   __shared__ uint32_t zl[256];
   __shared__ uint32_t base_sh;
+  __shared__ uint32_t akey[kAgg6];
+  __shared__ uint64_t aval[kAgg6];
   if (st[kStatus] != 0) return;
   uint32_t* lab = labels + (int64_t)blockIdx.x * label_words;
   auto lab_get = [&](int32_t v) {
@@ -412,12 +421,36 @@ __global__ __launch_bounds__(kB6) void k6_census(DevGraph G, const int4* __restr
       atomicMin(&st[kStatus], MOTIF_EINTERNAL);
       return;
     }
-    atomicAdd(&acc[c], w);
+    uint32_t h = (c * 2654435761u) >> (32 - kAggBits6);
+    for (int i = 0; i < kAggProbe6; ++i) {
+      const uint32_t old = atomicCAS(&akey[h], kEmpty6, c);
+      if (old == kEmpty6) atomicAdd(&nagg, 1);
+      if (old == kEmpty6 || old == c) {
+        atomicAdd(&aval[h], w);
+        return;
+      }
+      h = (h + 1) & (kAgg6 - 1);
+    }
+    atomicAdd(&acc[c], w);  // a crowded stretch of the table
+  };
+  auto flush = [&] {  // between barriers
+    for (int i = threadIdx.x; i < kAgg6; i += kB6) {
+      if (akey[i] != kEmpty6) {
+        atomicAdd(&acc[akey[i]], aval[i]);
+        akey[i] = kEmpty6;
+        aval[i] = 0;
+      }
+    }
   };
   cnt[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < kAgg6; i += kB6) {
+    akey[i] = kEmpty6;
+    aval[i] = 0;
+  }
   if (threadIdx.x == 0) {
     nmem = 0;
     nz = 0;
+    nagg = 0;
     base_sh = 0;
   }
   __syncthreads();
@@ -498,13 +531,18 @@ __global__ __launch_bounds__(kB6) void k6_census(DevGraph G, const int4* __restr
     cnt[threadIdx.x] = 0;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    const bool full = nagg > kAgg6 / 2;  // read by every thread between the same barriers
+    if (full) flush();
+    __syncthreads();
     if (threadIdx.x == 0) {
       nmem = 0;
       nz = 0;
       base_sh = 0;
+      if (full) nagg = 0;
     }
     __syncthreads();
   }
+  flush();
 }
 
 // The bit map of every relabelling of 6 vertices (lexicographic order,
