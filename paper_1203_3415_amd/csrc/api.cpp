@@ -534,6 +534,7 @@ int32_t motif_shutdown(void) {
       if (pp.second->ev_fork) (void)hipEventDestroy(pp.second->ev_fork);
       if (pp.second->ev_join) (void)hipEventDestroy(pp.second->ev_join);
       if (pp.second->ev_pre) (void)hipEventDestroy(pp.second->ev_pre);
+      if (pp.second->k6_buf) (void)hipFree(pp.second->k6_buf);
       if (pp.second->arena.base) (void)hipFree(pp.second->arena.base);
       if (pp.second->wpool) (void)hipFree(pp.second->wpool);
       if (pp.second->status) (void)hipFree(pp.second->status);
@@ -683,18 +684,19 @@ int32_t motif_census6(const int32_t* out_off, const int32_t* out_idx, const int3
   in.m = m;
   const int cus = device_cus(dev);
   Pipeline* p = nullptr;
-  if (int32_t rc = get_pipeline(dev, s, build_bytes(n, m, 1, false), &p)) return rc;
+  if (int32_t rc = get_pipeline(dev, s, build_bytes(n, m, 1, false) + 4096, &p)) return rc;
   DevGraph g;
+  unsigned long long* ctr = nullptr;
   try {
     p->arena.reset();
     enqueue_zero(p->status, sizeof(int32_t) * kStatusWords, s);
     g = enqueue_build(*p, in, s);
+    ctr = p->arena.take<unsigned long long>(2);
   } catch (const WorkspaceError&) {
     return drain_after_error(*p, s);
   }
   if (int32_t rc = read_status(*p, s)) return rc;
   // the anchors: counted, then listed (each connected 4-set once)
-  unsigned long long* ctr = nullptr;
   int4* anchors = nullptr;
   uint64_t* acc = nullptr;
   uint32_t* labels = nullptr;
@@ -708,7 +710,6 @@ int32_t motif_census6(const int32_t* out_off, const int32_t* out_idx, const int3
   const int64_t label_words = ((int64_t)n + 3) / 4;
   do {
     unsigned long long host_ctr[2] = {0, 0};
-    if (hipMalloc(&ctr, sizeof(host_ctr)) != hipSuccess) { rc = MOTIF_ENOMEM; break; }
     enqueue_zero(ctr, sizeof(host_ctr), s);
     if ((rc = enqueue_anchors6(g, nullptr, ctr, 0, false, cus, p->status, s))) break;
     if (hipMemcpyAsync(host_ctr, ctr, sizeof(host_ctr), hipMemcpyDeviceToHost, s) != hipSuccess) {
@@ -718,12 +719,25 @@ int32_t motif_census6(const int32_t* out_off, const int32_t* out_idx, const int3
     if ((rc = read_status(*p, s))) break;  // also waits for the count
     const unsigned long long na = host_ctr[1];
     if (na >= (1ull << 31)) { rc = MOTIF_ETOOBIG; break; }
-    if (hipMalloc(&acc, sizeof(uint64_t) * kClasses6) != hipSuccess ||
-        hipMalloc(&labels, sizeof(uint32_t) * (size_t)grid * (size_t)label_words) != hipSuccess ||
-        (na > 0 && hipMalloc(&anchors, sizeof(int4) * na) != hipSuccess)) {
-      rc = MOTIF_ENOMEM;
-      break;
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t acc_b = al(sizeof(uint64_t) * kClasses6);
+    const size_t lab_b = al(sizeof(uint32_t) * (size_t)grid * (size_t)label_words);
+    const size_t need = acc_b + lab_b + al(sizeof(int4) * (size_t)std::max(na, 1ull));
+    if (p->k6_bytes < need) {  // nothing of an earlier call is in flight: read_status waited above
+      const size_t want = std::max(need, p->k6_bytes + p->k6_bytes / 2);
+      (void)hipFree(p->k6_buf);
+      p->k6_buf = nullptr;
+      p->k6_bytes = 0;
+      if (hipMalloc(&p->k6_buf, want) != hipSuccess) {
+        p->k6_buf = nullptr;
+        rc = MOTIF_ENOMEM;
+        break;
+      }
+      p->k6_bytes = want;
     }
+    acc = reinterpret_cast<uint64_t*>(p->k6_buf);
+    labels = reinterpret_cast<uint32_t*>(p->k6_buf + acc_b);
+    anchors = reinterpret_cast<int4*>(p->k6_buf + acc_b + lab_b);
     enqueue_zero(acc, sizeof(uint64_t) * kClasses6, s);
     enqueue_zero(labels, sizeof(uint32_t) * (size_t)grid * (size_t)label_words, s);
     if (na > 0) {
@@ -734,11 +748,7 @@ int32_t motif_census6(const int32_t* out_off, const int32_t* out_idx, const int3
     enqueue_divide(acc, T->mult, kClasses6, kClasses6, hist, p->status, s);
     rc = read_status(*p, s);
   } while (false);
-  (void)hipStreamSynchronize(s);  // the buffers below are released after the work that uses them
-  (void)hipFree(ctr);
-  (void)hipFree(anchors);
-  (void)hipFree(acc);
-  (void)hipFree(labels);
+  if (rc) (void)hipStreamSynchronize(s);  // the buffers are reused by the next call only after this work
   return rc;
 }
 

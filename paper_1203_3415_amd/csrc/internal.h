@@ -127,6 +127,10 @@ struct Pipeline {
   // no call has to clear them.  Null where the W rows come from the arena.
   uint32_t* wpool = nullptr;
   size_t wpool_bytes = 0;
+  // k = 6 census buffers (class sums, label slices, anchor list), grown on
+  // demand and kept for the next call on this stream
+  uint8_t* k6_buf = nullptr;
+  size_t k6_bytes = 0;
 };
 
 // Bytes the arena needs for a union graph of N vertices, M arcs, G graphs
