@@ -12,9 +12,13 @@
 // caller):
 //   offsets check -> arc check + in-degree count -> half-edge offsets (scan)
 //   -> half-edge scatter (key = id<<1 | dir) -> per-row sort (small rows in
-//   registers, mid rows by LDS bitonic sort, big rows by a bitmap over the key
-//   space) -> merge of equal ids into typed entries -> G* offsets (scan) ->
-//   G* write -> N+ count, scan, write -> optional in-CSR transpose check.
+//   registers, mid rows by LDS bitonic sort, long rows by a bitmap over the
+//   key space) -> merge of equal ids into typed entries -> G* offsets (scan)
+//   -> G* write -> N+ flags, scan, write -> optional in-CSR transpose check.
+// A single graph given with an in-CSR whose rows, like the out-CSR's, are
+// strictly increasing skips the count, scatter and sort: each row's two
+// halves are merged in place, and the in-CSR is checked on the way.  The
+// scans are single-pass look-back scans whose values come from functors.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
