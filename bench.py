@@ -168,8 +168,8 @@ def kr5_kernel_bytes(st) -> float:
 
 
 def k5_method_bytes(st) -> float:
-    """The survey's per-anchor byte model for k = 5 (the paper's method, one
-    connected triple at a time): per triple (a, b, c) its three rows and the
+    """The per-anchor byte model for k = 5 (what the paper's method, one
+    connected triple at a time, reads): per triple (a, b, c) its three rows and the
     N+ rows of adj(T): 4 (d_a + d_b + d_c) + 4 sum over x in N(a), N(b), N(c)
     of d+(x).  Neighbourhood overlaps are not subtracted, so this is an upper
     estimate; triples are counted at their centre (a triangle three times)."""
@@ -253,8 +253,8 @@ def bench_census(args):
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(kname, args.workload),
                     "kernel": kname, "kernel_ms": round(kms, 3), "algorithmic_bytes": kbytes}
-        # The survey's per-anchor byte model (what the paper's method, one
-        # anchor at a time, must read).  The core-reuse kernel reads far fewer
+        # The per-anchor byte model (what the paper's method, one anchor at a
+        # time, must read).  The core-reuse kernel reads far fewer
         # bytes than that, from a working set that sits in the caches, so the
         # model's rate can exceed the HBM peak: it is reported beside the
         # kernel's own floor, and the counters below say what binds.

@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kB) void k_scatter(const int32_t* off, const int32_
 // out row of s.  With both CSRs strictly increasing (no repeats) and m arcs
 // each, in-arcs that are all out-arcs make the in-CSR the transpose.  A miss
 // is only recorded (st[kInMismatch]): a search in an out row that is itself
-// out of order proves nothing, so the verdict waits until the order is known.
+// out of order proves nothing, so the outcome waits until the order is known.
 __global__ __launch_bounds__(kB) void k_place_sorted(const int32_t* off, const int32_t* idx, const int32_t* in_off,
                                                      const int32_t* in_idx, int32_t n, int64_t m, int32_t* hoff,
                                                      uint32_t* keys, int32_t* hrow, int32_t* st) {

@@ -168,7 +168,7 @@ struct InCheck {
 };
 DevGraph enqueue_build(Pipeline& p, const BuildInput& in, hipStream_t s, hipEvent_t graph_ready = nullptr,
                        bool* ready_ok = nullptr, InCheck* deferred = nullptr);
-// The in-CSR check of a build (nothing when no in-CSR was given); its verdict
+// The in-CSR check of a build (nothing when no in-CSR was given); its outcome
 // lands in the status word.  background: a bounded grid, for a stream that
 // runs beside a census.
 void enqueue_check_in(const BuildInput& in, const DevGraph& g, const InCheck& c, int32_t* status, hipStream_t s,
