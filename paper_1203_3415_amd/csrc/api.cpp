@@ -64,6 +64,12 @@ TuningSet g_tuning = {{
     // k = 5: core reuse, light-partner limit from a sweep on the n = 2e4 workload
     {1024, 1, 128, 1, 64, 192, 384},
 }};
+// Batches (one fused census of many graphs): for k = 4 the autotuner's choice
+// on 1,001 graphs of n = 2,000 (null-model ensembles: many small cores, so
+// smaller workgroups, two per CU, finer tiles; fused census 25.0 -> 23.0 ms).
+// Used while k's tuning has not been set explicitly.
+const Tuning kBatchTuning4 = {512, 2, 16, 1, 32, 256, 512};
+bool g_batch_default[6] = {false, false, false, false, true, false};
 
 int32_t current_device(int* dev) {
   if (hipGetDevice(dev) != hipSuccess) return MOTIF_EDEVICE;
@@ -230,6 +236,7 @@ int32_t size_bucket(int64_t arcs) { return arcs > 1 ? 63 - __builtin_clzll((unsi
 TuningSet tuning_for_call(int dev, int32_t nk, const int32_t* ks, bool batch, int64_t arcs) {
   std::lock_guard<std::mutex> lk(g_mu);
   TuningSet t = g_tuning;
+  if (batch && g_batch_default[4]) t.k[4] = kBatchTuning4;
   const DeviceState& d = g_dev[dev];
   for (int32_t i = 0; i < nk; ++i) {
     auto it = d.tuned.find(TuneKey{ks[i], batch ? 1 : 0, size_bucket(arcs)});
@@ -1000,6 +1007,7 @@ int32_t motif_set_tuning(int32_t k, const motif_tuning_t* in) {
   Tuning t = g_tuning.k[k];
   if (int32_t rc = apply_public(k, *in, &t)) return rc;
   g_tuning.k[k] = t;
+  g_batch_default[k] = false;  // an explicit choice holds for batches too
   // an explicit choice replaces what the autotuner cached for k
   for (auto& d : g_dev)
     for (auto it = d.second.tuned.begin(); it != d.second.tuned.end();)
