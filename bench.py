@@ -619,7 +619,7 @@ def bench_nullmodel(args):
         out = torch.empty((len(d), 199), dtype=torch.int64, device=dev)
         # without --autotune the fused census of a batch runs under the
         # library's batch default for k = 4 (motif.h, motif_set_tuning)
-        tuned = pm.autotune(d, 4) if args.autotune else "library batch default
+        tuned = pm.autotune(d, 4) if args.autotune else "library batch default"
         for _ in range(args.warmup):
             pm.census_batch(d, 4, out=out)
         timings = {"fused": timed(lambda: pm.census_batch(d, 4, out=out), args.steps)}
