@@ -38,3 +38,22 @@ def test_zscores_exact_for_huge_counts():
     z = zscores(big)
     # randomised rows: 0, 2, 4 above 2^62 -> mean 2, sd 2; real is +5 -> z = 1.5
     assert z[0] == pytest.approx(1.5, rel=1e-12)
+
+
+def test_bench_script_on_the_host():
+    """bench.py parses, refuses more than one GPU with a message, and its byte
+    models order as the kernels do: core reuse reads less than the per-anchor
+    method, and every model is positive on a small graph."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+    sys.path.insert(0, root)
+    import bench
+    st = bench.graph_stats(gg.chung_lu(2000, 10000, 2.2, 2.2, 0.2, seed=7))
+    per_anchor, reuse, k3 = bench.k4_kernel_bytes(st), bench.kr4_kernel_bytes(st), bench.k3_kernel_bytes(st)
+    assert 0 < reuse < per_anchor and k3 > 0
