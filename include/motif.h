@@ -389,10 +389,10 @@ typedef struct motif_tuning {
 
 /* Read / override the default parameters for k (0 in a field = keep).
  * Setting them also drops the autotuner's cached entries for k.  Fused
- * censuses of more than one graph at k = 4 start from their own default
- * (block 512, grid 2 per CU, tile 16, solo 32, light 256: many small cores)
- * until k's parameters are set here; motif_get_tuning reads the single-graph
- * defaults. */
+ * censuses of more than one graph at k = 4, each of at most 16,384 vertices,
+ * start from their own default (block 512, grid 2 per CU, tile 16, solo 32,
+ * light 256: many small cores) until k's parameters are set here;
+ * motif_get_tuning reads the single-graph defaults. */
 int32_t motif_get_tuning(int32_t k, motif_tuning_t* out);
 int32_t motif_set_tuning(int32_t k, const motif_tuning_t* in);
 

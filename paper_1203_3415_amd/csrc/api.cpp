@@ -64,11 +64,13 @@ TuningSet g_tuning = {{
     // k = 5: core reuse, light-partner limit from a sweep on the n = 2e4 workload
     {1024, 1, 128, 1, 64, 192, 384},
 }};
-// Batches (one fused census of many graphs): for k = 4 the autotuner's choice
-// on 1,001 graphs of n = 2,000 (null-model ensembles: many small cores, so
-// smaller workgroups, two per CU, finer tiles; fused census 25.0 -> 23.0 ms).
-// Used while k's tuning has not been set explicitly.
+// Batches of small graphs (one fused census of many graphs of at most
+// kBatchSmallN vertices): for k = 4 the autotuner's choice on 1,001 graphs of
+// n = 2,000 (null-model ensembles: many small cores, so smaller workgroups,
+// two per CU, finer tiles; fused census 25.0 -> 23.0 ms).  Used while k's
+// tuning has not been set explicitly.
 const Tuning kBatchTuning4 = {512, 2, 16, 1, 32, 256, 512};
+constexpr int64_t kBatchSmallN = 16384;
 bool g_batch_default[6] = {false, false, false, false, true, false};
 
 int32_t current_device(int* dev) {
@@ -233,10 +235,10 @@ namespace {
 int32_t size_bucket(int64_t arcs) { return arcs > 1 ? 63 - __builtin_clzll((unsigned long long)arcs) : 0; }
 }  // namespace
 
-TuningSet tuning_for_call(int dev, int32_t nk, const int32_t* ks, bool batch, int64_t arcs) {
+TuningSet tuning_for_call(int dev, int32_t nk, const int32_t* ks, bool batch, int64_t arcs, int64_t max_n) {
   std::lock_guard<std::mutex> lk(g_mu);
   TuningSet t = g_tuning;
-  if (batch && g_batch_default[4]) t.k[4] = kBatchTuning4;
+  if (batch && max_n >= 0 && max_n <= kBatchSmallN && g_batch_default[4]) t.k[4] = kBatchTuning4;
   const DeviceState& d = g_dev[dev];
   for (int32_t i = 0; i < nk; ++i) {
     auto it = d.tuned.find(TuneKey{ks[i], batch ? 1 : 0, size_bucket(arcs)});
@@ -975,9 +977,13 @@ int32_t motif_census_batch(const motif_graph_t* graphs, int32_t count, int32_t k
   int dev;
   int32_t rc = ensure_init(&dev);
   if (rc) return rc;
-  int64_t arcs = 0;
-  for (int32_t g = 0; g < count; ++g) arcs += std::max<int64_t>(0, graphs[g].m);
-  return census_batch_with(graphs, count, k, hists, (hipStream_t)stream, tuning_for_call(dev, 1, &k, count > 1, arcs));
+  int64_t arcs = 0, max_n = 0;
+  for (int32_t g = 0; g < count; ++g) {
+    arcs += std::max<int64_t>(0, graphs[g].m);
+    max_n = std::max<int64_t>(max_n, graphs[g].n);
+  }
+  return census_batch_with(graphs, count, k, hists, (hipStream_t)stream,
+                           tuning_for_call(dev, 1, &k, count > 1, arcs, max_n));
 }
 
 int32_t motif_census_batch_loop(const motif_graph_t* graphs, int32_t count, int32_t k, uint64_t* hists,
@@ -1252,7 +1258,7 @@ int32_t motif_null_model(const motif_graph_t* real, int32_t count, int32_t k, in
   if (int32_t rc = run_switch(*p, sg, (flags & MOTIF_SWITCH_MUTUAL) != 0, s)) return rc;
   // 3. one fused census of the real graph and its copies
   int32_t rc = census_batch_with(all.data(), count + 1, k, hists, s,
-                                 tuning_for_call(dev, 1, &k, true, real->m * (count + 1)));
+                                 tuning_for_call(dev, 1, &k, true, real->m * (count + 1), real->n));
   if (rc) return rc;
   // 4. z-scores of the real graph against the copies
   enqueue_zscores(hists, C, count, z, p->status, s);
@@ -1360,7 +1366,7 @@ motif_batch_plan_t* motif_batch_plan_create(const motif_graph_t* graphs, int32_t
   b->p.num_cus = device_cus(dev);
   int64_t maxn = 0;
   for (int32_t g = 0; g < count; ++g) maxn = std::max<int64_t>(maxn, graphs[g].n);
-  b->p.tune = tuning_for_call(dev, 1, &k, count > 1, M);
+  b->p.tune = tuning_for_call(dev, 1, &k, count > 1, M, maxn);
   const size_t bytes = pipeline_bytes(N, M, count, true, k, b->p.num_cus, maxn, b->p.tune.k[k]);
   if (hipMalloc(&b->p.arena.base, bytes) != hipSuccess || hipMalloc(&b->p.status, kStatusWords * 4) != hipSuccess ||
       hipHostMalloc(&b->p.host_status, kStatusWords * 4, hipHostMallocDefault) != hipSuccess ||

@@ -104,10 +104,11 @@ struct TuningSet {
   Tuning k[6];
 };
 TuningSet tuning_snapshot();
-// The tuning a call uses on device `dev`: the defaults, with the autotuner's
-// cached entry for (k, batch, floor(log2 arcs)) in place of k's when there is
-// one, for each of ks[0..nk).
-TuningSet tuning_for_call(int dev, int32_t nk, const int32_t* ks, bool batch, int64_t arcs);
+// The tuning a call uses on device `dev`: the defaults (for a batch whose
+// graphs have at most max_n >= 0 vertices, the small-graph batch default of
+// k = 4 where it applies), with the autotuner's cached entry for (k, batch,
+// floor(log2 arcs)) in place of k's when there is one, for each of ks[0..nk).
+TuningSet tuning_for_call(int dev, int32_t nk, const int32_t* ks, bool batch, int64_t arcs, int64_t max_n = -1);
 
 // Buffers of one census pipeline (one stream).
 struct Pipeline {
