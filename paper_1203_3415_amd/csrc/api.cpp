@@ -97,7 +97,8 @@ int32_t init_device_locked(int dev) {
     d.owned.push_back(mult);
     if (hipMalloc(&und, t->und_of.size() * sizeof(int16_t)) != hipSuccess) return MOTIF_ENOMEM;
     d.owned.push_back(und);
-    if (hipMemcpy(lut, t->lut.data(), t->lut.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess ||
+    const std::vector<uint16_t> dlut = device_lut_order(k, t->lut.data(), t->lut.size());
+    if (hipMemcpy(lut, dlut.data(), dlut.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(mult, t->mult.data(), t->mult.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(und, t->und_of.data(), t->und_of.size() * sizeof(int16_t), hipMemcpyHostToDevice) != hipSuccess)
       return MOTIF_EDEVICE;

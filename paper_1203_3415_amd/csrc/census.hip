@@ -43,10 +43,25 @@ namespace motif {
 
 namespace {
 
+// Bit of the arc i -> j (i != j) in the adjacency codes that index the
+// device class tables.  Row-major with the diagonal left out, except for
+// k = 4 and 5, where the two arcs between slots K-2 and K-1 (the members of
+// a pair in the closed forms) are moved to bits 0 and 1 and the rest keep
+// their order above them: a code without that edge and its three variants
+// with it are then four consecutive table entries, one aligned 8-byte read
+// (lut_quad).  The host table keeps row-major order; device_lut_order
+// writes the device copy in this one.
 template <int K>
 __host__ __device__ constexpr int cbit(int i, int j) {
-  return i * (K - 1) + (j < i ? j : j - 1);
+  const int n = i * (K - 1) + (j < i ? j : j - 1);
+  if (K < 4) return n;
+  const int a = (K - 2) * K, b = (K - 1) * (K - 1) + K - 2;  // row-major bits of (K-2, K-1) and (K-1, K-2)
+  return n == a ? 0 : n == b ? 1 : n < a ? n + 2 : n < b ? n + 1 : n;
 }
+static_assert(cbit<4>(2, 3) == 0 && cbit<4>(3, 2) == 1 && cbit<4>(0, 1) == 2 && cbit<4>(3, 1) == 11, "k = 4 order");
+static_assert(cbit<5>(3, 4) == 0 && cbit<5>(4, 3) == 1 && cbit<5>(0, 1) == 2 && cbit<5>(4, 2) == 19 &&
+                  cbit<5>(3, 2) == 16 && cbit<5>(4, 0) == 17,
+              "k = 5 order");
 
 // Code bits of a neighbour placed in slot S whose types towards the anchor
 // vertices 0..K-3 are packed 2 bits each in L (1 = arc anchor->x, 2 = arc
@@ -69,6 +84,15 @@ template <int K>
 __device__ __forceinline__ uint32_t rel_code(uint32_t t) {
   return ((t & 1u) ? (1u << cbit<K>(K - 2, K - 1)) : 0u) | ((t & 2u) ? (1u << cbit<K>(K - 1, K - 2)) : 0u);
 }
+
+// k = 4, 5: the classes of code c0 (no edge between slots K-2 and K-1) and
+// of c0 with that edge of each type, in one read; entry r of the word is the
+// class of c0 | rel_code<K>(r), r = 0..3 (rel_code<K>(r) == r in the order
+// of cbit).  lut must be 8-byte aligned.
+__device__ __forceinline__ uint64_t lut_quad(const uint16_t* lut, uint32_t c0) {
+  return *reinterpret_cast<const uint64_t*>(lut + c0);
+}
+__device__ __forceinline__ uint32_t quad_at(uint64_t q, uint32_t r) { return (uint32_t)(q >> (16u * r)) & 0xFFFFu; }
 
 __device__ __forceinline__ uint32_t flip(uint32_t t) { return ((t & 1u) << 1) | ((t & 2u) >> 1); }
 
@@ -691,7 +715,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   constexpr int HUBS = (K == 5 && LCAP == 32768) ? 80 : (K == 4 && LCAP == 65536) ? 384 : kMaxHubs;
   constexpr bool GL = LCAP == 0;
   __shared__ u64 hist[C];
-  __shared__ uint16_t lut_lds[K == 4 ? 4096 : 1];
+  __shared__ __align__(8) uint16_t lut_lds[K == 4 ? 4096 : 4];
   __shared__ int32_t cnt[NL], nzl[NL], nz_count;
   __shared__ uint32_t Mc[27];
   __shared__ uint32_t W[HUBS * 9];
@@ -811,9 +835,9 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   };
   // contribution of one edge between slots S1 (x) and S2 (y) of weight w
   auto edge = [&](uint32_t base, uint32_t Lx, uint32_t Ly, uint32_t r, u64 w) {
-    const uint32_t c0 = base | slot_code<K, S1>(Lx) | slot_code<K, S2>(Ly);
-    atomicAdd(&hist[lut[c0 | rel_code<K>(r)]], w);
-    atomicAdd(&hist[lut[c0]], (u64)0 - w);
+    const uint64_t q = lut_quad(lut, base | slot_code<K, S1>(Lx) | slot_code<K, S2>(Ly));
+    atomicAdd(&hist[quad_at(q, r)], w);
+    atomicAdd(&hist[quad_at(q, 0)], (u64)0 - w);
   };
   // k = 4: the same move counted in the anchor's table T at (min label, max
   // label, arc type seen from the smaller label's member): swapping the two
@@ -838,11 +862,12 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       T[3 * t + 2] = 0u;
     }
     const u64 w0 = (La == Lb ? na * (na - (na > 0)) / 2 : na * nb) - (u64)((int64_t)s1 + s2 + s3);
-    const uint32_t c0 = base | slot_code<K, S1>(La) | slot_code<K, S2>(Lb);
-    if (w0) atomicAdd(&hist[lut[c0]], w0);
-    if (s1) atomicAdd(&hist[lut[c0 | rel_code<K>(1u)]], (u64)(int64_t)s1);
-    if (s2) atomicAdd(&hist[lut[c0 | rel_code<K>(2u)]], (u64)(int64_t)s2);
-    if (s3) atomicAdd(&hist[lut[c0 | rel_code<K>(3u)]], (u64)(int64_t)s3);
+    if (w0 == 0 && (s1 | s2 | s3) == 0) return;
+    const uint64_t q = lut_quad(lut, base | slot_code<K, S1>(La) | slot_code<K, S2>(Lb));
+    if (w0) atomicAdd(&hist[quad_at(q, 0)], w0);
+    if (s1) atomicAdd(&hist[quad_at(q, 1)], (u64)(int64_t)s1);
+    if (s2) atomicAdd(&hist[quad_at(q, 2)], (u64)(int64_t)s2);
+    if (s3) atomicAdd(&hist[quad_at(q, 3)], (u64)(int64_t)s3);
   };
   // Flattened scan of the N+ rows of the vertices pick(0 .. items-1): pick
   // returns a vertex (or -1) and does the per-vertex work, visit(v, f, info)
@@ -1346,24 +1371,23 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     const bool it = sy || (Ly >> 2);
     const uint32_t cq = Lq & 3u, cy = Ly & 3u;
     const bool e1 = cq && cy && !it, e2 = mq && !sy, e3 = cq && it && !sy;
-    const uint32_t rc = rel_code<K>(r);
     const uint32_t b1 = base | slot_code<K, S1>(cq) | slot_code<K, S2>(cy);
     const uint32_t b2 = base | slot_code<K, S1>(Lq) | slot_code<K, S2>(Ly);
     const uint32_t b3 = base | slot_code<K, S1>(cq) | slot_code<K, S2>(Ly);
-    const uint32_t k1a = e1 ? lut[b1 | rc] : 0u, k1b = e1 ? lut[b1] : 0u;
-    const uint32_t k2a = e2 ? lut[b2 | rc] : 0u, k2b = e2 ? lut[b2] : 0u;
-    const uint32_t k3a = e3 ? lut[b3 | rc] : 0u, k3b = e3 ? lut[b3] : 0u;
+    const uint64_t q1 = e1 ? lut_quad(lut, b1) : 0ull;
+    const uint64_t q2 = e2 ? lut_quad(lut, b2) : 0ull;
+    const uint64_t q3 = e3 ? lut_quad(lut, b3) : 0ull;
     if (e1) {
-      atomicAdd(&hist[k1a], (u64)0 - s);
-      atomicAdd(&hist[k1b], s);
+      atomicAdd(&hist[quad_at(q1, r)], (u64)0 - s);
+      atomicAdd(&hist[quad_at(q1, 0)], s);
     }
     if (e2) {
-      atomicAdd(&hist[k2a], s);
-      atomicAdd(&hist[k2b], (u64)0 - s);
+      atomicAdd(&hist[quad_at(q2, r)], s);
+      atomicAdd(&hist[quad_at(q2, 0)], (u64)0 - s);
     }
     if (e3) {
-      atomicAdd(&hist[k3a], (u64)0 - s);
-      atomicAdd(&hist[k3b], s);
+      atomicAdd(&hist[quad_at(q3, r)], (u64)0 - s);
+      atomicAdd(&hist[quad_at(q3, 0)], s);
     }
   };
   auto umove = [&](uint32_t Lq, bool mq, uint32_t Ly, bool sy, uint32_t r) {
@@ -1439,27 +1463,20 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     for (int t3 = 0; t3 < 3; ++t3) {
       const uint32_t bt = bp | slot_code<K, S1>((uint32_t)t3 + 1u);
       const uint32_t cpl = bt | slot_code<K, S2>(LT), cmi = bt | slot_code<K, S2>(Lm);
-      uint32_t kp[3][2], km[3][2];
-#pragma unroll
-      for (int r3 = 0; r3 < 3; ++r3) {
-        const uint32_t rc = rel_code<K>((uint32_t)r3 + 1u);
-        const bool on = wv.v[t3 * 3 + r3] != 0u;
-        kp[r3][0] = on && plus ? lut[cpl | rc] : 0u;
-        kp[r3][1] = on && plus ? lut[cpl] : 0u;
-        km[r3][0] = on && minus ? lut[cmi | rc] : 0u;
-        km[r3][1] = on && minus ? lut[cmi] : 0u;
-      }
+      const bool on = (wv.v[t3 * 3] | wv.v[t3 * 3 + 1] | wv.v[t3 * 3 + 2]) != 0u;
+      const uint64_t qp = on && plus ? lut_quad(lut, cpl) : 0ull;
+      const uint64_t qm = on && minus ? lut_quad(lut, cmi) : 0ull;
 #pragma unroll
       for (int r3 = 0; r3 < 3; ++r3) {
         const u64 w = wv.v[t3 * 3 + r3];
         if (!w) continue;
         if (plus) {
-          atomicAdd(&hist[kp[r3][0]], w);
-          atomicAdd(&hist[kp[r3][1]], (u64)0 - w);
+          atomicAdd(&hist[quad_at(qp, (uint32_t)r3 + 1u)], w);
+          atomicAdd(&hist[quad_at(qp, 0)], (u64)0 - w);
         }
         if (minus) {
-          atomicAdd(&hist[km[r3][0]], (u64)0 - w);
-          atomicAdd(&hist[km[r3][1]], w);
+          atomicAdd(&hist[quad_at(qm, (uint32_t)r3 + 1u)], (u64)0 - w);
+          atomicAdd(&hist[quad_at(qm, 0)], w);
         }
       }
     }
@@ -2023,21 +2040,17 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
                     U5[t] = 0u;
                     const uint32_t X = (uint32_t)t / 48u, Y = ((uint32_t)t / 3u) % 16u, r = (uint32_t)t % 3u + 1u;
                     const u64 w64 = (u64)(int64_t)(int32_t)w;
-                    const uint32_t sx = slot_code<K, S1>(X) | slot_code<K, S2>(Y), rc = rel_code<K>(r);
+                    const uint32_t sx = slot_code<K, S1>(X) | slot_code<K, S2>(Y);
                     for (int32_t d0 = 0; d0 < nd; d0 += 4) {  // table reads of 4 bases, then the counters
-                      uint32_t kf[4], kn[4];
+                      uint64_t kq[4];
 #pragma unroll
-                      for (int u = 0; u < 4; ++u) {
-                        const uint32_t c0 = p5_db[min(d0 + u, nd - 1)] | sx;
-                        kf[u] = lut[c0 | rc];
-                        kn[u] = lut[c0];
-                      }
+                      for (int u = 0; u < 4; ++u) kq[u] = lut_quad(lut, p5_db[min(d0 + u, nd - 1)] | sx);
 #pragma unroll
                       for (int u = 0; u < 4; ++u) {
                         if (d0 + u >= nd) break;
                         const u64 wd = w64 * (u64)p5_dc[d0 + u];
-                        atomicAdd(&hist[kf[u]], wd);
-                        atomicAdd(&hist[kn[u]], (u64)0 - wd);
+                        atomicAdd(&hist[quad_at(kq[u], r)], wd);
+                        atomicAdd(&hist[quad_at(kq[u], 0)], (u64)0 - wd);
                       }
                     }
                   }
@@ -2273,6 +2286,24 @@ int32_t cost_cap(int64_t gs_cap) {
 }
 
 }  // namespace
+
+std::vector<uint16_t> device_lut_order(int k, const uint16_t* lut, size_t len) {
+  if (k != 4 && k != 5) return std::vector<uint16_t>(lut, lut + len);
+  // row-major bit n of the arc (i, j) goes to bit to[n]
+  int to[20] = {};
+  for (int i = 0, n = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j)
+      if (i != j) to[n++] = k == 4 ? cbit<4>(i, j) : cbit<5>(i, j);
+  const int bits = k * (k - 1);
+  std::vector<uint16_t> out(len);
+  for (size_t x = 0; x < len; ++x) {
+    uint32_t y = 0;
+    for (int n = 0; n < bits; ++n)
+      if ((x >> n) & 1u) y |= 1u << to[n];
+    out[y] = lut[x];
+  }
+  return out;
+}
 
 size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int num_cus, int64_t maxn,
                       const Tuning& t) {

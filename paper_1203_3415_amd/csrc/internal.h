@@ -134,6 +134,10 @@ struct Pipeline {
   size_t k6_bytes = 0;
 };
 
+// The class table of size k (len = 2^(k(k-1)) entries, indexed by row-major
+// adjacency codes) rewritten in the code order the census kernels use.
+std::vector<uint16_t> device_lut_order(int k, const uint16_t* lut, size_t len);
+
 // Bytes the arena needs for a union graph of N vertices, M arcs, G graphs
 // (G > 1 includes the packing buffers of a batch) under tuning t.
 size_t pipeline_bytes(int64_t N, int64_t M, int32_t G, bool batch, int k, int num_cus, int64_t maxn,
