@@ -45,20 +45,20 @@ namespace {
 
 // Bit of the arc i -> j (i != j) in the adjacency codes that index the
 // device class tables.  Row-major with the diagonal left out, except for
-// k = 4 and 5, where the two arcs between slots K-2 and K-1 (the members of
-// a pair in the closed forms) are moved to bits 0 and 1 and the rest keep
-// their order above them: a code without that edge and its three variants
-// with it are then four consecutive table entries, one aligned 8-byte read
-// (lut_quad).  The host table keeps row-major order; device_lut_order
-// writes the device copy in this one.
+// k = 5, where the two arcs between slots 3 and 4 (the members of a pair in
+// the closed forms) are moved to bits 0 and 1 and the rest keep their order
+// above them: a code without that edge and its three variants with it are
+// then four consecutive entries of the 2 MB table, one aligned 8-byte read
+// (lut_quad) instead of two.  (For k = 4 the table sits in LDS, and the same
+// order measured slightly slower.)  The host table keeps row-major order;
+// device_lut_order writes the device copy in this one.
 template <int K>
 __host__ __device__ constexpr int cbit(int i, int j) {
   const int n = i * (K - 1) + (j < i ? j : j - 1);
-  if (K < 4) return n;
-  const int a = (K - 2) * K, b = (K - 1) * (K - 1) + K - 2;  // row-major bits of (K-2, K-1) and (K-1, K-2)
+  if (K != 5) return n;
+  const int a = (K - 2) * K, b = (K - 1) * (K - 1) + K - 2;  // row-major bits of (3, 4) and (4, 3)
   return n == a ? 0 : n == b ? 1 : n < a ? n + 2 : n < b ? n + 1 : n;
 }
-static_assert(cbit<4>(2, 3) == 0 && cbit<4>(3, 2) == 1 && cbit<4>(0, 1) == 2 && cbit<4>(3, 1) == 11, "k = 4 order");
 static_assert(cbit<5>(3, 4) == 0 && cbit<5>(4, 3) == 1 && cbit<5>(0, 1) == 2 && cbit<5>(4, 2) == 19 &&
                   cbit<5>(3, 2) == 16 && cbit<5>(4, 0) == 17,
               "k = 5 order");
@@ -85,10 +85,10 @@ __device__ __forceinline__ uint32_t rel_code(uint32_t t) {
   return ((t & 1u) ? (1u << cbit<K>(K - 2, K - 1)) : 0u) | ((t & 2u) ? (1u << cbit<K>(K - 1, K - 2)) : 0u);
 }
 
-// k = 4, 5: the classes of code c0 (no edge between slots K-2 and K-1) and
-// of c0 with that edge of each type, in one read; entry r of the word is the
-// class of c0 | rel_code<K>(r), r = 0..3 (rel_code<K>(r) == r in the order
-// of cbit).  lut must be 8-byte aligned.
+// k = 5: the classes of code c0 (no edge between slots 3 and 4) and of c0
+// with that edge of each type, in one read; entry r of the word is the class
+// of c0 | rel_code<5>(r), r = 0..3 (rel_code<5>(r) == r in the order of
+// cbit).  lut must be 8-byte aligned.
 __device__ __forceinline__ uint64_t lut_quad(const uint16_t* lut, uint32_t c0) {
   return *reinterpret_cast<const uint64_t*>(lut + c0);
 }
@@ -715,7 +715,7 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   constexpr int HUBS = (K == 5 && LCAP == 32768) ? 80 : (K == 4 && LCAP == 65536) ? 384 : kMaxHubs;
   constexpr bool GL = LCAP == 0;
   __shared__ u64 hist[C];
-  __shared__ __align__(8) uint16_t lut_lds[K == 4 ? 4096 : 4];
+  __shared__ uint16_t lut_lds[K == 4 ? 4096 : 1];
   __shared__ int32_t cnt[NL], nzl[NL], nz_count;
   __shared__ uint32_t Mc[27];
   __shared__ uint32_t W[HUBS * 9];
@@ -835,9 +835,15 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
   };
   // contribution of one edge between slots S1 (x) and S2 (y) of weight w
   auto edge = [&](uint32_t base, uint32_t Lx, uint32_t Ly, uint32_t r, u64 w) {
-    const uint64_t q = lut_quad(lut, base | slot_code<K, S1>(Lx) | slot_code<K, S2>(Ly));
-    atomicAdd(&hist[quad_at(q, r)], w);
-    atomicAdd(&hist[quad_at(q, 0)], (u64)0 - w);
+    const uint32_t c0 = base | slot_code<K, S1>(Lx) | slot_code<K, S2>(Ly);
+    if constexpr (K == 5) {
+      const uint64_t q = lut_quad(lut, c0);
+      atomicAdd(&hist[quad_at(q, r)], w);
+      atomicAdd(&hist[quad_at(q, 0)], (u64)0 - w);
+    } else {
+      atomicAdd(&hist[lut[c0 | rel_code<K>(r)]], w);
+      atomicAdd(&hist[lut[c0]], (u64)0 - w);
+    }
   };
   // k = 4: the same move counted in the anchor's table T at (min label, max
   // label, arc type seen from the smaller label's member): swapping the two
@@ -862,12 +868,11 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
       T[3 * t + 2] = 0u;
     }
     const u64 w0 = (La == Lb ? na * (na - (na > 0)) / 2 : na * nb) - (u64)((int64_t)s1 + s2 + s3);
-    if (w0 == 0 && (s1 | s2 | s3) == 0) return;
-    const uint64_t q = lut_quad(lut, base | slot_code<K, S1>(La) | slot_code<K, S2>(Lb));
-    if (w0) atomicAdd(&hist[quad_at(q, 0)], w0);
-    if (s1) atomicAdd(&hist[quad_at(q, 1)], (u64)(int64_t)s1);
-    if (s2) atomicAdd(&hist[quad_at(q, 2)], (u64)(int64_t)s2);
-    if (s3) atomicAdd(&hist[quad_at(q, 3)], (u64)(int64_t)s3);
+    const uint32_t c0 = base | slot_code<K, S1>(La) | slot_code<K, S2>(Lb);
+    if (w0) atomicAdd(&hist[lut[c0]], w0);
+    if (s1) atomicAdd(&hist[lut[c0 | rel_code<K>(1u)]], (u64)(int64_t)s1);
+    if (s2) atomicAdd(&hist[lut[c0 | rel_code<K>(2u)]], (u64)(int64_t)s2);
+    if (s3) atomicAdd(&hist[lut[c0 | rel_code<K>(3u)]], (u64)(int64_t)s3);
   };
   // Flattened scan of the N+ rows of the vertices pick(0 .. items-1): pick
   // returns a vertex (or -1) and does the per-vertex work, visit(v, f, info)
@@ -2288,12 +2293,12 @@ int32_t cost_cap(int64_t gs_cap) {
 }  // namespace
 
 std::vector<uint16_t> device_lut_order(int k, const uint16_t* lut, size_t len) {
-  if (k != 4 && k != 5) return std::vector<uint16_t>(lut, lut + len);
+  if (k != 5) return std::vector<uint16_t>(lut, lut + len);
   // row-major bit n of the arc (i, j) goes to bit to[n]
   int to[20] = {};
   for (int i = 0, n = 0; i < k; ++i)
     for (int j = 0; j < k; ++j)
-      if (i != j) to[n++] = k == 4 ? cbit<4>(i, j) : cbit<5>(i, j);
+      if (i != j) to[n++] = cbit<5>(i, j);
   const int bits = k * (k - 1);
   std::vector<uint16_t> out(len);
   for (size_t x = 0; x < len; ++x) {
