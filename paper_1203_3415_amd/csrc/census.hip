@@ -1370,37 +1370,33 @@ __global__ __launch_bounds__(BLOCK) void kr_kernel(DevGraph G, const uint16_t* _
     return kT5;
   };
   // moves of one edge q -> y (r = type of y relative to q, sign s): the edge
-  // terms of anchor() with the pair that cancels when y is in R' left out
-  // (the table reads of all three terms are issued before their counters)
+  // terms of anchor() with the pair that cancels when y is in R' left out.
+  // Of its three terms the first (y outside the sides and R', core-labelled)
+  // and the third (y a side or in R') never apply together and carry the
+  // same signs, so they share one table read and one pair of counters; the
+  // table reads are issued before the counters.
   auto emove = [&](uint32_t base, uint32_t Lq, bool mq, uint32_t Ly, bool sy, uint32_t r, u64 s) {
     const bool it = sy || (Ly >> 2);
     const uint32_t cq = Lq & 3u, cy = Ly & 3u;
-    const bool e1 = cq && cy && !it, e2 = mq && !sy, e3 = cq && it && !sy;
-    const uint32_t b1 = base | slot_code<K, S1>(cq) | slot_code<K, S2>(cy);
+    const bool e13 = cq && (it ? !sy : cy != 0u), e2 = mq && !sy;
+    const uint32_t b13 = base | slot_code<K, S1>(cq) | slot_code<K, S2>(it ? Ly : cy);
     const uint32_t b2 = base | slot_code<K, S1>(Lq) | slot_code<K, S2>(Ly);
-    const uint32_t b3 = base | slot_code<K, S1>(cq) | slot_code<K, S2>(Ly);
-    const uint64_t q1 = e1 ? lut_quad(lut, b1) : 0ull;
+    const uint64_t q13 = e13 ? lut_quad(lut, b13) : 0ull;
     const uint64_t q2 = e2 ? lut_quad(lut, b2) : 0ull;
-    const uint64_t q3 = e3 ? lut_quad(lut, b3) : 0ull;
-    if (e1) {
-      atomicAdd(&hist[quad_at(q1, r)], (u64)0 - s);
-      atomicAdd(&hist[quad_at(q1, 0)], s);
+    if (e13) {
+      atomicAdd(&hist[quad_at(q13, r)], (u64)0 - s);
+      atomicAdd(&hist[quad_at(q13, 0)], s);
     }
     if (e2) {
       atomicAdd(&hist[quad_at(q2, r)], s);
       atomicAdd(&hist[quad_at(q2, 0)], (u64)0 - s);
     }
-    if (e3) {
-      atomicAdd(&hist[quad_at(q3, r)], (u64)0 - s);
-      atomicAdd(&hist[quad_at(q3, 0)], s);
-    }
   };
   auto umove = [&](uint32_t Lq, bool mq, uint32_t Ly, bool sy, uint32_t r) {
     const bool it = sy || (Ly >> 2);
     const uint32_t cq = Lq & 3u, cy = Ly & 3u;
-    if (cq && cy && !it) atomicAdd(&U5[u5i(cq, cy, r)], ~0u);
+    if (cq && (it ? !sy : cy != 0u)) atomicAdd(&U5[u5i(cq, it ? Ly : cy, r)], ~0u);
     if (mq && !sy) atomicAdd(&U5[u5i(Lq, Ly, r)], 1u);
-    if (cq && it && !sy) atomicAdd(&U5[u5i(cq, Ly, r)], ~0u);
   };
   auto pairs2 = [](u64 t) { return (t | (t >> 1)) & 0x5555555555555555ull; };  // bit 2p: partner p present
   auto t5_get = [&](uint32_t v, uint32_t lv, u64& t, int32_t& pv) {
