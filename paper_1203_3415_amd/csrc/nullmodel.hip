@@ -138,7 +138,10 @@ __device__ __forceinline__ void sw_barrier() {
 // the graph is held in LDS ((n + 1) + m + n words, + n target claims when
 // MUT), kSwLds / PER_CU words: with PER_CU = 2 two workgroups share a CU
 // (a round is a short chain of LDS reads between barriers, and a second
-// workgroup fills the gaps), for lists whose graphs all fit in half.
+// workgroup fills the gaps), for lists whose graphs all fit in half.  When
+// the words left over hold a 16-bit source row per arc slot (n <= 65,536),
+// the rows of a round's two slots are read from that table instead of a
+// binary search of the offsets (a switch moves targets, never slots).
 // Otherwise it is switched in place in global memory with this
 // workgroup's lock slice glock + blockIdx.x * lock_stride (lock_stride >= n,
 // or 2n when MUT, of every listed graph).  MUT: the slots ordered by kind go
@@ -182,6 +185,17 @@ __global__ __launch_bounds__(kSwB, PER_CU * kSwB / 256) void k_switch(const Swit
       if constexpr (MUT) claim = lock + n;
     }
     sw_barrier<LDS>();
+    const uint16_t* srow = nullptr;  // source row of each slot, when it fits (uniform per graph)
+    if constexpr (LDS) {
+      const int64_t used = (int64_t)(n + 1) + m + (MUT ? 2 : 1) * (int64_t)n;
+      if (n <= 65536 && used + (m + 1) / 2 <= kSwLds / PER_CU) {
+        uint16_t* s16 = reinterpret_cast<uint16_t*>(lds + used);
+        for (int32_t i = tid; i < m; i += kSwB) s16[i] = (uint16_t)row_of(off, n, i);
+        srow = s16;
+        sw_barrier<LDS>();
+      }
+    }
+    auto slot_row = [&](int32_t i) { return srow ? (int32_t)srow[i] : row_of(off, n, i); };
     int32_t* perm = nullptr;  // MUT: slot indices, reciprocated first, each kind in slot order
     int32_t nmut = 0;         // MUT: reciprocated slots
     if constexpr (MUT) {
@@ -190,7 +204,7 @@ __global__ __launch_bounds__(kSwB, PER_CU * kSwB / 256) void k_switch(const Swit
       const int32_t lane = (int32_t)(tid & 63u), wv = (int32_t)(tid >> 6);
       int32_t mine = 0;
       for (int32_t i = tid; i < m; i += kSwB) {
-        const int32_t a = row_of(off, n, i), b = idx[i] & kTarget;
+        const int32_t a = slot_row(i), b = idx[i] & kTarget;
         if (row_has(idx, off[b], off[b + 1], a)) {
           idx[i] |= kMutualBit;
           ++mine;
@@ -246,7 +260,7 @@ __global__ __launch_bounds__(kSwB, PER_CU * kSwB / 256) void k_switch(const Swit
         j = perm[lo + (int32_t)(((x >> 32) * (uint64_t)nk) >> 32)];
         i = perm[i];
       }
-      const int32_t a = row_of(off, n, i), c = row_of(off, n, j);
+      const int32_t a = slot_row(i), c = slot_row(j);
       const bool cand = a != c;  // two arcs of one row: the switch changes nothing
       if (cand) {
         lock_min<LDS>(&lock[a], tid);
