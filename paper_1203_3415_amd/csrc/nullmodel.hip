@@ -250,26 +250,43 @@ __global__ __launch_bounds__(kSwB, PER_CU * kSwB / 256) void k_switch(const Swit
       __syncthreads();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    for (int64_t r = 0; r < G.rounds; ++r) {
-      const uint64_t x = sm64_mix(G.key + (uint64_t)(r * kSwB + tid + 1) * kGamma);
-      int32_t i = (int32_t)(((x & 0xFFFFFFFFull) * (uint64_t)m) >> 32);
-      int32_t j = (int32_t)(((x >> 32) * (uint64_t)m) >> 32);
-      if constexpr (MUT) {  // first slot uniform, second uniform among the slots of its kind
-        const bool km = i < nmut;
-        const int32_t lo = km ? 0 : nmut, nk = km ? nmut : m - nmut;
-        j = perm[lo + (int32_t)(((x >> 32) * (uint64_t)nk) >> 32)];
-        i = perm[i];
+    // Round-tagged reservations (one-way switches in LDS): a reservation
+    // word holds (round + 1) << 11 | (2047 - index) and is raised with
+    // atomicMax, so within a round the largest word is the lowest proposal
+    // index, the winner atomicMin gives on cleared words, and words of
+    // earlier rounds never win.  Two sets are used on alternate rounds: a
+    // set is raised again only two rounds later, after a barrier that every
+    // reader of its earlier round has passed, so nothing is cleared and a
+    // round needs one barrier instead of three.  The switches are the same.
+    // Taken when n more words fit beside the source rows and the tags stay
+    // below 2^31.
+    uint32_t* lock2 = nullptr;
+    if constexpr (LDS && !MUT) {
+      const int64_t used = (int64_t)(n + 1) + m + n + (m + 1) / 2;
+      if (srow && used + n <= kSwLds / PER_CU && G.rounds < (int64_t(1) << 20)) {
+        lock2 = reinterpret_cast<uint32_t*>(lds + used);
+        for (int32_t i = tid; i < n; i += kSwB) {
+          lock[i] = 0u;
+          lock2[i] = 0u;
+        }
+        sw_barrier<LDS>();
       }
-      const int32_t a = slot_row(i), c = slot_row(j);
-      const bool cand = a != c;  // two arcs of one row: the switch changes nothing
-      if (cand) {
-        lock_min<LDS>(&lock[a], tid);
-        lock_min<LDS>(&lock[c], tid);
-      }
-      sw_barrier<LDS>();
-      if constexpr (!MUT) {
-        if (cand && lock_get<LDS>(&lock[a]) == tid && lock_get<LDS>(&lock[c]) == tid) {
-          // rows a and c are this proposal's alone until the next barrier
+    }
+    if (lock2) {
+      for (int64_t r = 0; r < G.rounds; ++r) {
+        const uint64_t x = sm64_mix(G.key + (uint64_t)(r * kSwB + tid + 1) * kGamma);
+        const int32_t i = (int32_t)(((x & 0xFFFFFFFFull) * (uint64_t)m) >> 32);
+        const int32_t j = (int32_t)(((x >> 32) * (uint64_t)m) >> 32);
+        const int32_t a = slot_row(i), c = slot_row(j);
+        const bool cand = a != c;
+        uint32_t* L = (r & 1) ? lock2 : lock;
+        const uint32_t v = ((uint32_t)(r + 1) << 11) | (2047u - tid);
+        if (cand) {
+          atomicMax(&L[a], v);
+          atomicMax(&L[c], v);
+        }
+        sw_barrier<LDS>();
+        if (cand && L[a] == v && L[c] == v) {
           const int32_t b = idx[i], d = idx[j];
           const bool ok = a != d && c != b && b != d && !row_has(idx, off[a], off[a + 1], d) &&
                           !row_has(idx, off[c], off[c + 1], b);
@@ -278,58 +295,90 @@ __global__ __launch_bounds__(kSwB, PER_CU * kSwB / 256) void k_switch(const Swit
             idx[j] = b;
           }
         }
-        sw_barrier<LDS>();
+      }
+      sw_barrier<LDS>();  // the last round's switches before the write-back
+    } else {
+      for (int64_t r = 0; r < G.rounds; ++r) {
+        const uint64_t x = sm64_mix(G.key + (uint64_t)(r * kSwB + tid + 1) * kGamma);
+        int32_t i = (int32_t)(((x & 0xFFFFFFFFull) * (uint64_t)m) >> 32);
+        int32_t j = (int32_t)(((x >> 32) * (uint64_t)m) >> 32);
+        if constexpr (MUT) {  // first slot uniform, second uniform among the slots of its kind
+          const bool km = i < nmut;
+          const int32_t lo = km ? 0 : nmut, nk = km ? nmut : m - nmut;
+          j = perm[lo + (int32_t)(((x >> 32) * (uint64_t)nk) >> 32)];
+          i = perm[i];
+        }
+        const int32_t a = slot_row(i), c = slot_row(j);
+        const bool cand = a != c;  // two arcs of one row: the switch changes nothing
         if (cand) {
-          lock_set<LDS>(&lock[a], kFree);
-          lock_set<LDS>(&lock[c], kFree);
-        }
-      } else {
-        // holds both source rows (then marked as held) and the two slots are of one kind
-        int32_t wi = 0, wj = 0;
-        bool held = cand && lock_get<LDS>(&lock[a]) == tid && lock_get<LDS>(&lock[c]) == tid;
-        if (held) {
-          lock_set<LDS>(&lock[a], tid | kHeld);
-          lock_set<LDS>(&lock[c], tid | kHeld);
-          wi = idx[i];
-          wj = idx[j];
-          held = (wi & kMutualBit) == (wj & kMutualBit);
-        }
-        const int32_t b = wi & kTarget, d = wj & kTarget;
-        if (held) {
-          lock_min<LDS>(&claim[b], tid);
-          lock_min<LDS>(&claim[d], tid);
+          lock_min<LDS>(&lock[a], tid);
+          lock_min<LDS>(&lock[c], tid);
         }
         sw_barrier<LDS>();
-        auto held_by_other = [&](int32_t row) {
-          return row != a && row != c && (lock_get<LDS>(&lock[row]) & kHeldMask) == kHeld;
-        };
-        if (held && lock_get<LDS>(&claim[b]) == tid && lock_get<LDS>(&claim[d]) == tid && !held_by_other(b) &&
-            !held_by_other(d)) {
-          // rows a, b, c and d are this proposal's alone until the next barrier
-          const bool ok = a != d && c != b && b != d && !row_has(idx, off[a], off[a + 1], d) &&
-                          !row_has(idx, off[d], off[d + 1], a) && !row_has(idx, off[c], off[c + 1], b) &&
-                          !row_has(idx, off[b], off[b + 1], c);
-          if (ok) {
-            const int32_t kind = wi & kMutualBit;
-            idx[i] = d | kind;
-            idx[j] = b | kind;
-            if (kind) {  // the reverse arcs: b->a becomes b->c, d->c becomes d->a
-              idx[row_find(idx, off[b], off[b + 1], a)] = c | kind;
-              idx[row_find(idx, off[d], off[d + 1], c)] = a | kind;
+        if constexpr (!MUT) {
+          if (cand && lock_get<LDS>(&lock[a]) == tid && lock_get<LDS>(&lock[c]) == tid) {
+            // rows a and c are this proposal's alone until the next barrier
+            const int32_t b = idx[i], d = idx[j];
+            const bool ok = a != d && c != b && b != d && !row_has(idx, off[a], off[a + 1], d) &&
+                            !row_has(idx, off[c], off[c + 1], b);
+            if (ok) {
+              idx[i] = d;
+              idx[j] = b;
             }
+          }
+          sw_barrier<LDS>();
+          if (cand) {
+            lock_set<LDS>(&lock[a], kFree);
+            lock_set<LDS>(&lock[c], kFree);
+          }
+        } else {
+          // holds both source rows (then marked as held) and the two slots are of one kind
+          int32_t wi = 0, wj = 0;
+          bool held = cand && lock_get<LDS>(&lock[a]) == tid && lock_get<LDS>(&lock[c]) == tid;
+          if (held) {
+            lock_set<LDS>(&lock[a], tid | kHeld);
+            lock_set<LDS>(&lock[c], tid | kHeld);
+            wi = idx[i];
+            wj = idx[j];
+            held = (wi & kMutualBit) == (wj & kMutualBit);
+          }
+          const int32_t b = wi & kTarget, d = wj & kTarget;
+          if (held) {
+            lock_min<LDS>(&claim[b], tid);
+            lock_min<LDS>(&claim[d], tid);
+          }
+          sw_barrier<LDS>();
+          auto held_by_other = [&](int32_t row) {
+            return row != a && row != c && (lock_get<LDS>(&lock[row]) & kHeldMask) == kHeld;
+          };
+          if (held && lock_get<LDS>(&claim[b]) == tid && lock_get<LDS>(&claim[d]) == tid && !held_by_other(b) &&
+              !held_by_other(d)) {
+            // rows a, b, c and d are this proposal's alone until the next barrier
+            const bool ok = a != d && c != b && b != d && !row_has(idx, off[a], off[a + 1], d) &&
+                            !row_has(idx, off[d], off[d + 1], a) && !row_has(idx, off[c], off[c + 1], b) &&
+                            !row_has(idx, off[b], off[b + 1], c);
+            if (ok) {
+              const int32_t kind = wi & kMutualBit;
+              idx[i] = d | kind;
+              idx[j] = b | kind;
+              if (kind) {  // the reverse arcs: b->a becomes b->c, d->c becomes d->a
+                idx[row_find(idx, off[b], off[b + 1], a)] = c | kind;
+                idx[row_find(idx, off[d], off[d + 1], c)] = a | kind;
+              }
+            }
+          }
+          sw_barrier<LDS>();
+          if (cand) {
+            lock_set<LDS>(&lock[a], kFree);
+            lock_set<LDS>(&lock[c], kFree);
+          }
+          if (held) {
+            lock_set<LDS>(&claim[b], kFree);
+            lock_set<LDS>(&claim[d], kFree);
           }
         }
         sw_barrier<LDS>();
-        if (cand) {
-          lock_set<LDS>(&lock[a], kFree);
-          lock_set<LDS>(&lock[c], kFree);
-        }
-        if (held) {
-          lock_set<LDS>(&claim[b], kFree);
-          lock_set<LDS>(&claim[d], kFree);
-        }
       }
-      sw_barrier<LDS>();
     }
     if constexpr (LDS) {
       for (int32_t i = tid; i < m; i += kSwB) G.idx[i] = idx[i] & kTarget;
